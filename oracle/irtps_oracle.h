@@ -1,0 +1,114 @@
+/*
+ * irtps_oracle.h -- plain, slow CPU oracle of Iterative Ray-Tracing Photometric
+ * Stereo (IRT-PS; Khadka, Remagnino, Argyriou, "Object 3D Reconstruction based on
+ * Photometric Stereo and Inverted Rendering", arXiv 1811.02357).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent checker of the HIP
+ * path: only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant generator
+ * with the GPU library.
+ *
+ * Precision.  The paper fixes none.  Every value of the IRT loop (normals, albedo,
+ * heights, gathered radiance) feeds the ray-surface hit tests of the next
+ * iteration, and a hit test is a floating-point comparison that decides an
+ * integer (which sample is hit).  The oracle therefore takes the loop in the
+ * kernel's precision, IEEE binary32, with one stated operation order: every
+ * fused multiply-add is written as fmaf, every other operation rounds on its own
+ * (built with -ffp-contract=off), divisions and square roots are correctly
+ * rounded, and no transcendental function enters compared arithmetic.  Closed
+ * forms and exact solvers that pin this oracle are evaluated in binary64.
+ *
+ * Layouts (row-major, W = width = columns i, Hh = height = rows j, p = j*W + i):
+ *   heights H[Hh][W], normals n[Hh][W][3], albedo rho[C][Hh][W],
+ *   images / gathered radiance / indirect estimate [K][C][Hh][W],
+ *   direct irradiance S[Hh][W][K], environment env[He][We][C] (radiance).
+ */
+#ifndef IRTPS_ORACLE_H
+#define IRTPS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_TAG_SOLVE = 0, OR_TAG_RENDER = 1 };
+enum { OR_RHO_FIT = 0, OR_RHO_PREV = 1 };
+enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2 };
+enum { OR_MISS = 0, OR_HIT = 1 };
+
+/* counters of one trace: [0] segments, [1] hits, [2] escapes, [3] continuations */
+typedef struct { uint64_t v[4]; } or_counters;
+
+/* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* sin and cos of a quarter turn times f, f in [0,1), by truncated Taylor series. */
+float or_sin_quarter(float f);
+float or_cos_quarter(float f);
+/* atan2 in binary32 by octant reduction and the arctangent series; result in [-pi, pi]. */
+float or_atan2(float y, float x);
+
+/* Cosine-weighted direction about unit normal n from uniforms (u1,u2) (Malley). */
+void or_sample_cosine(const float n[3], float u1, float u2, float d[3]);
+/* Equirectangular nearest texel of direction d: row from polar angle, column from azimuth. */
+void or_env_texel(const float d[3], int He, int We, int* row, int* col);
+
+/* First crossing of a ray from sample (i0,j0) along d that lies strictly below the
+ * grid-line surface.  Returns OR_HIT and the shading sample (qi,qj), or OR_MISS. */
+int or_traverse(const float* H, int W, int Hh, float hmax, int i0, int j0,
+                const float d[3], int* qi, int* qj);
+
+/* Eq.4 solve matrix M = (L^T L)^-1 L^T, L rows = s_k l_k, built in binary64 and
+ * rounded to binary32.  M is [3][K].  Returns 0, or -1 if K < 3 or the lights are
+ * (nearly) coplanar. */
+int or_ps_matrix(int K, const float* l, const float* s, float* M);
+
+/* Eq.4 per pixel: g_c = M A_c, rho_c = |g_c|, n = (sum_c g_c)/|sum_c g_c|. */
+void or_ps_solve(int W, int Hh, int C, int K, const float* M, const float* A,
+                 float* n, float* rho);
+
+/* Direct irradiance S[q][k] = s_k max(0, n(q).l_k) V_k(q) (Eq.2 without albedo). */
+void or_direct(int W, int Hh, int K, const float* H, const float* n,
+               const float* l, const float* s, float* S);
+
+/* Monte Carlo gather of indirect light (Eq.5-7): G[k][c][p]. */
+void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
+              const float* rho, const float* S, const float* env, int He, int We,
+              int spp, int B, uint64_t seed, int t, int tag, int flags,
+              float* G, or_counters* cnt);
+
+/* Stage-5 subtraction: E = rho~ G, A_next = I0 - E (or A_prev - E). */
+void or_correct(int W, int Hh, int C, int K, int rho_mode, int flags,
+                const float* I0, const float* Aprev, const float* G, const float* S,
+                const float* rho, float* E, float* Anext);
+
+/* Least-squares integration of the normal field into heights, min(H) = 0. */
+void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles, float* H);
+
+/* Forward render I0 = rho (S + G) of a ground-truth surface (tag RENDER). */
+int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
+              const float* rho, const float* l, const float* s, const float* env,
+              int He, int We, int spp, int B, uint64_t seed, float* I0, or_counters* cnt);
+
+/* The whole IRT-PS loop.  Returns 0 or -1 (singular lights). */
+int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
+             const float* s, const float* env, int He, int We, int spp, int B,
+             int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
+             int cycles_warm, float* n, float* rho, float* H, float* E,
+             or_counters* cnt);
+
+/* Element-wise batch forms (independent calls), used by the exhaustive checks. */
+void or_sincos_quarter_n(long long count, const float* f, float* s, float* c);
+void or_atan2_n(long long count, const float* y, const float* x, float* a);
+void or_traverse_n(const float* H, int W, int Hh, long long count, const int* ij,
+                   const float* d, int* q);
+void or_sample_cosine_n(long long count, const float* n, const float* u, float* d);
+void or_env_texel_n(long long count, const float* d, int He, int We, int* rc);
+void or_philox_n(long long count, const uint32_t* ctr, const uint32_t key[2], uint32_t* out);
+
+int or_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
