@@ -1,0 +1,235 @@
+/*
+ * irtps.h -- C ABI of the MI355X (gfx950) implementation of Iterative Ray-Tracing
+ * Photometric Stereo (IRT-PS): Khadka, Remagnino, Argyriou, "Object 3D
+ * Reconstruction based on Photometric Stereo and Inverted Rendering",
+ * arXiv 1811.02357.
+ *
+ * The problem is the paper's: K images of a Lambertian object taken from one
+ * viewpoint under calibrated distant lights (Sec. III, Eq.2-3), with the
+ * surroundings known (Sec. IV, stages 0, 3, 4).  The library returns the
+ * per-pixel normals and albedo (Eq.4), the integrated surface H_t (Sec. IV,
+ * stage 1) and the estimated indirect light E_t (Sec. IV, stage 5).
+ *
+ * Conventions (all calls):
+ *   - Sample (i, j) is world (x, y) = (i, j): i is the column in [0, W), j the row
+ *     in [0, H); heights are in pixel units; z points towards the orthographic
+ *     camera.  A light direction is a unit vector from the surface towards the
+ *     light; its intensity is the irradiance it gives at normal incidence.
+ *   - An image value is albedo x irradiance (Eq.2).  Environment texels are
+ *     radiance on an equirectangular map: row r covers polar angle
+ *     [r pi/He, (r+1) pi/He) from +z, column c covers azimuth
+ *     [2 pi c/We, 2 pi (c+1)/We) from +x towards +y.
+ *   - Layouts are row-major float32: images, gathered and indirect radiance
+ *     [K][C][H][W]; normals [H][W][3]; albedo [C][H][W]; depth [H][W];
+ *     direct irradiance [H][W][K]; environment [He][We][C].  C is 1 or 3,
+ *     W and H are 2..16384 with W H <= 2^28, K is 3..64.
+ *   - Pointers named *_dev are device memory (any hipMalloc'd or
+ *     caching-allocator memory of the current device); pointers named *_host
+ *     are host memory read before the call returns.  The caller owns every
+ *     buffer; the library never frees caller memory and never keeps a pointer
+ *     after the call, except the server (see below).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it and the call returns without waiting;
+ *     device faults surface on a later call or on stream synchronisation.
+ *   - Every call returns an irtps_status.  No exception or abort crosses the
+ *     ABI.  NaN inputs are not checked.  Results are deterministic: the same
+ *     inputs, parameters and seed give the same bits, alone, batched or served.
+ */
+#ifndef IRTPS_H
+#define IRTPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IRTPS_ABI_VERSION 1
+
+typedef enum irtps_status {
+    IRTPS_OK = 0,
+    IRTPS_ERR_INVALID_ARG = 1,     /* a size, pointer or parameter out of range */
+    IRTPS_ERR_SINGULAR_LIGHTS = 2, /* K < 3 or the lights are (nearly) coplanar (Eq.4) */
+    IRTPS_ERR_WORKSPACE = 3,       /* workspace missing or smaller than required */
+    IRTPS_ERR_OOM = 4,             /* server: job larger than the memory budget */
+    IRTPS_ERR_DEVICE = 5,          /* a HIP call failed: see irtps_last_hip_error() */
+    IRTPS_ERR_CANCELLED = 6,       /* server: the job was cancelled */
+    IRTPS_ERR_NOT_FOUND = 7,       /* server: unknown job id */
+    IRTPS_ERR_BUSY = 8             /* server: job still queued or running */
+} irtps_status;
+
+/* Albedo used to turn the gathered radiance into the indirect image (stage 5). */
+enum {
+    IRTPS_RHO_FIT = 0,  /* albedo fitted per pixel to I0 = rho (S + G) over the K images */
+    IRTPS_RHO_PREV = 1  /* the previous photometric-stereo albedo rho_t (literal) */
+};
+
+/* Option bits of irtps_params.flags and of irtps_trace. */
+enum {
+    IRTPS_FLAG_QUADRATURE = 1,         /* first segment on sqrt(spp)^2 stratum midpoints */
+    IRTPS_FLAG_LITERAL_CUMULATIVE = 2, /* A_{t+1} = A_t - E_t instead of I0 - E_t */
+    IRTPS_FLAG_FLAT_TRAVERSAL = 4      /* walk every grid-line crossing (no pyramid skips) */
+};
+
+/* Sample-stream tags (word 3 of the Philox counter). */
+enum { IRTPS_TAG_SOLVE = 0, IRTPS_TAG_RENDER = 1 };
+
+/* Counters of traced segments, accumulated by the trace kernels into a device
+ * array of four uint64: [0] segments, [1] surface hits, [2] escapes to the
+ * environment, [3] continuations (hits that start another segment). */
+#define IRTPS_NUM_COUNTERS 4
+
+typedef struct irtps_problem {
+    int32_t width, height, channels, num_lights; /* W, H, C in {1,3}, K in 3..64 */
+    const float* images_dev;          /* [K][C][H][W] input images I0 (stage 0) */
+    const float* light_dirs_host;     /* [K][3] unit, towards the light, z > 0 */
+    const float* light_intensity_host;/* [K] or NULL (all 1) */
+    const float* env_dev;             /* [He][We][C] radiance of the known surroundings */
+    int32_t env_h, env_w;             /* He, We >= 1 */
+} irtps_problem;
+
+typedef struct irtps_params {
+    int32_t spp;            /* paths per pixel and iteration, >= 1 */
+    int32_t bounces;        /* B: segments per path, 0..8 (Sec. IV: up to 3 reflections) */
+    int32_t iterations;     /* T >= 0 tracer passes; T + 1 PS + integration passes */
+    int32_t rho_mode;       /* IRTPS_RHO_FIT (default) or IRTPS_RHO_PREV */
+    int32_t flags;          /* IRTPS_FLAG_* */
+    int32_t mg_cycles_cold; /* V-cycles of the first integration (0 = 8) */
+    int32_t mg_cycles_warm; /* V-cycles of each warm-started integration (0 = 4) */
+    int32_t reserved;       /* must be 0 */
+    uint64_t seed;          /* Philox key */
+} irtps_params;
+
+typedef struct irtps_outputs {
+    float* normals_dev;   /* [H][W][3] n_T */
+    float* albedo_dev;    /* [C][H][W] rho_T */
+    float* depth_dev;     /* [H][W] H_T, pixel units, min(H_T) = 0 */
+    float* indirect_dev;  /* [K][C][H][W] E_{T-1} (zeros for T = 0), or NULL */
+    uint64_t* counters_dev; /* IRTPS_NUM_COUNTERS uint64 accumulated over the solve, or NULL */
+} irtps_outputs;
+
+/* ---- library ------------------------------------------------------------ */
+int irtps_abi_version(void);
+const char* irtps_status_string(int status);
+/* The hipError_t of the last failed HIP call made by the library on this thread. */
+int irtps_last_hip_error(void);
+
+/* ---- Eq.4 solve matrix (host only) --------------------------------------- */
+/* M = (L^T L)^-1 L^T with rows of L = s_k l_k (Sec. III, Eq.3-4), computed in
+ * binary64 with the 3x3 adjugate and rounded to float.  M_host is [3][K].
+ * Returns IRTPS_ERR_SINGULAR_LIGHTS when K < 3 or det(L^T L) <= 1e-7 (tr/3)^3. */
+int irtps_ps_matrix(int32_t K, const float* light_dirs_host,
+                    const float* light_intensity_host, float* M_host);
+
+/* ---- whole IRT-PS solve (Sec. IV, stages 1-5 iterated) ----------------- */
+/* Bytes of device workspace irtps_solve needs for this problem and params. */
+int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* params,
+                          size_t* bytes);
+/* t = 0: PS of I0 (Eq.4) and integration; then T times: trace the current
+ * surface (Eq.5-7), subtract the indirect estimate (stage 5), PS and integrate
+ * warm-started from H_t.  ws_dev must hold irtps_workspace_bytes() bytes,
+ * 256-byte aligned. */
+int irtps_solve(const irtps_problem* problem, const irtps_params* params,
+                const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
+                void* stream);
+
+/* ---- stages (teacher-forced parity and custom loops) -------------------- */
+/* Eq.4 per pixel: g_c = M A_c, albedo_c = |g_c|, normal = sum_c g_c / |sum_c g_c|
+ * ((0,0,1) where that sum is 0).  A_dev is [K][C][H][W]. */
+int irtps_ps_solve(int32_t W, int32_t H, int32_t C, int32_t K,
+                   const float* light_dirs_host, const float* light_intensity_host,
+                   const float* A_dev, float* normals_dev, float* albedo_dev, void* stream);
+
+/* Bytes of workspace for irtps_integrate. */
+int irtps_integrate_workspace_bytes(int32_t W, int32_t H, size_t* bytes);
+/* Least-squares integration of the normals (Sec. IV, stage 1): edge height
+ * differences fitted to the mean end-point gradients -(n_x, n_y)/max(n_z, 0.05);
+ * `cycles` multigrid V-cycles (free boundaries) started from depth_init_dev
+ * (or from 0 if NULL; it may equal depth_dev); result shifted to min 0. */
+int irtps_integrate(int32_t W, int32_t H, const float* normals_dev,
+                    const float* depth_init_dev, int32_t cycles, float* depth_dev,
+                    void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Bytes of the min-max pyramid of a W x H surface. */
+int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes);
+/* Per level l, cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l]
+ * and stores the max over that box grown by one sample on each side; the top
+ * level is the global maximum. */
+int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyramid_dev,
+                        void* stream);
+
+/* Direct irradiance without albedo (Eq.2): S[q][k] = s_k max(0, n(q).l_k) V_k(q),
+ * V_k = 1 when the shadow ray from sample q towards light k escapes the surface.
+ * pyramid_dev from irtps_build_pyramid of the same depth.  S_dev is [H][W][K]. */
+int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev,
+                 const float* normals_dev, const float* light_dirs_host,
+                 const float* light_intensity_host, const float* pyramid_dev,
+                 float* S_dev, void* stream);
+
+/* Monte Carlo gather of indirect light (Sec. IV, Eq.5-7): per pixel, spp
+ * cosine-weighted paths of up to B segments on the current surface.  A hit at
+ * sample q adds beta_c albedo_c(q) S[q][k] for every light k; an escape adds
+ * beta_c pi L_env,c(d) and ends the path; beta is the product of the albedos
+ * met so far.  G_dev[k][c][p] = (sum over paths) / spp.  Sample s, segment b of
+ * pixel p = j W + i draw Philox4x32-10(key = seed, counter = (p, s, t 256 + b,
+ * tag)).  counters_dev (IRTPS_NUM_COUNTERS uint64, accumulated) may be NULL. */
+int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev,
+                const float* normals_dev, const float* albedo_dev, const float* S_dev,
+                const float* env_dev, int32_t env_h, int32_t env_w,
+                const float* pyramid_dev, int32_t spp, int32_t B, uint64_t seed,
+                int32_t t, int32_t tag, int32_t flags, float* G_dev,
+                uint64_t* counters_dev, void* stream);
+
+/* Stage 5: E = rho~ G and A_next = I0 - E (or A_prev - E with
+ * IRTPS_FLAG_LITERAL_CUMULATIVE).  rho~ per IRTPS_RHO_*: the fit is
+ * sum_k I0 (S + G) / sum_k (S + G)^2 (0 where the denominator is 0).
+ * E_dev may be NULL; A_prev_dev is read only in the cumulative mode. */
+int irtps_correct(int32_t W, int32_t H, int32_t C, int32_t K, int32_t rho_mode,
+                  int32_t flags, const float* I0_dev, const float* A_prev_dev,
+                  const float* G_dev, const float* S_dev, const float* albedo_dev,
+                  float* E_dev, float* A_next_dev, void* stream);
+
+/* Bytes of workspace for irtps_render. */
+int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, size_t* bytes);
+/* Forward render of a known surface (Sec. III, n-bounce sum truncated at B + 1):
+ * images = albedo (S + G) with G traced under tag RENDER, t = 0.  B = 0 renders
+ * direct light only. */
+int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev,
+                 const float* normals_dev, const float* albedo_dev,
+                 const float* light_dirs_host, const float* light_intensity_host,
+                 const float* env_dev, int32_t env_h, int32_t env_w, int32_t spp,
+                 int32_t B, uint64_t seed, float* images_dev, void* ws_dev,
+                 size_t ws_bytes, void* stream);
+
+/* ---- timing of the tracer ------------------------------------------------ */
+/* irtps_profile_begin() makes this thread's later calls record a hipEvent pair
+ * around every tracer launch on the call's stream; irtps_profile_end() waits for
+ * those events, returns the summed elapsed milliseconds and the number of
+ * launches, destroys the events and stops recording.  Either pointer may be NULL. */
+int irtps_profile_begin(void);
+int irtps_profile_end(double* trace_ms, int64_t* launches);
+
+/* ---- probes of the device arithmetic (parity checks) -------------------- */
+/* Philox4x32-10 of count counters [count][4] under key (seed lo, hi) -> out [count][4]. */
+int irtps_probe_philox(int64_t count, const uint32_t* ctr_dev, uint64_t seed,
+                       uint32_t* out_dev, void* stream);
+/* Cosine-weighted direction about normals [count][3] from uniforms [count][2]. */
+int irtps_probe_sample(int64_t count, const float* normals_dev, const float* u_dev,
+                       float* dirs_dev, void* stream);
+/* Equirectangular texel (row, col) of directions [count][3] -> rc [count][2]. */
+int irtps_probe_env_texel(int64_t count, const float* dirs_dev, int32_t env_h,
+                          int32_t env_w, int32_t* rc_dev, void* stream);
+/* First hit of rays from samples ij [count][2] along dirs [count][3] on a
+ * W x H surface with its pyramid (irtps_build_pyramid); q [count][2] = shading
+ * sample, or (-1, -1) on escape.  flat != 0 walks every crossing, flat == 0
+ * skips pyramid cells; both must give the same q. */
+int irtps_probe_traverse(int32_t W, int32_t H, const float* depth_dev,
+                         const float* pyramid_dev, int32_t flat, int64_t count,
+                         const int32_t* ij_dev, const float* dirs_dev, int32_t* q_dev,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRTPS_H */

@@ -658,9 +658,12 @@ void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles,
         }
     if (Hinit) memcpy(X[0], Hinit, sizeof(float) * npx);
     for (int c = 0; c < cycles; ++c) mg_vcycle(lv, nlev, 0, W, Hh, X, b, r);
-    float mn = X[0][0];
-    for (size_t v = 1; v < npx; ++v)
-        if (X[0][v] < mn) mn = X[0][v];
+    /* the minimum is taken over X + 0, so that a -0 and a +0 count as one zero */
+    float mn = X[0][0] + 0.0f;
+    for (size_t v = 1; v < npx; ++v) {
+        const float x = X[0][v] + 0.0f;
+        if (x < mn) mn = x;
+    }
     for (size_t v = 0; v < npx; ++v) Hout[v] = X[0][v] - mn;
     for (int l = 0; l < nlev; ++l) {
         free(X[l]);

@@ -1,0 +1,539 @@
+// capi.cpp -- the C ABI of libirtps (include/irtps.h): validation, workspace
+// layout and the host side of the IRT-PS loop (Sec. IV of the paper).
+#include "irtps.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace irtps;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return IRTPS_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        const hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_);     \
+    } while (0)
+
+#define STATUS_TRY(expr)                               \
+    do {                                               \
+        const int s_ = (expr);                         \
+        if (s_ != IRTPS_OK) return s_;                 \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+// Event pairs around tracer launches while profiling is on (per thread).
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+thread_local Profiler g_prof;
+
+hipError_t traced(const kern::TraceArgs& ta, hipStream_t st) {
+    if (!g_prof.on) return kern::trace(ta, st);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = kern::trace(ta, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        return e;
+    }
+    g_prof.ev.emplace_back(a, b);
+    return hipSuccess;
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sides up to 16384 keep the pyramid within trv::kMaxLevels levels and every
+// pixel index within int32.
+bool dims_ok(int W, int H) { return W >= 2 && H >= 2 && W <= 16384 && H <= 16384 && (long long)W * H <= (1LL << 28); }
+bool channels_ok(int C) { return C == 1 || C == 3; }
+bool lights_ok(int K) { return K >= 3 && K <= kern::kMaxLights; }
+
+trv::Pyramid pyramid_plan(int W, int H) {
+    trv::Pyramid P{};
+    int wc = W - 1, hc = H - 1;
+    long long off = 0;
+    int l = 0;
+    for (;;) {
+        P.wc[l] = wc;
+        P.hc[l] = hc;
+        P.off[l] = off;
+        off += (long long)wc * hc;
+        ++l;
+        if (wc == 1 && hc == 1) break;
+        wc = (wc + 1) / 2;
+        hc = (hc + 1) / 2;
+    }
+    P.levels = l;
+    return P;
+}
+
+long long pyramid_floats(const trv::Pyramid& P) {
+    const int t = P.levels - 1;
+    return P.off[t] + (long long)P.wc[t] * P.hc[t];
+}
+
+kern::MgPlan mg_plan(int W, int H) {
+    kern::MgPlan m{};
+    m.W[0] = W;
+    m.H[0] = H;
+    m.levels = 1;
+    while ((m.W[m.levels - 1] > 4 || m.H[m.levels - 1] > 4) && m.levels < kern::kMaxMgLevels) {
+        m.W[m.levels] = (m.W[m.levels - 1] + 1) / 2;
+        m.H[m.levels] = (m.H[m.levels - 1] + 1) / 2;
+        ++m.levels;
+    }
+    long long off = 0;
+    for (int l = 0; l < m.levels; ++l) {
+        const long long n = (long long)m.W[l] * m.H[l];
+        m.xoff[l] = off;
+        off += (n + 63) / 64 * 64;
+        m.boff[l] = off;
+        off += (n + 63) / 64 * 64;
+    }
+    m.keyoff = off;
+    off += 64;
+    m.total = off;
+    return m;
+}
+
+// Eq.3-4 in binary64: A = L^T L, inverse by the adjugate, M = A^-1 L^T.
+int ps_matrix_host(int K, const float* l, const float* s, float* M) {
+    if (K < 3 || !l || !M) return K < 3 ? IRTPS_ERR_SINGULAR_LIGHTS : IRTPS_ERR_INVALID_ARG;
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < K; ++k) {
+        const double sk = s ? (double)s[k] : 1.0;
+        const double v[3] = {sk * (double)l[3 * k], sk * (double)l[3 * k + 1], sk * (double)l[3 * k + 2]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + v[a] * v[b];
+    }
+    double adj_t[3][3];  // cofactor matrix C[a][b]; inverse = C^T / det
+    adj_t[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    adj_t[0][1] = -(A[1][0] * A[2][2] - A[1][2] * A[2][0]);
+    adj_t[0][2] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    adj_t[1][0] = -(A[0][1] * A[2][2] - A[0][2] * A[2][1]);
+    adj_t[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+    adj_t[1][2] = -(A[0][0] * A[2][1] - A[0][1] * A[2][0]);
+    adj_t[2][0] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+    adj_t[2][1] = -(A[0][0] * A[1][2] - A[0][2] * A[1][0]);
+    adj_t[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const double det = A[0][0] * adj_t[0][0] + A[0][1] * adj_t[0][1] + A[0][2] * adj_t[0][2];
+    const double mean_eig = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+    if (!(det > 1e-7 * mean_eig * mean_eig * mean_eig)) return IRTPS_ERR_SINGULAR_LIGHTS;
+    for (int k = 0; k < K; ++k) {
+        const double sk = s ? (double)s[k] : 1.0;
+        const double v[3] = {sk * (double)l[3 * k], sk * (double)l[3 * k + 1], sk * (double)l[3 * k + 2]};
+        for (int a = 0; a < 3; ++a) {
+            const double i0 = adj_t[0][a] / det, i1 = adj_t[1][a] / det, i2 = adj_t[2][a] / det;
+            M[(size_t)a * K + k] = (float)(i0 * v[0] + i1 * v[1] + i2 * v[2]);
+        }
+    }
+    return IRTPS_OK;
+}
+
+int make_lights(int K, const float* l, const float* s, kern::LightSet& L) {
+    if (!lights_ok(K) || !l) return IRTPS_ERR_INVALID_ARG;
+    std::memset(&L, 0, sizeof(L));
+    L.K = K;
+    for (int k = 0; k < K; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(l[3 * k + a])) return IRTPS_ERR_INVALID_ARG;
+            L.l[k][a] = l[3 * k + a];
+        }
+        L.s[k] = s ? s[k] : 1.0f;
+        if (!std::isfinite(L.s[k])) return IRTPS_ERR_INVALID_ARG;
+    }
+    return IRTPS_OK;
+}
+
+int make_psmatrix(int K, const float* l, const float* s, kern::PsMatrix& M) {
+    if (!lights_ok(K)) return K < 3 ? IRTPS_ERR_SINGULAR_LIGHTS : IRTPS_ERR_INVALID_ARG;
+    float tmp[3 * kern::kMaxLights];
+    STATUS_TRY(ps_matrix_host(K, l, s, tmp));
+    std::memset(&M, 0, sizeof(M));
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < K; ++k) M.m[a][k] = tmp[(size_t)a * K + k];
+    return IRTPS_OK;
+}
+
+kern::SurfaceArgs surface(int W, int H, const float* depth, const float* pyr) {
+    kern::SurfaceArgs sa;
+    sa.H = depth;
+    sa.pyr = pyr;
+    sa.W = W;
+    sa.Hh = H;
+    sa.P = pyramid_plan(W, H);
+    return sa;
+}
+
+// Workspace layout of one solve (byte offsets, each 256-aligned).
+struct SolveLayout {
+    size_t A, S, G, pyr, mg, total;
+    kern::MgPlan plan;
+};
+
+SolveLayout solve_layout(int W, int H, int C, int K) {
+    SolveLayout L{};
+    const size_t npx = (size_t)W * H;
+    size_t off = 0;
+    L.A = off;
+    off = align_up(off + sizeof(float) * npx * K * C);
+    L.S = off;
+    off = align_up(off + sizeof(float) * npx * K);
+    L.G = off;
+    off = align_up(off + sizeof(float) * npx * K * C);
+    L.pyr = off;
+    off = align_up(off + sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H)));
+    L.plan = mg_plan(W, H);
+    L.mg = off;
+    off = align_up(off + sizeof(float) * (size_t)L.plan.total);
+    L.total = off;
+    return L;
+}
+
+int check_problem(const irtps_problem* pr, const irtps_params* pa) {
+    if (!pr || !pa) return IRTPS_ERR_INVALID_ARG;
+    if (!dims_ok(pr->width, pr->height) || !channels_ok(pr->channels) || !lights_ok(pr->num_lights))
+        return IRTPS_ERR_INVALID_ARG;
+    if (!pr->images_dev || !pr->light_dirs_host || !pr->env_dev || pr->env_h < 1 || pr->env_w < 1)
+        return IRTPS_ERR_INVALID_ARG;
+    if (pa->spp < 1 || pa->bounces < 0 || pa->bounces > 8 || pa->iterations < 0 ||
+        pa->iterations > 1000 || (pa->rho_mode != IRTPS_RHO_FIT && pa->rho_mode != IRTPS_RHO_PREV) ||
+        pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || pa->reserved != 0 ||
+        (pa->flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_LITERAL_CUMULATIVE | IRTPS_FLAG_FLAT_TRAVERSAL)))
+        return IRTPS_ERR_INVALID_ARG;
+    return IRTPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int irtps_abi_version(void) { return IRTPS_ABI_VERSION; }
+
+const char* irtps_status_string(int status) {
+    switch (status) {
+        case IRTPS_OK: return "ok";
+        case IRTPS_ERR_INVALID_ARG: return "invalid argument";
+        case IRTPS_ERR_SINGULAR_LIGHTS: return "singular light configuration";
+        case IRTPS_ERR_WORKSPACE: return "workspace missing or too small";
+        case IRTPS_ERR_OOM: return "job larger than the memory budget";
+        case IRTPS_ERR_DEVICE: return "HIP error";
+        case IRTPS_ERR_CANCELLED: return "cancelled";
+        case IRTPS_ERR_NOT_FOUND: return "unknown job";
+        case IRTPS_ERR_BUSY: return "job not finished";
+        default: return "unknown status";
+    }
+}
+
+int irtps_last_hip_error(void) { return g_last_hip; }
+
+int irtps_ps_matrix(int32_t K, const float* light_dirs_host, const float* light_intensity_host,
+                    float* M_host) {
+    if (K > kern::kMaxLights) return IRTPS_ERR_INVALID_ARG;
+    return ps_matrix_host(K, light_dirs_host, light_intensity_host, M_host);
+}
+
+int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* params, size_t* bytes) {
+    STATUS_TRY(check_problem(problem, params));
+    if (!bytes) return IRTPS_ERR_INVALID_ARG;
+    *bytes = solve_layout(problem->width, problem->height, problem->channels, problem->num_lights).total;
+    return IRTPS_OK;
+}
+
+int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
+                size_t ws_bytes, void* stream) {
+    STATUS_TRY(check_problem(pr, pa));
+    if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
+    const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
+    const SolveLayout lay = solve_layout(W, H, C, K);
+    if (!ws || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return IRTPS_ERR_WORKSPACE;
+    kern::PsMatrix M;
+    kern::LightSet Ls;
+    STATUS_TRY(make_psmatrix(K, pr->light_dirs_host, pr->light_intensity_host, M));
+    STATUS_TRY(make_lights(K, pr->light_dirs_host, pr->light_intensity_host, Ls));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    float* A = reinterpret_cast<float*>(base + lay.A);
+    float* S = reinterpret_cast<float*>(base + lay.S);
+    float* G = reinterpret_cast<float*>(base + lay.G);
+    float* pyr = reinterpret_cast<float*>(base + lay.pyr);
+    float* mg = reinterpret_cast<float*>(base + lay.mg);
+    const int npx = W * H;
+    const int cold = pa->mg_cycles_cold ? pa->mg_cycles_cold : 8;
+    const int warm = pa->mg_cycles_warm ? pa->mg_cycles_warm : 4;
+    const bool cumulative = (pa->flags & IRTPS_FLAG_LITERAL_CUMULATIVE) != 0;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(out->counters_dev);
+
+    if (cnt) HIP_TRY(kern::fill_u64_zero(cnt, IRTPS_NUM_COUNTERS, st));
+    // t = 0: plain photometric stereo and integration (stage 1)
+    HIP_TRY(kern::ps_solve(npx, C, K, M, pr->images_dev, out->normals_dev, out->albedo_dev, st));
+    HIP_TRY(kern::integrate(lay.plan, out->normals_dev, nullptr, cold, out->depth_dev, mg, st));
+    if (out->indirect_dev) HIP_TRY(kern::fill_f32(out->indirect_dev, 0.0f, (long long)npx * K * C, st));
+
+    const kern::SurfaceArgs sa = surface(W, H, out->depth_dev, pyr);
+    for (int t = 0; t < pa->iterations; ++t) {
+        HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, sa.P, pyr, st));
+        HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
+        kern::TraceArgs ta{};
+        ta.sa = sa;
+        ta.n = out->normals_dev;
+        ta.rho = out->albedo_dev;
+        ta.S = S;
+        ta.env = pr->env_dev;
+        ta.G = G;
+        ta.counters = cnt;
+        ta.env_h = pr->env_h;
+        ta.env_w = pr->env_w;
+        ta.C = C;
+        ta.K = K;
+        ta.spp = pa->spp;
+        ta.B = pa->bounces;
+        ta.t = t;
+        ta.tag = IRTPS_TAG_SOLVE;
+        ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
+        ta.key0 = (uint32_t)pa->seed;
+        ta.key1 = (uint32_t)(pa->seed >> 32);
+        HIP_TRY(traced(ta, st));
+        // stage 5: subtract; the cumulative reading starts from A_0 = I0
+        const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
+        float* E = (t == pa->iterations - 1) ? out->indirect_dev : nullptr;
+        HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
+                              out->albedo_dev, E, A, st));
+        HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
+        HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st));
+    }
+    return IRTPS_OK;
+}
+
+int irtps_ps_solve(int32_t W, int32_t H, int32_t C, int32_t K, const float* light_dirs_host,
+                   const float* light_intensity_host, const float* A_dev, float* normals_dev,
+                   float* albedo_dev, void* stream) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !A_dev || !normals_dev || !albedo_dev) return IRTPS_ERR_INVALID_ARG;
+    kern::PsMatrix M;
+    STATUS_TRY(make_psmatrix(K, light_dirs_host, light_intensity_host, M));
+    HIP_TRY(kern::ps_solve(W * H, C, K, M, A_dev, normals_dev, albedo_dev, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_integrate_workspace_bytes(int32_t W, int32_t H, size_t* bytes) {
+    if (!dims_ok(W, H) || !bytes) return IRTPS_ERR_INVALID_ARG;
+    *bytes = align_up(sizeof(float) * (size_t)mg_plan(W, H).total);
+    return IRTPS_OK;
+}
+
+int irtps_integrate(int32_t W, int32_t H, const float* normals_dev, const float* depth_init_dev,
+                    int32_t cycles, float* depth_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!dims_ok(W, H) || !normals_dev || !depth_dev || cycles < 0) return IRTPS_ERR_INVALID_ARG;
+    const kern::MgPlan plan = mg_plan(W, H);
+    if (!ws_dev || ws_bytes < sizeof(float) * (size_t)plan.total || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign))
+        return IRTPS_ERR_WORKSPACE;
+    HIP_TRY(kern::integrate(plan, normals_dev, depth_init_dev, cycles, depth_dev, static_cast<float*>(ws_dev),
+                            reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes) {
+    if (!dims_ok(W, H) || !bytes) return IRTPS_ERR_INVALID_ARG;
+    *bytes = sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H));
+    return IRTPS_OK;
+}
+
+int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyramid_dev, void* stream) {
+    if (!dims_ok(W, H) || !depth_dev || !pyramid_dev) return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::build_pyramid(W, H, depth_dev, pyramid_plan(W, H), pyramid_dev,
+                                reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev, const float* normals_dev,
+                 const float* light_dirs_host, const float* light_intensity_host, const float* pyramid_dev,
+                 float* S_dev, void* stream) {
+    if (!dims_ok(W, H) || !depth_dev || !normals_dev || !pyramid_dev || !S_dev) return IRTPS_ERR_INVALID_ARG;
+    kern::LightSet Ls;
+    STATUS_TRY(make_lights(K, light_dirs_host, light_intensity_host, Ls));
+    HIP_TRY(kern::direct(surface(W, H, depth_dev, pyramid_dev), normals_dev, Ls, 0, S_dev,
+                         reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev, const float* normals_dev,
+                const float* albedo_dev, const float* S_dev, const float* env_dev, int32_t env_h,
+                int32_t env_w, const float* pyramid_dev, int32_t spp, int32_t B, uint64_t seed, int32_t t,
+                int32_t tag, int32_t flags, float* G_dev, uint64_t* counters_dev, void* stream) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !depth_dev || !normals_dev || !albedo_dev ||
+        !S_dev || !env_dev || env_h < 1 || env_w < 1 || !pyramid_dev || spp < 1 || B < 0 || B > 8 || t < 0 ||
+        t >= (1 << 23) || tag < 0 || !G_dev ||
+        (flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL)))
+        return IRTPS_ERR_INVALID_ARG;
+    kern::TraceArgs ta{};
+    ta.sa = surface(W, H, depth_dev, pyramid_dev);
+    ta.n = normals_dev;
+    ta.rho = albedo_dev;
+    ta.S = S_dev;
+    ta.env = env_dev;
+    ta.G = G_dev;
+    ta.counters = reinterpret_cast<unsigned long long*>(counters_dev);
+    ta.env_h = env_h;
+    ta.env_w = env_w;
+    ta.C = C;
+    ta.K = K;
+    ta.spp = spp;
+    ta.B = B;
+    ta.t = t;
+    ta.tag = tag;
+    ta.flags = flags;
+    ta.key0 = (uint32_t)seed;
+    ta.key1 = (uint32_t)(seed >> 32);
+    HIP_TRY(traced(ta, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_correct(int32_t W, int32_t H, int32_t C, int32_t K, int32_t rho_mode, int32_t flags,
+                  const float* I0_dev, const float* A_prev_dev, const float* G_dev, const float* S_dev,
+                  const float* albedo_dev, float* E_dev, float* A_next_dev, void* stream) {
+    const bool cumulative = (flags & IRTPS_FLAG_LITERAL_CUMULATIVE) != 0;
+    if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !I0_dev || !G_dev || !S_dev || !albedo_dev ||
+        !A_next_dev || (cumulative && !A_prev_dev) || (rho_mode != IRTPS_RHO_FIT && rho_mode != IRTPS_RHO_PREV))
+        return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::correct(W * H, C, K, rho_mode, cumulative ? 1 : 0, I0_dev, cumulative ? A_prev_dev : I0_dev,
+                          G_dev, S_dev, albedo_dev, E_dev, A_next_dev, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, size_t* bytes) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !bytes) return IRTPS_ERR_INVALID_ARG;
+    const size_t npx = (size_t)W * H;
+    *bytes = align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C) +
+             align_up(sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H)));
+    return IRTPS_OK;
+}
+
+int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev, const float* normals_dev,
+                 const float* albedo_dev, const float* light_dirs_host, const float* light_intensity_host,
+                 const float* env_dev, int32_t env_h, int32_t env_w, int32_t spp, int32_t B, uint64_t seed,
+                 float* images_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    size_t need = 0;
+    STATUS_TRY(irtps_render_workspace_bytes(W, H, C, K, &need));
+    if (!depth_dev || !normals_dev || !albedo_dev || !env_dev || env_h < 1 || env_w < 1 || !images_dev ||
+        spp < 1 || B < 0 || B > 8)
+        return IRTPS_ERR_INVALID_ARG;
+    if (!ws_dev || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign)) return IRTPS_ERR_WORKSPACE;
+    kern::LightSet Ls;
+    STATUS_TRY(make_lights(K, light_dirs_host, light_intensity_host, Ls));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t npx = (size_t)W * H;
+    char* base = static_cast<char*>(ws_dev);
+    float* S = reinterpret_cast<float*>(base);
+    float* G = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K));
+    float* pyr = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C));
+    const kern::SurfaceArgs sa = surface(W, H, depth_dev, pyr);
+    HIP_TRY(kern::build_pyramid(W, H, depth_dev, sa.P, pyr, st));
+    HIP_TRY(kern::direct(sa, normals_dev, Ls, 0, S, st));
+    kern::TraceArgs ta{};
+    ta.sa = sa;
+    ta.n = normals_dev;
+    ta.rho = albedo_dev;
+    ta.S = S;
+    ta.env = env_dev;
+    ta.G = G;
+    ta.counters = nullptr;
+    ta.env_h = env_h;
+    ta.env_w = env_w;
+    ta.C = C;
+    ta.K = K;
+    ta.spp = spp;
+    ta.B = B;
+    ta.t = 0;
+    ta.tag = IRTPS_TAG_RENDER;
+    ta.flags = 0;
+    ta.key0 = (uint32_t)seed;
+    ta.key1 = (uint32_t)(seed >> 32);
+    HIP_TRY(traced(ta, st));
+    HIP_TRY(kern::compose((int)npx, C, K, albedo_dev, S, G, images_dev, st));
+    return IRTPS_OK;
+}
+
+int irtps_profile_begin(void) {
+    for (auto& pr : g_prof.ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    g_prof.ev.clear();
+    g_prof.on = true;
+    return IRTPS_OK;
+}
+
+int irtps_profile_end(double* trace_ms, int64_t* launches) {
+    double total = 0.0;
+    hipError_t err = hipSuccess;
+    for (auto& pr : g_prof.ev) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        total += ms;
+    }
+    const int64_t n = (int64_t)g_prof.ev.size();
+    for (auto& pr : g_prof.ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    g_prof.ev.clear();
+    g_prof.on = false;
+    if (trace_ms) *trace_ms = total;
+    if (launches) *launches = n;
+    if (err != hipSuccess) return hip_fail(err);
+    return IRTPS_OK;
+}
+
+int irtps_probe_philox(int64_t count, const uint32_t* ctr_dev, uint64_t seed, uint32_t* out_dev, void* stream) {
+    if (count < 0 || (count > 0 && (!ctr_dev || !out_dev))) return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::probe_philox(count, ctr_dev, (uint32_t)seed, (uint32_t)(seed >> 32), out_dev,
+                               reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_probe_sample(int64_t count, const float* normals_dev, const float* u_dev, float* dirs_dev, void* stream) {
+    if (count < 0 || (count > 0 && (!normals_dev || !u_dev || !dirs_dev))) return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::probe_sample(count, normals_dev, u_dev, dirs_dev, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_probe_env_texel(int64_t count, const float* dirs_dev, int32_t env_h, int32_t env_w, int32_t* rc_dev,
+                          void* stream) {
+    if (count < 0 || env_h < 1 || env_w < 1 || (count > 0 && (!dirs_dev || !rc_dev))) return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::probe_env(count, dirs_dev, env_h, env_w, rc_dev, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_probe_traverse(int32_t W, int32_t H, const float* depth_dev, const float* pyramid_dev, int32_t flat,
+                         int64_t count, const int32_t* ij_dev, const float* dirs_dev, int32_t* q_dev,
+                         void* stream) {
+    if (!dims_ok(W, H) || !depth_dev || !pyramid_dev || count < 0 || (count > 0 && (!ij_dev || !dirs_dev || !q_dev)))
+        return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::probe_traverse(surface(W, H, depth_dev, pyramid_dev), flat, count, ij_dev, dirs_dev, q_dev,
+                                 reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+}  // extern "C"

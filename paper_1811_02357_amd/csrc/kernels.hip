@@ -1,0 +1,645 @@
+// kernels.hip -- HIP kernels of the IRT-PS hot path for gfx950 (MI355X).
+//
+// Every kernel is a plain per-sample or per-pixel map over HBM-resident planes;
+// the only dense arithmetic is the 3xK photometric-stereo product, far too
+// small for MFMA.  The tracer is the hot loop.
+#include "kernels.hpp"
+
+#include "device_math.hpp"
+#include "traverse.hpp"
+
+namespace irtps {
+namespace kern {
+
+using trv::Surface;
+
+// Blocks are dealt round-robin over the 8 XCDs; remap so that each XCD gets a
+// contiguous run of tiles (neighbouring tiles share that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int per = (nb + 7) / 8;
+    const int xcd = b % 8, k = b / 8;
+    const int t = xcd * per + k;
+    return t;
+}
+
+__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a) {
+    Surface S;
+    S.H = a.H;
+    S.pyr = a.pyr;
+    S.W = a.W;
+    S.Hh = a.Hh;
+    S.top = a.P.levels - 1;
+    S.P = a.P;
+    S.hmax = a.pyr[a.P.off[a.P.levels - 1]];
+    return S;
+}
+
+__device__ __forceinline__ bool walk(const Surface& S, bool flat, int i, int j, dm::V3 d, int& qi,
+                                     int& qj) {
+    return flat ? trv::walk_flat(S, i, j, d.x, d.y, d.z, qi, qj)
+                : trv::walk_pyramid(S, i, j, d.x, d.y, d.z, qi, qj);
+}
+
+// ---------------------------------------------------------------------------
+// Eq.4: g_c = M A_c (sum over lights in order, fused), albedo = |g_c|,
+// normal = sum_c g_c normalised.
+template <int C>
+__global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, const float* __restrict__ A,
+                                                  float* __restrict__ n, float* __restrict__ rho) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const float a = A[((size_t)k * C + c) * npx + p];
+            g0 = fmaf(M.m[0][k], a, g0);
+            g1 = fmaf(M.m[1][k], a, g1);
+            g2 = fmaf(M.m[2][k], a, g2);
+        }
+        rho[(size_t)c * npx + p] = sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2)));
+        sx = sx + g0;
+        sy = sy + g1;
+        sz = sz + g2;
+    }
+    const float len = sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
+    float nx = 0.0f, ny = 0.0f, nz = 1.0f;
+    if (len > 0.0f) {
+        nx = sx / len;
+        ny = sy / len;
+        nz = sz / len;
+    }
+    n[3 * (size_t)p + 0] = nx;
+    n[3 * (size_t)p + 1] = ny;
+    n[3 * (size_t)p + 2] = nz;
+}
+
+// ---------------------------------------------------------------------------
+// Eq.2 without albedo, with cast shadows.
+__global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
+                                                int flat, float* __restrict__ S_out) {
+    const int npx = sa.W * sa.Hh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+    const Surface S = make_surface(sa);
+    const int i = p % sa.W, j = p / sa.W;
+    const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
+    for (int k = 0; k < L.K; ++k) {
+        const float lx = L.l[k][0], ly = L.l[k][1], lz = L.l[k][2];
+        const float c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
+        float v = 0.0f;
+        if (c > 0.0f) {
+            int qi, qj;
+            const bool blocked = walk(S, flat != 0, i, j, dm::V3{lx, ly, lz}, qi, qj);
+            if (!blocked) v = L.s[k] * c;
+        }
+        S_out[(size_t)p * L.K + k] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments.
+// One lane owns one pixel and keeps K x C accumulators in registers; lights
+// [k0, k0 + KMAX) are gathered per launch.
+template <int C, int KMAX>
+__global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
+    const int tiles_x = (a.sa.W + 15) / 16;
+    const int tiles_y = (a.sa.Hh + 15) / 16;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= tiles_x * tiles_y) return;
+    const int i = (tile % tiles_x) * 16 + (threadIdx.x & 15);
+    const int j = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
+    const bool live = i < a.sa.W && j < a.sa.Hh;
+    const int npx = a.sa.W * a.sa.Hh;
+    const int p = j * a.sa.W + i;
+    const Surface S = make_surface(a.sa);
+    const int kc = a.kcount;
+    const bool flat = (a.flags & kFlagFlat) != 0;
+
+    float acc[KMAX * C];
+#pragma unroll
+    for (int x = 0; x < KMAX * C; ++x) acc[x] = 0.0f;
+    float eacc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) eacc[c] = 0.0f;
+    unsigned long long n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
+
+    int M = 0;
+    if (a.flags & kFlagQuadrature) {
+        M = 1;
+        while (M * M < a.spp) ++M;
+    }
+    if (live) {
+        for (int s = 0; s < a.spp; ++s) {
+            float beta[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+            int ci = i, cj = j;
+            size_t cp = (size_t)p;
+            for (int b = 1; b <= a.B; ++b) {
+                float u1, u2;
+                if (M > 0 && b == 1) {
+                    u1 = ((float)(s / M) + 0.5f) / (float)M;
+                    u2 = ((float)(s % M) + 0.5f) / (float)M;
+                } else {
+                    const dm::U4 r = dm::philox((uint32_t)p, (uint32_t)s,
+                                                (uint32_t)a.t * 256u + (uint32_t)b, (uint32_t)a.tag,
+                                                a.key0, a.key1);
+                    u1 = dm::unit24(r.x);
+                    u2 = dm::unit24(r.y);
+                }
+                const float nx = a.n[3 * cp], ny = a.n[3 * cp + 1], nz = a.n[3 * cp + 2];
+                const dm::V3 d = dm::cosine_dir(nx, ny, nz, u1, u2);
+                int qi, qj;
+                ++n_seg;
+                if (!walk(S, flat, ci, cj, d, qi, qj)) {
+                    int er, ec;
+                    dm::env_texel(d.x, d.y, d.z, a.env_h, a.env_w, er, ec);
+                    const float* L = a.env + ((size_t)er * a.env_w + ec) * C;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
+                    ++n_esc;
+                    break;
+                }
+                ++n_hit;
+                const size_t q = (size_t)qj * a.sa.W + qi;
+                float w[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) w[c] = beta[c] * a.rho[(size_t)c * npx + q];
+                const float* Sq = a.S + q * a.K + a.k0;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (k < kc) {
+                        const float sq = Sq[k];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(w[c], sq, acc[k * C + c]);
+                    }
+                }
+                if (b < a.B) {
+                    ++n_cont;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) beta[c] = w[c];
+                    ci = qi;
+                    cj = qj;
+                    cp = q;
+                }
+            }
+        }
+        const float fspp = (float)a.spp;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < kc) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    a.G[((size_t)(a.k0 + k) * C + c) * npx + p] = (acc[k * C + c] + eacc[c]) / fspp;
+            }
+        }
+    }
+    if (a.counters) {
+        // wave-level sums, one atomic per wave
+        for (int o = 32; o > 0; o >>= 1) {
+            n_seg += __shfl_xor(n_seg, o);
+            n_hit += __shfl_xor(n_hit, o);
+            n_esc += __shfl_xor(n_esc, o);
+            n_cont += __shfl_xor(n_cont, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&a.counters[0], n_seg);
+            atomicAdd(&a.counters[1], n_hit);
+            atomicAdd(&a.counters[2], n_esc);
+            atomicAdd(&a.counters[3], n_cont);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 5.
+template <int C>
+__global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, int cumulative,
+                                                 const float* __restrict__ I0, const float* __restrict__ Aprev,
+                                                 const float* __restrict__ G, const float* __restrict__ S,
+                                                 const float* __restrict__ rho, float* __restrict__ E,
+                                                 float* __restrict__ Anext) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float rt;
+        if (rho_mode == 0) {
+            float num = 0.0f, den = 0.0f;
+            for (int k = 0; k < K; ++k) {
+                const size_t x = ((size_t)k * C + c) * npx + p;
+                const float v = S[(size_t)p * K + k] + G[x];
+                num = fmaf(I0[x], v, num);
+                den = fmaf(v, v, den);
+            }
+            rt = den > 0.0f ? num / den : 0.0f;
+        } else {
+            rt = rho[(size_t)c * npx + p];
+        }
+        for (int k = 0; k < K; ++k) {
+            const size_t x = ((size_t)k * C + c) * npx + p;
+            const float e = rt * G[x];
+            if (E) E[x] = e;
+            Anext[x] = (cumulative ? Aprev[x] : I0[x]) - e;
+        }
+    }
+}
+
+// Forward render: images = albedo (S + G).
+template <int C>
+__global__ void __launch_bounds__(256) k_compose(int npx, int K, const float* __restrict__ rho,
+                                                 const float* __restrict__ S, const float* __restrict__ G,
+                                                 float* __restrict__ I) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const size_t x = ((size_t)k * C + c) * npx + p;
+            I[x] = rho[(size_t)c * npx + p] * (S[(size_t)p * K + k] + G[x]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Apron-max pyramid.
+__global__ void __launch_bounds__(256) k_pyr_level0(int W, int Hh, const float* __restrict__ H,
+                                                    float* __restrict__ out, int wc, int hc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= wc * hc) return;
+    const int cx = c % wc, cy = c / wc;
+    const int x0 = cx - 1 < 0 ? 0 : cx - 1, x1 = cx + 2 > W - 1 ? W - 1 : cx + 2;
+    const int y0 = cy - 1 < 0 ? 0 : cy - 1, y1 = cy + 2 > Hh - 1 ? Hh - 1 : cy + 2;
+    float m = H[(size_t)y0 * W + x0];
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            const float v = H[(size_t)y * W + x];
+            m = v > m ? v : m;
+        }
+    out[c] = m;
+}
+
+__global__ void __launch_bounds__(256) k_pyr_reduce(const float* __restrict__ in, int wi, int hi,
+                                                    float* __restrict__ out, int wo, int ho) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= wo * ho) return;
+    const int cx = c % wo, cy = c / wo;
+    float m = in[(size_t)(2 * cy) * wi + 2 * cx];
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            const int x = 2 * cx + dx, y = 2 * cy + dy;
+            if (x < wi && y < hi) {
+                const float v = in[(size_t)y * wi + x];
+                m = v > m ? v : m;
+            }
+        }
+    out[c] = m;
+}
+
+// ---------------------------------------------------------------------------
+// Integration: right-hand side of the normal equations from the normals.
+__device__ __forceinline__ void grad_at(const float* n, size_t v, float& p, float& q) {
+    const float nz0 = n[3 * v + 2];
+    const float nz = nz0 > 0.05f ? nz0 : 0.05f;
+    p = -(n[3 * v + 0] / nz);
+    q = -(n[3 * v + 1] / nz);
+}
+
+__global__ void __launch_bounds__(256) k_mg_rhs(int W, int Hh, const float* __restrict__ n,
+                                                float* __restrict__ b) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= W * Hh) return;
+    const int i = v % W, j = v / W;
+    float p, q;
+    grad_at(n, v, p, q);
+    float acc = 0.0f;
+    float pn, qn;
+    if (i > 0) { grad_at(n, v - 1, pn, qn); acc = acc + (pn + p) * 0.5f; }
+    if (i < W - 1) { grad_at(n, v + 1, pn, qn); acc = acc - (p + pn) * 0.5f; }
+    if (j > 0) { grad_at(n, v - W, pn, qn); acc = acc + (qn + q) * 0.5f; }
+    if (j < Hh - 1) { grad_at(n, v + W, pn, qn); acc = acc - (q + qn) * 0.5f; }
+    b[v] = acc;
+}
+
+// Edge weights of level `shift`: horizontal edges of row J carry the number of
+// finest rows in that aggregate, vertical edges of column I its column count.
+__device__ __forceinline__ float w_row(int H0, int shift, int J) {
+    const int s = 1 << shift, rows = H0 - J * s;
+    return (float)(rows < s ? rows : s);
+}
+__device__ __forceinline__ float w_col(int W0, int shift, int I) {
+    const int s = 1 << shift, cols = W0 - I * s;
+    return (float)(cols < s ? cols : s);
+}
+
+__global__ void __launch_bounds__(256) k_mg_smooth(int Wl, int Hl, int shift, int W0, int H0,
+                                                   float* __restrict__ X, const float* __restrict__ b,
+                                                   int colour) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Wl * Hl) return;
+    const int I = v % Wl, J = v / Wl;
+    if (((I + J) & 1) != colour) return;
+    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
+    float num = b[v], den = 0.0f;
+    if (I > 0) { num = fmaf(wx, X[v - 1], num); den = den + wx; }
+    if (I < Wl - 1) { num = fmaf(wx, X[v + 1], num); den = den + wx; }
+    if (J > 0) { num = fmaf(wy, X[v - Wl], num); den = den + wy; }
+    if (J < Hl - 1) { num = fmaf(wy, X[v + Wl], num); den = den + wy; }
+    if (den > 0.0f) X[v] = num / den;
+}
+
+__device__ __forceinline__ float mg_resid(int Wl, int Hl, int shift, int W0, int H0, const float* X,
+                                          const float* b, int I, int J) {
+    const size_t v = (size_t)J * Wl + I;
+    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
+    const float xv = X[v];
+    float lx = 0.0f;
+    if (I > 0) lx = fmaf(wx, xv - X[v - 1], lx);
+    if (I < Wl - 1) lx = fmaf(wx, xv - X[v + 1], lx);
+    if (J > 0) lx = fmaf(wy, xv - X[v - Wl], lx);
+    if (J < Hl - 1) lx = fmaf(wy, xv - X[v + Wl], lx);
+    return b[v] - lx;
+}
+
+// Coarse right-hand side = sum of the four fine residuals; coarse guess = 0.
+__global__ void __launch_bounds__(256) k_mg_restrict(int Wf, int Hf, int shift, int W0, int H0,
+                                                     const float* __restrict__ Xf,
+                                                     const float* __restrict__ bf, int Wc, int Hc,
+                                                     float* __restrict__ bc, float* __restrict__ Xc) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Wc * Hc) return;
+    const int I = v % Wc, J = v / Wc;
+    float acc = 0.0f;
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            const int fi = 2 * I + di, fj = 2 * J + dj;
+            if (fi < Wf && fj < Hf) acc = acc + mg_resid(Wf, Hf, shift, W0, H0, Xf, bf, fi, fj);
+        }
+    bc[v] = acc;
+    Xc[v] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_mg_prolong(int Wf, int Hf, float* __restrict__ Xf, int Wc,
+                                                    const float* __restrict__ Xc) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Wf * Hf) return;
+    const int I = v % Wf, J = v / Wf;
+    Xf[v] = Xf[v] + 2.0f * Xc[(size_t)(J / 2) * Wc + I / 2];
+}
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
+}
+
+__global__ void k_fill_f32(float* p, float v, long long n) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = v;
+}
+
+// Order-preserving map of binary32 (no NaN) to uint32.
+__device__ __forceinline__ unsigned order_key(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float order_val(unsigned k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void __launch_bounds__(256) k_min_key(const float* __restrict__ X, int n, unsigned* key) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned k = 0xffffffffu;
+    if (v < n) k = order_key(X[v] + 0.0f);  // +0.0f: one zero
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned other = __shfl_xor(k, o);
+        k = other < k ? other : k;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(key, k);
+}
+
+__global__ void __launch_bounds__(256) k_anchor(const float* __restrict__ X, int n, const unsigned* key,
+                                                float* __restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    out[v] = X[v] - order_val(*key);
+}
+
+// ---------------------------------------------------------------------------
+// Probes.
+__global__ void k_probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
+                               uint32_t* out) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const dm::U4 o = dm::philox(ctr[4 * r], ctr[4 * r + 1], ctr[4 * r + 2], ctr[4 * r + 3], k0, k1);
+    out[4 * r] = o.x;
+    out[4 * r + 1] = o.y;
+    out[4 * r + 2] = o.z;
+    out[4 * r + 3] = o.w;
+}
+
+__global__ void k_probe_sample(long long count, const float* n, const float* u, float* d) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const dm::V3 v = dm::cosine_dir(n[3 * r], n[3 * r + 1], n[3 * r + 2], u[2 * r], u[2 * r + 1]);
+    d[3 * r] = v.x;
+    d[3 * r + 1] = v.y;
+    d[3 * r + 2] = v.z;
+}
+
+__global__ void k_probe_env(long long count, const float* d, int He, int We, int* rc) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    int row, col;
+    dm::env_texel(d[3 * r], d[3 * r + 1], d[3 * r + 2], He, We, row, col);
+    rc[2 * r] = row;
+    rc[2 * r + 1] = col;
+}
+
+__global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, const int* ij,
+                                 const float* d, int* q) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const int i0 = ij[2 * r], j0 = ij[2 * r + 1];
+    if (i0 < 0 || i0 >= sa.W || j0 < 0 || j0 >= sa.Hh) {  // not a sample: reported, not traced
+        q[2 * r] = -2;
+        q[2 * r + 1] = -2;
+        return;
+    }
+    const Surface S = make_surface(sa);
+    int qi = -1, qj = -1;
+    const bool hit = walk(S, flat != 0, i0, j0,
+                          dm::V3{d[3 * r], d[3 * r + 1], d[3 * r + 2]}, qi, qj);
+    q[2 * r] = hit ? qi : -1;
+    q[2 * r + 1] = hit ? qj : -1;
+}
+
+// ===========================================================================
+// Host launchers.
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, float* n, float* rho,
+                    hipStream_t st) {
+    const unsigned g = blocks_for(npx, 256);
+    if (C == 1) hipLaunchKernelGGL(k_ps_solve<1>, dim3(g), dim3(256), 0, st, npx, K, M, A, n, rho);
+    else hipLaunchKernelGGL(k_ps_solve<3>, dim3(g), dim3(256), 0, st, npx, K, M, A, n, rho);
+    return hipGetLastError();
+}
+
+hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_direct, dim3(blocks_for((long long)sa.W * sa.Hh, 256)), dim3(256), 0, st,
+                       sa, n, L, flat, S);
+    return hipGetLastError();
+}
+
+template <int C, int KMAX>
+static void launch_trace(const TraceArgs& a, hipStream_t st) {
+    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
+    const int per = (tiles + 7) / 8;
+    hipLaunchKernelGGL((k_trace<C, KMAX>), dim3(per * 8), dim3(256), 0, st, a);
+}
+
+hipError_t trace(TraceArgs a, hipStream_t st) {
+    // lights in chunks that fit the register accumulators
+    const int cap = a.C == 1 ? 64 : 16;
+    for (int k0 = 0; k0 < a.K; k0 += cap) {
+        a.k0 = k0;
+        a.kcount = a.K - k0 < cap ? a.K - k0 : cap;
+        if (k0 > 0) a.counters = nullptr;  // count each segment once
+        if (a.C == 1) {
+            if (a.kcount <= 8) launch_trace<1, 8>(a, st);
+            else if (a.kcount <= 16) launch_trace<1, 16>(a, st);
+            else if (a.kcount <= 32) launch_trace<1, 32>(a, st);
+            else launch_trace<1, 64>(a, st);
+        } else {
+            if (a.kcount <= 8) launch_trace<3, 8>(a, st);
+            else launch_trace<3, 16>(a, st);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
+                   const float* Aprev, const float* G, const float* S, const float* rho, float* E,
+                   float* Anext, hipStream_t st) {
+    const unsigned g = blocks_for(npx, 256);
+    if (C == 1)
+        hipLaunchKernelGGL(k_correct<1>, dim3(g), dim3(256), 0, st, npx, K, rho_mode, cumulative, I0,
+                           Aprev, G, S, rho, E, Anext);
+    else
+        hipLaunchKernelGGL(k_correct<3>, dim3(g), dim3(256), 0, st, npx, K, rho_mode, cumulative, I0,
+                           Aprev, G, S, rho, E, Anext);
+    return hipGetLastError();
+}
+
+hipError_t compose(int npx, int C, int K, const float* rho, const float* S, const float* G, float* I,
+                   hipStream_t st) {
+    const unsigned g = blocks_for(npx, 256);
+    if (C == 1) hipLaunchKernelGGL(k_compose<1>, dim3(g), dim3(256), 0, st, npx, K, rho, S, G, I);
+    else hipLaunchKernelGGL(k_compose<3>, dim3(g), dim3(256), 0, st, npx, K, rho, S, G, I);
+    return hipGetLastError();
+}
+
+hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
+                       st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
+    for (int l = 1; l < P.levels; ++l)
+        hipLaunchKernelGGL(k_pyr_reduce, dim3(blocks_for((long long)P.wc[l] * P.hc[l], 256)), dim3(256),
+                           0, st, pyr + P.off[l - 1], P.wc[l - 1], P.hc[l - 1], pyr + P.off[l], P.wc[l],
+                           P.hc[l]);
+    return hipGetLastError();
+}
+
+hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
+                     float* ws, hipStream_t st) {
+    const int W0 = plan.W[0], H0 = plan.H[0];
+    const int npx = W0 * H0;
+    float* X[kMaxMgLevels];
+    float* b[kMaxMgLevels];
+    for (int l = 0; l < plan.levels; ++l) {
+        X[l] = ws + plan.xoff[l];
+        b[l] = ws + plan.boff[l];
+    }
+    unsigned* key = reinterpret_cast<unsigned*>(ws + plan.keyoff);
+    hipLaunchKernelGGL(k_mg_rhs, dim3(blocks_for(npx, 256)), dim3(256), 0, st, W0, H0, n, b[0]);
+    if (Hinit) {
+        if (hipMemcpyAsync(X[0], Hinit, sizeof(float) * (size_t)npx, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return hipGetLastError();
+    } else {
+        hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], 0.0f,
+                           (long long)npx);
+    }
+    auto smooth = [&](int l, int sweeps) {
+        const int nl = plan.W[l] * plan.H[l];
+        for (int s = 0; s < sweeps; ++s)
+            for (int colour = 0; colour < 2; ++colour)
+                hipLaunchKernelGGL(k_mg_smooth, dim3(blocks_for(nl, 256)), dim3(256), 0, st, plan.W[l],
+                                   plan.H[l], l, W0, H0, X[l], b[l], colour);
+    };
+    for (int c = 0; c < cycles; ++c) {
+        for (int l = 0; l < plan.levels - 1; ++l) {
+            smooth(l, 2);
+            const int nc = plan.W[l + 1] * plan.H[l + 1];
+            hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(nc, 256)), dim3(256), 0, st, plan.W[l],
+                               plan.H[l], l, W0, H0, X[l], b[l], plan.W[l + 1], plan.H[l + 1], b[l + 1],
+                               X[l + 1]);
+        }
+        smooth(plan.levels - 1, 16);
+        for (int l = plan.levels - 2; l >= 0; --l) {
+            hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(plan.W[l] * plan.H[l], 256)), dim3(256), 0,
+                               st, plan.W[l], plan.H[l], X[l], plan.W[l + 1], X[l + 1]);
+            smooth(l, 2);
+        }
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, key, 0xffffffffu, 1);
+    hipLaunchKernelGGL(k_min_key, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key);
+    hipLaunchKernelGGL(k_anchor, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key, Hout);
+    return hipGetLastError();
+}
+
+hipError_t fill_f32(float* p, float v, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(p), 0u, 2 * n);
+    return hipGetLastError();
+}
+
+hipError_t probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                        hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_philox, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, ctr, k0, k1,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t probe_sample(long long count, const float* n, const float* u, float* d, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_sample, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, n, u, d);
+    return hipGetLastError();
+}
+
+hipError_t probe_env(long long count, const float* d, int He, int We, int* rc, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_env, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, d, He, We, rc);
+    return hipGetLastError();
+}
+
+hipError_t probe_traverse(const SurfaceArgs& sa, int flat, long long count, const int* ij,
+                          const float* d, int* q, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_traverse, dim3(blocks_for(count, 256)), dim3(256), 0, st, sa, flat, count,
+                       ij, d, q);
+    return hipGetLastError();
+}
+
+}  // namespace kern
+}  // namespace irtps

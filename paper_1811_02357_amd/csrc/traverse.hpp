@@ -1,0 +1,221 @@
+// traverse.hpp -- ray against the grid-line heightfield on gfx950.
+//
+// The surface is linear between neighbouring samples along every grid line.
+// A ray leaves a sample; it is tested where it crosses each vertical line
+// x = X and each horizontal line y = Y, in order of its parameter t (an x-line
+// first on a tie).  A crossing hits when the ray is strictly below the surface
+// there; the shading sample is the nearer end of that grid segment.  The ray
+// escapes at the first crossing outside the domain, or when it is at or above
+// the highest sample and not descending.
+//
+// Two walks give the same answer bit for bit.  The flat walk visits every
+// crossing.  The pyramid walk skips, in one step, every crossing inside a
+// pyramid cell when the ray's height over the cell's t-range (exact: fmaf is
+// monotone in t) is at or above the cell's maximum; that maximum is taken over
+// the cell grown by one sample, which covers the samples any crossing in the
+// cell can read after binary32 rounding of its minor coordinate (off by far
+// less than a sample).  Cells touching the domain border are never skipped, so
+// the escape test is always taken at the same crossing as in the flat walk.
+#pragma once
+
+#include "device_math.hpp"
+
+namespace irtps {
+namespace trv {
+
+constexpr int kMaxLevels = 16;
+
+// Apron-max pyramid.  Level l has cells (cx, cy), cx < wc[l], cy < hc[l];
+// cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l].
+struct Pyramid {
+    int levels;
+    int wc[kMaxLevels];
+    int hc[kMaxLevels];
+    long long off[kMaxLevels];
+};
+
+struct Surface {
+    const float* H;      // [Hh][W]
+    const float* pyr;    // apron maxima, levels concatenated; top level = global max
+    int W, Hh;
+    int top;             // index of the 1x1 level
+    float hmax;
+    Pyramid P;
+};
+
+// Per-ray state shared by both walks.
+struct Ray {
+    float ox, oy, oz, dx, dy, dz, inv_dx, inv_dy;
+    int i0, j0, sx, sy;
+};
+
+__device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float dx, float dy,
+                                        float dz) {
+    Ray r;
+    r.i0 = i0;
+    r.j0 = j0;
+    r.ox = (float)i0;
+    r.oy = (float)j0;
+    r.oz = S.H[(size_t)j0 * S.W + i0];
+    r.dx = dx;
+    r.dy = dy;
+    r.dz = dz;
+    r.sx = signbit(dx) ? -1 : 1;
+    r.sy = signbit(dy) ? -1 : 1;
+    r.inv_dx = 1.0f / dx;
+    r.inv_dy = 1.0f / dy;
+    return r;
+}
+
+__device__ __forceinline__ float t_x(const Ray& r, int m) { return (float)(r.sx * m) * r.inv_dx; }
+__device__ __forceinline__ float t_y(const Ray& r, int m) { return (float)(r.sy * m) * r.inv_dy; }
+
+enum : int { kMiss = 0, kHit = 1, kGoOn = 2 };
+
+// Evaluate one crossing; returns kHit (q set), kMiss (escaped) or kGoOn.
+__device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xline, float t,
+                                        int mx, int my, int& qi, int& qj) {
+    const int major = xline ? r.i0 + r.sx * mx : r.j0 + r.sy * my;
+    const int n_major = xline ? S.W : S.Hh;
+    const int n_minor = xline ? S.Hh : S.W;
+    if (major < 0 || major > n_major - 1) return kMiss;
+    const float minor = fmaf(t, xline ? r.dy : r.dx, xline ? r.oy : r.ox);
+    if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
+    const int m0 = (int)floorf(minor);
+    const float f = minor - (float)m0;
+    const size_t idx0 = xline ? (size_t)m0 * S.W + major : (size_t)major * S.W + m0;
+    const float h0 = S.H[idx0];
+    float h = h0;
+    if (f != 0.0f) {
+        const float h1 = S.H[idx0 + (xline ? (size_t)S.W : (size_t)1)];
+        h = fmaf(f, h1 - h0, h0);
+        const float lo = h0 < h1 ? h0 : h1;
+        const float hi = h0 < h1 ? h1 : h0;
+        h = h < lo ? lo : h;
+        h = h > hi ? hi : h;
+    }
+    const float z = fmaf(t, r.dz, r.oz);
+    if (z < h) {
+        const int qm = f < 0.5f ? m0 : m0 + 1;
+        qi = xline ? major : qm;
+        qj = xline ? qm : major;
+        return kHit;
+    }
+    if (z >= S.hmax && r.dz >= 0.0f) return kMiss;
+    return kGoOn;
+}
+
+// Flat walk: every crossing in t order.
+__device__ __forceinline__ bool walk_flat(const Surface& S, int i0, int j0, float dx, float dy,
+                                          float dz, int& qi, int& qj) {
+    if (dx == 0.0f && dy == 0.0f) return false;
+    const Ray r = make_ray(S, i0, j0, dx, dy, dz);
+    int mx = 1, my = 1;
+    float tX = t_x(r, 1), tY = t_y(r, 1);
+    for (;;) {
+        if (isinf(tX) && isinf(tY)) return false;
+        const bool xline = tX <= tY;
+        const int res = crossing(S, r, xline, xline ? tX : tY, mx, my, qi, qj);
+        if (res != kGoOn) return res == kHit;
+        if (xline) {
+            ++mx;
+            tX = t_x(r, mx);
+        } else {
+            ++my;
+            tY = t_y(r, my);
+        }
+    }
+}
+
+// Smallest crossing index m >= m_lo whose t (same formula as the walk) is >= t_lim.
+__device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline, int m_lo,
+                                                       float t_lim, float d_abs) {
+    // estimate from the geometry, then correct with the exact formula
+    float est = ceilf(t_lim * d_abs);
+    int m = est > 2.0e9f ? 2000000000 : (int)est;
+    if (m < m_lo) m = m_lo;
+    while (m > m_lo && (xline ? t_x(r, m - 1) : t_y(r, m - 1)) >= t_lim) --m;
+    while ((xline ? t_x(r, m) : t_y(r, m)) < t_lim) ++m;
+    return m;
+}
+
+// Pyramid walk.  At the next crossing (t_now) pick the coarsest level whose
+// cell around the ray's current position can be skipped: the cell (grown by
+// one sample) lies inside the domain interior and the ray's height at t_now and
+// at the cell's exit t are both at or above the cell's apron maximum.  All
+// crossings with t < t_exit are then skipped.  Otherwise evaluate the one
+// crossing at t_now exactly as the flat walk does.
+__device__ __forceinline__ bool walk_pyramid(const Surface& S, int i0, int j0, float dx, float dy,
+                                             float dz, int& qi, int& qj) {
+    if (dx == 0.0f && dy == 0.0f) return false;
+    const Ray r = make_ray(S, i0, j0, dx, dy, dz);
+    const float adx = fabsf(dx), ady = fabsf(dy);
+    int mx = 1, my = 1;
+    float tX = t_x(r, 1), tY = t_y(r, 1);
+    int level = 0;
+    for (;;) {
+        if (isinf(tX) && isinf(tY)) return false;
+        const bool xline = tX <= tY;
+        const float t_now = xline ? tX : tY;
+        // position of the next crossing (approximate: only used to choose a cell)
+        const float px = xline ? (float)(r.i0 + r.sx * mx) : fmaf(t_now, dx, r.ox);
+        const float py = xline ? fmaf(t_now, dy, r.oy) : (float)(r.j0 + r.sy * my);
+        const float z_now = fmaf(t_now, dz, r.oz);
+        bool skipped = false;
+        const bool inside = px >= 0.0f && px <= (float)(S.W - 1) && py >= 0.0f && py <= (float)(S.Hh - 1);
+        if (!inside) level = -1;  // the crossing below is outside the domain: escape
+        // try from the current level upwards-first strategy: climb while skips succeed
+        for (int l = level; l >= 0; --l) {
+            const int size = 1 << l;
+            // cell ahead of the ray in each axis
+            int cx = (int)floorf(px) >> l;
+            int cy = (int)floorf(py) >> l;
+            if (r.sx < 0 && (float)(cx << l) == px) cx -= 1;
+            if (r.sy < 0 && (float)(cy << l) == py) cy -= 1;
+            if (cx < 0 || cy < 0 || cx >= S.P.wc[l] || cy >= S.P.hc[l]) continue;
+            const int X0 = cx << l, X1 = X0 + size, Y0 = cy << l, Y1 = Y0 + size;
+            if (X0 < 2 || Y0 < 2 || X1 > S.W - 3 || Y1 > S.Hh - 3) continue;
+            const float cmax = S.pyr[S.P.off[l] + (long long)cy * S.P.wc[l] + cx];
+            if (!(z_now >= cmax)) continue;
+            // exit lines of the cell in the direction of travel
+            const int Xe = r.sx > 0 ? X1 : X0;
+            const int Ye = r.sy > 0 ? Y1 : Y0;
+            const int mxe = (Xe - r.i0) * r.sx;
+            const int mye = (Ye - r.j0) * r.sy;
+            const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
+            const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
+            const float t_exit = txe < tye ? txe : tye;
+            if (!(t_exit > t_now) || isinf(t_exit)) continue;
+            const float z_exit = fmaf(t_exit, dz, r.oz);
+            if (!(z_exit >= cmax)) continue;
+            // skip every crossing with t < t_exit
+            if (!isinf(tX)) {
+                mx = first_index_at_or_after(r, true, mx, t_exit, adx);
+                tX = t_x(r, mx);
+            }
+            if (!isinf(tY)) {
+                my = first_index_at_or_after(r, false, my, t_exit, ady);
+                tY = t_y(r, my);
+            }
+            level = l + 1 < S.top ? l + 1 : S.top;
+            skipped = true;
+            break;
+        }
+        if (skipped) continue;
+        level = 0;
+        const int res = crossing(S, r, xline, t_now, mx, my, qi, qj);
+        if (res != kGoOn) return res == kHit;
+        if (xline) {
+            ++mx;
+            tX = t_x(r, mx);
+        } else {
+            ++my;
+            tY = t_y(r, my);
+        }
+        // a crossing outside the domain was checked above; keep climbing lazily
+        level = 1;
+    }
+}
+
+}  // namespace trv
+}  // namespace irtps

@@ -1,0 +1,333 @@
+"""Python binding of libirtps (include/irtps.h): argument marshalling only.
+
+Every function here checks shapes, takes device pointers and the current HIP
+stream from torch tensors, and calls the C ABI of the same name; all work runs
+in the library's HIP kernels.  torch provides device memory and streams only.
+If libirtps.so is missing the import of the library fails loudly: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirtps.so")
+
+OK = 0
+RHO_FIT, RHO_PREV = 0, 1
+FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL = 1, 2, 4
+TAG_SOLVE, TAG_RENDER = 0, 1
+NUM_COUNTERS = 4
+
+_vp = ct.c_void_p
+_i32 = ct.c_int32
+_i64 = ct.c_int64
+_u64 = ct.c_uint64
+_sz = ct.c_size_t
+
+
+class IrtpsError(RuntimeError):
+    def __init__(self, name, status, lib):
+        msg = lib.irtps_status_string(status).decode()
+        if status == 5:
+            msg += f" (hipError {lib.irtps_last_hip_error()})"
+        super().__init__(f"{name}: {msg} [{status}]")
+        self.status = status
+
+
+class Problem(ct.Structure):
+    _fields_ = [("width", _i32), ("height", _i32), ("channels", _i32), ("num_lights", _i32),
+                ("images_dev", _vp), ("light_dirs_host", _vp), ("light_intensity_host", _vp),
+                ("env_dev", _vp), ("env_h", _i32), ("env_w", _i32)]
+
+
+class Params(ct.Structure):
+    _fields_ = [("spp", _i32), ("bounces", _i32), ("iterations", _i32), ("rho_mode", _i32),
+                ("flags", _i32), ("mg_cycles_cold", _i32), ("mg_cycles_warm", _i32),
+                ("reserved", _i32), ("seed", _u64)]
+
+
+class Outputs(ct.Structure):
+    _fields_ = [("normals_dev", _vp), ("albedo_dev", _vp), ("depth_dev", _vp),
+                ("indirect_dev", _vp), ("counters_dev", _vp)]
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(the HIP library is required; there is no fallback)")
+        L = ct.CDLL(LIB_PATH)
+        L.irtps_status_string.restype = ct.c_char_p
+        L.irtps_status_string.argtypes = [ct.c_int]
+        L.irtps_abi_version.restype = ct.c_int
+        L.irtps_last_hip_error.restype = ct.c_int
+        P = ct.POINTER
+        sigs = {
+            "irtps_ps_matrix": [_i32, _vp, _vp, _vp],
+            "irtps_workspace_bytes": [P(Problem), P(Params), P(_sz)],
+            "irtps_solve": [P(Problem), P(Params), P(Outputs), _vp, _sz, _vp],
+            "irtps_ps_solve": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
+            "irtps_integrate_workspace_bytes": [_i32, _i32, P(_sz)],
+            "irtps_integrate": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp],
+            "irtps_pyramid_bytes": [_i32, _i32, P(_sz)],
+            "irtps_build_pyramid": [_i32, _i32, _vp, _vp, _vp],
+            "irtps_direct": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+            "irtps_trace": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
+                            _i32, _i32, _u64, _i32, _i32, _i32, _vp, _vp, _vp],
+            "irtps_correct": [_i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _vp],
+            "irtps_render_workspace_bytes": [_i32, _i32, _i32, _i32, P(_sz)],
+            "irtps_render": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
+                             _i32, _i32, _u64, _vp, _vp, _sz, _vp],
+            "irtps_profile_begin": [],
+            "irtps_profile_end": [P(ct.c_double), P(_i64)],
+            "irtps_probe_philox": [_i64, _vp, _u64, _vp, _vp],
+            "irtps_probe_sample": [_i64, _vp, _vp, _vp, _vp],
+            "irtps_probe_env_texel": [_i64, _vp, _i32, _i32, _vp, _vp],
+            "irtps_probe_traverse": [_i32, _i32, _vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ct.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(name, status):
+    if status != OK:
+        raise IrtpsError(name, status, lib())
+
+
+def _dev(t, dtype=torch.float32, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _host_f32(a, shape=None, name="array"):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None and arr.shape != tuple(shape):
+        raise ValueError(f"{name} has shape {arr.shape}, expected {tuple(shape)}")
+    return arr, arr.ctypes.data_as(ct.c_void_p)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _alloc_ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+def ps_matrix(light_dirs, light_intensity=None):
+    """Eq.4 solve matrix M = (L^T L)^-1 L^T, [3][K] (host computation)."""
+    l, lp = _host_f32(light_dirs, name="light_dirs")
+    K = l.shape[0]
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    M = np.zeros((3, K), np.float32)
+    _check("irtps_ps_matrix", lib().irtps_ps_matrix(K, lp, sp, M.ctypes.data_as(ct.c_void_p)))
+    return M
+
+
+def _problem(images, light_dirs, light_intensity, env):
+    K, C, H, W = images.shape
+    l, lp = _host_f32(light_dirs, (K, 3), "light_dirs")
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    if env.dim() != 3 or env.shape[2] != C:
+        raise ValueError("env must be [He][We][C]")
+    pr = Problem(W, H, C, K, _dev(images, name="images"), lp, sp, _dev(env, name="env"),
+                 env.shape[0], env.shape[1])
+    return pr, (l, s)
+
+
+def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
+          rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None,
+          workspace=None, stream=None):
+    """The whole IRT-PS loop.  images [K][C][H][W], env [He][We][C] on the device.
+    Returns a dict of device tensors: normals, albedo, depth, indirect, counters."""
+    K, C, H, W = images.shape
+    dev = images.device
+    pr, keep = _problem(images, light_dirs, light_intensity, env)
+    pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, 0, seed)
+    if out is None:
+        out = {"normals": torch.empty((H, W, 3), device=dev),
+               "albedo": torch.empty((C, H, W), device=dev),
+               "depth": torch.empty((H, W), device=dev),
+               "indirect": torch.empty((K, C, H, W), device=dev),
+               "counters": torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=dev)}
+    o = Outputs(_dev(out["normals"], shape=(H, W, 3), name="normals"),
+                _dev(out["albedo"], shape=(C, H, W), name="albedo"),
+                _dev(out["depth"], shape=(H, W), name="depth"),
+                _dev(out.get("indirect"), shape=(K, C, H, W), name="indirect"),
+                _dev(out.get("counters"), dtype=torch.int64, shape=(NUM_COUNTERS,), name="counters"))
+    need = workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iterations,
+                           seed, rho_mode, flags)
+    if workspace is None:
+        workspace = _alloc_ws(need, dev)
+    _check("irtps_solve", lib().irtps_solve(ct.byref(pr), ct.byref(pa), ct.byref(o),
+                                            ct.c_void_p(workspace.data_ptr()),
+                                            workspace.numel(), _stream(stream)))
+    return out
+
+
+def workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
+                    rho_mode=RHO_FIT, flags=0):
+    pr, keep = _problem(images, light_dirs, light_intensity, env)
+    pa = Params(spp, bounces, iterations, rho_mode, flags, 0, 0, 0, seed)
+    n = _sz()
+    _check("irtps_workspace_bytes", lib().irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n)))
+    return n.value
+
+
+def ps_solve(A, light_dirs, light_intensity=None, stream=None):
+    K, C, H, W = A.shape
+    l, lp = _host_f32(light_dirs, (K, 3), "light_dirs")
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    n = torch.empty((H, W, 3), device=A.device)
+    rho = torch.empty((C, H, W), device=A.device)
+    _check("irtps_ps_solve", lib().irtps_ps_solve(W, H, C, K, lp, sp, _dev(A, name="A"),
+                                                  _dev(n), _dev(rho), _stream(stream)))
+    return n, rho
+
+
+def integrate(normals, depth_init=None, cycles=8, stream=None):
+    H, W = normals.shape[:2]
+    nb = _sz()
+    _check("irtps_integrate_workspace_bytes", lib().irtps_integrate_workspace_bytes(W, H, ct.byref(nb)))
+    ws = _alloc_ws(nb.value, normals.device)
+    depth = torch.empty((H, W), device=normals.device)
+    _check("irtps_integrate", lib().irtps_integrate(
+        W, H, _dev(normals, shape=(H, W, 3), name="normals"),
+        _dev(depth_init, shape=(H, W), name="depth_init"), cycles, _dev(depth),
+        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return depth
+
+
+def build_pyramid(depth, stream=None):
+    H, W = depth.shape
+    nb = _sz()
+    _check("irtps_pyramid_bytes", lib().irtps_pyramid_bytes(W, H, ct.byref(nb)))
+    pyr = torch.empty(nb.value // 4, device=depth.device)
+    _check("irtps_build_pyramid", lib().irtps_build_pyramid(W, H, _dev(depth, name="depth"),
+                                                            _dev(pyr), _stream(stream)))
+    return pyr
+
+
+def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, stream=None):
+    H, W = depth.shape
+    l, lp = _host_f32(light_dirs, name="light_dirs")
+    K = l.shape[0]
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    if pyramid is None:
+        pyramid = build_pyramid(depth, stream)
+    S = torch.empty((H, W, K), device=depth.device)
+    _check("irtps_direct", lib().irtps_direct(W, H, K, _dev(depth), _dev(normals, shape=(H, W, 3)),
+                                              lp, sp, _dev(pyramid), _dev(S), _stream(stream)))
+    return S
+
+
+def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOLVE, flags=0,
+          pyramid=None, counters=None, stream=None):
+    H, W = depth.shape
+    C = albedo.shape[0]
+    K = S.shape[2]
+    if pyramid is None:
+        pyramid = build_pyramid(depth, stream)
+    G = torch.empty((K, C, H, W), device=depth.device)
+    _check("irtps_trace", lib().irtps_trace(
+        W, H, C, K, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)),
+        _dev(S, shape=(H, W, K)), _dev(env), env.shape[0], env.shape[1], _dev(pyramid),
+        spp, bounces, seed, t, tag, flags, _dev(G),
+        _dev(counters, dtype=torch.int64, shape=(NUM_COUNTERS,)), _stream(stream)))
+    return G
+
+
+def correct(I0, G, S, albedo, rho_mode=RHO_FIT, flags=0, A_prev=None, want_E=True, stream=None):
+    K, C, H, W = I0.shape
+    E = torch.empty_like(I0) if want_E else None
+    A = torch.empty_like(I0)
+    _check("irtps_correct", lib().irtps_correct(
+        W, H, C, K, rho_mode, flags, _dev(I0), _dev(A_prev), _dev(G, shape=I0.shape),
+        _dev(S, shape=(H, W, K)), _dev(albedo, shape=(C, H, W)), _dev(E), _dev(A), _stream(stream)))
+    return E, A
+
+
+def render(depth, normals, albedo, light_dirs, light_intensity, env, spp, bounces, seed=0,
+           stream=None):
+    H, W = depth.shape
+    C = albedo.shape[0]
+    l, lp = _host_f32(light_dirs, name="light_dirs")
+    K = l.shape[0]
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    nb = _sz()
+    _check("irtps_render_workspace_bytes", lib().irtps_render_workspace_bytes(W, H, C, K, ct.byref(nb)))
+    ws = _alloc_ws(nb.value, depth.device)
+    I = torch.empty((K, C, H, W), device=depth.device)
+    _check("irtps_render", lib().irtps_render(
+        W, H, C, K, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)),
+        lp, sp, _dev(env), env.shape[0], env.shape[1], spp, bounces, seed, _dev(I),
+        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return I
+
+
+def profile_begin():
+    _check("irtps_profile_begin", lib().irtps_profile_begin())
+
+
+def profile_end():
+    """(summed tracer milliseconds, tracer launches) since profile_begin()."""
+    ms, n = ct.c_double(), _i64()
+    _check("irtps_profile_end", lib().irtps_profile_end(ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value
+
+
+# ---- probes ----------------------------------------------------------------
+def probe_philox(ctr, seed):
+    out = torch.empty_like(ctr)
+    _check("irtps_probe_philox", lib().irtps_probe_philox(ctr.shape[0], _dev(ctr, dtype=torch.int32),
+                                                          seed, _dev(out, dtype=torch.int32), _stream()))
+    return out
+
+
+def probe_sample(normals, u):
+    d = torch.empty((u.shape[0], 3), device=u.device)
+    _check("irtps_probe_sample", lib().irtps_probe_sample(u.shape[0], _dev(normals), _dev(u), _dev(d), _stream()))
+    return d
+
+
+def probe_env_texel(d, He, We):
+    rc = torch.empty((d.shape[0], 2), dtype=torch.int32, device=d.device)
+    _check("irtps_probe_env_texel", lib().irtps_probe_env_texel(d.shape[0], _dev(d), He, We,
+                                                                _dev(rc, dtype=torch.int32), _stream()))
+    return rc
+
+
+def probe_traverse(depth, ij, d, flat, pyramid=None):
+    H, W = depth.shape
+    if pyramid is None:
+        pyramid = build_pyramid(depth)
+    q = torch.empty_like(ij)
+    _check("irtps_probe_traverse", lib().irtps_probe_traverse(
+        W, H, _dev(depth), _dev(pyramid), 1 if flat else 0, ij.shape[0],
+        _dev(ij, dtype=torch.int32), _dev(d), _dev(q, dtype=torch.int32), _stream()))
+    return q

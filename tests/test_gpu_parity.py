@@ -1,0 +1,345 @@
+"""GPU (gfx950) against the CPU oracle, through the C ABI.
+
+Bar (from the paper's FP32 radiance and the 0.05 degree normal target):
+radiance |gpu - oracle| <= 1e-4 max(|oracle|, 1e-3 max|oracle|) per element,
+normals within 0.05 degrees at every pixel, albedo within 1e-4 relative,
+depth within 1e-4 px, and integer results (Philox words, texels, hit samples,
+counters) exactly equal.  Both sides take every hit decision in binary32 with
+the same operation order, so equality is expected and reported.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1811_02357_amd import irtps, scenes
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def T(a, dev, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def angle_deg(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    c = (a * b).sum(-1) / np.maximum(np.linalg.norm(a, axis=-1) * np.linalg.norm(b, axis=-1), 1e-300)
+    return np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def assert_radiance(gpu, ref, name):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.maximum(np.abs(ref), 1e-3 * max(np.abs(ref).max(), 1e-30))
+    err = np.abs(gpu - ref) / scale
+    say(f"  {name}: max rel err {err.max():.3e}, bitwise equal {np.mean(gpu == ref) * 100:.4f}%")
+    assert err.max() <= 1e-4, (name, err.max())
+
+
+def assert_normals(gpu, ref, name):
+    a = angle_deg(gpu, ref)
+    say(f"  {name}: max angle {a.max():.3e} deg, p99.9 {np.quantile(a, 0.999):.3e}")
+    assert a.max() <= 0.05, (name, a.max())
+
+
+def assert_albedo(gpu, ref, name):
+    err = np.abs(np.asarray(gpu, np.float64) - ref) / np.maximum(np.abs(ref), 1e-6)
+    say(f"  {name}: max rel err {err.max():.3e}")
+    assert err.max() <= 1e-4
+
+
+def assert_depth(gpu, ref, name):
+    err = np.abs(np.asarray(gpu, np.float64) - ref)
+    say(f"  {name}: max abs err {err.max():.3e} px")
+    assert err.max() <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Probes of the per-lane arithmetic.
+def test_philox_probe(dev):
+    say("case: philox probe, 200k counters")
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(200_000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:10] = [[0, 0, 0, 0], [1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1],
+                [2 ** 32 - 1] * 4, [5, 6, 7, 8], [7, 0, 257, 1], [12345, 63, 3 * 256 + 2, 0], [0, 0, 0, 3]]
+    for seed in (0, 1, 0xDEADBEEFCAFEF00D):
+        got = H(irtps.probe_philox(T(ctr.view(np.int32), dev), seed)).view(np.uint32)
+        ref = O.philox_n(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+        assert np.array_equal(got, ref)
+
+
+def test_sample_probe(dev):
+    say("case: cosine sampling probe, 300k normals")
+    rng = np.random.default_rng(1)
+    N = 300_000
+    n = rng.standard_normal((N, 3))
+    n[:8] = [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0], [0, 0, 1e-8], [1, 1, 0], [1e-7, 0, -1], [-0.0, 0, 1]]
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    n = n.astype(F32)
+    u = (rng.integers(0, 1 << 24, size=(N, 2)) * 2.0 ** -24).astype(F32)
+    u[:4] = [[0, 0], [0, 0.25], [0.99999994, 0.5], [0.5, 0.75]]
+    got = H(irtps.probe_sample(T(n, dev), T(u, dev)))
+    ref = O.sample_cosine_n(n, u)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_env_texel_probe(dev):
+    say("case: environment texel probe")
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal((300_000, 3)).astype(F32)
+    d[:6] = [[0, 0, 1], [0, 0, -1], [1, 0, 0], [-1, 0, 0], [0, -1, 0], [-1, -0.0, 0]]
+    for He, We in [(2, 4), (32, 64), (256, 512), (1, 1), (7, 13)]:
+        got = H(irtps.probe_env_texel(T(d, dev), He, We))
+        assert np.array_equal(got, O.env_texel_n(d, He, We)), (He, We)
+
+
+def _rays(rng, W, Hh, R):
+    ij = np.stack([rng.integers(0, W, R), rng.integers(0, Hh, R)], 1).astype(np.int32)
+    d = rng.standard_normal((R, 3))
+    kind = rng.integers(0, 7, R)
+    d[kind == 1, 0] = 0.0
+    d[kind == 2, 1] = -0.0
+    diag = kind == 3
+    d[diag, 1] = d[diag, 0] * rng.choice([-1, 1], diag.sum())
+    d[kind == 4, 0] *= 1e-6
+    d[kind == 5, 2] = np.abs(d[kind == 5, 2]) * 0.05
+    d[kind == 6, 2] = np.abs(d[kind == 6, 2]) + 0.5
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return ij, d.astype(F32)
+
+
+SURFACES = [
+    ("random8", lambda rng: rng.uniform(-2, 2, (8, 8))),
+    ("random61x37", lambda rng: rng.uniform(-3, 3, (37, 61))),
+    ("bowl64", lambda rng: scenes.bowl_64().heights),
+    ("groove256", lambda rng: scenes.vgroove_heights(256, 256, 32.0, 4.0, 32.0)),
+    ("fbm300", lambda rng: scenes.fbm_heights(300, 0.7, 40.0, rng)[:300, :277]),
+    ("steps97", lambda rng: np.floor(rng.uniform(0, 4, (97, 53))) * 2.0),
+]
+
+
+@pytest.mark.parametrize("name,make", SURFACES, ids=[s[0] for s in SURFACES])
+def test_traverse_probe_flat_and_pyramid(dev, name, make):
+    say(f"case: traversal probe on {name}")
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    Hf = np.ascontiguousarray(make(rng), dtype=F32)
+    Hh, W = Hf.shape
+    ij, d = _rays(rng, W, Hh, 200_000)
+    ref = O.traverse_n(Hf, ij, d)
+    depth = T(Hf, dev)
+    pyr = irtps.build_pyramid(depth)
+    for flat in (True, False):
+        got = H(irtps.probe_traverse(depth, T(ij, dev), T(d, dev), flat, pyr))
+        bad = np.where((got != ref).any(1))[0]
+        assert bad.size == 0, (name, flat, bad.size, ij[bad[:3]], d[bad[:3]], got[bad[:3]], ref[bad[:3]])
+    say(f"  {name}: hits {np.mean(ref[:, 0] >= 0) * 100:.1f}%")
+
+
+def test_pyramid_is_apron_max(dev):
+    say("case: pyramid contents")
+    rng = np.random.default_rng(3)
+    Hf = rng.uniform(-5, 5, (45, 70)).astype(F32)
+    pyr = H(irtps.build_pyramid(T(Hf, dev)))
+    Hh, W = Hf.shape
+    wc, hc, off, l = W - 1, Hh - 1, 0, 0
+    while True:
+        lvl = pyr[off:off + wc * hc].reshape(hc, wc)
+        s = 1 << l
+        for cy in range(hc):
+            for cx in range(wc):
+                x0, x1 = max(cx * s - 1, 0), min((cx + 1) * s + 1, W - 1)
+                y0, y1 = max(cy * s - 1, 0), min((cy + 1) * s + 1, Hh - 1)
+                assert lvl[cy, cx] == Hf[y0:y1 + 1, x0:x1 + 1].max()
+        off += wc * hc
+        if wc == 1 and hc == 1:
+            assert lvl[0, 0] == Hf.max()
+            break
+        wc, hc, l = (wc + 1) // 2, (hc + 1) // 2, l + 1
+
+
+# ---------------------------------------------------------------------------
+# Stages, teacher-forced: both sides get the same seeded inputs.
+@pytest.mark.parametrize("C,K,shape", [(1, 8, (64, 64)), (3, 16, (33, 47)), (1, 64, (20, 19)), (3, 5, (5, 300))])
+def test_ps_solve_stage(dev, C, K, shape):
+    say(f"case: ps_solve C={C} K={K} {shape}")
+    rng = np.random.default_rng(C * 100 + K)
+    Hh, W = shape
+    A = rng.uniform(-0.2, 1.5, (K, C, Hh, W)).astype(F32)
+    l = scenes.fibonacci_lights(K)
+    s = rng.uniform(0.5, 1.5, K).astype(F32)
+    n, rho = irtps.ps_solve(T(A, dev), l, s)
+    rn, rr = O.ps_solve(O.ps_matrix(l, s), A)
+    assert np.array_equal(H(n), rn) and np.array_equal(H(rho), rr)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (37, 61), (3, 200), (2, 2), (257, 129)])
+def test_integrate_stage(dev, shape):
+    say(f"case: integrate {shape}")
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    n = rng.standard_normal((*shape, 3))
+    n[..., 2] = np.abs(n[..., 2]) + 0.3
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    n = n.astype(F32)
+    depth = irtps.integrate(T(n, dev), None, 8)
+    ref = O.integrate(n, None, 8)
+    assert np.array_equal(H(depth), ref)
+    warm = irtps.integrate(T(n, dev), depth, 3)
+    assert np.array_equal(H(warm), O.integrate(n, ref, 3))
+
+
+@pytest.mark.parametrize("name,make", SURFACES[1:4], ids=[s[0] for s in SURFACES[1:4]])
+def test_direct_stage(dev, name, make):
+    say(f"case: direct {name}")
+    rng = np.random.default_rng(11)
+    Hf = np.ascontiguousarray(make(rng), dtype=F32)
+    n = scenes.normals_from_heights(Hf)
+    l = scenes.fibonacci_lights(12)
+    s = rng.uniform(0.5, 1.5, 12).astype(F32)
+    S = irtps.direct(T(Hf, dev), T(n, dev), l, s)
+    assert np.array_equal(H(S), O.direct(Hf, n, l, s))
+
+
+TRACE_CASES = [
+    # name, scene maker, spp, B, flags, t, tag
+    ("bowl_B1", lambda: scenes.bowl_64(), 16, 1, 0, 0, 0),
+    ("bowl_B3_flat", lambda: scenes.bowl_64(), 8, 3, irtps.FLAG_FLAT_TRAVERSAL, 2, 0),
+    ("tiny_rgb_B4", lambda: scenes.tiny_scene(13, 11, seed=4, channels=3, num_lights=20), 9, 4, 0, 1, 1),
+    ("tiny_quadrature", lambda: scenes.tiny_scene(8, 8, seed=5, num_lights=4), 64 * 64, 1,
+     irtps.FLAG_QUADRATURE, 0, 0),
+    ("groove_rgb", lambda: scenes._scene("g", scenes.vgroove_heights(96, 80, 24, 3, 24),
+                                         np.random.default_rng(0).uniform(0.3, 0.9, (3, 80, 96)),
+                                         scenes.fibonacci_lights(16), np.ones(16),
+                                         np.random.default_rng(1).uniform(0, 1, (16, 32, 3))), 16, 3, 0, 4, 0),
+    ("K64_grey", lambda: scenes.tiny_scene(40, 24, seed=6, num_lights=64, amp=6.0), 4, 2, 0, 0, 0),
+]
+
+
+@pytest.mark.parametrize("case", TRACE_CASES, ids=[c[0] for c in TRACE_CASES])
+def test_trace_stage(dev, case):
+    name, make, spp, B, flags, t, tag = case
+    say(f"case: trace {name} spp={spp} B={B} flags={flags}")
+    sc = make()
+    Hf, n, rho, env = sc.heights, sc.normals, sc.albedo, sc.env
+    S = O.direct(Hf, n, sc.light_dirs, sc.light_intensity)
+    seed = 0x1234_5678_9ABC
+    ref, rc = O.trace(Hf, n, rho, S, env, spp, B, seed, t=t, tag=tag,
+                      flags=flags & irtps.FLAG_QUADRATURE)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    G = irtps.trace(T(Hf, dev), T(n, dev), T(rho, dev), T(S, dev), T(env, dev), spp, B, seed, t=t,
+                    tag=tag, flags=flags, counters=cnt)
+    assert_radiance(H(G), ref, name)
+    assert H(cnt).tolist() == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"]]
+    assert np.array_equal(H(G), ref)
+
+
+@pytest.mark.parametrize("mode,flags", [(irtps.RHO_FIT, 0), (irtps.RHO_PREV, 0),
+                                        (irtps.RHO_FIT, irtps.FLAG_LITERAL_CUMULATIVE)])
+def test_correct_stage(dev, mode, flags):
+    say(f"case: correct mode={mode} flags={flags}")
+    rng = np.random.default_rng(21)
+    K, C, Hh, W = 7, 3, 30, 41
+    I0 = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
+    G = rng.uniform(0, 0.5, (K, C, Hh, W)).astype(F32)
+    S = rng.uniform(0, 1, (Hh, W, K)).astype(F32)
+    S[S < 0.2] = 0
+    S[0, 0, :] = 0
+    G[:, :, 0, 0] = 0
+    rho = rng.uniform(0.2, 1, (C, Hh, W)).astype(F32)
+    Ap = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
+    E, A = irtps.correct(T(I0, dev), T(G, dev), T(S, dev), T(rho, dev), mode, flags,
+                         T(Ap, dev) if flags else None)
+    rE, rA = O.correct(I0, G, S, rho, mode, flags, Ap if flags else None)
+    assert np.array_equal(H(E), rE) and np.array_equal(H(A), rA)
+
+
+def test_render_stage(dev):
+    say("case: render bowl64 spp 256 B 2")
+    sc = scenes.bowl_64()
+    ref, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 256, 2, 3)
+    I = irtps.render(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), sc.light_dirs,
+                     sc.light_intensity, T(sc.env, dev), 256, 2, 3)
+    assert_radiance(H(I), ref, "render")
+    assert np.array_equal(H(I), ref)
+
+
+# ---------------------------------------------------------------------------
+# The whole loop.
+def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None):
+    if I0 is None:
+        I0, _ = O.render_scene(sc)
+    Tn = sc.iterations if T_ is None else T_
+    ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, Tn,
+                  seed=sc.seed, rho_mode=rho_mode,
+                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE))
+    out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
+                      sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags)
+    return ref, {k: H(v) for k, v in out.items()}
+
+
+def _compare_solve(ref, got, name):
+    assert_normals(got["normals"], ref["normals"], name + " normals")
+    assert_albedo(got["albedo"], ref["albedo"], name + " albedo")
+    assert_depth(got["depth"], ref["depth"], name + " depth")
+    assert_radiance(got["indirect"], ref["indirect"], name + " indirect")
+    c = ref["counters"]
+    assert got["counters"].tolist() == [c["segments"], c["hits"], c["escapes"], c["continuations"]]
+
+
+@pytest.mark.parametrize("rho_mode,flags", [(irtps.RHO_FIT, 0), (irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE),
+                                            (irtps.RHO_FIT, irtps.FLAG_FLAT_TRAVERSAL)])
+def test_solve_bowl64(dev, rho_mode, flags):
+    say(f"case: solve bowl64 rho_mode={rho_mode} flags={flags}")
+    sc = scenes.bowl_64()
+    ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags)
+    _compare_solve(ref, got, "bowl64")
+
+
+def test_solve_groove512(dev):
+    say("case: solve vgroove512 (spp 64, B 2, T 5)")
+    sc = scenes.vgroove_512()
+    ref, got = _solve_both(sc, dev)
+    _compare_solve(ref, got, "vgroove512")
+
+
+def test_solve_rgb_ragged(dev):
+    say("case: solve RGB fbm 150x97, K=16, spp 16, B 3, T 2")
+    sc = scenes.fbm_terrain(seed=3, size=160, channels=3, num_lights=16, env_shape=(32, 64),
+                            ptp=20.0, spp=16, bounces=3, iterations=2, render_spp=16, render_bounces=3)
+    sc.heights = np.ascontiguousarray(sc.heights[:97, :150])
+    sc.normals = np.ascontiguousarray(sc.normals[:97, :150])
+    sc.albedo = np.ascontiguousarray(sc.albedo[:, :97, :150])
+    ref, got = _solve_both(sc, dev)
+    _compare_solve(ref, got, "fbm150x97")
+
+
+def test_solve_T0_is_plain_ps(dev):
+    say("case: solve T=0")
+    sc = scenes.bowl_64()
+    ref, got = _solve_both(sc, dev, T_=0)
+    _compare_solve(ref, got, "bowl64 T0")
+    assert (got["indirect"] == 0).all()
