@@ -36,8 +36,7 @@ __device__ __forceinline__ Surface make_surface(const SurfaceArgs& a) {
 
 __device__ __forceinline__ bool walk(const Surface& S, bool flat, int i, int j, dm::V3 d, int& qi,
                                      int& qj) {
-    return flat ? trv::walk_flat(S, i, j, d.x, d.y, d.z, qi, qj)
-                : trv::walk_pyramid(S, i, j, d.x, d.y, d.z, qi, qj);
+    return trv::walk(S, flat, i, j, d.x, d.y, d.z, qi, qj);
 }
 
 // ---------------------------------------------------------------------------
@@ -100,8 +99,14 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
 
 // ---------------------------------------------------------------------------
 // Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments.
-// One lane owns one pixel and keeps K x C accumulators in registers; lights
-// [k0, k0 + KMAX) are gathered per launch.
+// One lane owns one pixel and keeps the K x C sums in registers (lights
+// [k0, k0 + KMAX) per launch).  Each lane runs its own sequence of segments:
+// the wave alternates a traversal phase, in which every lane advances its own
+// ray until at least kReadyBatch lanes (or all that still have work) have
+// finished theirs, with a phase that shades the finished segments and starts
+// the next ones.  A lane's segments are still summed in (sample, bounce) order.
+constexpr int kReadyBatch = 24;
+
 template <int C, int KMAX>
 __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     const int tiles_x = (a.sa.W + 15) / 16;
@@ -112,7 +117,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     const int j = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
     const bool live = i < a.sa.W && j < a.sa.Hh;
     const int npx = a.sa.W * a.sa.Hh;
-    const int p = j * a.sa.W + i;
+    const int p = live ? j * a.sa.W + i : 0;
     const Surface S = make_surface(a.sa);
     const int kc = a.kcount;
     const bool flat = (a.flags & kFlagFlat) != 0;
@@ -130,62 +135,99 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
         M = 1;
         while (M * M < a.spp) ++M;
     }
-    if (live) {
-        for (int s = 0; s < a.spp; ++s) {
-            float beta[C];
+
+    // lane state
+    bool finished = !live || a.B < 1;
+    bool ready = false;  // current segment has a result
+    int s = 0, b = 1;    // current sample and segment
+    int res = trv::kGoOn, qi = 0, qj = 0;
+    float beta[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) beta[c] = 1.0f;
-            int ci = i, cj = j;
-            size_t cp = (size_t)p;
-            for (int b = 1; b <= a.B; ++b) {
-                float u1, u2;
-                if (M > 0 && b == 1) {
-                    u1 = ((float)(s / M) + 0.5f) / (float)M;
-                    u2 = ((float)(s % M) + 0.5f) / (float)M;
-                } else {
-                    const dm::U4 r = dm::philox((uint32_t)p, (uint32_t)s,
-                                                (uint32_t)a.t * 256u + (uint32_t)b, (uint32_t)a.tag,
-                                                a.key0, a.key1);
-                    u1 = dm::unit24(r.x);
-                    u2 = dm::unit24(r.y);
-                }
-                const float nx = a.n[3 * cp], ny = a.n[3 * cp + 1], nz = a.n[3 * cp + 2];
-                const dm::V3 d = dm::cosine_dir(nx, ny, nz, u1, u2);
-                int qi, qj;
-                ++n_seg;
-                if (!walk(S, flat, ci, cj, d, qi, qj)) {
-                    int er, ec;
-                    dm::env_texel(d.x, d.y, d.z, a.env_h, a.env_w, er, ec);
-                    const float* L = a.env + ((size_t)er * a.env_w + ec) * C;
+    for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+    int ci = i, cj = j;
+    size_t cp = (size_t)p;
+    trv::Walker w;
+    bool need_setup = !finished;
+
+    for (;;) {
+        if (need_setup) {
+            float u1, u2;
+            if (M > 0 && b == 1) {
+                u1 = ((float)(s / M) + 0.5f) / (float)M;
+                u2 = ((float)(s % M) + 0.5f) / (float)M;
+            } else {
+                const dm::U4 r = dm::philox((uint32_t)p, (uint32_t)s, (uint32_t)a.t * 256u + (uint32_t)b,
+                                            (uint32_t)a.tag, a.key0, a.key1);
+                u1 = dm::unit24(r.x);
+                u2 = dm::unit24(r.y);
+            }
+            const dm::V3 d = dm::cosine_dir(a.n[3 * cp], a.n[3 * cp + 1], a.n[3 * cp + 2], u1, u2);
+            trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
+            ++n_seg;
+            need_setup = false;
+            ready = false;
+        }
+        if (__all(finished)) break;
+        // traversal phase
+        for (;;) {
+            if (!finished && !ready) {
+                res = trv::walker_step(w, S, qi, qj);
+                ready = res != trv::kGoOn;
+            }
+            const int n_act = __popcll(__ballot(!finished));
+            const int n_rdy = __popcll(__ballot(!finished && ready));
+            if (n_rdy >= (n_act < kReadyBatch ? n_act : kReadyBatch)) break;
+        }
+        // shading phase
+        if (!finished && ready) {
+            bool next_sample = true;
+            if (res == trv::kMiss) {
+                int er, ec;
+                dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
+                const float* L = a.env + ((size_t)er * a.env_w + ec) * C;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
-                    ++n_esc;
-                    break;
-                }
+                for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
+                ++n_esc;
+            } else {
                 ++n_hit;
                 const size_t q = (size_t)qj * a.sa.W + qi;
-                float w[C];
+                float wgt[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) w[c] = beta[c] * a.rho[(size_t)c * npx + q];
+                for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[(size_t)c * npx + q];
                 const float* Sq = a.S + q * a.K + a.k0;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
                     if (k < kc) {
                         const float sq = Sq[k];
 #pragma unroll
-                        for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(w[c], sq, acc[k * C + c]);
+                        for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(wgt[c], sq, acc[k * C + c]);
                     }
                 }
                 if (b < a.B) {
                     ++n_cont;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) beta[c] = w[c];
+                    for (int c = 0; c < C; ++c) beta[c] = wgt[c];
                     ci = qi;
                     cj = qj;
                     cp = q;
+                    ++b;
+                    next_sample = false;
                 }
             }
+            if (next_sample) {
+                ++s;
+                b = 1;
+#pragma unroll
+                for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+                ci = i;
+                cj = j;
+                cp = (size_t)p;
+                finished = s >= a.spp;
+            }
+            need_setup = !finished;
         }
+    }
+    if (live) {
         const float fspp = (float)a.spp;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {

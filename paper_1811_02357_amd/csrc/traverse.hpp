@@ -105,33 +105,11 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
     return kGoOn;
 }
 
-// Flat walk: every crossing in t order.
-__device__ __forceinline__ bool walk_flat(const Surface& S, int i0, int j0, float dx, float dy,
-                                          float dz, int& qi, int& qj) {
-    if (dx == 0.0f && dy == 0.0f) return false;
-    const Ray r = make_ray(S, i0, j0, dx, dy, dz);
-    int mx = 1, my = 1;
-    float tX = t_x(r, 1), tY = t_y(r, 1);
-    for (;;) {
-        if (isinf(tX) && isinf(tY)) return false;
-        const bool xline = tX <= tY;
-        const int res = crossing(S, r, xline, xline ? tX : tY, mx, my, qi, qj);
-        if (res != kGoOn) return res == kHit;
-        if (xline) {
-            ++mx;
-            tX = t_x(r, mx);
-        } else {
-            ++my;
-            tY = t_y(r, my);
-        }
-    }
-}
-
 // Smallest crossing index m >= m_lo whose t (same formula as the walk) is >= t_lim.
 __device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline, int m_lo,
                                                        float t_lim, float d_abs) {
     // estimate from the geometry, then correct with the exact formula
-    float est = ceilf(t_lim * d_abs);
+    const float est = ceilf(t_lim * d_abs);
     int m = est > 2.0e9f ? 2000000000 : (int)est;
     if (m < m_lo) m = m_lo;
     while (m > m_lo && (xline ? t_x(r, m - 1) : t_y(r, m - 1)) >= t_lim) --m;
@@ -139,81 +117,105 @@ __device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline,
     return m;
 }
 
-// Pyramid walk.  At the next crossing (t_now) pick the coarsest level whose
-// cell around the ray's current position can be skipped: the cell (grown by
-// one sample) lies inside the domain interior and the ray's height at t_now and
-// at the cell's exit t are both at or above the cell's apron maximum.  All
-// crossings with t < t_exit are then skipped.  Otherwise evaluate the one
-// crossing at t_now exactly as the flat walk does.
-__device__ __forceinline__ bool walk_pyramid(const Surface& S, int i0, int j0, float dx, float dy,
-                                             float dz, int& qi, int& qj) {
-    if (dx == 0.0f && dy == 0.0f) return false;
-    const Ray r = make_ray(S, i0, j0, dx, dy, dz);
-    const float adx = fabsf(dx), ady = fabsf(dy);
-    int mx = 1, my = 1;
-    float tX = t_x(r, 1), tY = t_y(r, 1);
-    int level = 0;
-    for (;;) {
-        if (isinf(tX) && isinf(tY)) return false;
-        const bool xline = tX <= tY;
-        const float t_now = xline ? tX : tY;
-        // position of the next crossing (approximate: only used to choose a cell)
-        const float px = xline ? (float)(r.i0 + r.sx * mx) : fmaf(t_now, dx, r.ox);
-        const float py = xline ? fmaf(t_now, dy, r.oy) : (float)(r.j0 + r.sy * my);
-        const float z_now = fmaf(t_now, dz, r.oz);
-        bool skipped = false;
-        const bool inside = px >= 0.0f && px <= (float)(S.W - 1) && py >= 0.0f && py <= (float)(S.Hh - 1);
-        if (!inside) level = -1;  // the crossing below is outside the domain: escape
-        // try from the current level upwards-first strategy: climb while skips succeed
-        for (int l = level; l >= 0; --l) {
+// Finest pyramid level the walker tries to skip (cells of 4 x 4 sample gaps).
+constexpr int kMinSkipLevel = 2;
+
+// Resumable walk: one call of step() either evaluates the next crossing or
+// tries one pyramid cell.  level < 0 walks every crossing.
+struct Walker {
+    Ray r;
+    int mx, my, level;
+    float tX, tY;
+};
+
+__device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0, int j0, float dx,
+                                            float dy, float dz, bool flat) {
+    w.r = make_ray(S, i0, j0, dx, dy, dz);
+    w.mx = 1;
+    w.my = 1;
+    w.level = flat ? -1 : kMinSkipLevel;
+    // a ray along z has no crossings: t = inf on both families ends the walk
+    const bool vertical = dx == 0.0f && dy == 0.0f;
+    w.tX = vertical ? __builtin_inff() : t_x(w.r, 1);
+    w.tY = vertical ? __builtin_inff() : t_y(w.r, 1);
+}
+
+// Returns kGoOn, kHit (qi, qj set) or kMiss.
+__device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi, int& qj) {
+    const Ray& r = w.r;
+    if (isinf(w.tX) && isinf(w.tY)) return kMiss;
+    const bool xline = w.tX <= w.tY;
+    const float t_now = xline ? w.tX : w.tY;
+    const float z_now = fmaf(t_now, r.dz, r.oz);
+    // at or above every sample and not descending: no crossing ahead can hit
+    if (z_now >= S.hmax && r.dz >= 0.0f) return kMiss;
+    if (w.level >= kMinSkipLevel) {
+        // approximate position of the next crossing: only chooses the cell
+        const float px = xline ? (float)(r.i0 + r.sx * w.mx) : fmaf(t_now, r.dx, r.ox);
+        const float py = xline ? fmaf(t_now, r.dy, r.oy) : (float)(r.j0 + r.sy * w.my);
+        if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
+            const int l = w.level;
             const int size = 1 << l;
-            // cell ahead of the ray in each axis
             int cx = (int)floorf(px) >> l;
             int cy = (int)floorf(py) >> l;
             if (r.sx < 0 && (float)(cx << l) == px) cx -= 1;
             if (r.sy < 0 && (float)(cy << l) == py) cy -= 1;
-            if (cx < 0 || cy < 0 || cx >= S.P.wc[l] || cy >= S.P.hc[l]) continue;
-            const int X0 = cx << l, X1 = X0 + size, Y0 = cy << l, Y1 = Y0 + size;
-            if (X0 < 2 || Y0 < 2 || X1 > S.W - 3 || Y1 > S.Hh - 3) continue;
-            const float cmax = S.pyr[S.P.off[l] + (long long)cy * S.P.wc[l] + cx];
-            if (!(z_now >= cmax)) continue;
-            // exit lines of the cell in the direction of travel
-            const int Xe = r.sx > 0 ? X1 : X0;
-            const int Ye = r.sy > 0 ? Y1 : Y0;
-            const int mxe = (Xe - r.i0) * r.sx;
-            const int mye = (Ye - r.j0) * r.sy;
-            const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
-            const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
-            const float t_exit = txe < tye ? txe : tye;
-            if (!(t_exit > t_now) || isinf(t_exit)) continue;
-            const float z_exit = fmaf(t_exit, dz, r.oz);
-            if (!(z_exit >= cmax)) continue;
-            // skip every crossing with t < t_exit
-            if (!isinf(tX)) {
-                mx = first_index_at_or_after(r, true, mx, t_exit, adx);
-                tX = t_x(r, mx);
+            const int X0 = cx << l, Y0 = cy << l;
+            const int X1 = X0 + size, Y1 = Y0 + size;
+            bool skip = false;
+            if (X0 >= 2 && Y0 >= 2 && X1 <= S.W - 3 && Y1 <= S.Hh - 3) {
+                const float cmax = S.pyr[S.P.off[l] + (long long)cy * S.P.wc[l] + cx];
+                if (z_now >= cmax) {
+                    const int mxe = ((r.sx > 0 ? X1 : X0) - r.i0) * r.sx;
+                    const int mye = ((r.sy > 0 ? Y1 : Y0) - r.j0) * r.sy;
+                    const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
+                    const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
+                    const float t_exit = txe < tye ? txe : tye;
+                    if (t_exit > t_now && !isinf(t_exit) && fmaf(t_exit, r.dz, r.oz) >= cmax) {
+                        // every crossing with t < t_exit lies in the cell: none can hit
+                        if (!isinf(w.tX)) {
+                            w.mx = first_index_at_or_after(r, true, w.mx, t_exit, fabsf(r.dx));
+                            w.tX = t_x(r, w.mx);
+                        }
+                        if (!isinf(w.tY)) {
+                            w.my = first_index_at_or_after(r, false, w.my, t_exit, fabsf(r.dy));
+                            w.tY = t_y(r, w.my);
+                        }
+                        skip = true;
+                    }
+                }
             }
-            if (!isinf(tY)) {
-                my = first_index_at_or_after(r, false, my, t_exit, ady);
-                tY = t_y(r, my);
+            if (skip) {
+                if (l < S.top) w.level = l + 1;
+                return kGoOn;
             }
-            level = l + 1 < S.top ? l + 1 : S.top;
-            skipped = true;
-            break;
+            if (l > kMinSkipLevel) {
+                w.level = l - 1;
+                return kGoOn;
+            }
         }
-        if (skipped) continue;
-        level = 0;
-        const int res = crossing(S, r, xline, t_now, mx, my, qi, qj);
-        if (res != kGoOn) return res == kHit;
+    }
+    const int res = crossing(S, r, xline, t_now, w.mx, w.my, qi, qj);
+    if (res == kGoOn) {
         if (xline) {
-            ++mx;
-            tX = t_x(r, mx);
+            ++w.mx;
+            w.tX = t_x(r, w.mx);
         } else {
-            ++my;
-            tY = t_y(r, my);
+            ++w.my;
+            w.tY = t_y(r, w.my);
         }
-        // a crossing outside the domain was checked above; keep climbing lazily
-        level = 1;
+    }
+    return res;
+}
+
+// Whole walk in one call (shadow rays, probes).
+__device__ __forceinline__ bool walk(const Surface& S, bool flat, int i0, int j0, float dx, float dy,
+                                     float dz, int& qi, int& qj) {
+    Walker w;
+    walker_init(w, S, i0, j0, dx, dy, dz, flat);
+    for (;;) {
+        const int res = walker_step(w, S, qi, qj);
+        if (res != kGoOn) return res == kHit;
     }
 }
 
