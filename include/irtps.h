@@ -19,8 +19,9 @@
  *     radiance on an equirectangular map: row r covers polar angle
  *     [r pi/He, (r+1) pi/He) from +z, column c covers azimuth
  *     [2 pi c/We, 2 pi (c+1)/We) from +x towards +y.
- *   - Layouts are row-major float32: images, gathered and indirect radiance
- *     [K][C][H][W]; normals [H][W][3]; albedo [C][H][W]; depth [H][W];
+ *   - Layouts are row-major float32: images and indirect radiance
+ *     [K][C][H][W]; gathered radiance G [H][W][K][C] (pixel-major: one pixel's
+ *     sums are contiguous); normals [H][W][3]; albedo [C][H][W]; depth [H][W];
  *     direct irradiance [H][W][K]; environment [He][We][C].  C is 1 or 3,
  *     W and H are 2..16384 with W H <= 2^28, K is 3..64.
  *   - Pointers named *_dev are device memory (any hipMalloc'd or
@@ -171,7 +172,7 @@ int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev,
  * cosine-weighted paths of up to B segments on the current surface.  A hit at
  * sample q adds beta_c albedo_c(q) S[q][k] for every light k; an escape adds
  * beta_c pi L_env,c(d) and ends the path; beta is the product of the albedos
- * met so far.  G_dev[k][c][p] = (sum over paths) / spp.  Sample s, segment b of
+ * met so far.  G_dev[p][k][c] = (sum over paths) / spp.  Sample s, segment b of
  * pixel p = j W + i draw Philox4x32-10(key = seed, counter = (p, s, t 256 + b,
  * tag)).  counters_dev (IRTPS_NUM_COUNTERS uint64, accumulated) may be NULL. */
 int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev,

@@ -87,10 +87,13 @@ trv::Pyramid pyramid_plan(int W, int H) {
     return P;
 }
 
-long long pyramid_floats(const trv::Pyramid& P) {
+long long pyramid_level_floats(const trv::Pyramid& P) {
     const int t = P.levels - 1;
-    return P.off[t] + (long long)P.wc[t] * P.hc[t];
+    return (P.off[t] + (long long)P.wc[t] * P.hc[t] + 63) / 64 * 64;
 }
+
+// Apron-max levels followed by the four quadrant-maximum planes.
+long long pyramid_floats(int W, int H) { return pyramid_level_floats(pyramid_plan(W, H)) + 4LL * W * H; }
 
 kern::MgPlan mg_plan(int W, int H) {
     kern::MgPlan m{};
@@ -181,7 +184,10 @@ kern::SurfaceArgs surface(int W, int H, const float* depth, const float* pyr) {
     sa.pyr = pyr;
     sa.W = W;
     sa.Hh = H;
-    sa.P = pyramid_plan(W, H);
+    const trv::Pyramid P = pyramid_plan(W, H);
+    sa.levels = P.levels;
+    sa.quad_off = (int)pyramid_level_floats(P);
+    for (int l = 0; l < trv::kMaxLevels; ++l) sa.off[l] = l < P.levels ? (int)P.off[l] : 0;
     return sa;
 }
 
@@ -202,7 +208,7 @@ SolveLayout solve_layout(int W, int H, int C, int K) {
     L.G = off;
     off = align_up(off + sizeof(float) * npx * K * C);
     L.pyr = off;
-    off = align_up(off + sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H)));
+    off = align_up(off + sizeof(float) * (size_t)pyramid_floats(W, H));
     L.plan = mg_plan(W, H);
     L.mg = off;
     off = align_up(off + sizeof(float) * (size_t)L.plan.total);
@@ -292,7 +298,7 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
 
     const kern::SurfaceArgs sa = surface(W, H, out->depth_dev, pyr);
     for (int t = 0; t < pa->iterations; ++t) {
-        HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, sa.P, pyr, st));
+        HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
         HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
         kern::TraceArgs ta{};
         ta.sa = sa;
@@ -354,13 +360,14 @@ int irtps_integrate(int32_t W, int32_t H, const float* normals_dev, const float*
 
 int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes) {
     if (!dims_ok(W, H) || !bytes) return IRTPS_ERR_INVALID_ARG;
-    *bytes = sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H));
+    *bytes = sizeof(float) * (size_t)pyramid_floats(W, H);
     return IRTPS_OK;
 }
 
 int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyramid_dev, void* stream) {
     if (!dims_ok(W, H) || !depth_dev || !pyramid_dev) return IRTPS_ERR_INVALID_ARG;
-    HIP_TRY(kern::build_pyramid(W, H, depth_dev, pyramid_plan(W, H), pyramid_dev,
+    const trv::Pyramid P = pyramid_plan(W, H);
+    HIP_TRY(kern::build_pyramid(W, H, depth_dev, P, pyramid_dev, pyramid_level_floats(P),
                                 reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
@@ -424,7 +431,7 @@ int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, siz
     if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !bytes) return IRTPS_ERR_INVALID_ARG;
     const size_t npx = (size_t)W * H;
     *bytes = align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C) +
-             align_up(sizeof(float) * (size_t)pyramid_floats(pyramid_plan(W, H)));
+             align_up(sizeof(float) * (size_t)pyramid_floats(W, H));
     return IRTPS_OK;
 }
 
@@ -447,7 +454,7 @@ int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_
     float* G = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K));
     float* pyr = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C));
     const kern::SurfaceArgs sa = surface(W, H, depth_dev, pyr);
-    HIP_TRY(kern::build_pyramid(W, H, depth_dev, sa.P, pyr, st));
+    HIP_TRY(kern::build_pyramid(W, H, depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
     HIP_TRY(kern::direct(sa, normals_dev, Ls, 0, S, st));
     kern::TraceArgs ta{};
     ta.sa = sa;

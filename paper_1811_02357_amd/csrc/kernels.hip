@@ -22,15 +22,25 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return t;
 }
 
-__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a) {
+// Every kernel that walks rays first copies the pyramid's level offsets to LDS
+// (constant indices only) and then builds its Surface view on that table.
+__device__ __forceinline__ void load_level_table(const SurfaceArgs& a, int* s_off) {
+#pragma unroll
+    for (int l = 0; l < trv::kMaxLevels; ++l)
+        if ((int)threadIdx.x == l) s_off[l] = a.off[l];
+    __syncthreads();
+}
+
+__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a, const int* s_off) {
     Surface S;
     S.H = a.H;
     S.pyr = a.pyr;
+    S.quad = a.pyr + a.quad_off;
+    S.lvl_off = s_off;
     S.W = a.W;
     S.Hh = a.Hh;
-    S.top = a.P.levels - 1;
-    S.P = a.P;
-    S.hmax = a.pyr[a.P.off[a.P.levels - 1]];
+    S.top = a.levels - 1;
+    S.hmax = a.pyr[s_off[S.top]];
     return S;
 }
 
@@ -78,10 +88,12 @@ __global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, co
 // Eq.2 without albedo, with cast shadows.
 __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
                                                 int flat, float* __restrict__ S_out) {
+    __shared__ int s_off[trv::kMaxLevels];
+    load_level_table(sa, s_off);
     const int npx = sa.W * sa.Hh;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npx) return;
-    const Surface S = make_surface(sa);
+    const Surface S = make_surface(sa, s_off);
     const int i = p % sa.W, j = p / sa.W;
     const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
     for (int k = 0; k < L.K; ++k) {
@@ -99,16 +111,19 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
 
 // ---------------------------------------------------------------------------
 // Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments.
-// One lane owns one pixel and keeps the K x C sums in registers (lights
-// [k0, k0 + KMAX) per launch).  Each lane runs its own sequence of segments:
-// the wave alternates a traversal phase, in which every lane advances its own
-// ray until at least kReadyBatch lanes (or all that still have work) have
-// finished theirs, with a phase that shades the finished segments and starts
-// the next ones.  A lane's segments are still summed in (sample, bounce) order.
-constexpr int kReadyBatch = 24;
+// One lane owns one pixel.  Its K x C hit sums live in that pixel's row of the
+// pixel-major output G[p][k][c] (only this lane touches it); the C environment
+// sums stay in registers.  Each lane runs its own sequence of segments: the
+// wave alternates a traversal phase, in which every lane advances its own ray
+// until at least kReadyBatch lanes (or all that still have work) have finished
+// theirs, with a phase that shades the finished segments and starts the next
+// ones.  A lane's segments are summed in (sample, bounce) order.
+constexpr int kReadyBatch = 32;
 
-template <int C, int KMAX>
+template <int C>
 __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
+    __shared__ int s_off[trv::kMaxLevels];
+    load_level_table(a.sa, s_off);
     const int tiles_x = (a.sa.W + 15) / 16;
     const int tiles_y = (a.sa.Hh + 15) / 16;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -118,17 +133,18 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     const bool live = i < a.sa.W && j < a.sa.Hh;
     const int npx = a.sa.W * a.sa.Hh;
     const int p = live ? j * a.sa.W + i : 0;
-    const Surface S = make_surface(a.sa);
-    const int kc = a.kcount;
+    const Surface S = make_surface(a.sa, s_off);
     const bool flat = (a.flags & kFlagFlat) != 0;
+    const int K = a.K;
+    const int KC = K * C;
+    float* __restrict__ gp = a.G + (size_t)p * KC;  // this pixel's sums
 
-    float acc[KMAX * C];
-#pragma unroll
-    for (int x = 0; x < KMAX * C; ++x) acc[x] = 0.0f;
+    if (live)
+        for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
     float eacc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) eacc[c] = 0.0f;
-    unsigned long long n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
+    unsigned n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
 
     int M = 0;
     if (a.flags & kFlagQuadrature) {
@@ -144,8 +160,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     float beta[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) beta[c] = 1.0f;
-    int ci = i, cj = j;
-    size_t cp = (size_t)p;
+    int cp = p, ci = i, cj = j;  // sample the current segment starts from
     trv::Walker w;
     bool need_setup = !finished;
 
@@ -184,32 +199,29 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
             if (res == trv::kMiss) {
                 int er, ec;
                 dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
-                const float* L = a.env + ((size_t)er * a.env_w + ec) * C;
+                const float* L = a.env + (er * a.env_w + ec) * C;
 #pragma unroll
                 for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
                 ++n_esc;
             } else {
                 ++n_hit;
-                const size_t q = (size_t)qj * a.sa.W + qi;
+                const int q = qj * a.sa.W + qi;
                 float wgt[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[(size_t)c * npx + q];
-                const float* Sq = a.S + q * a.K + a.k0;
+                for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[c * npx + q];
+                const float* __restrict__ Sq = a.S + (size_t)q * K;
+                for (int k = 0; k < K; ++k) {
+                    const float sq = Sq[k];
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kc) {
-                        const float sq = Sq[k];
-#pragma unroll
-                        for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(wgt[c], sq, acc[k * C + c]);
-                    }
+                    for (int c = 0; c < C; ++c) gp[k * C + c] = fmaf(wgt[c], sq, gp[k * C + c]);
                 }
                 if (b < a.B) {
                     ++n_cont;
 #pragma unroll
                     for (int c = 0; c < C; ++c) beta[c] = wgt[c];
+                    cp = q;
                     ci = qi;
                     cj = qj;
-                    cp = q;
                     ++b;
                     next_sample = false;
                 }
@@ -219,9 +231,9 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
                 b = 1;
 #pragma unroll
                 for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+                cp = p;
                 ci = i;
                 cj = j;
-                cp = (size_t)p;
                 finished = s >= a.spp;
             }
             need_setup = !finished;
@@ -229,34 +241,31 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     }
     if (live) {
         const float fspp = (float)a.spp;
+        for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            if (k < kc) {
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    a.G[((size_t)(a.k0 + k) * C + c) * npx + p] = (acc[k * C + c] + eacc[c]) / fspp;
-            }
+            for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
         }
     }
     if (a.counters) {
         // wave-level sums, one atomic per wave
+        unsigned long long v0 = n_seg, v1 = n_hit, v2 = n_esc, v3 = n_cont;
         for (int o = 32; o > 0; o >>= 1) {
-            n_seg += __shfl_xor(n_seg, o);
-            n_hit += __shfl_xor(n_hit, o);
-            n_esc += __shfl_xor(n_esc, o);
-            n_cont += __shfl_xor(n_cont, o);
+            v0 += __shfl_xor(v0, o);
+            v1 += __shfl_xor(v1, o);
+            v2 += __shfl_xor(v2, o);
+            v3 += __shfl_xor(v3, o);
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&a.counters[0], n_seg);
-            atomicAdd(&a.counters[1], n_hit);
-            atomicAdd(&a.counters[2], n_esc);
-            atomicAdd(&a.counters[3], n_cont);
+            atomicAdd(&a.counters[0], v0);
+            atomicAdd(&a.counters[1], v1);
+            atomicAdd(&a.counters[2], v2);
+            atomicAdd(&a.counters[3], v3);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Stage 5.
+// Stage 5 (G is pixel-major [p][k][c], images and E are [k][c][p]).
 template <int C>
 __global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, int cumulative,
                                                  const float* __restrict__ I0, const float* __restrict__ Aprev,
@@ -272,7 +281,7 @@ __global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, i
             float num = 0.0f, den = 0.0f;
             for (int k = 0; k < K; ++k) {
                 const size_t x = ((size_t)k * C + c) * npx + p;
-                const float v = S[(size_t)p * K + k] + G[x];
+                const float v = S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c];
                 num = fmaf(I0[x], v, num);
                 den = fmaf(v, v, den);
             }
@@ -282,14 +291,14 @@ __global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, i
         }
         for (int k = 0; k < K; ++k) {
             const size_t x = ((size_t)k * C + c) * npx + p;
-            const float e = rt * G[x];
+            const float e = rt * G[((size_t)p * K + k) * C + c];
             if (E) E[x] = e;
             Anext[x] = (cumulative ? Aprev[x] : I0[x]) - e;
         }
     }
 }
 
-// Forward render: images = albedo (S + G).
+// Forward render: images = albedo (S + G); G is pixel-major [p][k][c].
 template <int C>
 __global__ void __launch_bounds__(256) k_compose(int npx, int K, const float* __restrict__ rho,
                                                  const float* __restrict__ S, const float* __restrict__ G,
@@ -300,7 +309,7 @@ __global__ void __launch_bounds__(256) k_compose(int npx, int K, const float* __
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const size_t x = ((size_t)k * C + c) * npx + p;
-            I[x] = rho[(size_t)c * npx + p] * (S[(size_t)p * K + k] + G[x]);
+            I[x] = rho[(size_t)c * npx + p] * (S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c]);
         }
     }
 }
@@ -338,6 +347,54 @@ __global__ void __launch_bounds__(256) k_pyr_reduce(const float* __restrict__ in
             }
         }
     out[c] = m;
+}
+
+// Quadrant maxima: quad[q][y][x] = max of H over samples (x', y') with
+// (x' - x) sx >= 0 and (y' - y) sy >= 0, q = (sx < 0) + 2 (sy < 0).
+// Rows first: q0 <- suffix max along x, q1 <- prefix max along x.
+__global__ void __launch_bounds__(64) k_quad_rows(int W, int Hh, const float* __restrict__ H,
+                                                  float* __restrict__ quad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Hh) return;
+    const int plane = W * Hh;
+    const float* row = H + j * W;
+    float* suf = quad + 0 * plane + j * W;
+    float* pre = quad + 1 * plane + j * W;
+    float m = row[W - 1];
+    for (int x = W - 1; x >= 0; --x) {
+        const float v = row[x];
+        m = v > m ? v : m;
+        suf[x] = m;
+    }
+    m = row[0];
+    for (int x = 0; x < W; ++x) {
+        const float v = row[x];
+        m = v > m ? v : m;
+        pre[x] = m;
+    }
+}
+
+// Columns: q2 <- prefix along y of q0, q3 <- prefix of q1, then q0, q1 <- suffixes in place.
+__global__ void __launch_bounds__(64) k_quad_cols(int W, int Hh, float* __restrict__ quad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W) return;
+    const int plane = W * Hh;
+    for (int h = 0; h < 2; ++h) {
+        float* src = quad + h * plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
+        float* pre = quad + (h + 2) * plane;  // sy = -1
+        float m = src[i];
+        for (int y = 0; y < Hh; ++y) {
+            const float v = src[y * W + i];
+            m = v > m ? v : m;
+            pre[y * W + i] = m;
+        }
+        m = src[(Hh - 1) * W + i];
+        for (int y = Hh - 1; y >= 0; --y) {
+            const float v = src[y * W + i];
+            m = v > m ? v : m;
+            src[y * W + i] = m;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -501,6 +558,8 @@ __global__ void k_probe_env(long long count, const float* d, int He, int We, int
 
 __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, const int* ij,
                                  const float* d, int* q) {
+    __shared__ int s_off[trv::kMaxLevels];
+    load_level_table(sa, s_off);
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= count) return;
     const int i0 = ij[2 * r], j0 = ij[2 * r + 1];
@@ -509,7 +568,7 @@ __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, cons
         q[2 * r + 1] = -2;
         return;
     }
-    const Surface S = make_surface(sa);
+    const Surface S = make_surface(sa, s_off);
     int qi = -1, qj = -1;
     const bool hit = walk(S, flat != 0, i0, j0,
                           dm::V3{d[3 * r], d[3 * r + 1], d[3 * r + 2]}, qi, qj);
@@ -536,33 +595,12 @@ hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int 
     return hipGetLastError();
 }
 
-template <int C, int KMAX>
-static void launch_trace(const TraceArgs& a, hipStream_t st) {
-    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
-    const int per = (tiles + 7) / 8;
-    hipLaunchKernelGGL((k_trace<C, KMAX>), dim3(per * 8), dim3(256), 0, st, a);
-}
-
 hipError_t trace(TraceArgs a, hipStream_t st) {
-    // lights in chunks that fit the register accumulators
-    const int cap = a.C == 1 ? 64 : 16;
-    for (int k0 = 0; k0 < a.K; k0 += cap) {
-        a.k0 = k0;
-        a.kcount = a.K - k0 < cap ? a.K - k0 : cap;
-        if (k0 > 0) a.counters = nullptr;  // count each segment once
-        if (a.C == 1) {
-            if (a.kcount <= 8) launch_trace<1, 8>(a, st);
-            else if (a.kcount <= 16) launch_trace<1, 16>(a, st);
-            else if (a.kcount <= 32) launch_trace<1, 32>(a, st);
-            else launch_trace<1, 64>(a, st);
-        } else {
-            if (a.kcount <= 8) launch_trace<3, 8>(a, st);
-            else launch_trace<3, 16>(a, st);
-        }
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
+    const int grid = (tiles + 7) / 8 * 8;
+    if (a.C == 1) hipLaunchKernelGGL(k_trace<1>, dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_trace<3>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
@@ -587,7 +625,12 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 }
 
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
-                         hipStream_t st) {
+                         long long quad_off, hipStream_t st) {
+    float* quad = pyr + quad_off;
+    const long long npx = (long long)W * Hh;
+    hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(Hh, 64)), dim3(64), 0, st, W, Hh, H, quad);
+    hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(W, 64)), dim3(64), 0, st, W, Hh, quad);
+    (void)npx;
     hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
                        st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
     for (int l = 1; l < P.levels; ++l)

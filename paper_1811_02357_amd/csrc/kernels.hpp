@@ -26,12 +26,14 @@ struct LightSet {
     float s[kMaxLights];
 };
 
-// A heightfield with its apron-max pyramid.
+// A heightfield with its apron-max pyramid (level offsets in floats).
 struct SurfaceArgs {
     const float* H;
-    const float* pyr;
+    const float* pyr;  // apron-max levels, then the four quadrant maxima
     int W, Hh;
-    trv::Pyramid P;
+    int levels;
+    int quad_off;      // floats from pyr to the quadrant tables
+    int off[trv::kMaxLevels];
 };
 
 struct TraceArgs {
@@ -40,10 +42,10 @@ struct TraceArgs {
     const float* rho;  // [C][H][W]
     const float* S;    // [H][W][K]
     const float* env;  // [He][We][C]
-    float* G;          // [K][C][H][W]
+    float* G;          // [H][W][K][C]: per-pixel sums during the trace, then the means
     unsigned long long* counters;  // 4 x u64 or null
     int env_h, env_w;
-    int C, K, k0, kcount;
+    int C, K;
     int spp, B, t, tag, flags;
     uint32_t key0, key1;
 };
@@ -67,8 +69,9 @@ hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const fl
                    float* Anext, hipStream_t st);
 hipError_t compose(int npx, int C, int K, const float* rho, const float* S, const float* G, float* I,
                    hipStream_t st);
+// Apron-max levels of P at pyr, then the quadrant maxima at pyr + quad_off.
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
-                         hipStream_t st);
+                         long long quad_off, hipStream_t st);
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
                      float* ws, hipStream_t st);
 hipError_t fill_f32(float* p, float v, long long n, hipStream_t st);

@@ -34,18 +34,25 @@ struct Pyramid {
     long long off[kMaxLevels];
 };
 
+// A surface as one lane sees it.  Level l of the pyramid has
+// ceil((W-1)/2^l) x ceil((H-1)/2^l) cells stored from offset lvl_off[l]; the
+// offsets live in LDS so that a per-lane level index does not spill.
 struct Surface {
     const float* H;      // [Hh][W]
     const float* pyr;    // apron maxima, levels concatenated; top level = global max
+    const float* quad;   // 4 quadrant maxima [q][Hh][W], q = (dx < 0) + 2 (dy < 0)
+    const int* lvl_off;  // LDS copy of the level offsets
     int W, Hh;
     int top;             // index of the 1x1 level
     float hmax;
-    Pyramid P;
 };
+
+__device__ __forceinline__ int level_cells_x(const Surface& S, int l) { return (S.W - 1 + (1 << l) - 1) >> l; }
 
 // Per-ray state shared by both walks.
 struct Ray {
-    float ox, oy, oz, dx, dy, dz, inv_dx, inv_dy;
+    float ox, oy, oz, dx, dy, dz;
+    float ainv_x, ainv_y;  // |1/dx|, |1/dy| (+inf for a zero component)
     int i0, j0, sx, sy;
 };
 
@@ -56,19 +63,21 @@ __device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float 
     r.j0 = j0;
     r.ox = (float)i0;
     r.oy = (float)j0;
-    r.oz = S.H[(size_t)j0 * S.W + i0];
+    r.oz = S.H[j0 * S.W + i0];
     r.dx = dx;
     r.dy = dy;
     r.dz = dz;
     r.sx = signbit(dx) ? -1 : 1;
     r.sy = signbit(dy) ? -1 : 1;
-    r.inv_dx = 1.0f / dx;
-    r.inv_dy = 1.0f / dy;
+    r.ainv_x = fabsf(1.0f / dx);
+    r.ainv_y = fabsf(1.0f / dy);
     return r;
 }
 
-__device__ __forceinline__ float t_x(const Ray& r, int m) { return (float)(r.sx * m) * r.inv_dx; }
-__device__ __forceinline__ float t_y(const Ray& r, int m) { return (float)(r.sy * m) * r.inv_dy; }
+// t of the m-th crossing: (X - ox) / dx with X - ox = sx m exact, written as
+// m |1/dx| (the sign flip is exact, so this is (sx m)(1/dx) bit for bit).
+__device__ __forceinline__ float t_x(const Ray& r, int m) { return (float)m * r.ainv_x; }
+__device__ __forceinline__ float t_y(const Ray& r, int m) { return (float)m * r.ainv_y; }
 
 enum : int { kMiss = 0, kHit = 1, kGoOn = 2 };
 
@@ -83,11 +92,11 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
     if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
     const int m0 = (int)floorf(minor);
     const float f = minor - (float)m0;
-    const size_t idx0 = xline ? (size_t)m0 * S.W + major : (size_t)major * S.W + m0;
+    const int idx0 = xline ? m0 * S.W + major : major * S.W + m0;
     const float h0 = S.H[idx0];
     float h = h0;
     if (f != 0.0f) {
-        const float h1 = S.H[idx0 + (xline ? (size_t)S.W : (size_t)1)];
+        const float h1 = S.H[idx0 + (xline ? S.W : 1)];
         h = fmaf(f, h1 - h0, h0);
         const float lo = h0 < h1 ? h0 : h1;
         const float hi = h0 < h1 ? h1 : h0;
@@ -105,35 +114,42 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
     return kGoOn;
 }
 
-// Smallest crossing index m >= m_lo whose t (same formula as the walk) is >= t_lim.
-__device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline, int m_lo,
-                                                       float t_lim, float d_abs) {
-    // estimate from the geometry, then correct with the exact formula
+// Smallest crossing index m >= 1 whose t (same formula as the walk) is >= t_lim.
+__device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline, float t_lim) {
+    const float d_abs = xline ? fabsf(r.dx) : fabsf(r.dy);
     const float est = ceilf(t_lim * d_abs);
-    int m = est > 2.0e9f ? 2000000000 : (int)est;
-    if (m < m_lo) m = m_lo;
-    while (m > m_lo && (xline ? t_x(r, m - 1) : t_y(r, m - 1)) >= t_lim) --m;
+    int m = est > 2.0e9f ? 2000000000 : (est < 1.0f ? 1 : (int)est);
+    while (m > 1 && (xline ? t_x(r, m - 1) : t_y(r, m - 1)) >= t_lim) --m;
     while ((xline ? t_x(r, m) : t_y(r, m)) < t_lim) ++m;
     return m;
 }
 
 // Finest pyramid level the walker tries to skip (cells of 4 x 4 sample gaps).
 constexpr int kMinSkipLevel = 2;
+// Cells are chosen at the ray's position nudged this far along the travel
+// direction, so that a ray sitting on a cell edge picks the cell ahead.  The
+// one-sample apron of every cell covers the nudge.
+constexpr float kNudge = 0.03125f;
 
-// Resumable walk: one call of step() either evaluates the next crossing or
-// tries one pyramid cell.  level < 0 walks every crossing.
+// Resumable walk.  Every crossing with t < t_cur has been evaluated or lies in
+// a skipped cell.  In fine mode (mx, my, tX, tY) name the next crossing of each
+// family; in coarse mode only t_cur is kept and the indices are rebuilt from it
+// when the walker drops to crossing evaluation.  level < 0 walks every crossing.
 struct Walker {
     Ray r;
+    float t_cur, tX, tY;
     int mx, my, level;
-    float tX, tY;
+    bool fine;
 };
 
 __device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0, int j0, float dx,
                                             float dy, float dz, bool flat) {
     w.r = make_ray(S, i0, j0, dx, dy, dz);
+    w.t_cur = 0.0f;
     w.mx = 1;
     w.my = 1;
     w.level = flat ? -1 : kMinSkipLevel;
+    w.fine = true;
     // a ray along z has no crossings: t = inf on both families ends the walk
     const bool vertical = dx == 0.0f && dy == 0.0f;
     w.tX = vertical ? __builtin_inff() : t_x(w.r, 1);
@@ -143,49 +159,45 @@ __device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0,
 // Returns kGoOn, kHit (qi, qj set) or kMiss.
 __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi, int& qj) {
     const Ray& r = w.r;
-    if (isinf(w.tX) && isinf(w.tY)) return kMiss;
-    const bool xline = w.tX <= w.tY;
-    const float t_now = xline ? w.tX : w.tY;
+    if (w.fine && isinf(w.tX) && isinf(w.tY)) return kMiss;
+    const float t_now = w.fine ? (w.tX <= w.tY ? w.tX : w.tY) : w.t_cur;
     const float z_now = fmaf(t_now, r.dz, r.oz);
     // at or above every sample and not descending: no crossing ahead can hit
     if (z_now >= S.hmax && r.dz >= 0.0f) return kMiss;
     if (w.level >= kMinSkipLevel) {
-        // approximate position of the next crossing: only chooses the cell
-        const float px = xline ? (float)(r.i0 + r.sx * w.mx) : fmaf(t_now, r.dx, r.ox);
-        const float py = xline ? fmaf(t_now, r.dy, r.oy) : (float)(r.j0 + r.sy * w.my);
+        const float px = fmaf(t_now, r.dx, r.ox) + (float)r.sx * kNudge;
+        const float py = fmaf(t_now, r.dy, r.oy) + (float)r.sy * kNudge;
         if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
             const int l = w.level;
-            const int size = 1 << l;
-            int cx = (int)floorf(px) >> l;
-            int cy = (int)floorf(py) >> l;
-            if (r.sx < 0 && (float)(cx << l) == px) cx -= 1;
-            if (r.sy < 0 && (float)(cy << l) == py) cy -= 1;
+            const int ix = (int)px, iy = (int)py;  // px, py > 0: truncation is floor
+            // Every sample a later crossing can read lies in the quadrant ahead of
+            // the ray's position: at most one sample behind floor(x) going +x, two
+            // ahead of it going -x (a lerp reads the next sample), and the nudge
+            // moves floor by at most one.  If the ray is not descending and is at
+            // or above the maximum of that quadrant, nothing ahead can hit.
+            const int qx = r.sx > 0 ? ix - 2 : (ix + 3 < S.W ? ix + 3 : S.W - 1);
+            const int qy = r.sy > 0 ? iy - 2 : (iy + 3 < S.Hh ? iy + 3 : S.Hh - 1);
+            const int quadrant = (r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0);
+            const float qmax = S.quad[(quadrant * S.Hh + qy) * S.W + qx];
+            const int cx = ix >> l;
+            const int cy = iy >> l;
             const int X0 = cx << l, Y0 = cy << l;
-            const int X1 = X0 + size, Y1 = Y0 + size;
-            bool skip = false;
-            if (X0 >= 2 && Y0 >= 2 && X1 <= S.W - 3 && Y1 <= S.Hh - 3) {
-                const float cmax = S.pyr[S.P.off[l] + (long long)cy * S.P.wc[l] + cx];
-                if (z_now >= cmax) {
-                    const int mxe = ((r.sx > 0 ? X1 : X0) - r.i0) * r.sx;
-                    const int mye = ((r.sy > 0 ? Y1 : Y0) - r.j0) * r.sy;
-                    const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
-                    const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
-                    const float t_exit = txe < tye ? txe : tye;
-                    if (t_exit > t_now && !isinf(t_exit) && fmaf(t_exit, r.dz, r.oz) >= cmax) {
-                        // every crossing with t < t_exit lies in the cell: none can hit
-                        if (!isinf(w.tX)) {
-                            w.mx = first_index_at_or_after(r, true, w.mx, t_exit, fabsf(r.dx));
-                            w.tX = t_x(r, w.mx);
-                        }
-                        if (!isinf(w.tY)) {
-                            w.my = first_index_at_or_after(r, false, w.my, t_exit, fabsf(r.dy));
-                            w.tY = t_y(r, w.my);
-                        }
-                        skip = true;
-                    }
-                }
-            }
-            if (skip) {
+            const int X1 = X0 + (1 << l), Y1 = Y0 + (1 << l);
+            const bool interior = X0 >= 2 && Y0 >= 2 && X1 <= S.W - 3 && Y1 <= S.Hh - 3;
+            const float cmax = interior ? S.pyr[S.lvl_off[l] + cy * level_cells_x(S, l) + cx] : 0.0f;
+            // exit of the cell along the ray (computed while the loads are in flight)
+            const int mxe = ((r.sx > 0 ? X1 : X0) - r.i0) * r.sx;
+            const int mye = ((r.sy > 0 ? Y1 : Y0) - r.j0) * r.sy;
+            const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
+            const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
+            const float t_exit = txe < tye ? txe : tye;
+            const float z_exit = fmaf(t_exit, r.dz, r.oz);
+            if (z_now >= qmax && r.dz >= 0.0f) return kMiss;
+            // every crossing with t in [t_now, t_exit) lies in the grown cell and
+            // the ray is at or above its maximum over that range
+            if (interior && z_now >= cmax && t_exit > t_now && !isinf(t_exit) && z_exit >= cmax) {
+                w.t_cur = t_exit;
+                w.fine = false;
                 if (l < S.top) w.level = l + 1;
                 return kGoOn;
             }
@@ -195,7 +207,21 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             }
         }
     }
-    const int res = crossing(S, r, xline, t_now, w.mx, w.my, qi, qj);
+    if (!w.fine) {
+        // back to crossing-by-crossing: the next crossings at or after t_cur
+        if (!isinf(r.ainv_x)) {
+            w.mx = first_index_at_or_after(r, true, w.t_cur);
+            w.tX = t_x(r, w.mx);
+        }
+        if (!isinf(r.ainv_y)) {
+            w.my = first_index_at_or_after(r, false, w.t_cur);
+            w.tY = t_y(r, w.my);
+        }
+        w.fine = true;
+        if (isinf(w.tX) && isinf(w.tY)) return kMiss;
+    }
+    const bool xline = w.tX <= w.tY;
+    const int res = crossing(S, r, xline, xline ? w.tX : w.tY, w.mx, w.my, qi, qj);
     if (res == kGoOn) {
         if (xline) {
             ++w.mx;

@@ -248,12 +248,13 @@ def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, strea
 
 def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOLVE, flags=0,
           pyramid=None, counters=None, stream=None):
+    """Gathered radiance G, pixel-major [H][W][K][C]."""
     H, W = depth.shape
     C = albedo.shape[0]
     K = S.shape[2]
     if pyramid is None:
         pyramid = build_pyramid(depth, stream)
-    G = torch.empty((K, C, H, W), device=depth.device)
+    G = torch.empty((H, W, K, C), device=depth.device)
     _check("irtps_trace", lib().irtps_trace(
         W, H, C, K, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)),
         _dev(S, shape=(H, W, K)), _dev(env), env.shape[0], env.shape[1], _dev(pyramid),
@@ -263,11 +264,12 @@ def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOL
 
 
 def correct(I0, G, S, albedo, rho_mode=RHO_FIT, flags=0, A_prev=None, want_E=True, stream=None):
+    """Stage 5: I0, A_prev [K][C][H][W]; G [H][W][K][C] (as irtps_trace returns it)."""
     K, C, H, W = I0.shape
     E = torch.empty_like(I0) if want_E else None
     A = torch.empty_like(I0)
     _check("irtps_correct", lib().irtps_correct(
-        W, H, C, K, rho_mode, flags, _dev(I0), _dev(A_prev), _dev(G, shape=I0.shape),
+        W, H, C, K, rho_mode, flags, _dev(I0), _dev(A_prev), _dev(G, shape=(H, W, K, C)),
         _dev(S, shape=(H, W, K)), _dev(albedo, shape=(C, H, W)), _dev(E), _dev(A), _stream(stream)))
     return E, A
 

@@ -252,6 +252,7 @@ def test_trace_stage(dev, case):
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
     G = irtps.trace(T(Hf, dev), T(n, dev), T(rho, dev), T(S, dev), T(env, dev), spp, B, seed, t=t,
                     tag=tag, flags=flags, counters=cnt)
+    ref = np.transpose(ref, (2, 3, 0, 1))  # oracle [K][C][H][W] -> library [H][W][K][C]
     assert_radiance(H(G), ref, name)
     assert H(cnt).tolist() == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"]]
     assert np.array_equal(H(G), ref)
@@ -271,7 +272,7 @@ def test_correct_stage(dev, mode, flags):
     G[:, :, 0, 0] = 0
     rho = rng.uniform(0.2, 1, (C, Hh, W)).astype(F32)
     Ap = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
-    E, A = irtps.correct(T(I0, dev), T(G, dev), T(S, dev), T(rho, dev), mode, flags,
+    E, A = irtps.correct(T(I0, dev), T(np.transpose(G, (2, 3, 0, 1)), dev), T(S, dev), T(rho, dev), mode, flags,
                          T(Ap, dev) if flags else None)
     rE, rA = O.correct(I0, G, S, rho, mode, flags, Ap if flags else None)
     assert np.array_equal(H(E), rE) and np.array_equal(H(A), rA)
@@ -343,3 +344,20 @@ def test_solve_T0_is_plain_ps(dev):
     ref, got = _solve_both(sc, dev, T_=0)
     _compare_solve(ref, got, "bowl64 T0")
     assert (got["indirect"] == 0).all()
+
+
+def test_quadrant_maxima(dev):
+    say("case: quadrant maxima in the pyramid buffer")
+    rng = np.random.default_rng(4)
+    Hf = rng.uniform(-5, 5, (37, 53)).astype(F32)
+    Hh, W = Hf.shape
+    pyr = H(irtps.build_pyramid(T(Hf, dev)))
+    quad = pyr[pyr.size - 4 * W * Hh:].reshape(4, Hh, W)
+    for q in range(4):
+        sx = -1 if q & 1 else 1
+        sy = -1 if q & 2 else 1
+        for y in range(0, Hh, 5):
+            for x in range(0, W, 7):
+                xs = slice(x, W) if sx > 0 else slice(0, x + 1)
+                ys = slice(y, Hh) if sy > 0 else slice(0, y + 1)
+                assert quad[q, y, x] == Hf[ys, xs].max()
