@@ -203,6 +203,32 @@ int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_
                  int32_t B, uint64_t seed, float* images_dev, void* ws_dev,
                  size_t ws_bytes, void* stream);
 
+/* ---- batched mode --------------------------------------------------------- */
+/* Options of irtps_batch_solve. */
+enum {
+    IRTPS_BATCH_GRAPH = 1  /* capture the batch's launches in a hipGraph; a later call with
+                              identical arguments and workspace replays it */
+};
+/* Bytes of device workspace irtps_batch_solve needs for these n jobs. */
+int irtps_batch_workspace_bytes(int32_t n, const irtps_problem* problems,
+                                const irtps_params* params, size_t* bytes);
+/* n independent reconstructions (each as irtps_solve with its own problem,
+ * params and outputs) run together: every stage of the loop is one launch for
+ * all jobs and the tracer is one persistent launch over all jobs' pixel tiles.
+ * Each job's outputs are bit-identical to irtps_solve of that job alone.  The
+ * arrays are host arrays of n elements; the problems' device pointers and the
+ * outputs must stay valid until the stream reaches the end of the call's work.
+ * With IRTPS_BATCH_GRAPH the stream must not be the legacy default stream. */
+int irtps_batch_solve(int32_t n, const irtps_problem* problems, const irtps_params* params,
+                      const irtps_outputs* outputs, int32_t options, void* ws_dev,
+                      size_t ws_bytes, void* stream);
+
+/* ---- tuning ----------------------------------------------------------------- */
+/* Lanes of a 64-lane tracer wave that must hold a finished segment before the
+ * wave shades (1..64; default 32).  It changes speed only, never results. */
+int irtps_set_ready_batch(int32_t lanes);
+int irtps_get_ready_batch(void);
+
 /* ---- timing of the tracer ------------------------------------------------ */
 /* irtps_profile_begin() makes this thread's later calls record a hipEvent pair
  * around every tracer launch on the call's stream; irtps_profile_end() waits for

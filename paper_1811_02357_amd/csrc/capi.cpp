@@ -6,231 +6,13 @@
 
 #include <cmath>
 #include <cstring>
-#include <utility>
-#include <vector>
 
+#include "host.hpp"
 #include "kernels.hpp"
 
 using namespace irtps;
 
-namespace {
-
-thread_local int g_last_hip = 0;
-
-int hip_fail(hipError_t e) {
-    g_last_hip = (int)e;
-    return IRTPS_ERR_DEVICE;
-}
-
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        const hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return hip_fail(e_);     \
-    } while (0)
-
-#define STATUS_TRY(expr)                               \
-    do {                                               \
-        const int s_ = (expr);                         \
-        if (s_ != IRTPS_OK) return s_;                 \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-
-// Event pairs around tracer launches while profiling is on (per thread).
-struct Profiler {
-    bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-};
-thread_local Profiler g_prof;
-
-hipError_t traced(const kern::TraceArgs& ta, hipStream_t st) {
-    if (!g_prof.on) return kern::trace(ta, st);
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
-    if (e == hipSuccess) e = hipEventRecord(a, st);
-    if (e == hipSuccess) e = kern::trace(ta, st);
-    if (e == hipSuccess) e = hipEventRecord(b, st);
-    if (e != hipSuccess) {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-        return e;
-    }
-    g_prof.ev.emplace_back(a, b);
-    return hipSuccess;
-}
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Sides up to 16384 keep the pyramid within trv::kMaxLevels levels and every
-// pixel index within int32.
-bool dims_ok(int W, int H) { return W >= 2 && H >= 2 && W <= 16384 && H <= 16384 && (long long)W * H <= (1LL << 28); }
-bool channels_ok(int C) { return C == 1 || C == 3; }
-bool lights_ok(int K) { return K >= 3 && K <= kern::kMaxLights; }
-
-trv::Pyramid pyramid_plan(int W, int H) {
-    trv::Pyramid P{};
-    int wc = W - 1, hc = H - 1;
-    long long off = 0;
-    int l = 0;
-    for (;;) {
-        P.wc[l] = wc;
-        P.hc[l] = hc;
-        P.off[l] = off;
-        off += (long long)wc * hc;
-        ++l;
-        if (wc == 1 && hc == 1) break;
-        wc = (wc + 1) / 2;
-        hc = (hc + 1) / 2;
-    }
-    P.levels = l;
-    return P;
-}
-
-long long pyramid_level_floats(const trv::Pyramid& P) {
-    const int t = P.levels - 1;
-    return (P.off[t] + (long long)P.wc[t] * P.hc[t] + 63) / 64 * 64;
-}
-
-// Apron-max levels followed by the four quadrant-maximum planes.
-long long pyramid_floats(int W, int H) { return pyramid_level_floats(pyramid_plan(W, H)) + 4LL * W * H; }
-
-kern::MgPlan mg_plan(int W, int H) {
-    kern::MgPlan m{};
-    m.W[0] = W;
-    m.H[0] = H;
-    m.levels = 1;
-    while ((m.W[m.levels - 1] > 4 || m.H[m.levels - 1] > 4) && m.levels < kern::kMaxMgLevels) {
-        m.W[m.levels] = (m.W[m.levels - 1] + 1) / 2;
-        m.H[m.levels] = (m.H[m.levels - 1] + 1) / 2;
-        ++m.levels;
-    }
-    long long off = 0;
-    for (int l = 0; l < m.levels; ++l) {
-        const long long n = (long long)m.W[l] * m.H[l];
-        m.xoff[l] = off;
-        off += (n + 63) / 64 * 64;
-        m.boff[l] = off;
-        off += (n + 63) / 64 * 64;
-    }
-    m.keyoff = off;
-    off += 64;
-    m.total = off;
-    return m;
-}
-
-// Eq.3-4 in binary64: A = L^T L, inverse by the adjugate, M = A^-1 L^T.
-int ps_matrix_host(int K, const float* l, const float* s, float* M) {
-    if (K < 3 || !l || !M) return K < 3 ? IRTPS_ERR_SINGULAR_LIGHTS : IRTPS_ERR_INVALID_ARG;
-    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int k = 0; k < K; ++k) {
-        const double sk = s ? (double)s[k] : 1.0;
-        const double v[3] = {sk * (double)l[3 * k], sk * (double)l[3 * k + 1], sk * (double)l[3 * k + 2]};
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + v[a] * v[b];
-    }
-    double adj_t[3][3];  // cofactor matrix C[a][b]; inverse = C^T / det
-    adj_t[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
-    adj_t[0][1] = -(A[1][0] * A[2][2] - A[1][2] * A[2][0]);
-    adj_t[0][2] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
-    adj_t[1][0] = -(A[0][1] * A[2][2] - A[0][2] * A[2][1]);
-    adj_t[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
-    adj_t[1][2] = -(A[0][0] * A[2][1] - A[0][1] * A[2][0]);
-    adj_t[2][0] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
-    adj_t[2][1] = -(A[0][0] * A[1][2] - A[0][2] * A[1][0]);
-    adj_t[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
-    const double det = A[0][0] * adj_t[0][0] + A[0][1] * adj_t[0][1] + A[0][2] * adj_t[0][2];
-    const double mean_eig = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
-    if (!(det > 1e-7 * mean_eig * mean_eig * mean_eig)) return IRTPS_ERR_SINGULAR_LIGHTS;
-    for (int k = 0; k < K; ++k) {
-        const double sk = s ? (double)s[k] : 1.0;
-        const double v[3] = {sk * (double)l[3 * k], sk * (double)l[3 * k + 1], sk * (double)l[3 * k + 2]};
-        for (int a = 0; a < 3; ++a) {
-            const double i0 = adj_t[0][a] / det, i1 = adj_t[1][a] / det, i2 = adj_t[2][a] / det;
-            M[(size_t)a * K + k] = (float)(i0 * v[0] + i1 * v[1] + i2 * v[2]);
-        }
-    }
-    return IRTPS_OK;
-}
-
-int make_lights(int K, const float* l, const float* s, kern::LightSet& L) {
-    if (!lights_ok(K) || !l) return IRTPS_ERR_INVALID_ARG;
-    std::memset(&L, 0, sizeof(L));
-    L.K = K;
-    for (int k = 0; k < K; ++k) {
-        for (int a = 0; a < 3; ++a) {
-            if (!std::isfinite(l[3 * k + a])) return IRTPS_ERR_INVALID_ARG;
-            L.l[k][a] = l[3 * k + a];
-        }
-        L.s[k] = s ? s[k] : 1.0f;
-        if (!std::isfinite(L.s[k])) return IRTPS_ERR_INVALID_ARG;
-    }
-    return IRTPS_OK;
-}
-
-int make_psmatrix(int K, const float* l, const float* s, kern::PsMatrix& M) {
-    if (!lights_ok(K)) return K < 3 ? IRTPS_ERR_SINGULAR_LIGHTS : IRTPS_ERR_INVALID_ARG;
-    float tmp[3 * kern::kMaxLights];
-    STATUS_TRY(ps_matrix_host(K, l, s, tmp));
-    std::memset(&M, 0, sizeof(M));
-    for (int a = 0; a < 3; ++a)
-        for (int k = 0; k < K; ++k) M.m[a][k] = tmp[(size_t)a * K + k];
-    return IRTPS_OK;
-}
-
-kern::SurfaceArgs surface(int W, int H, const float* depth, const float* pyr) {
-    kern::SurfaceArgs sa;
-    sa.H = depth;
-    sa.pyr = pyr;
-    sa.W = W;
-    sa.Hh = H;
-    const trv::Pyramid P = pyramid_plan(W, H);
-    sa.levels = P.levels;
-    sa.quad_off = (int)pyramid_level_floats(P);
-    for (int l = 0; l < trv::kMaxLevels; ++l) sa.off[l] = l < P.levels ? (int)P.off[l] : 0;
-    return sa;
-}
-
-// Workspace layout of one solve (byte offsets, each 256-aligned).
-struct SolveLayout {
-    size_t A, S, G, pyr, mg, total;
-    kern::MgPlan plan;
-};
-
-SolveLayout solve_layout(int W, int H, int C, int K) {
-    SolveLayout L{};
-    const size_t npx = (size_t)W * H;
-    size_t off = 0;
-    L.A = off;
-    off = align_up(off + sizeof(float) * npx * K * C);
-    L.S = off;
-    off = align_up(off + sizeof(float) * npx * K);
-    L.G = off;
-    off = align_up(off + sizeof(float) * npx * K * C);
-    L.pyr = off;
-    off = align_up(off + sizeof(float) * (size_t)pyramid_floats(W, H));
-    L.plan = mg_plan(W, H);
-    L.mg = off;
-    off = align_up(off + sizeof(float) * (size_t)L.plan.total);
-    L.total = off;
-    return L;
-}
-
-int check_problem(const irtps_problem* pr, const irtps_params* pa) {
-    if (!pr || !pa) return IRTPS_ERR_INVALID_ARG;
-    if (!dims_ok(pr->width, pr->height) || !channels_ok(pr->channels) || !lights_ok(pr->num_lights))
-        return IRTPS_ERR_INVALID_ARG;
-    if (!pr->images_dev || !pr->light_dirs_host || !pr->env_dev || pr->env_h < 1 || pr->env_w < 1)
-        return IRTPS_ERR_INVALID_ARG;
-    if (pa->spp < 1 || pa->bounces < 0 || pa->bounces > 8 || pa->iterations < 0 ||
-        pa->iterations > 1000 || (pa->rho_mode != IRTPS_RHO_FIT && pa->rho_mode != IRTPS_RHO_PREV) ||
-        pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || pa->reserved != 0 ||
-        (pa->flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_LITERAL_CUMULATIVE | IRTPS_FLAG_FLAT_TRAVERSAL)))
-        return IRTPS_ERR_INVALID_ARG;
-    return IRTPS_OK;
-}
-
-}  // namespace
+using namespace irtps::host;
 
 extern "C" {
 
@@ -319,6 +101,7 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
         ta.key0 = (uint32_t)pa->seed;
         ta.key1 = (uint32_t)(pa->seed >> 32);
+        ta.ready_batch = g_ready_batch;
         HIP_TRY(traced(ta, st));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
@@ -411,6 +194,7 @@ int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_d
     ta.flags = flags;
     ta.key0 = (uint32_t)seed;
     ta.key1 = (uint32_t)(seed >> 32);
+    ta.ready_batch = g_ready_batch;
     HIP_TRY(traced(ta, reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
@@ -475,10 +259,19 @@ int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_
     ta.flags = 0;
     ta.key0 = (uint32_t)seed;
     ta.key1 = (uint32_t)(seed >> 32);
+    ta.ready_batch = g_ready_batch;
     HIP_TRY(traced(ta, st));
     HIP_TRY(kern::compose((int)npx, C, K, albedo_dev, S, G, images_dev, st));
     return IRTPS_OK;
 }
+
+int irtps_set_ready_batch(int32_t lanes) {
+    if (lanes < 1 || lanes > 64) return IRTPS_ERR_INVALID_ARG;
+    g_ready_batch = lanes;
+    return IRTPS_OK;
+}
+
+int irtps_get_ready_batch(void) { return g_ready_batch; }
 
 int irtps_profile_begin(void) {
     for (auto& pr : g_prof.ev) {

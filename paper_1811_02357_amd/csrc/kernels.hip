@@ -2,7 +2,11 @@
 //
 // Every kernel is a plain per-sample or per-pixel map over HBM-resident planes;
 // the only dense arithmetic is the 3xK photometric-stereo product, far too
-// small for MFMA.  The tracer is the hot loop.
+// small for MFMA.  The tracer is the hot loop.  Each step exists as a
+// per-element device function used by two kinds of kernel: single-job kernels
+// (arguments by value) and multi-job kernels that walk a job table in device
+// memory (grid.y = job, or a persistent tile queue for the tracer), so that a
+// batch of reconstructions of different sizes runs as one launch per step.
 #include "kernels.hpp"
 
 #include "device_math.hpp"
@@ -18,54 +22,54 @@ using trv::Surface;
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int per = (nb + 7) / 8;
     const int xcd = b % 8, k = b / 8;
-    const int t = xcd * per + k;
-    return t;
+    return xcd * per + k;
 }
 
 // Every kernel that walks rays first copies the pyramid's level offsets to LDS
 // (constant indices only) and then builds its Surface view on that table.
-__device__ __forceinline__ void load_level_table(const SurfaceArgs& a, int* s_off) {
+__device__ __forceinline__ void load_level_table(const int* off, int* s_off) {
 #pragma unroll
     for (int l = 0; l < trv::kMaxLevels; ++l)
-        if ((int)threadIdx.x == l) s_off[l] = a.off[l];
+        if ((int)threadIdx.x == l) s_off[l] = off[l];
     __syncthreads();
 }
 
-__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a, const int* s_off) {
+__device__ __forceinline__ Surface make_surface(const float* H, const float* pyr, int W, int Hh,
+                                                int levels, int quad_off, const int* s_off) {
     Surface S;
-    S.H = a.H;
-    S.pyr = a.pyr;
-    S.quad = a.pyr + a.quad_off;
+    S.H = H;
+    S.pyr = pyr;
+    S.quad = pyr + quad_off;
     S.lvl_off = s_off;
-    S.W = a.W;
-    S.Hh = a.Hh;
-    S.top = a.levels - 1;
-    S.hmax = a.pyr[s_off[S.top]];
+    S.W = W;
+    S.Hh = Hh;
+    S.top = levels - 1;
+    S.hmax = pyr[s_off[S.top]];
     return S;
 }
 
-__device__ __forceinline__ bool walk(const Surface& S, bool flat, int i, int j, dm::V3 d, int& qi,
-                                     int& qj) {
-    return trv::walk(S, flat, i, j, d.x, d.y, d.z, qi, qj);
+__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a, const int* s_off) {
+    return make_surface(a.H, a.pyr, a.W, a.Hh, a.levels, a.quad_off, s_off);
 }
 
-// ---------------------------------------------------------------------------
+// ===========================================================================
+// Per-element bodies.
+
 // Eq.4: g_c = M A_c (sum over lights in order, fused), albedo = |g_c|,
-// normal = sum_c g_c normalised.
+// normal = sum_c g_c normalised.  M rows have stride kMaxLights.
 template <int C>
-__global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, const float* __restrict__ A,
-                                                  float* __restrict__ n, float* __restrict__ rho) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npx) return;
+__device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __restrict__ M,
+                                      const float* __restrict__ A, float* __restrict__ n,
+                                      float* __restrict__ rho) {
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
         for (int k = 0; k < K; ++k) {
             const float a = A[((size_t)k * C + c) * npx + p];
-            g0 = fmaf(M.m[0][k], a, g0);
-            g1 = fmaf(M.m[1][k], a, g1);
-            g2 = fmaf(M.m[2][k], a, g2);
+            g0 = fmaf(M[k], a, g0);
+            g1 = fmaf(M[kMaxLights + k], a, g1);
+            g2 = fmaf(M[2 * kMaxLights + k], a, g2);
         }
         rho[(size_t)c * npx + p] = sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2)));
         sx = sx + g0;
@@ -84,59 +88,278 @@ __global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, co
     n[3 * (size_t)p + 2] = nz;
 }
 
-// ---------------------------------------------------------------------------
-// Eq.2 without albedo, with cast shadows.
-__global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
-                                                int flat, float* __restrict__ S_out) {
-    __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(sa, s_off);
-    const int npx = sa.W * sa.Hh;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npx) return;
-    const Surface S = make_surface(sa, s_off);
-    const int i = p % sa.W, j = p / sa.W;
+// Eq.2 without albedo, with cast shadows: K any-hit walks from sample p.
+__device__ __forceinline__ void direct_px(const Surface& S, int p, const float* __restrict__ n, int K,
+                                          const float* __restrict__ L, const float* __restrict__ s,
+                                          bool flat, float* __restrict__ S_out) {
+    const int i = p % S.W, j = p / S.W;
     const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
-    for (int k = 0; k < L.K; ++k) {
-        const float lx = L.l[k][0], ly = L.l[k][1], lz = L.l[k][2];
+    for (int k = 0; k < K; ++k) {
+        const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
         const float c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
         float v = 0.0f;
         if (c > 0.0f) {
             int qi, qj;
-            const bool blocked = walk(S, flat != 0, i, j, dm::V3{lx, ly, lz}, qi, qj);
-            if (!blocked) v = L.s[k] * c;
+            const bool blocked = trv::walk(S, flat, i, j, lx, ly, lz, qi, qj);
+            if (!blocked) v = s[k] * c;
         }
-        S_out[(size_t)p * L.K + k] = v;
+        S_out[(size_t)p * K + k] = v;
     }
 }
 
+// Stage 5 (G is pixel-major [p][k][c], images and E are [k][c][p]).
+template <int C>
+__device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, int cumulative,
+                                           const float* __restrict__ I0, const float* __restrict__ Aprev,
+                                           const float* __restrict__ G, const float* __restrict__ S,
+                                           const float* __restrict__ rho, float* __restrict__ E,
+                                           float* __restrict__ Anext) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float rt;
+        if (rho_mode == 0) {
+            float num = 0.0f, den = 0.0f;
+            for (int k = 0; k < K; ++k) {
+                const size_t x = ((size_t)k * C + c) * npx + p;
+                const float v = S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c];
+                num = fmaf(I0[x], v, num);
+                den = fmaf(v, v, den);
+            }
+            rt = den > 0.0f ? num / den : 0.0f;
+        } else {
+            rt = rho[(size_t)c * npx + p];
+        }
+        for (int k = 0; k < K; ++k) {
+            const size_t x = ((size_t)k * C + c) * npx + p;
+            const float e = rt * G[((size_t)p * K + k) * C + c];
+            if (E) E[x] = e;
+            Anext[x] = (cumulative ? Aprev[x] : I0[x]) - e;
+        }
+    }
+}
+
+// Forward render: images = albedo (S + G).
+template <int C>
+__device__ __forceinline__ void compose_px(int p, int npx, int K, const float* __restrict__ rho,
+                                           const float* __restrict__ S, const float* __restrict__ G,
+                                           float* __restrict__ I) {
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const size_t x = ((size_t)k * C + c) * npx + p;
+            I[x] = rho[(size_t)c * npx + p] * (S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c]);
+        }
+    }
+}
+
+// Apron-max pyramid, level 0: max over the 4 x 4 samples around cell (cx, cy).
+__device__ __forceinline__ void pyr0_cell(int c, int W, int Hh, int wc, const float* __restrict__ H,
+                                          float* __restrict__ out) {
+    const int cx = c % wc, cy = c / wc;
+    const int x0 = cx - 1 < 0 ? 0 : cx - 1, x1 = cx + 2 > W - 1 ? W - 1 : cx + 2;
+    const int y0 = cy - 1 < 0 ? 0 : cy - 1, y1 = cy + 2 > Hh - 1 ? Hh - 1 : cy + 2;
+    float m = H[(size_t)y0 * W + x0];
+    for (int y = y0; y <= y1; ++y)
+        for (int x = x0; x <= x1; ++x) {
+            const float v = H[(size_t)y * W + x];
+            m = v > m ? v : m;
+        }
+    out[c] = m;
+}
+
+// Level l+1 from level l: max of the (up to) four children.
+__device__ __forceinline__ void pyr_reduce_cell(int c, const float* __restrict__ in, int wi, int hi,
+                                                float* __restrict__ out, int wo) {
+    const int cx = c % wo, cy = c / wo;
+    float m = in[(size_t)(2 * cy) * wi + 2 * cx];
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            const int x = 2 * cx + dx, y = 2 * cy + dy;
+            if (x < wi && y < hi) {
+                const float v = in[(size_t)y * wi + x];
+                m = v > m ? v : m;
+            }
+        }
+    out[c] = m;
+}
+
+// Quadrant maxima: quad[q][y][x] = max of H over samples (x', y') with
+// (x' - x) sx >= 0 and (y' - y) sy >= 0, q = (sx < 0) + 2 (sy < 0).
+// Rows first: q0 <- suffix max along x, q1 <- prefix max along x.
+__device__ __forceinline__ void quad_row(int j, int W, int Hh, const float* __restrict__ H,
+                                         float* __restrict__ quad) {
+    const size_t plane = (size_t)W * Hh;
+    const float* row = H + (size_t)j * W;
+    float* suf = quad + (size_t)j * W;
+    float* pre = quad + plane + (size_t)j * W;
+    float m = row[W - 1];
+    for (int x = W - 1; x >= 0; --x) {
+        const float v = row[x];
+        m = v > m ? v : m;
+        suf[x] = m;
+    }
+    m = row[0];
+    for (int x = 0; x < W; ++x) {
+        const float v = row[x];
+        m = v > m ? v : m;
+        pre[x] = m;
+    }
+}
+
+// Columns: q2 <- prefix along y of q0, q3 <- prefix of q1, then q0, q1 <- suffixes in place.
+__device__ __forceinline__ void quad_col(int i, int W, int Hh, float* __restrict__ quad) {
+    const size_t plane = (size_t)W * Hh;
+    for (int h = 0; h < 2; ++h) {
+        float* src = quad + h * plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
+        float* pre = quad + (h + 2) * plane;  // sy = -1
+        float m = src[i];
+        for (int y = 0; y < Hh; ++y) {
+            const float v = src[(size_t)y * W + i];
+            m = v > m ? v : m;
+            pre[(size_t)y * W + i] = m;
+        }
+        m = src[(size_t)(Hh - 1) * W + i];
+        for (int y = Hh - 1; y >= 0; --y) {
+            const float v = src[(size_t)y * W + i];
+            m = v > m ? v : m;
+            src[(size_t)y * W + i] = m;
+        }
+    }
+}
+
+// Integration: right-hand side of the normal equations at node v.
+__device__ __forceinline__ void grad_at(const float* n, size_t v, float& p, float& q) {
+    const float nz0 = n[3 * v + 2];
+    const float nz = nz0 > 0.05f ? nz0 : 0.05f;
+    p = -(n[3 * v + 0] / nz);
+    q = -(n[3 * v + 1] / nz);
+}
+
+__device__ __forceinline__ void mg_rhs_node(int v, int W, int Hh, const float* __restrict__ n,
+                                            float* __restrict__ b) {
+    const int i = v % W, j = v / W;
+    float p, q;
+    grad_at(n, v, p, q);
+    float acc = 0.0f;
+    float pn, qn;
+    if (i > 0) { grad_at(n, v - 1, pn, qn); acc = acc + (pn + p) * 0.5f; }
+    if (i < W - 1) { grad_at(n, v + 1, pn, qn); acc = acc - (p + pn) * 0.5f; }
+    if (j > 0) { grad_at(n, v - W, pn, qn); acc = acc + (qn + q) * 0.5f; }
+    if (j < Hh - 1) { grad_at(n, v + W, pn, qn); acc = acc - (q + qn) * 0.5f; }
+    b[v] = acc;
+}
+
+// Edge weights of level `shift`: horizontal edges of row J carry the number of
+// finest rows in that aggregate, vertical edges of column I its column count.
+__device__ __forceinline__ float w_row(int H0, int shift, int J) {
+    const int s = 1 << shift, rows = H0 - J * s;
+    return (float)(rows < s ? rows : s);
+}
+__device__ __forceinline__ float w_col(int W0, int shift, int I) {
+    const int s = 1 << shift, cols = W0 - I * s;
+    return (float)(cols < s ? cols : s);
+}
+
+// One red-black Gauss-Seidel update of node v (if it has the given colour).
+__device__ __forceinline__ void mg_smooth_node(int v, int Wl, int Hl, int shift, int W0, int H0,
+                                               float* __restrict__ X, const float* __restrict__ b,
+                                               int colour) {
+    const int I = v % Wl, J = v / Wl;
+    if (((I + J) & 1) != colour) return;
+    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
+    float num = b[v], den = 0.0f;
+    if (I > 0) { num = fmaf(wx, X[v - 1], num); den = den + wx; }
+    if (I < Wl - 1) { num = fmaf(wx, X[v + 1], num); den = den + wx; }
+    if (J > 0) { num = fmaf(wy, X[v - Wl], num); den = den + wy; }
+    if (J < Hl - 1) { num = fmaf(wy, X[v + Wl], num); den = den + wy; }
+    if (den > 0.0f) X[v] = num / den;
+}
+
+__device__ __forceinline__ float mg_resid(int Wl, int Hl, int shift, int W0, int H0, const float* X,
+                                          const float* b, int I, int J) {
+    const size_t v = (size_t)J * Wl + I;
+    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
+    const float xv = X[v];
+    float lx = 0.0f;
+    if (I > 0) lx = fmaf(wx, xv - X[v - 1], lx);
+    if (I < Wl - 1) lx = fmaf(wx, xv - X[v + 1], lx);
+    if (J > 0) lx = fmaf(wy, xv - X[v - Wl], lx);
+    if (J < Hl - 1) lx = fmaf(wy, xv - X[v + Wl], lx);
+    return b[v] - lx;
+}
+
+// Coarse right-hand side = sum of the four fine residuals; coarse guess = 0.
+__device__ __forceinline__ void mg_restrict_node(int v, int Wf, int Hf, int shift, int W0, int H0,
+                                                 const float* __restrict__ Xf, const float* __restrict__ bf,
+                                                 int Wc, float* __restrict__ bc, float* __restrict__ Xc) {
+    const int I = v % Wc, J = v / Wc;
+    float acc = 0.0f;
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            const int fi = 2 * I + di, fj = 2 * J + dj;
+            if (fi < Wf && fj < Hf) acc = acc + mg_resid(Wf, Hf, shift, W0, H0, Xf, bf, fi, fj);
+        }
+    bc[v] = acc;
+    Xc[v] = 0.0f;
+}
+
+__device__ __forceinline__ void mg_prolong_node(int v, int Wf, float* __restrict__ Xf, int Wc,
+                                                const float* __restrict__ Xc) {
+    const int I = v % Wf, J = v / Wf;
+    Xf[v] = Xf[v] + 2.0f * Xc[(size_t)(J / 2) * Wc + I / 2];
+}
+
+// The coarsest grid (at most 4 x 4): 16 red-black sweeps by one thread, in the
+// same colour order as the parallel sweeps (nodes of one colour are independent).
+__device__ __forceinline__ void mg_coarse(int Wl, int Hl, int shift, int W0, int H0, float* X,
+                                          const float* b) {
+    for (int sw = 0; sw < 16; ++sw)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int v = 0; v < Wl * Hl; ++v) mg_smooth_node(v, Wl, Hl, shift, W0, H0, X, b, colour);
+}
+
+// Order-preserving map of binary32 (no NaN) to uint32.
+__device__ __forceinline__ unsigned order_key(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float order_val(unsigned k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// Minimum of X + 0 over a block's nodes into *key (one atomic per wave).
+__device__ __forceinline__ void min_key_block(const float* __restrict__ X, int v, int n, unsigned* key) {
+    unsigned k = 0xffffffffu;
+    if (v < n) k = order_key(X[v] + 0.0f);  // +0.0f: one zero
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned other = __shfl_xor(k, o);
+        k = other < k ? other : k;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(key, k);
+}
+
 // ---------------------------------------------------------------------------
-// Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments.
+// Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments, for one
+// 16 x 16 tile of pixels (one 256-thread block).
 // One lane owns one pixel.  Its K x C hit sums live in that pixel's row of the
 // pixel-major output G[p][k][c] (only this lane touches it); the C environment
 // sums stay in registers.  Each lane runs its own sequence of segments: the
 // wave alternates a traversal phase, in which every lane advances its own ray
-// until at least kReadyBatch lanes (or all that still have work) have finished
+// until at least ready_batch lanes (or all that still have work) have finished
 // theirs, with a phase that shades the finished segments and starts the next
 // ones.  A lane's segments are summed in (sample, bounce) order.
-constexpr int kReadyBatch = 32;
-
 template <int C>
-__global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
-    __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(a.sa, s_off);
+__device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
     const int tiles_x = (a.sa.W + 15) / 16;
-    const int tiles_y = (a.sa.Hh + 15) / 16;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= tiles_x * tiles_y) return;
     const int i = (tile % tiles_x) * 16 + (threadIdx.x & 15);
     const int j = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
     const bool live = i < a.sa.W && j < a.sa.Hh;
     const int npx = a.sa.W * a.sa.Hh;
     const int p = live ? j * a.sa.W + i : 0;
-    const Surface S = make_surface(a.sa, s_off);
     const bool flat = (a.flags & kFlagFlat) != 0;
     const int K = a.K;
     const int KC = K * C;
+    const int batch = a.ready_batch;
     float* __restrict__ gp = a.G + (size_t)p * KC;  // this pixel's sums
 
     if (live)
@@ -191,7 +414,7 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
             }
             const int n_act = __popcll(__ballot(!finished));
             const int n_rdy = __popcll(__ballot(!finished && ready));
-            if (n_rdy >= (n_act < kReadyBatch ? n_act : kReadyBatch)) break;
+            if (n_rdy >= (n_act < batch ? n_act : batch)) break;
         }
         // shading phase
         if (!finished && ready) {
@@ -264,8 +487,38 @@ __global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Stage 5 (G is pixel-major [p][k][c], images and E are [k][c][p]).
+// ===========================================================================
+// Single-job kernels.
+
+template <int C>
+__global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, const float* __restrict__ A,
+                                                  float* __restrict__ n, float* __restrict__ rho) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+    ps_px<C>(p, npx, K, &M.m[0][0], A, n, rho);
+}
+
+__global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
+                                                int flat, float* __restrict__ S_out) {
+    __shared__ int s_off[trv::kMaxLevels];
+    load_level_table(sa.off, s_off);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sa.W * sa.Hh) return;
+    const Surface S = make_surface(sa, s_off);
+    direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
+    __shared__ int s_off[trv::kMaxLevels];
+    load_level_table(a.sa.off, s_off);
+    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= tiles) return;
+    const Surface S = make_surface(a.sa, s_off);
+    trace_tile<C>(a, S, tile);
+}
+
 template <int C>
 __global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, int cumulative,
                                                  const float* __restrict__ I0, const float* __restrict__ Aprev,
@@ -274,218 +527,72 @@ __global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, i
                                                  float* __restrict__ Anext) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npx) return;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        float rt;
-        if (rho_mode == 0) {
-            float num = 0.0f, den = 0.0f;
-            for (int k = 0; k < K; ++k) {
-                const size_t x = ((size_t)k * C + c) * npx + p;
-                const float v = S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c];
-                num = fmaf(I0[x], v, num);
-                den = fmaf(v, v, den);
-            }
-            rt = den > 0.0f ? num / den : 0.0f;
-        } else {
-            rt = rho[(size_t)c * npx + p];
-        }
-        for (int k = 0; k < K; ++k) {
-            const size_t x = ((size_t)k * C + c) * npx + p;
-            const float e = rt * G[((size_t)p * K + k) * C + c];
-            if (E) E[x] = e;
-            Anext[x] = (cumulative ? Aprev[x] : I0[x]) - e;
-        }
-    }
+    correct_px<C>(p, npx, K, rho_mode, cumulative, I0, Aprev, G, S, rho, E, Anext);
 }
 
-// Forward render: images = albedo (S + G); G is pixel-major [p][k][c].
 template <int C>
 __global__ void __launch_bounds__(256) k_compose(int npx, int K, const float* __restrict__ rho,
                                                  const float* __restrict__ S, const float* __restrict__ G,
                                                  float* __restrict__ I) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npx) return;
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const size_t x = ((size_t)k * C + c) * npx + p;
-            I[x] = rho[(size_t)c * npx + p] * (S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c]);
-        }
-    }
+    compose_px<C>(p, npx, K, rho, S, G, I);
 }
 
-// ---------------------------------------------------------------------------
-// Apron-max pyramid.
 __global__ void __launch_bounds__(256) k_pyr_level0(int W, int Hh, const float* __restrict__ H,
                                                     float* __restrict__ out, int wc, int hc) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= wc * hc) return;
-    const int cx = c % wc, cy = c / wc;
-    const int x0 = cx - 1 < 0 ? 0 : cx - 1, x1 = cx + 2 > W - 1 ? W - 1 : cx + 2;
-    const int y0 = cy - 1 < 0 ? 0 : cy - 1, y1 = cy + 2 > Hh - 1 ? Hh - 1 : cy + 2;
-    float m = H[(size_t)y0 * W + x0];
-    for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) {
-            const float v = H[(size_t)y * W + x];
-            m = v > m ? v : m;
-        }
-    out[c] = m;
+    pyr0_cell(c, W, Hh, wc, H, out);
 }
 
 __global__ void __launch_bounds__(256) k_pyr_reduce(const float* __restrict__ in, int wi, int hi,
                                                     float* __restrict__ out, int wo, int ho) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= wo * ho) return;
-    const int cx = c % wo, cy = c / wo;
-    float m = in[(size_t)(2 * cy) * wi + 2 * cx];
-    for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx) {
-            const int x = 2 * cx + dx, y = 2 * cy + dy;
-            if (x < wi && y < hi) {
-                const float v = in[(size_t)y * wi + x];
-                m = v > m ? v : m;
-            }
-        }
-    out[c] = m;
+    pyr_reduce_cell(c, in, wi, hi, out, wo);
 }
 
-// Quadrant maxima: quad[q][y][x] = max of H over samples (x', y') with
-// (x' - x) sx >= 0 and (y' - y) sy >= 0, q = (sx < 0) + 2 (sy < 0).
-// Rows first: q0 <- suffix max along x, q1 <- prefix max along x.
 __global__ void __launch_bounds__(64) k_quad_rows(int W, int Hh, const float* __restrict__ H,
                                                   float* __restrict__ quad) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= Hh) return;
-    const int plane = W * Hh;
-    const float* row = H + j * W;
-    float* suf = quad + 0 * plane + j * W;
-    float* pre = quad + 1 * plane + j * W;
-    float m = row[W - 1];
-    for (int x = W - 1; x >= 0; --x) {
-        const float v = row[x];
-        m = v > m ? v : m;
-        suf[x] = m;
-    }
-    m = row[0];
-    for (int x = 0; x < W; ++x) {
-        const float v = row[x];
-        m = v > m ? v : m;
-        pre[x] = m;
-    }
+    if (j < Hh) quad_row(j, W, Hh, H, quad);
 }
 
-// Columns: q2 <- prefix along y of q0, q3 <- prefix of q1, then q0, q1 <- suffixes in place.
 __global__ void __launch_bounds__(64) k_quad_cols(int W, int Hh, float* __restrict__ quad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= W) return;
-    const int plane = W * Hh;
-    for (int h = 0; h < 2; ++h) {
-        float* src = quad + h * plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
-        float* pre = quad + (h + 2) * plane;  // sy = -1
-        float m = src[i];
-        for (int y = 0; y < Hh; ++y) {
-            const float v = src[y * W + i];
-            m = v > m ? v : m;
-            pre[y * W + i] = m;
-        }
-        m = src[(Hh - 1) * W + i];
-        for (int y = Hh - 1; y >= 0; --y) {
-            const float v = src[y * W + i];
-            m = v > m ? v : m;
-            src[y * W + i] = m;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Integration: right-hand side of the normal equations from the normals.
-__device__ __forceinline__ void grad_at(const float* n, size_t v, float& p, float& q) {
-    const float nz0 = n[3 * v + 2];
-    const float nz = nz0 > 0.05f ? nz0 : 0.05f;
-    p = -(n[3 * v + 0] / nz);
-    q = -(n[3 * v + 1] / nz);
+    if (i < W) quad_col(i, W, Hh, quad);
 }
 
 __global__ void __launch_bounds__(256) k_mg_rhs(int W, int Hh, const float* __restrict__ n,
                                                 float* __restrict__ b) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= W * Hh) return;
-    const int i = v % W, j = v / W;
-    float p, q;
-    grad_at(n, v, p, q);
-    float acc = 0.0f;
-    float pn, qn;
-    if (i > 0) { grad_at(n, v - 1, pn, qn); acc = acc + (pn + p) * 0.5f; }
-    if (i < W - 1) { grad_at(n, v + 1, pn, qn); acc = acc - (p + pn) * 0.5f; }
-    if (j > 0) { grad_at(n, v - W, pn, qn); acc = acc + (qn + q) * 0.5f; }
-    if (j < Hh - 1) { grad_at(n, v + W, pn, qn); acc = acc - (q + qn) * 0.5f; }
-    b[v] = acc;
-}
-
-// Edge weights of level `shift`: horizontal edges of row J carry the number of
-// finest rows in that aggregate, vertical edges of column I its column count.
-__device__ __forceinline__ float w_row(int H0, int shift, int J) {
-    const int s = 1 << shift, rows = H0 - J * s;
-    return (float)(rows < s ? rows : s);
-}
-__device__ __forceinline__ float w_col(int W0, int shift, int I) {
-    const int s = 1 << shift, cols = W0 - I * s;
-    return (float)(cols < s ? cols : s);
+    if (v < W * Hh) mg_rhs_node(v, W, Hh, n, b);
 }
 
 __global__ void __launch_bounds__(256) k_mg_smooth(int Wl, int Hl, int shift, int W0, int H0,
                                                    float* __restrict__ X, const float* __restrict__ b,
                                                    int colour) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= Wl * Hl) return;
-    const int I = v % Wl, J = v / Wl;
-    if (((I + J) & 1) != colour) return;
-    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
-    float num = b[v], den = 0.0f;
-    if (I > 0) { num = fmaf(wx, X[v - 1], num); den = den + wx; }
-    if (I < Wl - 1) { num = fmaf(wx, X[v + 1], num); den = den + wx; }
-    if (J > 0) { num = fmaf(wy, X[v - Wl], num); den = den + wy; }
-    if (J < Hl - 1) { num = fmaf(wy, X[v + Wl], num); den = den + wy; }
-    if (den > 0.0f) X[v] = num / den;
+    if (v < Wl * Hl) mg_smooth_node(v, Wl, Hl, shift, W0, H0, X, b, colour);
 }
 
-__device__ __forceinline__ float mg_resid(int Wl, int Hl, int shift, int W0, int H0, const float* X,
-                                          const float* b, int I, int J) {
-    const size_t v = (size_t)J * Wl + I;
-    const float wx = w_row(H0, shift, J), wy = w_col(W0, shift, I);
-    const float xv = X[v];
-    float lx = 0.0f;
-    if (I > 0) lx = fmaf(wx, xv - X[v - 1], lx);
-    if (I < Wl - 1) lx = fmaf(wx, xv - X[v + 1], lx);
-    if (J > 0) lx = fmaf(wy, xv - X[v - Wl], lx);
-    if (J < Hl - 1) lx = fmaf(wy, xv - X[v + Wl], lx);
-    return b[v] - lx;
-}
-
-// Coarse right-hand side = sum of the four fine residuals; coarse guess = 0.
 __global__ void __launch_bounds__(256) k_mg_restrict(int Wf, int Hf, int shift, int W0, int H0,
                                                      const float* __restrict__ Xf,
                                                      const float* __restrict__ bf, int Wc, int Hc,
                                                      float* __restrict__ bc, float* __restrict__ Xc) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= Wc * Hc) return;
-    const int I = v % Wc, J = v / Wc;
-    float acc = 0.0f;
-    for (int dj = 0; dj < 2; ++dj)
-        for (int di = 0; di < 2; ++di) {
-            const int fi = 2 * I + di, fj = 2 * J + dj;
-            if (fi < Wf && fj < Hf) acc = acc + mg_resid(Wf, Hf, shift, W0, H0, Xf, bf, fi, fj);
-        }
-    bc[v] = acc;
-    Xc[v] = 0.0f;
+    if (v < Wc * Hc) mg_restrict_node(v, Wf, Hf, shift, W0, H0, Xf, bf, Wc, bc, Xc);
 }
 
 __global__ void __launch_bounds__(256) k_mg_prolong(int Wf, int Hf, float* __restrict__ Xf, int Wc,
                                                     const float* __restrict__ Xc) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= Wf * Hf) return;
-    const int I = v % Wf, J = v / Wf;
-    Xf[v] = Xf[v] + 2.0f * Xc[(size_t)(J / 2) * Wc + I / 2];
+    if (v < Wf * Hf) mg_prolong_node(v, Wf, Xf, Wc, Xc);
+}
+
+__global__ void k_mg_coarse(int Wl, int Hl, int shift, int W0, int H0, float* X, const float* b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) mg_coarse(Wl, Hl, shift, W0, H0, X, b);
 }
 
 __global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
@@ -498,34 +605,238 @@ __global__ void k_fill_f32(float* p, float v, long long n) {
     if (x < n) p[x] = v;
 }
 
-// Order-preserving map of binary32 (no NaN) to uint32.
-__device__ __forceinline__ unsigned order_key(float f) {
-    const unsigned u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float order_val(unsigned k) {
-    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+__global__ void k_copy_f32(float* __restrict__ dst, const float* __restrict__ src, long long n) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) dst[x] = src[x];
 }
 
 __global__ void __launch_bounds__(256) k_min_key(const float* __restrict__ X, int n, unsigned* key) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned k = 0xffffffffu;
-    if (v < n) k = order_key(X[v] + 0.0f);  // +0.0f: one zero
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned other = __shfl_xor(k, o);
-        k = other < k ? other : k;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMin(key, k);
+    min_key_block(X, blockIdx.x * blockDim.x + threadIdx.x, n, key);
 }
 
 __global__ void __launch_bounds__(256) k_anchor(const float* __restrict__ X, int n, const unsigned* key,
                                                 float* __restrict__ out) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    out[v] = X[v] - order_val(*key);
+    if (v < n) out[v] = X[v] - order_val(*key);
 }
 
-// ---------------------------------------------------------------------------
+// ===========================================================================
+// Multi-job kernels: blockIdx.y selects the job; blocks past a job's extent
+// return at once.
+
+// A job takes part in the iteration steps while t < T; the t = 0 steps (PS of
+// I0, cold integration) run for every active job.
+__device__ __forceinline__ bool iterating(const JobDesc& J) { return J.active && J.t < J.T; }
+__device__ __forceinline__ bool participates(const JobDesc& J, int init) {
+    return init ? J.active != 0 : iterating(J);
+}
+
+__device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, int ready_batch) {
+    TraceArgs a;
+    a.sa.H = J.depth;
+    a.sa.pyr = J.pyr;
+    a.sa.W = J.W;
+    a.sa.Hh = J.Hh;
+    a.sa.levels = J.pyr_levels;
+    a.sa.quad_off = J.quad_off;
+#pragma unroll
+    for (int l = 0; l < trv::kMaxLevels; ++l) a.sa.off[l] = J.pyr_off[l];
+    a.n = J.n;
+    a.rho = J.rho;
+    a.S = J.S;
+    a.env = J.env;
+    a.G = J.G;
+    a.counters = J.counters;
+    a.env_h = J.env_h;
+    a.env_w = J.env_w;
+    a.C = J.C;
+    a.K = J.K;
+    a.spp = J.spp;
+    a.B = J.B;
+    a.t = J.t;
+    a.tag = tag;
+    a.flags = J.flags & (kFlagQuadrature | kFlagFlat);
+    a.ready_batch = ready_batch;
+    a.key0 = J.key0;
+    a.key1 = J.key1;
+    return a;
+}
+
+// Persistent tracer: each block takes (job, tile) pairs from a queue.
+template <int C>
+__global__ void __launch_bounds__(256) k_trace_multi(const JobDesc* __restrict__ jobs,
+                                                     const int2* __restrict__ tiles, int ntiles,
+                                                     unsigned* queue, int tag, int ready_batch) {
+    __shared__ int s_off[trv::kMaxLevels];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();  // every thread has read s_item before it is replaced
+        if (item >= ntiles) return;
+        const int2 jt = tiles[item];
+        const JobDesc& J = jobs[jt.x];
+        if (!iterating(J)) continue;  // uniform per block; s_item was read above
+        const TraceArgs a = job_trace_args(J, tag, ready_batch);
+        load_level_table(a.sa.off, s_off);
+        const Surface S = make_surface(a.sa, s_off);
+        trace_tile<C>(a, S, jt.y);
+        __syncthreads();  // s_off is reloaded for the next item
+    }
+}
+
+__global__ void __launch_bounds__(256) k_begin_multi(JobDesc* jobs) {
+    JobDesc& J = jobs[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0) J.t = 0;
+    if (!J.active) return;
+    if (J.counters && blockIdx.x == 0 && threadIdx.x < 4) J.counters[threadIdx.x] = 0ull;
+    if (J.E) {
+        const long long n = (long long)J.K * J.C * J.W * J.Hh;
+        for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+             x += (long long)gridDim.x * blockDim.x)
+            J.E[x] = 0.0f;
+    }
+}
+
+__global__ void k_advance_multi(JobDesc* jobs, int njobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs && iterating(jobs[j])) jobs[j].t += 1;
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) k_ps_multi(const JobDesc* __restrict__ jobs, int from_A) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int npx = J.W * J.Hh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!participates(J, !from_A) || J.C != C || p >= npx) return;
+    ps_px<C>(p, npx, J.K, &J.M[0][0], from_A ? J.A : J.I0, J.n, J.rho);
+}
+
+__global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict__ jobs) {
+    __shared__ int s_off[trv::kMaxLevels];
+    const JobDesc& J = jobs[blockIdx.y];
+    load_level_table(J.pyr_off, s_off);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!iterating(J) || p >= J.W * J.Hh) return;
+    const Surface S = make_surface(J.depth, J.pyr, J.W, J.Hh, J.pyr_levels, J.quad_off, s_off);
+    direct_px(S, p, J.n, J.K, &J.L[0][0], J.s, (J.flags & kFlagFlat) != 0, J.S);
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) k_correct_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int npx = J.W * J.Hh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!iterating(J) || J.C != C || p >= npx) return;
+    const bool cumulative = (J.flags & 2) != 0;
+    float* E = (J.t == J.T - 1) ? J.E : nullptr;
+    correct_px<C>(p, npx, J.K, J.rho_mode, cumulative ? 1 : 0, J.I0, (cumulative && J.t > 0) ? J.A : J.I0,
+                  J.G, J.S, J.rho, E, J.A);
+}
+
+__global__ void __launch_bounds__(256) k_pyr0_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!iterating(J) || c >= J.pyr_wc[0] * J.pyr_hc[0]) return;
+    pyr0_cell(c, J.W, J.Hh, J.pyr_wc[0], J.depth, J.pyr);
+}
+
+__global__ void __launch_bounds__(256) k_pyr_reduce_multi(const JobDesc* __restrict__ jobs, int l) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!iterating(J) || l >= J.pyr_levels || c >= J.pyr_wc[l] * J.pyr_hc[l]) return;
+    pyr_reduce_cell(c, J.pyr + J.pyr_off[l - 1], J.pyr_wc[l - 1], J.pyr_hc[l - 1], J.pyr + J.pyr_off[l],
+                    J.pyr_wc[l]);
+}
+
+__global__ void __launch_bounds__(64) k_quad_rows_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && j < J.Hh) quad_row(j, J.W, J.Hh, J.depth, J.pyr + J.quad_off);
+}
+
+__global__ void __launch_bounds__(64) k_quad_cols_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && i < J.W) quad_col(i, J.W, J.Hh, J.pyr + J.quad_off);
+}
+
+__global__ void __launch_bounds__(256) k_mg_rhs_multi(const JobDesc* __restrict__ jobs, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (participates(J, cold) && v < J.W * J.Hh) mg_rhs_node(v, J.W, J.Hh, J.n, J.mg_ws + J.mg.boff[0]);
+}
+
+// X0 <- depth (warm) or 0 (cold).
+__global__ void __launch_bounds__(256) k_mg_init_multi(const JobDesc* __restrict__ jobs, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!participates(J, cold) || v >= J.W * J.Hh) return;
+    J.mg_ws[J.mg.xoff[0] + v] = cold ? 0.0f : J.depth[v];
+}
+
+// A job takes part in V-cycle c only while c is below its own cycle count.
+__device__ __forceinline__ bool in_cycle(const JobDesc& J, int c, int cold) {
+    return participates(J, cold) && c < (cold ? J.cycles_cold : J.cycles_warm);
+}
+
+__global__ void __launch_bounds__(256) k_mg_smooth_multi(const JobDesc* __restrict__ jobs, int l, int colour,
+                                                         int c, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l] * J.mg.H[l]) return;
+    mg_smooth_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
+                   colour);
+}
+
+__global__ void __launch_bounds__(256) k_mg_restrict_multi(const JobDesc* __restrict__ jobs, int l, int c,
+                                                           int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l + 1] * J.mg.H[l + 1]) return;
+    mg_restrict_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
+                     J.mg.W[l + 1], J.mg_ws + J.mg.boff[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
+}
+
+__global__ void k_mg_coarse_multi(const JobDesc* __restrict__ jobs, int c, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (!in_cycle(J, c, cold) || threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int l = J.mg.levels - 1;
+    mg_coarse(J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l]);
+}
+
+__global__ void __launch_bounds__(256) k_mg_prolong_multi(const JobDesc* __restrict__ jobs, int l, int c,
+                                                          int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l] * J.mg.H[l]) return;
+    mg_prolong_node(v, J.mg.W[l], J.mg_ws + J.mg.xoff[l], J.mg.W[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
+}
+
+__global__ void __launch_bounds__(256) k_min_key_multi(const JobDesc* __restrict__ jobs, int init, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (!participates(J, cold)) return;
+    unsigned* key = reinterpret_cast<unsigned*>(J.mg_ws + J.mg.keyoff);
+    if (init) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *key = 0xffffffffu;
+        return;
+    }
+    const int n = J.W * J.Hh;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int)(blockIdx.x * blockDim.x) >= n) return;  // whole block past the end
+    min_key_block(J.mg_ws + J.mg.xoff[0], v, n, key);
+}
+
+__global__ void __launch_bounds__(256) k_anchor_multi(const JobDesc* __restrict__ jobs, int cold) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!participates(J, cold) || v >= J.W * J.Hh) return;
+    const unsigned* key = reinterpret_cast<const unsigned*>(J.mg_ws + J.mg.keyoff);
+    J.depth[v] = J.mg_ws[J.mg.xoff[0] + v] - order_val(*key);
+}
+
+// ===========================================================================
 // Probes.
 __global__ void k_probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
                                uint32_t* out) {
@@ -559,7 +870,7 @@ __global__ void k_probe_env(long long count, const float* d, int He, int We, int
 __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, const int* ij,
                                  const float* d, int* q) {
     __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(sa, s_off);
+    load_level_table(sa.off, s_off);
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= count) return;
     const int i0 = ij[2 * r], j0 = ij[2 * r + 1];
@@ -570,8 +881,7 @@ __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, cons
     }
     const Surface S = make_surface(sa, s_off);
     int qi = -1, qj = -1;
-    const bool hit = walk(S, flat != 0, i0, j0,
-                          dm::V3{d[3 * r], d[3 * r + 1], d[3 * r + 2]}, qi, qj);
+    const bool hit = trv::walk(S, flat != 0, i0, j0, d[3 * r], d[3 * r + 1], d[3 * r + 2], qi, qj);
     q[2 * r] = hit ? qi : -1;
     q[2 * r + 1] = hit ? qj : -1;
 }
@@ -627,10 +937,8 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st) {
     float* quad = pyr + quad_off;
-    const long long npx = (long long)W * Hh;
     hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(Hh, 64)), dim3(64), 0, st, W, Hh, H, quad);
     hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(W, 64)), dim3(64), 0, st, W, Hh, quad);
-    (void)npx;
     hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
                        st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
     for (int l = 1; l < P.levels; ++l)
@@ -652,13 +960,12 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
     }
     unsigned* key = reinterpret_cast<unsigned*>(ws + plan.keyoff);
     hipLaunchKernelGGL(k_mg_rhs, dim3(blocks_for(npx, 256)), dim3(256), 0, st, W0, H0, n, b[0]);
-    if (Hinit) {
-        if (hipMemcpyAsync(X[0], Hinit, sizeof(float) * (size_t)npx, hipMemcpyDeviceToDevice, st) != hipSuccess)
-            return hipGetLastError();
-    } else {
+    if (Hinit)
+        hipLaunchKernelGGL(k_copy_f32, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], Hinit,
+                           (long long)npx);
+    else
         hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], 0.0f,
                            (long long)npx);
-    }
     auto smooth = [&](int l, int sweeps) {
         const int nl = plan.W[l] * plan.H[l];
         for (int s = 0; s < sweeps; ++s)
@@ -666,16 +973,18 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
                 hipLaunchKernelGGL(k_mg_smooth, dim3(blocks_for(nl, 256)), dim3(256), 0, st, plan.W[l],
                                    plan.H[l], l, W0, H0, X[l], b[l], colour);
     };
+    const int top = plan.levels - 1;
     for (int c = 0; c < cycles; ++c) {
-        for (int l = 0; l < plan.levels - 1; ++l) {
+        for (int l = 0; l < top; ++l) {
             smooth(l, 2);
             const int nc = plan.W[l + 1] * plan.H[l + 1];
             hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(nc, 256)), dim3(256), 0, st, plan.W[l],
                                plan.H[l], l, W0, H0, X[l], b[l], plan.W[l + 1], plan.H[l + 1], b[l + 1],
                                X[l + 1]);
         }
-        smooth(plan.levels - 1, 16);
-        for (int l = plan.levels - 2; l >= 0; --l) {
+        hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(64), 0, st, plan.W[top], plan.H[top], top, W0, H0,
+                           X[top], b[top]);
+        for (int l = top - 1; l >= 0; --l) {
             hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(plan.W[l] * plan.H[l], 256)), dim3(256), 0,
                                st, plan.W[l], plan.H[l], X[l], plan.W[l + 1], X[l + 1]);
             smooth(l, 2);
@@ -695,6 +1004,94 @@ hipError_t fill_f32(float* p, float v, long long n, hipStream_t st) {
 
 hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(p), 0u, 2 * n);
+    return hipGetLastError();
+}
+
+// ---- multi-job ----
+hipError_t trace_multi(const JobDesc* jobs, int C, const int2* tiles, int ntiles, unsigned* queue,
+                       int tag, int ready_batch, int resident_blocks, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, queue, 0u, 1);
+    // enough resident blocks to fill every CU several times over; the queue balances them
+    int grid = resident_blocks;
+    if (grid > ntiles) grid = ntiles;
+    if (C == 1)
+        hipLaunchKernelGGL(k_trace_multi<1>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag,
+                           ready_batch);
+    else
+        hipLaunchKernelGGL(k_trace_multi<3>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag,
+                           ready_batch);
+    return hipGetLastError();
+}
+
+hipError_t batch_begin(const JobDesc* jobs, const BatchShape& bs, hipStream_t st) {
+    hipLaunchKernelGGL(k_begin_multi, dim3(256, bs.njobs), dim3(256), 0, st, const_cast<JobDesc*>(jobs));
+    return hipGetLastError();
+}
+
+hipError_t batch_advance(JobDesc* jobs, int njobs, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_multi, dim3(blocks_for(njobs, 64)), dim3(64), 0, st, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t batch_ps(const JobDesc* jobs, const BatchShape& bs, int from_A, hipStream_t st) {
+    const dim3 g(blocks_for(bs.max_npx, 256), bs.njobs);
+    hipLaunchKernelGGL(k_ps_multi<1>, g, dim3(256), 0, st, jobs, from_A);
+    hipLaunchKernelGGL(k_ps_multi<3>, g, dim3(256), 0, st, jobs, from_A);
+    return hipGetLastError();
+}
+
+hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t st) {
+    hipLaunchKernelGGL(k_quad_rows_multi, dim3(blocks_for(bs.max_rows, 64), bs.njobs), dim3(64), 0, st, jobs);
+    hipLaunchKernelGGL(k_quad_cols_multi, dim3(blocks_for(bs.max_cols, 64), bs.njobs), dim3(64), 0, st, jobs);
+    hipLaunchKernelGGL(k_pyr0_multi, dim3(blocks_for(bs.max_pyr_cells[0], 256), bs.njobs), dim3(256), 0, st,
+                       jobs);
+    for (int l = 1; l < bs.max_pyr_levels; ++l)
+        hipLaunchKernelGGL(k_pyr_reduce_multi, dim3(blocks_for(bs.max_pyr_cells[l], 256), bs.njobs), dim3(256),
+                           0, st, jobs, l);
+    return hipGetLastError();
+}
+
+hipError_t batch_direct(const JobDesc* jobs, const BatchShape& bs, hipStream_t st) {
+    hipLaunchKernelGGL(k_direct_multi, dim3(blocks_for(bs.max_npx, 256), bs.njobs), dim3(256), 0, st, jobs);
+    return hipGetLastError();
+}
+
+hipError_t batch_correct(const JobDesc* jobs, const BatchShape& bs, int /*last_only*/, hipStream_t st) {
+    const dim3 g(blocks_for(bs.max_npx, 256), bs.njobs);
+    hipLaunchKernelGGL(k_correct_multi<1>, g, dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_correct_multi<3>, g, dim3(256), 0, st, jobs);
+    return hipGetLastError();
+}
+
+hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, hipStream_t st) {
+    const int nj = bs.njobs;
+    const dim3 gpx(blocks_for(bs.max_npx, 256), nj);
+    hipLaunchKernelGGL(k_mg_rhs_multi, gpx, dim3(256), 0, st, jobs, cold);
+    hipLaunchKernelGGL(k_mg_init_multi, gpx, dim3(256), 0, st, jobs, cold);
+    const int cycles = cold ? bs.max_cycles_cold : bs.max_cycles_warm;
+    const int L = bs.max_mg_levels;
+    for (int c = 0; c < cycles; ++c) {
+        for (int l = 0; l < L - 1; ++l) {
+            const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
+            for (int s = 0; s < 2; ++s)
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL(k_mg_smooth_multi, g, dim3(256), 0, st, jobs, l, colour, c, cold);
+            hipLaunchKernelGGL(k_mg_restrict_multi, dim3(blocks_for(bs.max_mg_nodes[l + 1], 256), nj), dim3(256),
+                               0, st, jobs, l, c, cold);
+        }
+        hipLaunchKernelGGL(k_mg_coarse_multi, dim3(1, nj), dim3(64), 0, st, jobs, c, cold);
+        for (int l = L - 2; l >= 0; --l) {
+            const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
+            hipLaunchKernelGGL(k_mg_prolong_multi, g, dim3(256), 0, st, jobs, l, c, cold);
+            for (int s = 0; s < 2; ++s)
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL(k_mg_smooth_multi, g, dim3(256), 0, st, jobs, l, colour, c, cold);
+        }
+    }
+    hipLaunchKernelGGL(k_min_key_multi, dim3(1, nj), dim3(64), 0, st, jobs, 1, cold);
+    hipLaunchKernelGGL(k_min_key_multi, gpx, dim3(256), 0, st, jobs, 0, cold);
+    hipLaunchKernelGGL(k_anchor_multi, gpx, dim3(256), 0, st, jobs, cold);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace irtps {
 namespace kern {
 
 constexpr int kMaxLights = 64;
-constexpr int kMaxMgLevels = 32;
+constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
 
@@ -47,6 +47,7 @@ struct TraceArgs {
     int env_h, env_w;
     int C, K;
     int spp, B, t, tag, flags;
+    int ready_batch;   // lanes that must have a result before the wave shades
     uint32_t key0, key1;
 };
 
@@ -57,6 +58,47 @@ struct MgPlan {
     long long xoff[kMaxMgLevels], boff[kMaxMgLevels];
     long long keyoff;  // one uint32 for the anchor's minimum
     long long total;   // floats
+};
+
+// One reconstruction as the multi-job kernels see it (device memory).
+struct JobDesc {
+    int W, Hh, C, K;
+    int spp, B, t, T;
+    int rho_mode, flags, cycles_cold, cycles_warm;
+    uint32_t key0, key1;
+    int active;         // 0: skipped by every multi-job kernel
+    int pyr_levels, quad_off;
+    int pyr_wc[trv::kMaxLevels], pyr_hc[trv::kMaxLevels], pyr_off[trv::kMaxLevels];
+    MgPlan mg;
+    const float* I0;     // [K][C][H][W]
+    const float* env;    // [He][We][C]
+    int env_h, env_w;
+    float* A;            // [K][C][H][W]
+    float* S;            // [H][W][K]
+    float* G;            // [H][W][K][C]
+    float* pyr;          // pyramid + quadrant maxima
+    float* mg_ws;        // multigrid workspace
+    float* n;            // [H][W][3]
+    float* rho;          // [C][H][W]
+    float* depth;        // [H][W]
+    float* E;            // [K][C][H][W] or null
+    unsigned long long* counters;  // 4 x u64 or null
+    float M[3][kMaxLights];
+    float L[kMaxLights][3];
+    float s[kMaxLights];
+};
+
+// Largest extents over the jobs of a batch, used to size the grids.
+struct BatchShape {
+    int njobs;
+    int max_npx;             // largest W * H
+    int max_pyr_cells[trv::kMaxLevels];
+    int max_pyr_levels;
+    int max_rows, max_cols;  // largest H, W
+    int max_mg_levels;
+    int max_mg_nodes[kMaxMgLevels];
+    int max_cycles_cold, max_cycles_warm;
+    int max_KCnpx;           // largest K * C * W * H
 };
 
 hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, float* n, float* rho,
@@ -76,6 +118,22 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
                      float* ws, hipStream_t st);
 hipError_t fill_f32(float* p, float v, long long n, hipStream_t st);
 hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st);
+// ---- multi-job launches: grid.y walks the job table, the tracer a tile queue ----
+// Persistent tracer over (job, tile) pairs; `queue` (one uint32) is cleared here.
+hipError_t trace_multi(const JobDesc* jobs, int C, const int2* tiles, int ntiles, unsigned* queue,
+                       int tag, int ready_batch, int resident_blocks, hipStream_t st);
+// t = 0, counters and E cleared.
+hipError_t batch_begin(const JobDesc* jobs, const BatchShape& bs, hipStream_t st);
+hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t st);
+hipError_t batch_direct(const JobDesc* jobs, const BatchShape& bs, hipStream_t st);
+hipError_t batch_correct(const JobDesc* jobs, const BatchShape& bs, int unused, hipStream_t st);
+// from_A = 0: PS of I0 (t = 0); 1: PS of A.
+hipError_t batch_ps(const JobDesc* jobs, const BatchShape& bs, int from_A, hipStream_t st);
+// cold != 0: from zero with each job's cold cycle count, else warm from depth.
+hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, hipStream_t st);
+hipError_t batch_advance(JobDesc* jobs, int njobs, hipStream_t st);
+
+// ---- probes ----
 hipError_t probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                         hipStream_t st);
 hipError_t probe_sample(long long count, const float* n, const float* u, float* d, hipStream_t st);

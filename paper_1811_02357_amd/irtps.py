@@ -88,6 +88,10 @@ def lib():
             "irtps_render_workspace_bytes": [_i32, _i32, _i32, _i32, P(_sz)],
             "irtps_render": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                              _i32, _i32, _u64, _vp, _vp, _sz, _vp],
+            "irtps_batch_workspace_bytes": [_i32, _vp, _vp, P(_sz)],
+            "irtps_batch_solve": [_i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp],
+            "irtps_set_ready_batch": [_i32],
+            "irtps_get_ready_batch": [],
             "irtps_profile_begin": [],
             "irtps_profile_end": [P(ct.c_double), P(_i64)],
             "irtps_probe_philox": [_i64, _vp, _u64, _vp, _vp],
@@ -290,6 +294,74 @@ def render(depth, normals, albedo, light_dirs, light_intensity, env, spp, bounce
         lp, sp, _dev(env), env.shape[0], env.shape[1], spp, bounces, seed, _dev(I),
         ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
     return I
+
+
+BATCH_GRAPH = 1
+
+
+def _outputs_for(images, dev):
+    K, C, H, W = images.shape
+    return {"normals": torch.empty((H, W, 3), device=dev),
+            "albedo": torch.empty((C, H, W), device=dev),
+            "depth": torch.empty((H, W), device=dev),
+            "indirect": torch.empty((K, C, H, W), device=dev),
+            "counters": torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=dev)}
+
+
+def _batch_structs(jobs, outs):
+    n = len(jobs)
+    probs = (Problem * n)()
+    pars = (Params * n)()
+    o = (Outputs * n)()
+    keep = []
+    for j, job in enumerate(jobs):
+        pr, k = _problem(job["images"], job["light_dirs"], job.get("light_intensity"), job["env"])
+        keep.append(k)
+        probs[j] = pr
+        pars[j] = Params(job["spp"], job["bounces"], job["iterations"], job.get("rho_mode", RHO_FIT),
+                         job.get("flags", 0), job.get("mg_cycles_cold", 0), job.get("mg_cycles_warm", 0), 0,
+                         job.get("seed", 0))
+        if outs is not None:
+            K, C, H, W = job["images"].shape
+            out = outs[j]
+            o[j] = Outputs(_dev(out["normals"], shape=(H, W, 3)), _dev(out["albedo"], shape=(C, H, W)),
+                           _dev(out["depth"], shape=(H, W)),
+                           _dev(out.get("indirect"), shape=(K, C, H, W)),
+                           _dev(out.get("counters"), dtype=torch.int64, shape=(NUM_COUNTERS,)))
+    return probs, pars, o, keep
+
+
+def batch_workspace_bytes(jobs):
+    probs, pars, _, keep = _batch_structs(jobs, None)
+    nb = _sz()
+    _check("irtps_batch_workspace_bytes", lib().irtps_batch_workspace_bytes(
+        len(jobs), ct.cast(probs, ct.c_void_p), ct.cast(pars, ct.c_void_p), ct.byref(nb)))
+    return nb.value
+
+
+def batch_solve(jobs, graph=False, outs=None, workspace=None, stream=None):
+    """Many reconstructions in one set of launches.  `jobs` is a list of dicts
+    with the arguments of solve() (images, light_dirs, light_intensity, env,
+    spp, bounces, iterations, seed, rho_mode, flags); returns a list of output
+    dicts like solve()."""
+    dev = jobs[0]["images"].device
+    if outs is None:
+        outs = [_outputs_for(job["images"], dev) for job in jobs]
+    probs, pars, o, keep = _batch_structs(jobs, outs)
+    if workspace is None:
+        workspace = _alloc_ws(batch_workspace_bytes(jobs), dev)
+    _check("irtps_batch_solve", lib().irtps_batch_solve(
+        len(jobs), ct.cast(probs, ct.c_void_p), ct.cast(pars, ct.c_void_p), ct.cast(o, ct.c_void_p),
+        BATCH_GRAPH if graph else 0, ct.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
+    return outs
+
+
+def set_ready_batch(lanes):
+    _check("irtps_set_ready_batch", lib().irtps_set_ready_batch(lanes))
+
+
+def get_ready_batch():
+    return lib().irtps_get_ready_batch()
 
 
 def profile_begin():

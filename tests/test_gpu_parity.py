@@ -361,3 +361,75 @@ def test_quadrant_maxima(dev):
                 xs = slice(x, W) if sx > 0 else slice(0, x + 1)
                 ys = slice(y, Hh) if sy > 0 else slice(0, y + 1)
                 assert quad[q, y, x] == Hf[ys, xs].max()
+
+
+# ---------------------------------------------------------------------------
+# Batched mode: every job bit-identical to its solve alone.
+def _batch_jobs(dev):
+    jobs, scs = [], []
+    specs = [  # (scene, spp, B, T, rho_mode, flags)
+        (scenes.bowl_64(), 16, 1, 3, irtps.RHO_FIT, 0),
+        (scenes.batched_job(3, 96, 160), 8, 2, 2, irtps.RHO_FIT, 0),
+        (scenes.batched_job(5, 96, 160), 8, 2, 4, irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE),
+        (scenes.fbm_terrain(seed=2, size=72, channels=3, num_lights=9, env_shape=(16, 32), ptp=12.0), 8, 3, 2,
+         irtps.RHO_FIT, 0),
+        (scenes.batched_job(9, 96, 160), 4, 1, 0, irtps.RHO_FIT, 0),
+    ]
+    for k, (sc, spp, B, Tn, mode, flags) in enumerate(specs):
+        I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 2,
+                         seed=k)  # inputs come from the oracle, never from the GPU
+        jobs.append(dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+                         env=T(sc.env, dev), spp=spp, bounces=B, iterations=Tn, seed=100 + k,
+                         rho_mode=mode, flags=flags))
+        scs.append(sc)
+    return jobs
+
+
+def test_batch_equals_alone(dev):
+    say("case: batch of 5 mixed jobs vs each alone")
+    jobs = _batch_jobs(dev)
+    outs = irtps.batch_solve(jobs)
+    for k, job in enumerate(jobs):
+        alone = irtps.solve(**job)
+        for key in ("normals", "albedo", "depth", "indirect", "counters"):
+            assert np.array_equal(H(outs[k][key]), H(alone[key])), (k, key)
+    say("  batch == alone for every job and output")
+
+
+def test_batch_graph_and_ready_batch_invariance(dev):
+    say("case: batch replayed from a hipGraph, tracer wave batch 8 and 64")
+    jobs = _batch_jobs(dev)
+    ref = [{k: H(v) for k, v in o.items()} for o in irtps.batch_solve(jobs)]
+    ws = torch.empty(irtps.batch_workspace_bytes(jobs), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for rep in range(3):
+            outs = irtps.batch_solve(jobs, graph=True, workspace=ws)
+            torch.cuda.synchronize()
+            for k in range(len(jobs)):
+                for key in ("normals", "albedo", "depth", "indirect", "counters"):
+                    assert np.array_equal(H(outs[k][key]), ref[k][key]), (rep, k, key)
+    old = irtps.get_ready_batch()
+    try:
+        for lanes in (8, 64):
+            irtps.set_ready_batch(lanes)
+            outs = irtps.batch_solve(jobs)
+            for k in range(len(jobs)):
+                assert np.array_equal(H(outs[k]["indirect"]), ref[k]["indirect"]), (lanes, k)
+            alone = irtps.solve(**jobs[0])
+            assert np.array_equal(H(alone["normals"]), ref[0]["normals"])
+    finally:
+        irtps.set_ready_batch(old)
+
+
+def test_batch_against_oracle(dev):
+    say("case: batched job against the oracle")
+    jobs = _batch_jobs(dev)
+    outs = irtps.batch_solve(jobs)
+    for k in (1, 3):
+        job = jobs[k]
+        ref = O.solve(H(job["images"]), job["light_dirs"], job["light_intensity"], H(job["env"]), job["spp"],
+                      job["bounces"], job["iterations"], seed=job["seed"], rho_mode=job["rho_mode"],
+                      flags=job["flags"] & irtps.FLAG_LITERAL_CUMULATIVE)
+        got = {kk: H(v) for kk, v in outs[k].items()}
+        _compare_solve(ref, got, f"batch job {k}")
