@@ -223,6 +223,67 @@ int irtps_batch_solve(int32_t n, const irtps_problem* problems, const irtps_para
                       const irtps_outputs* outputs, int32_t options, void* ws_dev,
                       size_t ws_bytes, void* stream);
 
+/* ---- served mode ------------------------------------------------------------ */
+/* A server runs reconstructions as they arrive (continuous batching): a
+ * scheduler thread admits queued jobs in FIFO order when their workspace
+ * footprint fits in the device memory the caller handed over, gives new jobs
+ * their t = 0 steps, and advances every resident job by one IRT iteration in
+ * the same set of launches (irtps_batch_solve's engine), so jobs join and leave
+ * at iteration boundaries.  Each job's outputs are bit-identical to
+ * irtps_solve of that job.  The server reads the job's device inputs and writes
+ * its outputs until the job is DONE, FAILED or CANCELLED; host arrays are
+ * copied at submission.  All calls are thread-safe. */
+typedef struct irtps_server irtps_server;
+
+typedef struct irtps_server_cfg {
+    int32_t max_resident_jobs; /* 0: limited by memory only */
+    int32_t dry_run;           /* 1: schedule and time jobs without launching any kernel
+                                  or touching any buffer (scheduler tests); 0: normal */
+    uint64_t table_bytes;      /* head of the workspace kept for job and tile tables
+                                  (0: workspace/64, at least 1 MiB) */
+    int32_t reserved;          /* must be 0 */
+    int32_t reserved2;
+} irtps_server_cfg;
+
+enum { IRTPS_JOB_QUEUED = 0, IRTPS_JOB_RUNNING = 1, IRTPS_JOB_DONE = 2, IRTPS_JOB_FAILED = 3,
+       IRTPS_JOB_CANCELLED = 4 };
+
+typedef struct irtps_job_status {
+    int32_t state;      /* IRTPS_JOB_* (>= DONE: finished) */
+    int32_t status;     /* irtps_status of a finished job */
+    int32_t iteration;  /* IRT iterations completed */
+    int32_t reserved;
+    double submit_s, start_s, end_s;  /* steady-clock seconds; 0 until reached */
+} irtps_job_status;
+
+typedef struct irtps_server_stats {
+    uint64_t submitted, completed, failed, cancelled;
+    int32_t resident, queued;
+    uint64_t bytes_in_use, bytes_budget;  /* job workspaces in use / available */
+    uint64_t iterations;                  /* scheduling rounds run */
+    double p50_latency_s, p99_latency_s;  /* submit -> done, over completed jobs */
+    double jobs_per_s;                    /* completed / (last done - first submit) */
+} irtps_server_statistics;
+
+/* ws_dev: device memory the server may use (table_bytes of tables, the rest for
+ * resident jobs' workspaces), 256-byte aligned; owned by the caller and used
+ * until irtps_server_destroy returns. */
+int irtps_server_create(const irtps_server_cfg* cfg, void* ws_dev, size_t ws_bytes,
+                        irtps_server** server);
+/* Queue a job.  IRTPS_ERR_OOM if it could never fit the budget alone. */
+int irtps_server_submit(irtps_server* server, const irtps_problem* problem,
+                        const irtps_params* params, const irtps_outputs* outputs,
+                        uint64_t* job_id);
+int irtps_server_poll(irtps_server* server, uint64_t job_id, irtps_job_status* status);
+/* Wait until the job finishes (timeout_s < 0: no limit); IRTPS_ERR_BUSY on timeout. */
+int irtps_server_wait(irtps_server* server, uint64_t job_id, double timeout_s,
+                      irtps_job_status* status);
+/* A queued job is dropped; a resident one stops at the next iteration boundary. */
+int irtps_server_cancel(irtps_server* server, uint64_t job_id);
+int irtps_server_stats(irtps_server* server, irtps_server_statistics* stats);
+/* Stops the scheduler (resident jobs are abandoned), waits for the device. */
+int irtps_server_destroy(irtps_server* server);
+
 /* ---- tuning ----------------------------------------------------------------- */
 /* Lanes of a 64-lane tracer wave that must hold a finished segment before the
  * wave shades (1..64; default 32).  It changes speed only, never results. */

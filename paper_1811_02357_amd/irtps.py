@@ -56,6 +56,25 @@ class Outputs(ct.Structure):
                 ("indirect_dev", _vp), ("counters_dev", _vp)]
 
 
+class ServerCfg(ct.Structure):
+    _fields_ = [("max_resident_jobs", _i32), ("dry_run", _i32), ("table_bytes", _u64),
+                ("reserved", _i32), ("reserved2", _i32)]
+
+
+class JobStatus(ct.Structure):
+    _fields_ = [("state", _i32), ("status", _i32), ("iteration", _i32), ("reserved", _i32),
+                ("submit_s", ct.c_double), ("start_s", ct.c_double), ("end_s", ct.c_double)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("failed", _u64), ("cancelled", _u64),
+                ("resident", _i32), ("queued", _i32), ("bytes_in_use", _u64), ("bytes_budget", _u64),
+                ("iterations", _u64), ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double),
+                ("jobs_per_s", ct.c_double)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = range(5)
+
 _LIB = None
 
 
@@ -91,6 +110,13 @@ def lib():
             "irtps_batch_workspace_bytes": [_i32, _vp, _vp, P(_sz)],
             "irtps_batch_solve": [_i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp],
             "irtps_set_ready_batch": [_i32],
+            "irtps_server_create": [P(ServerCfg), _vp, _sz, P(_vp)],
+            "irtps_server_submit": [_vp, P(Problem), P(Params), P(Outputs), P(_u64)],
+            "irtps_server_poll": [_vp, _u64, P(JobStatus)],
+            "irtps_server_wait": [_vp, _u64, ct.c_double, P(JobStatus)],
+            "irtps_server_cancel": [_vp, _u64],
+            "irtps_server_stats": [_vp, P(ServerStats)],
+            "irtps_server_destroy": [_vp],
             "irtps_get_ready_batch": [],
             "irtps_profile_begin": [],
             "irtps_profile_end": [P(ct.c_double), P(_i64)],
@@ -354,6 +380,73 @@ def batch_solve(jobs, graph=False, outs=None, workspace=None, stream=None):
         len(jobs), ct.cast(probs, ct.c_void_p), ct.cast(pars, ct.c_void_p), ct.cast(o, ct.c_void_p),
         BATCH_GRAPH if graph else 0, ct.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
     return outs
+
+
+class Server:
+    """Continuous-batching server over a device memory budget (irtps_server_*).
+    submit() takes the arguments of solve() as a dict and returns a job id; the
+    job's output tensors are returned by outputs(id) and are valid once wait(id)
+    reports JOB_DONE.  dry_run=True schedules without launching kernels."""
+
+    def __init__(self, budget_bytes, device=None, max_resident_jobs=0, dry_run=False, table_bytes=0):
+        self.device = device
+        self.ws = None
+        ptr = None
+        if not dry_run:
+            self.ws = torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
+            ptr = ct.c_void_p(self.ws.data_ptr())
+        cfg = ServerCfg(max_resident_jobs, 1 if dry_run else 0, table_bytes, 0, 0)
+        h = ct.c_void_p()
+        _check("irtps_server_create", lib().irtps_server_create(ct.byref(cfg), ptr, int(budget_bytes), ct.byref(h)))
+        self.h = h
+        self._jobs = {}
+
+    def submit(self, job, outs=None):
+        dev = job["images"].device
+        if outs is None:
+            outs = _outputs_for(job["images"], dev)
+        probs, pars, o, keep = _batch_structs([job], [outs])
+        # the server runs on a stream of its own: inputs and fresh outputs must be settled
+        torch.cuda.current_stream(dev).synchronize()
+        jid = _u64()
+        _check("irtps_server_submit", lib().irtps_server_submit(self.h, ct.byref(probs[0]), ct.byref(pars[0]),
+                                                                ct.byref(o[0]), ct.byref(jid)))
+        self._jobs[jid.value] = (job, outs)  # keeps the device buffers alive
+        return jid.value
+
+    def poll(self, jid):
+        st = JobStatus()
+        _check("irtps_server_poll", lib().irtps_server_poll(self.h, jid, ct.byref(st)))
+        return st
+
+    def wait(self, jid, timeout_s=-1.0):
+        st = JobStatus()
+        rc = lib().irtps_server_wait(self.h, jid, timeout_s, ct.byref(st))
+        if rc not in (OK, 8):
+            _check("irtps_server_wait", rc)
+        return st
+
+    def cancel(self, jid):
+        _check("irtps_server_cancel", lib().irtps_server_cancel(self.h, jid))
+
+    def outputs(self, jid):
+        return self._jobs[jid][1]
+
+    def stats(self):
+        st = ServerStats()
+        _check("irtps_server_stats", lib().irtps_server_stats(self.h, ct.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            _check("irtps_server_destroy", lib().irtps_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def set_ready_batch(lanes):

@@ -433,3 +433,35 @@ def test_batch_against_oracle(dev):
                       flags=job["flags"] & irtps.FLAG_LITERAL_CUMULATIVE)
         got = {kk: H(v) for kk, v in outs[k].items()}
         _compare_solve(ref, got, f"batch job {k}")
+
+
+# ---------------------------------------------------------------------------
+# Served mode: jobs that join and leave a running mix, each bit-identical to
+# its solve alone.
+def test_served_equals_alone(dev):
+    say("case: server with staggered submissions and a tight budget")
+    jobs = _batch_jobs(dev)
+    # budget for about three of the five jobs at once, so admission has to wait
+    sizes = sorted(irtps.workspace_bytes(**j) for j in jobs)
+    budget = (4 << 20) + sum(sizes[-3:]) + (1 << 20)
+    srv = irtps.Server(budget, device=dev, table_bytes=4 << 20)
+    try:
+        ids = []
+        for k, job in enumerate(jobs):
+            ids.append(srv.submit(job))
+            if k == 1:
+                srv.wait(ids[0], 60.0)  # later jobs join a mix already running
+        for jid in ids:
+            st = srv.wait(jid, 120.0)
+            assert st.state == irtps.JOB_DONE and st.status == 0, (jid, st.state, st.status)
+        torch.cuda.synchronize()
+        stats = srv.stats()
+        assert stats["completed"] == len(jobs) and stats["bytes_in_use"] == 0
+        for k, job in enumerate(jobs):
+            alone = irtps.solve(**job)
+            got = srv.outputs(ids[k])
+            for key in ("normals", "albedo", "depth", "indirect", "counters"):
+                assert np.array_equal(H(got[key]), H(alone[key])), (k, key)
+        say(f"  served == alone for every job; p50 {stats['p50_latency_s']:.3f}s p99 {stats['p99_latency_s']:.3f}s")
+    finally:
+        srv.close()
