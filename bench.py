@@ -15,6 +15,17 @@ Prints one JSON line.  `value` is traced gather segments (rays) per second of
 the whole job; the roofline object is for the tracer kernel, timed with HIP
 events around its launches inside the timed steps; `cpu_baseline` is the CPU
 oracle on a bounded sample of the same workload.
+
+Two more legs compare the multi-job modes with the plain per-job path on the
+same GPU (objects `batched` and `served`):
+- batched: 64 independent jobs (side log-uniform 128..1024, bowl / V-groove /
+  fBm, grey, K 6..20; 64 spp, 2 bounces, 4 iterations) run one at a time
+  through the plain solve and then as one batch replayed from a HIP graph;
+- served: the first jobs of a seeded Poisson arrival trace at 20 jobs/s (side
+  log-uniform 256..2048, RGB fBm, K 8..16; 128 spp, 2 bounces, 5 iterations)
+  replayed through a FIFO loop over the plain solve and through the
+  continuous-batching server; latency is arrival to completion.
+Both legs require every job's outputs to be bit-identical to the plain path.
 """
 import argparse
 import json
@@ -75,6 +86,130 @@ def cpu_baseline(sc, args):
                        f"C {sc.channels}): {seg} segments in {dt:.1f} s")}
 
 
+def _job(sc, dev, irtps, torch, np):
+    """Render one job's input images on the GPU and return solve() arguments."""
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    env = T(sc.env)
+    I0 = irtps.render(T(sc.heights), T(sc.normals), T(sc.albedo), sc.light_dirs, sc.light_intensity,
+                      env, sc.render_spp, sc.render_bounces, seed=sc.seed)
+    return dict(images=I0, light_dirs=sc.light_dirs, light_intensity=sc.light_intensity, env=env,
+                spp=sc.spp, bounces=sc.bounces, iterations=sc.iterations, seed=sc.seed)
+
+
+def _same(a, b, torch):
+    return all(torch.equal(a[k], b[k]) for k in ("normals", "albedo", "depth", "indirect", "counters"))
+
+
+def batched_leg(args, dev):
+    """64 jobs one at a time through the plain solve vs one batched solve."""
+    import numpy as np
+    import torch
+    from paper_1811_02357_amd import irtps, scenes
+    n = args.batched_jobs
+    log(f"bench: batched leg, generating {n} jobs")
+    jobs = [_job(scenes.batched_job(j), dev, irtps, torch, np) for j in range(n)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / 1e3
+
+    plain_outs = [irtps.solve(**j) for j in jobs]  # warm-up and reference outputs
+    torch.cuda.synchronize()
+    plain_t = []
+    for r in range(args.mode_reps):
+        outs, dt = timed(lambda: [irtps.solve(**j, out=o) for j, o in zip(jobs, plain_outs)])
+        plain_t.append(dt)
+    ws = torch.empty(irtps.batch_workspace_bytes(jobs), dtype=torch.uint8, device=dev)
+    bouts = [irtps._outputs_for(j["images"], dev) for j in jobs]
+    irtps.batch_solve(jobs, graph=True, outs=bouts, workspace=ws)  # warm-up, graph capture
+    torch.cuda.synchronize()
+    batch_t = []
+    for r in range(args.mode_reps):
+        _, dt = timed(lambda: irtps.batch_solve(jobs, graph=True, outs=bouts, workspace=ws))
+        batch_t.append(dt)
+    same = all(_same(a, b, torch) for a, b in zip(plain_outs, bouts))
+    seg = int(sum(int(o["counters"][0]) for o in plain_outs))
+    px = sum(int(j["images"].shape[2] * j["images"].shape[3]) for j in jobs)
+    tp, tb = float(np.median(plain_t)), float(np.median(batch_t))
+    log(f"bench: batched {tb * 1e3:.1f} ms vs plain {tp * 1e3:.1f} ms for {n} jobs")
+    return {"jobs": n, "pixels": px, "segments": seg, "equal_to_plain": bool(same),
+            "plain": {"s": tp, "rays_per_s": seg / tp, "reconstructions_per_s": n / tp,
+                      "p99_s": float(np.quantile(plain_t, 0.99))},
+            "batched": {"s": tb, "rays_per_s": seg / tb, "reconstructions_per_s": n / tb,
+                        "p99_s": float(np.quantile(batch_t, 0.99)), "graph": True,
+                        "ready_batch": irtps.get_ready_batch()},
+            "speedup": tp / tb, "repeats": args.mode_reps}
+
+
+def served_leg(args, dev):
+    """A truncated Poisson arrival trace through a FIFO loop over the plain
+    solve and through the continuous-batching server."""
+    import numpy as np
+    import torch
+    from paper_1811_02357_amd import irtps, scenes
+    arr = scenes.served_arrivals(20.0, 60.0, seed=0)[:args.served_jobs]
+    n = len(arr)
+    log(f"bench: served leg, generating {n} jobs")
+    jobs = [_job(scenes.served_job(j), dev, irtps, torch, np) for j in range(n)]
+    torch.cuda.synchronize()
+
+    def replay_plain():
+        outs, lat, done = [], [], 0.0
+        t0 = time.perf_counter()
+        for a, job in zip(arr, jobs):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            outs.append(irtps.solve(**job))
+            torch.cuda.synchronize()
+            done = time.perf_counter() - t0
+            lat.append(done - a)
+        return outs, np.asarray(lat), done - arr[0]
+
+    irtps.solve(**jobs[0])  # warm-up
+    torch.cuda.synchronize()
+    log("bench: served leg, FIFO over the plain solve")
+    plain_outs, plain_lat, plain_span = replay_plain()
+    seg = int(sum(int(o["counters"][0]) for o in plain_outs))
+
+    log("bench: served leg, continuous-batching server")
+    budget = int(args.served_budget_gib * (1 << 30))
+    srv = irtps.Server(budget, device=dev)
+    try:
+        ids = []
+        t0 = time.perf_counter()
+        for a, job in zip(arr, jobs):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            ids.append(srv.submit(job))
+        sts = [srv.wait(i, 600.0) for i in ids]
+        torch.cuda.synchronize()
+        ok = all(st.state == irtps.JOB_DONE for st in sts)
+        lat = np.asarray([st.end_s - st.submit_s for st in sts])
+        span = max(st.end_s for st in sts) - min(st.submit_s for st in sts)
+        same = ok and all(_same(a, srv.outputs(i), torch) for a, i in zip(plain_outs, ids))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    log(f"bench: served {span:.2f} s vs FIFO plain {plain_span:.2f} s for {n} jobs")
+
+    def summary(l, sp):
+        return {"jobs_per_s": n / sp, "rays_per_s": seg / sp, "p50_latency_s": float(np.quantile(l, 0.5)),
+                "p99_latency_s": float(np.quantile(l, 0.99)), "span_s": sp}
+    return {"jobs": n, "arrival_rate_per_s": 20.0, "offered_s": float(arr[-1]), "segments": seg,
+            "equal_to_plain": bool(same), "plain_fifo": summary(plain_lat, plain_span),
+            "served": dict(summary(lat, span), budget_gib=args.served_budget_gib,
+                           scheduler_iterations=int(stats["iterations"])),
+            "speedup": plain_span / span}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +219,14 @@ def main():
     ap.add_argument("--flat", action="store_true", help="walk every crossing (no pyramid skips)")
     ap.add_argument("--cpu-tile", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="all", choices=["all", "plain", "batched", "served"],
+                    help="plain: the main workload only; batched/served: the main workload and that leg")
+    ap.add_argument("--batched-jobs", type=int, default=64)
+    ap.add_argument("--served-jobs", type=int, default=24)
+    ap.add_argument("--served-budget-gib", type=float, default=96.0)
+    ap.add_argument("--mode-reps", type=int, default=3)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device to device three times (calibrates byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,6 +240,16 @@ def main():
     from paper_1811_02357_amd import irtps, scenes
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     log(f"bench: building scene {args.workload}")
     sc = scenes.fbm_terrain(seed=0, **wl)
@@ -163,6 +316,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
+    del ws, out, I0
+    torch.cuda.empty_cache()
+    if args.mode in ("all", "batched"):
+        line["batched"] = batched_leg(args, dev)
+        torch.cuda.empty_cache()
+    if args.mode in ("all", "served"):
+        line["served"] = served_leg(args, dev)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on a tile")
         line["cpu_baseline"] = cpu_baseline(sc, args)

@@ -43,6 +43,8 @@ __device__ __forceinline__ Surface make_surface(const float* H, const float* pyr
     S.lvl_off = s_off;
     S.W = W;
     S.Hh = Hh;
+    S.QW = trv::quad_cells(W);
+    S.QH = trv::quad_cells(Hh);
     S.top = levels - 1;
     S.hmax = pyr[s_off[S.top]];
     return S;
@@ -183,46 +185,61 @@ __device__ __forceinline__ void pyr_reduce_cell(int c, const float* __restrict__
     out[c] = m;
 }
 
-// Quadrant maxima: quad[q][y][x] = max of H over samples (x', y') with
-// (x' - x) sx >= 0 and (y' - y) sy >= 0, q = (sx < 0) + 2 (sy < 0).
-// Rows first: q0 <- suffix max along x, q1 <- prefix max along x.
-__device__ __forceinline__ void quad_row(int j, int W, int Hh, const float* __restrict__ H,
-                                         float* __restrict__ quad) {
-    const size_t plane = (size_t)W * Hh;
-    const float* row = H + (size_t)j * W;
-    float* suf = quad + (size_t)j * W;
-    float* pre = quad + plane + (size_t)j * W;
-    float m = row[W - 1];
-    for (int x = W - 1; x >= 0; --x) {
+// Quadrant maxima over 8 x 8 sample blocks: quad[q][by][bx] = max of H over
+// samples (x', y') with x' >= 8 bx (sx > 0) or x' <= 8 bx + 7 (sx < 0), and the
+// same along y, q = (sx < 0) + 2 (sy < 0).  Block maxima go to plane 3 first;
+// the rows then fill planes 0 (suffix along x) and 1 (prefix); the columns fill
+// planes 2 and 3 (prefix along y of planes 0 and 1) and finish 0 and 1
+// (suffix along y) in place.
+__device__ __forceinline__ void quad_block(int b, int W, int Hh, const float* __restrict__ H, int QW, int QH,
+                                           float* __restrict__ quad) {
+    const int bx = b % QW, by = b / QW;
+    const int x0 = bx << trv::kQuadShift, y0 = by << trv::kQuadShift;
+    const int x1 = min(x0 + (1 << trv::kQuadShift), W), y1 = min(y0 + (1 << trv::kQuadShift), Hh);
+    float m = H[(size_t)y0 * W + x0];
+    for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) {
+            const float v = H[(size_t)y * W + x];
+            m = v > m ? v : m;
+        }
+    quad[(size_t)3 * QW * QH + b] = m;
+}
+
+__device__ __forceinline__ void quad_row(int j, int QW, int QH, float* __restrict__ quad) {
+    const size_t plane = (size_t)QW * QH;
+    const float* row = quad + 3 * plane + (size_t)j * QW;
+    float* suf = quad + (size_t)j * QW;
+    float* pre = quad + plane + (size_t)j * QW;
+    float m = row[QW - 1];
+    for (int x = QW - 1; x >= 0; --x) {
         const float v = row[x];
         m = v > m ? v : m;
         suf[x] = m;
     }
     m = row[0];
-    for (int x = 0; x < W; ++x) {
+    for (int x = 0; x < QW; ++x) {
         const float v = row[x];
         m = v > m ? v : m;
         pre[x] = m;
     }
 }
 
-// Columns: q2 <- prefix along y of q0, q3 <- prefix of q1, then q0, q1 <- suffixes in place.
-__device__ __forceinline__ void quad_col(int i, int W, int Hh, float* __restrict__ quad) {
-    const size_t plane = (size_t)W * Hh;
+__device__ __forceinline__ void quad_col(int i, int QW, int QH, float* __restrict__ quad) {
+    const size_t plane = (size_t)QW * QH;
     for (int h = 0; h < 2; ++h) {
         float* src = quad + h * plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
         float* pre = quad + (h + 2) * plane;  // sy = -1
         float m = src[i];
-        for (int y = 0; y < Hh; ++y) {
-            const float v = src[(size_t)y * W + i];
+        for (int y = 0; y < QH; ++y) {
+            const float v = src[(size_t)y * QW + i];
             m = v > m ? v : m;
-            pre[(size_t)y * W + i] = m;
+            pre[(size_t)y * QW + i] = m;
         }
-        m = src[(size_t)(Hh - 1) * W + i];
-        for (int y = Hh - 1; y >= 0; --y) {
-            const float v = src[(size_t)y * W + i];
+        m = src[(size_t)(QH - 1) * QW + i];
+        for (int y = QH - 1; y >= 0; --y) {
+            const float v = src[(size_t)y * QW + i];
             m = v > m ? v : m;
-            src[(size_t)y * W + i] = m;
+            src[(size_t)y * QW + i] = m;
         }
     }
 }
@@ -553,15 +570,21 @@ __global__ void __launch_bounds__(256) k_pyr_reduce(const float* __restrict__ in
     pyr_reduce_cell(c, in, wi, hi, out, wo);
 }
 
-__global__ void __launch_bounds__(64) k_quad_rows(int W, int Hh, const float* __restrict__ H,
-                                                  float* __restrict__ quad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < Hh) quad_row(j, W, Hh, H, quad);
+__global__ void __launch_bounds__(256) k_quad_blocks(int W, int Hh, const float* __restrict__ H,
+                                                    float* __restrict__ quad) {
+    const int QW = trv::quad_cells(W), QH = trv::quad_cells(Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < QW * QH) quad_block(b, W, Hh, H, QW, QH, quad);
 }
 
-__global__ void __launch_bounds__(64) k_quad_cols(int W, int Hh, float* __restrict__ quad) {
+__global__ void __launch_bounds__(64) k_quad_rows(int QW, int QH, float* __restrict__ quad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < QH) quad_row(j, QW, QH, quad);
+}
+
+__global__ void __launch_bounds__(64) k_quad_cols(int QW, int QH, float* __restrict__ quad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < W) quad_col(i, W, Hh, quad);
+    if (i < QW) quad_col(i, QW, QH, quad);
 }
 
 __global__ void __launch_bounds__(256) k_mg_rhs(int W, int Hh, const float* __restrict__ n,
@@ -750,16 +773,25 @@ __global__ void __launch_bounds__(256) k_pyr_reduce_multi(const JobDesc* __restr
                     J.pyr_wc[l]);
 }
 
+__global__ void __launch_bounds__(256) k_quad_blocks_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && b < QW * QH) quad_block(b, J.W, J.Hh, J.depth, QW, QH, J.pyr + J.quad_off);
+}
+
 __global__ void __launch_bounds__(64) k_quad_rows_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (iterating(J) && j < J.Hh) quad_row(j, J.W, J.Hh, J.depth, J.pyr + J.quad_off);
+    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
+    if (iterating(J) && j < QH) quad_row(j, QW, QH, J.pyr + J.quad_off);
 }
 
 __global__ void __launch_bounds__(64) k_quad_cols_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (iterating(J) && i < J.W) quad_col(i, J.W, J.Hh, J.pyr + J.quad_off);
+    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
+    if (iterating(J) && i < QW) quad_col(i, QW, QH, J.pyr + J.quad_off);
 }
 
 __global__ void __launch_bounds__(256) k_mg_rhs_multi(const JobDesc* __restrict__ jobs, int cold) {
@@ -937,8 +969,10 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st) {
     float* quad = pyr + quad_off;
-    hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(Hh, 64)), dim3(64), 0, st, W, Hh, H, quad);
-    hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(W, 64)), dim3(64), 0, st, W, Hh, quad);
+    const int QW = trv::quad_cells(W), QH = trv::quad_cells(Hh);
+    hipLaunchKernelGGL(k_quad_blocks, dim3(blocks_for((long long)QW * QH, 256)), dim3(256), 0, st, W, Hh, H, quad);
+    hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(QH, 64)), dim3(64), 0, st, QW, QH, quad);
+    hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(QW, 64)), dim3(64), 0, st, QW, QH, quad);
     hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
                        st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
     for (int l = 1; l < P.levels; ++l)
@@ -1042,8 +1076,12 @@ hipError_t batch_ps(const JobDesc* jobs, const BatchShape& bs, int from_A, hipSt
 }
 
 hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t st) {
-    hipLaunchKernelGGL(k_quad_rows_multi, dim3(blocks_for(bs.max_rows, 64), bs.njobs), dim3(64), 0, st, jobs);
-    hipLaunchKernelGGL(k_quad_cols_multi, dim3(blocks_for(bs.max_cols, 64), bs.njobs), dim3(64), 0, st, jobs);
+    const long long qcells = (long long)trv::quad_cells(bs.max_cols) * trv::quad_cells(bs.max_rows);
+    hipLaunchKernelGGL(k_quad_blocks_multi, dim3(blocks_for(qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_quad_rows_multi, dim3(blocks_for(trv::quad_cells(bs.max_rows), 64), bs.njobs), dim3(64), 0,
+                       st, jobs);
+    hipLaunchKernelGGL(k_quad_cols_multi, dim3(blocks_for(trv::quad_cells(bs.max_cols), 64), bs.njobs), dim3(64), 0,
+                       st, jobs);
     hipLaunchKernelGGL(k_pyr0_multi, dim3(blocks_for(bs.max_pyr_cells[0], 256), bs.njobs), dim3(256), 0, st,
                        jobs);
     for (int l = 1; l < bs.max_pyr_levels; ++l)

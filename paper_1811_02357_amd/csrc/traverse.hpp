@@ -24,6 +24,9 @@ namespace irtps {
 namespace trv {
 
 constexpr int kMaxLevels = 16;
+// Quadrant maxima are kept per 2^kQuadShift x 2^kQuadShift block of samples.
+constexpr int kQuadShift = 3;
+__host__ __device__ inline int quad_cells(int n) { return (n + (1 << kQuadShift) - 1) >> kQuadShift; }
 
 // Apron-max pyramid.  Level l has cells (cx, cy), cx < wc[l], cy < hc[l];
 // cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l].
@@ -40,9 +43,10 @@ struct Pyramid {
 struct Surface {
     const float* H;      // [Hh][W]
     const float* pyr;    // apron maxima, levels concatenated; top level = global max
-    const float* quad;   // 4 quadrant maxima [q][Hh][W], q = (dx < 0) + 2 (dy < 0)
+    const float* quad;   // 4 quadrant maxima [q][QH][QW] over blocks, q = (dx < 0) + 2 (dy < 0)
     const int* lvl_off;  // LDS copy of the level offsets
     int W, Hh;
+    int QW, QH;          // blocks of the quadrant tables
     int top;             // index of the 1x1 level
     float hmax;
 };
@@ -173,12 +177,13 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             // Every sample a later crossing can read lies in the quadrant ahead of
             // the ray's position: at most one sample behind floor(x) going +x, two
             // ahead of it going -x (a lerp reads the next sample), and the nudge
-            // moves floor by at most one.  If the ray is not descending and is at
-            // or above the maximum of that quadrant, nothing ahead can hit.
+            // moves floor by at most one.  The table's block quadrant containing
+            // that corner covers it.  If the ray is not descending and is at or
+            // above the maximum there, nothing ahead can hit.
             const int qx = r.sx > 0 ? ix - 2 : (ix + 3 < S.W ? ix + 3 : S.W - 1);
             const int qy = r.sy > 0 ? iy - 2 : (iy + 3 < S.Hh ? iy + 3 : S.Hh - 1);
             const int quadrant = (r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0);
-            const float qmax = S.quad[(quadrant * S.Hh + qy) * S.W + qx];
+            const float qmax = S.quad[(quadrant * S.QH + (qy >> kQuadShift)) * S.QW + (qx >> kQuadShift)];
             const int cx = ix >> l;
             const int cy = iy >> l;
             const int X0 = cx << l, Y0 = cy << l;

@@ -352,15 +352,16 @@ def test_quadrant_maxima(dev):
     Hf = rng.uniform(-5, 5, (37, 53)).astype(F32)
     Hh, W = Hf.shape
     pyr = H(irtps.build_pyramid(T(Hf, dev)))
-    quad = pyr[pyr.size - 4 * W * Hh:].reshape(4, Hh, W)
+    QH, QW = (Hh + 7) // 8, (W + 7) // 8
+    quad = pyr[pyr.size - 4 * QW * QH:].reshape(4, QH, QW)
     for q in range(4):
         sx = -1 if q & 1 else 1
         sy = -1 if q & 2 else 1
-        for y in range(0, Hh, 5):
-            for x in range(0, W, 7):
-                xs = slice(x, W) if sx > 0 else slice(0, x + 1)
-                ys = slice(y, Hh) if sy > 0 else slice(0, y + 1)
-                assert quad[q, y, x] == Hf[ys, xs].max()
+        for by in range(QH):
+            for bx in range(QW):
+                xs = slice(8 * bx, W) if sx > 0 else slice(0, 8 * bx + 8)
+                ys = slice(8 * by, Hh) if sy > 0 else slice(0, 8 * by + 8)
+                assert quad[q, by, bx] == Hf[ys, xs].max(), (q, by, bx)
 
 
 # ---------------------------------------------------------------------------
