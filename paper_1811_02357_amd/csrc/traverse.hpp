@@ -123,8 +123,12 @@ __device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline,
     const float d_abs = xline ? fabsf(r.dx) : fabsf(r.dy);
     const float est = ceilf(t_lim * d_abs);
     int m = est > 2.0e9f ? 2000000000 : (est < 1.0f ? 1 : (int)est);
-    while (m > 1 && (xline ? t_x(r, m - 1) : t_y(r, m - 1)) >= t_lim) --m;
-    while ((xline ? t_x(r, m) : t_y(r, m)) < t_lim) ++m;
+    const float ainv = xline ? r.ainv_x : r.ainv_y;
+    // the estimate is almost always exact or one off: keep the loops rolled
+#pragma unroll 1
+    while (m > 1 && (float)(m - 1) * ainv >= t_lim) --m;
+#pragma unroll 1
+    while ((float)m * ainv < t_lim) ++m;
     return m;
 }
 
