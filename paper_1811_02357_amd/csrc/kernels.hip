@@ -90,22 +90,40 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
     n[3 * (size_t)p + 2] = nz;
 }
 
-// Eq.2 without albedo, with cast shadows: K any-hit walks from sample p.
+// Eq.2 without albedo, with cast shadows: K any-hit walks from sample p.  Each
+// lane runs through its own lights: when one shadow ray ends it starts the next
+// at once, so a wave waits for its slowest lane's total, not for the slowest
+// lane of every light in turn.
 __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* __restrict__ n, int K,
                                           const float* __restrict__ L, const float* __restrict__ s,
                                           bool flat, float* __restrict__ S_out) {
     const int i = p % S.W, j = p / S.W;
     const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
-    for (int k = 0; k < K; ++k) {
-        const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
-        const float c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
-        float v = 0.0f;
-        if (c > 0.0f) {
-            int qi, qj;
-            const bool blocked = trv::walk(S, flat, i, j, lx, ly, lz, qi, qj);
-            if (!blocked) v = s[k] * c;
+    float* __restrict__ out = S_out + (size_t)p * K;
+    int k = 0;
+    float c = 0.0f;
+    trv::Walker w;
+    // move to the next light facing the sample (the others give 0)
+    auto start = [&]() {
+        for (; k < K; ++k) {
+            const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
+            c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
+            if (c > 0.0f) {
+                trv::walker_init(w, S, i, j, lx, ly, lz, flat);
+                return;
+            }
+            out[k] = 0.0f;
         }
-        S_out[(size_t)p * K + k] = v;
+    };
+    start();
+    while (k < K) {
+        int qi, qj;
+        const int res = trv::walker_step(w, S, qi, qj);
+        if (res != trv::kGoOn) {
+            out[k] = res == trv::kHit ? 0.0f : s[k] * c;
+            ++k;
+            start();
+        }
     }
 }
 
@@ -384,7 +402,8 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     float eacc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) eacc[c] = 0.0f;
-    unsigned n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
+    // wave-wide event counts (uniform across the wave, so they live in SGPRs)
+    unsigned long long n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
 
     int M = 0;
     if (a.flags & kFlagQuadrature) {
@@ -400,11 +419,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     float beta[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) beta[c] = 1.0f;
-    int cp = p, ci = i, cj = j;  // sample the current segment starts from
+    int ci = i, cj = j;  // sample the current segment starts from
     trv::Walker w;
     bool need_setup = !finished;
 
     for (;;) {
+        n_seg += __popcll(__ballot(need_setup));
         if (need_setup) {
             float u1, u2;
             if (M > 0 && b == 1) {
@@ -416,9 +436,9 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                 u1 = dm::unit24(r.x);
                 u2 = dm::unit24(r.y);
             }
-            const dm::V3 d = dm::cosine_dir(a.n[3 * cp], a.n[3 * cp + 1], a.n[3 * cp + 2], u1, u2);
+            const float* nq = a.n + 3 * (cj * a.sa.W + ci);
+            const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
             trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
-            ++n_seg;
             need_setup = false;
             ready = false;
         }
@@ -434,6 +454,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             if (n_rdy >= (n_act < batch ? n_act : batch)) break;
         }
         // shading phase
+        {
+            const bool shade = !finished && ready;
+            n_esc += __popcll(__ballot(shade && res == trv::kMiss));
+            n_hit += __popcll(__ballot(shade && res != trv::kMiss));
+            n_cont += __popcll(__ballot(shade && res != trv::kMiss && b < a.B));
+        }
         if (!finished && ready) {
             bool next_sample = true;
             if (res == trv::kMiss) {
@@ -442,9 +468,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                 const float* L = a.env + (er * a.env_w + ec) * C;
 #pragma unroll
                 for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
-                ++n_esc;
             } else {
-                ++n_hit;
                 const int q = qj * a.sa.W + qi;
                 float wgt[C];
 #pragma unroll
@@ -456,10 +480,8 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                     for (int c = 0; c < C; ++c) gp[k * C + c] = fmaf(wgt[c], sq, gp[k * C + c]);
                 }
                 if (b < a.B) {
-                    ++n_cont;
 #pragma unroll
                     for (int c = 0; c < C; ++c) beta[c] = wgt[c];
-                    cp = q;
                     ci = qi;
                     cj = qj;
                     ++b;
@@ -471,7 +493,6 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                 b = 1;
 #pragma unroll
                 for (int c = 0; c < C; ++c) beta[c] = 1.0f;
-                cp = p;
                 ci = i;
                 cj = j;
                 finished = s >= a.spp;
@@ -486,21 +507,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
         }
     }
-    if (a.counters) {
-        // wave-level sums, one atomic per wave
-        unsigned long long v0 = n_seg, v1 = n_hit, v2 = n_esc, v3 = n_cont;
-        for (int o = 32; o > 0; o >>= 1) {
-            v0 += __shfl_xor(v0, o);
-            v1 += __shfl_xor(v1, o);
-            v2 += __shfl_xor(v2, o);
-            v3 += __shfl_xor(v3, o);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&a.counters[0], v0);
-            atomicAdd(&a.counters[1], v1);
-            atomicAdd(&a.counters[2], v2);
-            atomicAdd(&a.counters[3], v3);
-        }
+    if (a.counters && (threadIdx.x & 63) == 0) {
+        // one atomic per wave and counter
+        atomicAdd(&a.counters[0], n_seg);
+        atomicAdd(&a.counters[1], n_hit);
+        atomicAdd(&a.counters[2], n_esc);
+        atomicAdd(&a.counters[3], n_cont);
     }
 }
 
@@ -525,8 +537,12 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
     direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
 }
 
+// The tracer is issue- and latency-bound: ask for eight waves per SIMD (at most
+// 64 VGPRs), which measures faster than seven with more registers.
+#define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+
 template <int C>
-__global__ void __launch_bounds__(256) k_trace(TraceArgs a) {
+__global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
     __shared__ int s_off[trv::kMaxLevels];
     load_level_table(a.sa.off, s_off);
     const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
@@ -687,7 +703,7 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, i
 
 // Persistent tracer: each block takes (job, tile) pairs from a queue.
 template <int C>
-__global__ void __launch_bounds__(256) k_trace_multi(const JobDesc* __restrict__ jobs,
+__global__ void IRTPS_TRACER_OCCUPANCY k_trace_multi(const JobDesc* __restrict__ jobs,
                                                      const int2* __restrict__ tiles, int ntiles,
                                                      unsigned* queue, int tag, int ready_batch) {
     __shared__ int s_off[trv::kMaxLevels];
