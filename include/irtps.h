@@ -155,8 +155,9 @@ int irtps_integrate(int32_t W, int32_t H, const float* normals_dev,
 /* Bytes of the min-max pyramid of a W x H surface. */
 int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes);
 /* Per level l, cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l]
- * and stores the max over that box grown by one sample on each side; the top
- * level is the global maximum.  Four quadrant tables follow the levels, one per
+ * and stores the max over that box grown by one sample on each side, or +inf
+ * when the box comes within two samples of the border (cx 2^l < 2 or
+ * (cx+1) 2^l > W - 3, likewise in y).  Four quadrant tables follow the levels, one per
  * sign pair (sx, sy) of a ray's travel, q = (sx < 0) + 2 (sy < 0), each
  * ceil(H/8) x ceil(W/8): entry (by, bx) is the max over the samples (x, y) with
  * x >= 8 bx (sx > 0) or x <= 8 bx + 7 (sx < 0), and likewise along y. */

@@ -194,7 +194,10 @@ inline kern::SurfaceArgs surface(int W, int H, const float* depth, const float* 
     const trv::Pyramid P = pyramid_plan(W, H);
     sa.levels = P.levels;
     sa.quad_off = (int)pyramid_level_floats(P);
-    for (int l = 0; l < trv::kMaxLevels; ++l) sa.off[l] = l < P.levels ? (int)P.off[l] : 0;
+    for (int l = 0; l < trv::kMaxLevels; ++l) {
+        sa.off[l] = l < P.levels ? (int)P.off[l] : 0;
+        sa.wc[l] = l < P.levels ? P.wc[l] : 0;
+    }
     return sa;
 }
 

@@ -25,33 +25,34 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd * per + k;
 }
 
-// Every kernel that walks rays first copies the pyramid's level offsets to LDS
-// (constant indices only) and then builds its Surface view on that table.
-__device__ __forceinline__ void load_level_table(const int* off, int* s_off) {
+// Every kernel that walks rays first copies the pyramid's level table (offset
+// and cells per row) to LDS (constant indices only) and then builds its
+// Surface view on that table.
+__device__ __forceinline__ void load_level_table(const int* off, const int* wc, int2* s_lvl) {
 #pragma unroll
     for (int l = 0; l < trv::kMaxLevels; ++l)
-        if ((int)threadIdx.x == l) s_off[l] = off[l];
+        if ((int)threadIdx.x == l) s_lvl[l] = make_int2(off[l], wc[l]);
     __syncthreads();
 }
 
 __device__ __forceinline__ Surface make_surface(const float* H, const float* pyr, int W, int Hh,
-                                                int levels, int quad_off, const int* s_off) {
+                                                int levels, int quad_off, const int2* s_lvl) {
     Surface S;
     S.H = H;
     S.pyr = pyr;
     S.quad = pyr + quad_off;
-    S.lvl_off = s_off;
+    S.lvl = s_lvl;
     S.W = W;
     S.Hh = Hh;
     S.QW = trv::quad_cells(W);
     S.QH = trv::quad_cells(Hh);
     S.top = levels - 1;
-    S.hmax = pyr[s_off[S.top]];
+    S.hmax = S.quad[0];  // quadrant (+x, +y) of block (0, 0): every sample
     return S;
 }
 
-__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a, const int* s_off) {
-    return make_surface(a.H, a.pyr, a.W, a.Hh, a.levels, a.quad_off, s_off);
+__device__ __forceinline__ Surface make_surface(const SurfaceArgs& a, const int2* s_lvl) {
+    return make_surface(a.H, a.pyr, a.W, a.Hh, a.levels, a.quad_off, s_lvl);
 }
 
 // ===========================================================================
@@ -172,33 +173,36 @@ __device__ __forceinline__ void compose_px(int p, int npx, int K, const float* _
     }
 }
 
-// Apron-max pyramid, level 0: max over the 4 x 4 samples around cell (cx, cy).
+// Apron-max pyramid, level 0: max over the 4 x 4 samples around cell (cx, cy);
+// +inf for a cell that comes within two samples of the border (the walker never
+// skips those, so the escape test is always taken where the flat walk takes it).
 __device__ __forceinline__ void pyr0_cell(int c, int W, int Hh, int wc, const float* __restrict__ H,
                                           float* __restrict__ out) {
     const int cx = c % wc, cy = c / wc;
-    const int x0 = cx - 1 < 0 ? 0 : cx - 1, x1 = cx + 2 > W - 1 ? W - 1 : cx + 2;
-    const int y0 = cy - 1 < 0 ? 0 : cy - 1, y1 = cy + 2 > Hh - 1 ? Hh - 1 : cy + 2;
-    float m = H[(size_t)y0 * W + x0];
-    for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) {
+    if (cx < 2 || cx + 1 > W - 3 || cy < 2 || cy + 1 > Hh - 3) {
+        out[c] = __builtin_inff();
+        return;
+    }
+    float m = H[(size_t)(cy - 1) * W + cx - 1];
+    for (int y = cy - 1; y <= cy + 2; ++y)
+        for (int x = cx - 1; x <= cx + 2; ++x) {
             const float v = H[(size_t)y * W + x];
             m = v > m ? v : m;
         }
     out[c] = m;
 }
 
-// Level l+1 from level l: max of the (up to) four children.
+// Level l+1 from level l: max of the four children; +inf where one is missing
+// (the cell reaches past the border) or +inf (it touches the border margin).
 __device__ __forceinline__ void pyr_reduce_cell(int c, const float* __restrict__ in, int wi, int hi,
                                                 float* __restrict__ out, int wo) {
     const int cx = c % wo, cy = c / wo;
-    float m = in[(size_t)(2 * cy) * wi + 2 * cx];
+    float m = -__builtin_inff();
     for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx) {
             const int x = 2 * cx + dx, y = 2 * cy + dy;
-            if (x < wi && y < hi) {
-                const float v = in[(size_t)y * wi + x];
-                m = v > m ? v : m;
-            }
+            const float v = (x < wi && y < hi) ? in[(size_t)y * wi + x] : __builtin_inff();
+            m = v > m ? v : m;
         }
     out[c] = m;
 }
@@ -529,11 +533,11 @@ __global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, co
 
 __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
                                                 int flat, float* __restrict__ S_out) {
-    __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(sa.off, s_off);
+    __shared__ int2 s_lvl[trv::kMaxLevels];
+    load_level_table(sa.off, sa.wc, s_lvl);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= sa.W * sa.Hh) return;
-    const Surface S = make_surface(sa, s_off);
+    const Surface S = make_surface(sa, s_lvl);
     direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
 }
 
@@ -543,12 +547,12 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
 
 template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
-    __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(a.sa.off, s_off);
+    __shared__ int2 s_lvl[trv::kMaxLevels];
+    load_level_table(a.sa.off, a.sa.wc, s_lvl);
     const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= tiles) return;
-    const Surface S = make_surface(a.sa, s_off);
+    const Surface S = make_surface(a.sa, s_lvl);
     trace_tile<C>(a, S, tile);
 }
 
@@ -679,7 +683,10 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, i
     a.sa.levels = J.pyr_levels;
     a.sa.quad_off = J.quad_off;
 #pragma unroll
-    for (int l = 0; l < trv::kMaxLevels; ++l) a.sa.off[l] = J.pyr_off[l];
+    for (int l = 0; l < trv::kMaxLevels; ++l) {
+        a.sa.off[l] = J.pyr_off[l];
+        a.sa.wc[l] = J.pyr_wc[l];
+    }
     a.n = J.n;
     a.rho = J.rho;
     a.S = J.S;
@@ -706,7 +713,7 @@ template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace_multi(const JobDesc* __restrict__ jobs,
                                                      const int2* __restrict__ tiles, int ntiles,
                                                      unsigned* queue, int tag, int ready_batch) {
-    __shared__ int s_off[trv::kMaxLevels];
+    __shared__ int2 s_lvl[trv::kMaxLevels];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
@@ -718,10 +725,10 @@ __global__ void IRTPS_TRACER_OCCUPANCY k_trace_multi(const JobDesc* __restrict__
         const JobDesc& J = jobs[jt.x];
         if (!iterating(J)) continue;  // uniform per block; s_item was read above
         const TraceArgs a = job_trace_args(J, tag, ready_batch);
-        load_level_table(a.sa.off, s_off);
-        const Surface S = make_surface(a.sa, s_off);
+        load_level_table(a.sa.off, a.sa.wc, s_lvl);
+        const Surface S = make_surface(a.sa, s_lvl);
         trace_tile<C>(a, S, jt.y);
-        __syncthreads();  // s_off is reloaded for the next item
+        __syncthreads();  // s_lvl is reloaded for the next item
     }
 }
 
@@ -753,12 +760,12 @@ __global__ void __launch_bounds__(256) k_ps_multi(const JobDesc* __restrict__ jo
 }
 
 __global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict__ jobs) {
-    __shared__ int s_off[trv::kMaxLevels];
+    __shared__ int2 s_lvl[trv::kMaxLevels];
     const JobDesc& J = jobs[blockIdx.y];
-    load_level_table(J.pyr_off, s_off);
+    load_level_table(J.pyr_off, J.pyr_wc, s_lvl);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (!iterating(J) || p >= J.W * J.Hh) return;
-    const Surface S = make_surface(J.depth, J.pyr, J.W, J.Hh, J.pyr_levels, J.quad_off, s_off);
+    const Surface S = make_surface(J.depth, J.pyr, J.W, J.Hh, J.pyr_levels, J.quad_off, s_lvl);
     direct_px(S, p, J.n, J.K, &J.L[0][0], J.s, (J.flags & kFlagFlat) != 0, J.S);
 }
 
@@ -917,8 +924,8 @@ __global__ void k_probe_env(long long count, const float* d, int He, int We, int
 
 __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, const int* ij,
                                  const float* d, int* q) {
-    __shared__ int s_off[trv::kMaxLevels];
-    load_level_table(sa.off, s_off);
+    __shared__ int2 s_lvl[trv::kMaxLevels];
+    load_level_table(sa.off, sa.wc, s_lvl);
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= count) return;
     const int i0 = ij[2 * r], j0 = ij[2 * r + 1];
@@ -927,7 +934,7 @@ __global__ void k_probe_traverse(SurfaceArgs sa, int flat, long long count, cons
         q[2 * r + 1] = -2;
         return;
     }
-    const Surface S = make_surface(sa, s_off);
+    const Surface S = make_surface(sa, s_lvl);
     int qi = -1, qj = -1;
     const bool hit = trv::walk(S, flat != 0, i0, j0, d[3 * r], d[3 * r + 1], d[3 * r + 2], qi, qj);
     q[2 * r] = hit ? qi : -1;

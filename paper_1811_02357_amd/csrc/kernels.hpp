@@ -34,6 +34,7 @@ struct SurfaceArgs {
     int levels;
     int quad_off;      // floats from pyr to the quadrant tables
     int off[trv::kMaxLevels];
+    int wc[trv::kMaxLevels];  // cells per row of every level
 };
 
 struct TraceArgs {

@@ -38,41 +38,48 @@ struct Pyramid {
 };
 
 // A surface as one lane sees it.  Level l of the pyramid has
-// ceil((W-1)/2^l) x ceil((H-1)/2^l) cells stored from offset lvl_off[l]; the
-// offsets live in LDS so that a per-lane level index does not spill.
+// ceil((W-1)/2^l) x ceil((H-1)/2^l) cells stored from offset lvl[l].x with
+// lvl[l].y cells per row; the table lives in LDS so that a per-lane level
+// index does not spill.  Cells that come within two samples of the domain
+// border hold +inf (never skipped).
 struct Surface {
     const float* H;      // [Hh][W]
-    const float* pyr;    // apron maxima, levels concatenated; top level = global max
+    const float* pyr;    // apron maxima, levels concatenated
     const float* quad;   // 4 quadrant maxima [q][QH][QW] over blocks, q = (dx < 0) + 2 (dy < 0)
-    const int* lvl_off;  // LDS copy of the level offsets
+    const int2* lvl;     // LDS copy of (offset, cells per row) of every level
     int W, Hh;
     int QW, QH;          // blocks of the quadrant tables
     int top;             // index of the 1x1 level
-    float hmax;
+    float hmax;          // highest sample
 };
 
-__device__ __forceinline__ int level_cells_x(const Surface& S, int l) { return (S.W - 1 + (1 << l) - 1) >> l; }
-
-// Per-ray state shared by both walks.
+// Per-ray state shared by both walks.  The cell search uses the origin nudged
+// by kNudge along the travel direction (nx0, ny0); crossings use the exact
+// origin (i0, j0).
 struct Ray {
-    float ox, oy, oz, dx, dy, dz;
+    float nx0, ny0, oz, dx, dy, dz;
     float ainv_x, ainv_y;  // |1/dx|, |1/dy| (+inf for a zero component)
     int i0, j0, sx, sy;
 };
+
+// Cells are chosen at the ray's position nudged this far along the travel
+// direction, so that a ray sitting on a cell edge picks the cell ahead.  The
+// one-sample apron of every cell covers the nudge.
+constexpr float kNudge = 0.03125f;
 
 __device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float dx, float dy,
                                         float dz) {
     Ray r;
     r.i0 = i0;
     r.j0 = j0;
-    r.ox = (float)i0;
-    r.oy = (float)j0;
     r.oz = S.H[j0 * S.W + i0];
     r.dx = dx;
     r.dy = dy;
     r.dz = dz;
     r.sx = signbit(dx) ? -1 : 1;
     r.sy = signbit(dy) ? -1 : 1;
+    r.nx0 = (float)i0 + (float)r.sx * kNudge;
+    r.ny0 = (float)j0 + (float)r.sy * kNudge;
     r.ainv_x = fabsf(1.0f / dx);
     r.ainv_y = fabsf(1.0f / dy);
     return r;
@@ -92,7 +99,7 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
     const int n_major = xline ? S.W : S.Hh;
     const int n_minor = xline ? S.Hh : S.W;
     if (major < 0 || major > n_major - 1) return kMiss;
-    const float minor = fmaf(t, xline ? r.dy : r.dx, xline ? r.oy : r.ox);
+    const float minor = fmaf(t, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
     if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
     const int m0 = (int)floorf(minor);
     const float f = minor - (float)m0;
@@ -134,15 +141,11 @@ __device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline,
 
 // Finest pyramid level the walker tries to skip (cells of 4 x 4 sample gaps).
 constexpr int kMinSkipLevel = 2;
-// Cells are chosen at the ray's position nudged this far along the travel
-// direction, so that a ray sitting on a cell edge picks the cell ahead.  The
-// one-sample apron of every cell covers the nudge.
-constexpr float kNudge = 0.03125f;
-
 // Resumable walk.  Every crossing with t < t_cur has been evaluated or lies in
 // a skipped cell.  In fine mode (mx, my, tX, tY) name the next crossing of each
-// family; in coarse mode only t_cur is kept and the indices are rebuilt from it
-// when the walker drops to crossing evaluation.  level < 0 walks every crossing.
+// family; in coarse mode only t_cur (the exit of the last skipped cell) is kept
+// and both families are rebuilt from it when the walker drops to crossing
+// evaluation.  level < 0 walks every crossing.
 struct Walker {
     Ray r;
     float t_cur, tX, tY;
@@ -170,11 +173,12 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
     if (w.fine && isinf(w.tX) && isinf(w.tY)) return kMiss;
     const float t_now = w.fine ? (w.tX <= w.tY ? w.tX : w.tY) : w.t_cur;
     const float z_now = fmaf(t_now, r.dz, r.oz);
+    const bool rising = r.dz >= 0.0f;
     // at or above every sample and not descending: no crossing ahead can hit
-    if (z_now >= S.hmax && r.dz >= 0.0f) return kMiss;
+    if (z_now >= S.hmax && rising) return kMiss;
     if (w.level >= kMinSkipLevel) {
-        const float px = fmaf(t_now, r.dx, r.ox) + (float)r.sx * kNudge;
-        const float py = fmaf(t_now, r.dy, r.oy) + (float)r.sy * kNudge;
+        const float px = fmaf(t_now, r.dx, r.nx0);
+        const float py = fmaf(t_now, r.dy, r.ny0);
         if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
             const int l = w.level;
             const int ix = (int)px, iy = (int)py;  // px, py > 0: truncation is floor
@@ -190,21 +194,23 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             const float qmax = S.quad[(quadrant * S.QH + (qy >> kQuadShift)) * S.QW + (qx >> kQuadShift)];
             const int cx = ix >> l;
             const int cy = iy >> l;
-            const int X0 = cx << l, Y0 = cy << l;
-            const int X1 = X0 + (1 << l), Y1 = Y0 + (1 << l);
-            const bool interior = X0 >= 2 && Y0 >= 2 && X1 <= S.W - 3 && Y1 <= S.Hh - 3;
-            const float cmax = interior ? S.pyr[S.lvl_off[l] + cy * level_cells_x(S, l) + cx] : 0.0f;
+            const int2 lv = S.lvl[l];
+            const float cmax = S.pyr[lv.x + cy * lv.y + cx];  // +inf near the border
+            // both loads are issued before either result is tested (one wait)
+            __asm__ volatile("" : : "v"(qmax), "v"(cmax));
             // exit of the cell along the ray (computed while the loads are in flight)
-            const int mxe = ((r.sx > 0 ? X1 : X0) - r.i0) * r.sx;
-            const int mye = ((r.sy > 0 ? Y1 : Y0) - r.j0) * r.sy;
-            const float txe = mxe >= 1 ? t_x(r, mxe) : __builtin_inff();
-            const float tye = mye >= 1 ? t_y(r, mye) : __builtin_inff();
-            const float t_exit = txe < tye ? txe : tye;
+            const int size = 1 << l;
+            const int mxe = (cx << l) + (r.sx > 0 ? size : 0) - r.i0;
+            const int mye = (cy << l) + (r.sy > 0 ? size : 0) - r.j0;
+            const int mxa = r.sx > 0 ? mxe : -mxe, mya = r.sy > 0 ? mye : -mye;
+            const float txe = mxa >= 1 ? t_x(r, mxa) : __builtin_inff();
+            const float tye = mya >= 1 ? t_y(r, mya) : __builtin_inff();
+            const float t_exit = txe <= tye ? txe : tye;
             const float z_exit = fmaf(t_exit, r.dz, r.oz);
-            if (z_now >= qmax && r.dz >= 0.0f) return kMiss;
+            if (z_now >= qmax && rising) return kMiss;
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
             // the ray is at or above its maximum over that range
-            if (interior && z_now >= cmax && t_exit > t_now && !isinf(t_exit) && z_exit >= cmax) {
+            if (z_now >= cmax && t_exit > t_now && !isinf(t_exit) && z_exit >= cmax) {
                 w.t_cur = t_exit;
                 w.fine = false;
                 if (l < S.top) w.level = l + 1;
@@ -217,7 +223,8 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
         }
     }
     if (!w.fine) {
-        // back to crossing-by-crossing: the next crossings at or after t_cur
+        // back to crossing-by-crossing: each family's first crossing at or
+        // after t_cur
         if (!isinf(r.ainv_x)) {
             w.mx = first_index_at_or_after(r, true, w.t_cur);
             w.tX = t_x(r, w.mx);
