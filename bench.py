@@ -52,6 +52,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRACER_SOURCES = ("kernels.hip", "kernels.hpp", "traverse.hpp", "device_math.hpp")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_fbm2048_rgb_counters.md")
+
+
+def tracer_digest():
+    """sha256 over the tracer's sources: a byte-counter profile is only quoted
+    for the kernel it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRACER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1811_02357_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload):
+    """HBM bytes per tracer launch from the committed FETCH_SIZE / WRITE_SIZE
+    profile (copy-calibrated), or None when the profile is missing, is for
+    another workload, or was taken on other tracer sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
+        if kv.get("workload") != workload or kv.get("tracer_sources_sha256") != tracer_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def algorithmic_bytes(cnt, npx, K, C):
     """Bytes the gather must move per the tracer's yardstick: a hit reads the
     direct radiance of every light and channel at the hit sample (4 K C), a
@@ -314,7 +343,8 @@ def main():
         "trace_kernel": {"launches": launches, "avg_ms": per_launch_ms,
                          "share_of_step": trace_ms / sum(step_ms)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if args.flat else profiled_traffic(args.workload)},
     }
     del ws, out, I0
     torch.cuda.empty_cache()
