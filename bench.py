@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fbm2048_rgb", choices=sorted(WORKLOADS))
     ap.add_argument("--flat", action="store_true", help="walk every crossing (no pyramid skips)")
-    ap.add_argument("--cpu-tile", type=int, default=256)
+    ap.add_argument("--cpu-tile", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="all", choices=["all", "plain", "batched", "served"],
                     help="plain: the main workload only; batched/served: the main workload and that leg")
