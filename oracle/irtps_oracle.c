@@ -379,29 +379,141 @@ void or_ps_solve(int W, int Hh, int C, int K, const float* M, const float* A,
 /* Eq.2 at every sample without the albedo: the irradiance from light k, zero
  * where the sample faces away or a shadow ray towards the light hits the
  * surface. */
+static void direct_pixel(int W, int Hh, int K, const float* H, float hmax, const float* n,
+                         const float* l, const float* s, size_t p, float* out) {
+    const int i = (int)(p % W), j = (int)(p / W);
+    for (int k = 0; k < K; ++k) {
+        const float* lk = l + 3 * k;
+        const float c = fmaf(n[3 * p + 0], lk[0], fmaf(n[3 * p + 1], lk[1], n[3 * p + 2] * lk[2]));
+        float v = 0.0f;
+        if (c > 0.0f) {
+            int qi, qj;
+            const int blocked = or_traverse(H, W, Hh, hmax, i, j, lk, &qi, &qj);
+            if (!blocked) v = (s ? s[k] : 1.0f) * c;
+        }
+        out[k] = v;
+    }
+}
+
 void or_direct(int W, int Hh, int K, const float* H, const float* n,
                const float* l, const float* s, float* S) {
     const size_t npx = (size_t)W * Hh;
     const float hmax = max_height(H, npx);
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long long pp = 0; pp < (long long)npx; ++pp) {
-        const size_t p = (size_t)pp;
-        const int i = (int)(p % W), j = (int)(p / W);
-        for (int k = 0; k < K; ++k) {
-            const float* lk = l + 3 * k;
-            const float c = fmaf(n[3 * p + 0], lk[0], fmaf(n[3 * p + 1], lk[1], n[3 * p + 2] * lk[2]));
-            float v = 0.0f;
-            if (c > 0.0f) {
-                int qi, qj;
-                const int blocked = or_traverse(H, W, Hh, hmax, i, j, lk, &qi, &qj);
-                if (!blocked) v = (s ? s[k] : 1.0f) * c;
-            }
-            S[p * K + k] = v;
-        }
-    }
+    for (long long pp = 0; pp < (long long)npx; ++pp)
+        direct_pixel(W, Hh, K, H, hmax, n, l, s, (size_t)pp, S + (size_t)pp * K);
+}
+
+/* The same at the listed samples only: S_sel[m][k] for pixel index pix[m]. */
+void or_direct_at(int W, int Hh, int K, const float* H, const float* n,
+                  const float* l, const float* s, long long count, const long long* pix, float* S_sel) {
+    const float hmax = max_height(H, (size_t)W * Hh);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long long m = 0; m < count; ++m)
+        direct_pixel(W, Hh, K, H, hmax, n, l, s, (size_t)pix[m], S_sel + (size_t)m * K);
 }
 
 /* ------------------------------------------------------------------------- */
+/* Eq.5-7 with a cosine-weighted pdf: for a Lambertian surface each sample
+ * contributes pi times the incident radiance times the albedo.  A path from
+ * pixel p picks up, at each surface hit q, the Lambertian reflection of the
+ * direct irradiance there (albedo rho(q) times S[q][k]) weighted by the product
+ * of the albedos met before (the colour products of Fig. 5), and at an escape the
+ * environment radiance times pi.  Up to B segments per path; G is the mean over
+ * spp paths of the summed contributions. */
+typedef struct {
+    int W, Hh, C, K;
+    const float *H, *n, *rho, *S, *env;
+    int He, We, spp, B, t, tag, M;
+    float hmax;
+    uint32_t key[2];
+} trace_ctx;
+
+/* One pixel's gather: out[k][c] = mean over the spp paths; events added to ev. */
+static void trace_pixel(const trace_ctx* x, size_t p, float* out, uint64_t ev[4]) {
+    const int W = x->W, C = x->C, K = x->K, B = x->B, spp = x->spp, M = x->M;
+    const size_t npx = (size_t)W * x->Hh;
+    float hitacc[64 * 4];
+    float envacc[4];
+    float* acc = hitacc;
+    float* big = NULL;
+    if ((size_t)K * C > sizeof(hitacc) / sizeof(float)) {
+        big = (float*)malloc(sizeof(float) * (size_t)K * C);
+        acc = big;
+    }
+    for (int q = 0; q < K * C; ++q) acc[q] = 0.0f;
+    for (int c = 0; c < C; ++c) envacc[c] = 0.0f;
+    for (int smp = 0; smp < spp; ++smp) {
+        float beta[4];
+        for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+        int ci = (int)(p % W), cj = (int)(p / W);
+        const float* N = x->n + 3 * p;
+        for (int b = 1; b <= B; ++b) {
+            float u1, u2;
+            if (M > 0 && b == 1) {
+                const int sa = smp / M, sb = smp % M;
+                u1 = ((float)sa + 0.5f) / (float)M;
+                u2 = ((float)sb + 0.5f) / (float)M;
+            } else {
+                const uint32_t ctr[4] = {(uint32_t)p, (uint32_t)smp,
+                                         (uint32_t)x->t * 256u + (uint32_t)b, (uint32_t)x->tag};
+                uint32_t r[4];
+                or_philox4x32_10(ctr, x->key, r);
+                u1 = u24(r[0]);
+                u2 = u24(r[1]);
+            }
+            float d[3];
+            or_sample_cosine(N, u1, u2, d);
+            int qi, qj;
+            ++ev[0];
+            if (!or_traverse(x->H, W, x->Hh, x->hmax, ci, cj, d, &qi, &qj)) {
+                int er, ec;
+                or_env_texel(d, x->He, x->We, &er, &ec);
+                const float* L = x->env + ((size_t)er * x->We + ec) * C;
+                for (int c = 0; c < C; ++c) envacc[c] = fmaf(beta[c], OR_PI * L[c], envacc[c]);
+                ++ev[2];
+                break;
+            }
+            ++ev[1];
+            const size_t q = (size_t)qj * W + qi;
+            float w[4];
+            for (int c = 0; c < C; ++c) w[c] = beta[c] * x->rho[(size_t)c * npx + q];
+            for (int k = 0; k < K; ++k) {
+                const float sq = x->S[q * K + k];
+                for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(w[c], sq, acc[k * C + c]);
+            }
+            if (b < B) {
+                ++ev[3];
+                for (int c = 0; c < C; ++c) beta[c] = w[c];
+                ci = qi;
+                cj = qj;
+                N = x->n + 3 * q;
+            }
+        }
+    }
+    for (int k = 0; k < K; ++k)
+        for (int c = 0; c < C; ++c) out[k * C + c] = (acc[k * C + c] + envacc[c]) / (float)spp;
+    free(big);
+}
+
+static trace_ctx make_trace_ctx(int W, int Hh, int C, int K, const float* H, const float* n,
+                                const float* rho, const float* S, const float* env, int He, int We,
+                                int spp, int B, uint64_t seed, int t, int tag, int flags) {
+    trace_ctx x;
+    x.W = W; x.Hh = Hh; x.C = C; x.K = K;
+    x.H = H; x.n = n; x.rho = rho; x.S = S; x.env = env;
+    x.He = He; x.We = We; x.spp = spp; x.B = B; x.t = t; x.tag = tag;
+    x.hmax = max_height(H, (size_t)W * Hh);
+    x.key[0] = (uint32_t)seed;
+    x.key[1] = (uint32_t)(seed >> 32);
+    x.M = 0;
+    if (flags & OR_FLAG_QUADRATURE) {
+        x.M = 1;
+        while (x.M * x.M < spp) ++x.M;
+    }
+    return x;
+}
+
 /* Eq.5-7 with a cosine-weighted pdf: for a Lambertian surface each sample
  * contributes pi times the incident radiance times the albedo.  A path from
  * pixel p picks up, at each surface hit q, the Lambertian reflection of the
@@ -414,79 +526,51 @@ void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
               int spp, int B, uint64_t seed, int t, int tag, int flags,
               float* G, or_counters* cnt) {
     const size_t npx = (size_t)W * Hh;
-    const float hmax = max_height(H, npx);
-    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    int M = 0;
-    if (flags & OR_FLAG_QUADRATURE) {
-        M = 1;
-        while (M * M < spp) ++M;
-    }
+    const trace_ctx x = make_trace_ctx(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, tag, flags);
     uint64_t tot_seg = 0, tot_hit = 0, tot_esc = 0, tot_cont = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : tot_seg, tot_hit, tot_esc, tot_cont)
     for (long long pp = 0; pp < (long long)npx; ++pp) {
-        const size_t p = (size_t)pp;
-        float hitacc[64 * 4];
-        float envacc[4];
-        float* acc = hitacc;
+        float out[64 * 4];
+        float* o = out;
         float* big = NULL;
-        if ((size_t)K * C > sizeof(hitacc) / sizeof(float)) {
+        if ((size_t)K * C > sizeof(out) / sizeof(float)) {
             big = (float*)malloc(sizeof(float) * (size_t)K * C);
-            acc = big;
+            o = big;
         }
-        for (int x = 0; x < K * C; ++x) acc[x] = 0.0f;
-        for (int c = 0; c < C; ++c) envacc[c] = 0.0f;
-        for (int smp = 0; smp < spp; ++smp) {
-            float beta[4];
-            for (int c = 0; c < C; ++c) beta[c] = 1.0f;
-            int ci = (int)(p % W), cj = (int)(p / W);
-            const float* N = n + 3 * p;
-            for (int b = 1; b <= B; ++b) {
-                float u1, u2;
-                if (M > 0 && b == 1) {
-                    const int sa = smp / M, sb = smp % M;
-                    u1 = ((float)sa + 0.5f) / (float)M;
-                    u2 = ((float)sb + 0.5f) / (float)M;
-                } else {
-                    const uint32_t ctr[4] = {(uint32_t)p, (uint32_t)smp,
-                                             (uint32_t)t * 256u + (uint32_t)b, (uint32_t)tag};
-                    uint32_t r[4];
-                    or_philox4x32_10(ctr, key, r);
-                    u1 = u24(r[0]);
-                    u2 = u24(r[1]);
-                }
-                float d[3];
-                or_sample_cosine(N, u1, u2, d);
-                int qi, qj;
-                ++tot_seg;
-                if (!or_traverse(H, W, Hh, hmax, ci, cj, d, &qi, &qj)) {
-                    int er, ec;
-                    or_env_texel(d, He, We, &er, &ec);
-                    const float* L = env + ((size_t)er * We + ec) * C;
-                    for (int c = 0; c < C; ++c) envacc[c] = fmaf(beta[c], OR_PI * L[c], envacc[c]);
-                    ++tot_esc;
-                    break;
-                }
-                ++tot_hit;
-                const size_t q = (size_t)qj * W + qi;
-                float w[4];
-                for (int c = 0; c < C; ++c) w[c] = beta[c] * rho[(size_t)c * npx + q];
-                for (int k = 0; k < K; ++k) {
-                    const float sq = S[q * K + k];
-                    for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(w[c], sq, acc[k * C + c]);
-                }
-                if (b < B) {
-                    ++tot_cont;
-                    for (int c = 0; c < C; ++c) beta[c] = w[c];
-                    ci = qi;
-                    cj = qj;
-                    N = n + 3 * q;
-                }
-            }
-        }
+        uint64_t ev[4] = {0, 0, 0, 0};
+        trace_pixel(&x, (size_t)pp, o, ev);
         for (int k = 0; k < K; ++k)
-            for (int c = 0; c < C; ++c)
-                G[((size_t)k * C + c) * npx + p] = (acc[k * C + c] + envacc[c]) / (float)spp;
+            for (int c = 0; c < C; ++c) G[((size_t)k * C + c) * npx + (size_t)pp] = o[k * C + c];
+        tot_seg += ev[0];
+        tot_hit += ev[1];
+        tot_esc += ev[2];
+        tot_cont += ev[3];
         free(big);
+    }
+    if (cnt) {
+        cnt->v[0] += tot_seg;
+        cnt->v[1] += tot_hit;
+        cnt->v[2] += tot_esc;
+        cnt->v[3] += tot_cont;
+    }
+}
+
+/* The same gather at the listed pixels only: G_sel[m][k][c] for pixel pix[m];
+ * cnt (may be NULL) gets the events of those pixels. */
+void or_trace_at(int W, int Hh, int C, int K, const float* H, const float* n,
+                 const float* rho, const float* S, const float* env, int He, int We,
+                 int spp, int B, uint64_t seed, int t, int tag, int flags,
+                 long long count, const long long* pix, float* G_sel, or_counters* cnt) {
+    const trace_ctx x = make_trace_ctx(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, tag, flags);
+    uint64_t tot_seg = 0, tot_hit = 0, tot_esc = 0, tot_cont = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot_seg, tot_hit, tot_esc, tot_cont)
+    for (long long m = 0; m < count; ++m) {
+        uint64_t ev[4] = {0, 0, 0, 0};
+        trace_pixel(&x, (size_t)pix[m], G_sel + (size_t)m * K * C, ev);
+        tot_seg += ev[0];
+        tot_hit += ev[1];
+        tot_esc += ev[2];
+        tot_cont += ev[3];
     }
     if (cnt) {
         cnt->v[0] += tot_seg;

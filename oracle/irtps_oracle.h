@@ -76,6 +76,14 @@ void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
               const float* rho, const float* S, const float* env, int He, int We,
               int spp, int B, uint64_t seed, int t, int tag, int flags,
               float* G, or_counters* cnt);
+/* Pixel-subset forms (same per-pixel arithmetic) for checks at full image
+ * sizes: rows for the pixel indices pix[0..count). */
+void or_direct_at(int W, int Hh, int K, const float* H, const float* n,
+                  const float* l, const float* s, long long count, const long long* pix, float* S_sel);
+void or_trace_at(int W, int Hh, int C, int K, const float* H, const float* n,
+                 const float* rho, const float* S, const float* env, int He, int We,
+                 int spp, int B, uint64_t seed, int t, int tag, int flags,
+                 long long count, const long long* pix, float* G_sel, or_counters* cnt);
 
 /* Stage-5 subtraction: E = rho~ G, A_next = I0 - E (or A_prev - E). */
 void or_correct(int W, int Hh, int C, int K, int rho_mode, int flags,

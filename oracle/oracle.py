@@ -56,6 +56,10 @@ def lib():
         L.or_trace.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
                                + [ct.c_int] * 3 + [_f, ct.POINTER(Counters)])
         L.or_correct.argtypes = [ct.c_int] * 6 + [_f] * 7
+        _pll = ct.POINTER(ct.c_longlong)
+        L.or_direct_at.argtypes = [ct.c_int] * 3 + [_f] * 4 + [ct.c_longlong, _pll, _f]
+        L.or_trace_at.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
+                                  + [ct.c_int] * 3 + [ct.c_longlong, _pll, _f, ct.POINTER(Counters)])
         L.or_integrate.argtypes = [ct.c_int, ct.c_int, _f, _f, ct.c_int, _f]
         L.or_render.argtypes = ([ct.c_int] * 4 + [_f] * 6 + [ct.c_int] * 4 + [ct.c_uint64]
                                 + [_f, ct.POINTER(Counters)])
@@ -226,6 +230,40 @@ def trace(H, n, rho, S, env, spp, B, seed, t=0, tag=TAG_SOLVE, flags=0):
     lib().or_trace(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(S), _p(env), He, We, spp, B,
                    int(seed), t, tag, flags, _p(G), ct.byref(cnt))
     return G, cnt.as_dict()
+
+
+def _pix(pix):
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    return pix, pix.ctypes.data_as(ct.POINTER(ct.c_longlong))
+
+
+def direct_at(H, n, l, pix, s=None):
+    """S rows [len(pix)][K] at pixel indices pix (p = j W + i)."""
+    H, n, l = _f32(H), _f32(n), _f32(l)
+    Hh, W = H.shape
+    K = l.shape[0]
+    pix, pp = _pix(pix)
+    assert pix.min() >= 0 and pix.max() < W * Hh
+    out = np.zeros((pix.size, K), np.float32)
+    lib().or_direct_at(W, Hh, K, _p(H), _p(n), _p(l), _p(_f32(s)), pix.size, pp, _p(out))
+    return out
+
+
+def trace_at(H, n, rho, S, env, spp, B, seed, pix, t=0, tag=TAG_SOLVE, flags=0):
+    """G at pixel indices pix: [len(pix)][K][C], and those pixels' event counts."""
+    H, n, rho, S, env = map(_f32, (H, n, rho, S, env))
+    Hh, W = H.shape
+    C = rho.shape[0]
+    K = S.shape[2]
+    He, We = env.shape[0], env.shape[1]
+    assert env.shape[2] == C and C <= 4
+    pix, pp = _pix(pix)
+    assert pix.min() >= 0 and pix.max() < W * Hh
+    out = np.zeros((pix.size, K, C), np.float32)
+    cnt = Counters()
+    lib().or_trace_at(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(S), _p(env), He, We, spp, B,
+                      int(seed), t, tag, flags, pix.size, pp, _p(out), ct.byref(cnt))
+    return out, cnt.as_dict()
 
 
 def correct(I0, G, S, rho, rho_mode=RHO_FIT, flags=0, Aprev=None, want_E=True):

@@ -714,3 +714,19 @@ def test_gather_paths_rebuilt_from_the_estimator():
             ref[:, :, j, i] = ((hit_acc + env_acc[None, :]) / F32(spp)).astype(F32)
     assert segs == cnt["segments"]
     assert np.array_equal(G, ref)
+
+
+def test_subset_entry_points_match_full_stages():
+    """The pixel-subset forms are the full stages restricted to those pixels
+    (they exist so that GPU results at full image sizes can be checked on a
+    sample)."""
+    sc = scenes.tiny_scene(24, 20, seed=3, channels=3, num_lights=5)
+    S = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity)
+    pix = np.array([0, 5, 77, 479, 200, 23])
+    assert np.array_equal(O.direct_at(sc.heights, sc.normals, sc.light_dirs, pix, sc.light_intensity),
+                          S.reshape(-1, 5)[pix])
+    G, c = O.trace(sc.heights, sc.normals, sc.albedo, S, sc.env, 16, 3, 99, t=1)
+    Ga, _ = O.trace_at(sc.heights, sc.normals, sc.albedo, S, sc.env, 16, 3, 99, pix, t=1)
+    assert np.array_equal(Ga, G.reshape(5, 3, -1)[:, :, pix].transpose(2, 0, 1))
+    _, call = O.trace_at(sc.heights, sc.normals, sc.albedo, S, sc.env, 16, 3, 99, np.arange(480), t=1)
+    assert call == c
