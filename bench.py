@@ -172,7 +172,7 @@ def batched_leg(args, dev):
                       "p99_s": float(np.quantile(plain_t, 0.99))},
             "batched": {"s": tb, "rays_per_s": seg / tb, "reconstructions_per_s": n / tb,
                         "p99_s": float(np.quantile(batch_t, 0.99)), "graph": True,
-                        "ready_batch": irtps.get_ready_batch()},
+                        "tuned_classes": irtps.tuning_entries()},
             "speedup": tp / tb, "repeats": args.mode_reps}
 
 
@@ -335,7 +335,8 @@ def main():
         "config": {"workload": f"{args.workload}: {W}x{Hh} fBm terrain, C={C}, K={K} Fibonacci lights, "
                                f"env {sc.env.shape[0]}x{sc.env.shape[1]} log-normal",
                    "spp": sc.spp, "bounces": sc.bounces, "iterations": sc.iterations,
-                   "traversal": "flat" if args.flat else "pyramid"},
+                   "traversal": "flat" if args.flat else "pyramid",
+                   "schedule": irtps.get_schedule(W, Hh, C, K, sc.bounces)},
         "reconstructions_per_s": args.steps / (sum(step_ms) / 1e3),
         "p99_ms": float(np.quantile(step_ms, 0.99)),
         "segments_per_step": seg_per_step,

@@ -289,10 +289,48 @@ int irtps_server_stats(irtps_server* server, irtps_server_statistics* stats);
 int irtps_server_destroy(irtps_server* server);
 
 /* ---- tuning ----------------------------------------------------------------- */
-/* Lanes of a 64-lane tracer wave that must hold a finished segment before the
- * wave shades (1..64; default 32).  It changes speed only, never results. */
+/* The tracer's schedule: a 256-thread block traces a tile of tile_w x (256 /
+ * tile_w) pixels (tile_w 8, 16, 32 or 64), and a 64-lane wave shades once
+ * ready_batch of its lanes hold a finished segment.  A schedule changes speed
+ * only, never a result bit.  Every trace uses, field by field, the forced value
+ * (irtps_set_schedule), else the tuning table's entry for its class (device
+ * architecture, round(log2 sqrt(W H)), ceil(log2 K), C, B), else 16 x 16 tiles
+ * and 32 lanes. */
+typedef struct {
+    int32_t tile_w;
+    int32_t ready_batch;
+} irtps_schedule;
+
+#define IRTPS_TUNE_CANDIDATES 16
+
+/* Force tile_w and/or ready_batch for every later trace in the process; 0
+ * returns that field to the table / default.  Process-wide, thread-safe. */
+int irtps_set_schedule(int32_t tile_w, int32_t ready_batch);
+/* The schedule a trace of this class would use now. */
+int irtps_get_schedule(int32_t W, int32_t H, int32_t C, int32_t K, int32_t B, irtps_schedule* schedule);
+/* Shorthands for the ready_batch field (0..64; 0 = table / default); get
+ * returns the forced value or 0. */
 int irtps_set_ready_batch(int32_t lanes);
 int irtps_get_ready_batch(void);
+
+/* Autotuner: brings the problem to the state of its first traced iteration (PS
+ * of the images, integration, pyramid, direct light, written to outputs and the
+ * workspace) and times trace launches (the faster of two) for each of the IRTPS_TUNE_CANDIDATES
+ * schedules (tile_w in 8, 16, 32, 64 times ready_batch in 16, 24, 32, 48, in that
+ * order; ms_out, if not NULL, receives the times in milliseconds).  The fastest
+ * goes into the process's tuning table for the problem's class and to *best.
+ * Workspace as for irtps_solve (irtps_workspace_bytes); the call synchronises
+ * the stream. */
+int irtps_autotune(const irtps_problem* problem, const irtps_params* params, const irtps_outputs* outputs,
+                   void* ws_dev, size_t ws_bytes, void* stream, irtps_schedule* best, float* ms_out);
+/* The tuning table as JSON: {"arch": "<gcnArchName>", "entries": [{"side",
+ * "kcls", "C", "B", "tile_w", "ready_batch", "ms"}, ...]}.  Load merges the
+ * entries of a file written on the same architecture (a file for another
+ * architecture loads nothing and is not an error); *loaded gets the count. */
+int irtps_tuning_save(const char* path);
+int irtps_tuning_load(const char* path, int32_t* loaded);
+int irtps_tuning_clear(void);
+int irtps_tuning_entries(void);
 
 /* ---- timing of the tracer ------------------------------------------------ */
 /* irtps_profile_begin() makes this thread's later calls record a hipEvent pair

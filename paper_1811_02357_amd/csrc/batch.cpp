@@ -66,6 +66,9 @@ int fill_job(kern::JobDesc& J, const irtps_problem& pr, const irtps_params& pa, 
     J.key0 = (uint32_t)pa.seed;
     J.key1 = (uint32_t)(pa.seed >> 32);
     J.active = 1;
+    const Schedule sched = schedule_for(W, H, C, K, pa.bounces);
+    J.tile_shift = sched.tile_shift;
+    J.ready_batch = sched.ready_batch;
     const trv::Pyramid P = pyramid_plan(W, H);
     J.pyr_levels = P.levels;
     J.quad_off = (int)pyramid_level_floats(P);
@@ -99,6 +102,12 @@ size_t table_bytes(int n, int tiles) {
     return align_up(sizeof(kern::JobDesc) * (size_t)n) + align_up(sizeof(int2) * (size_t)tiles) + kAlign;
 }
 
+int max_tracer_tiles(int W, int H) {
+    int m = 0;
+    for (int shift = 3; shift <= 6; ++shift) m = std::max(m, kern::tiles_for(W, H, 1 << shift));
+    return m;
+}
+
 void Batch::build(const std::vector<kern::JobDesc>& js) {
     jobs = js;
     tiles1.clear();
@@ -114,7 +123,7 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
     for (int j : order) {
         const kern::JobDesc& J = jobs[j];
         if (!J.active || J.B < 1) continue;
-        const int tiles = ((J.W + 15) / 16) * ((J.Hh + 15) / 16);
+        const int tiles = kern::tiles_for(J.W, J.Hh, 1 << J.tile_shift);
         auto& list = J.C == 1 ? tiles1 : tiles3;
         for (int t = 0; t < tiles; ++t) list.push_back(make_int2(j, t));
     }
@@ -137,7 +146,8 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
     }
 }
 
-int Batch::place(char* table_dev) {
+int Batch::place(char* table_dev, size_t capacity) {
+    if (table_bytes((int)jobs.size(), (int)(tiles1.size() + tiles3.size())) > capacity) return IRTPS_ERR_WORKSPACE;
     d_jobs = reinterpret_cast<kern::JobDesc*>(table_dev);
     char* p = table_dev + align_up(sizeof(kern::JobDesc) * jobs.size());
     d_tiles1 = reinterpret_cast<int2*>(p);
@@ -164,13 +174,13 @@ int Batch::run_init(hipStream_t st) const {
     return IRTPS_OK;
 }
 
-int Batch::run_iteration(hipStream_t st, int ready_batch) const {
+int Batch::run_iteration(hipStream_t st) const {
     const int resident = resident_trace_blocks();
     HIP_TRY(kern::batch_pyramid(d_jobs, shape, st));
     HIP_TRY(kern::batch_direct(d_jobs, shape, st));
-    HIP_TRY(kern::trace_multi(d_jobs, 1, d_tiles1, (int)tiles1.size(), d_queue, IRTPS_TAG_SOLVE, ready_batch,
+    HIP_TRY(kern::trace_multi(d_jobs, 1, d_tiles1, (int)tiles1.size(), d_queue, IRTPS_TAG_SOLVE,
                               resident, st));
-    HIP_TRY(kern::trace_multi(d_jobs, 3, d_tiles3, (int)tiles3.size(), d_queue, IRTPS_TAG_SOLVE, ready_batch,
+    HIP_TRY(kern::trace_multi(d_jobs, 3, d_tiles3, (int)tiles3.size(), d_queue, IRTPS_TAG_SOLVE,
                               resident, st));
     HIP_TRY(kern::batch_correct(d_jobs, shape, 0, st));
     HIP_TRY(kern::batch_ps(d_jobs, shape, 1, st));
@@ -210,10 +220,10 @@ std::vector<char> graph_key(const Batch& b) {
 
 }  // namespace
 
-int Batch::run_all(hipStream_t st, bool use_graph, int ready_batch) {
+int Batch::run_all(hipStream_t st, bool use_graph) {
     auto launches = [&](hipStream_t s) -> int {
         STATUS_TRY(run_init(s));
-        for (int t = 0; t < max_T; ++t) STATUS_TRY(run_iteration(s, ready_batch));
+        for (int t = 0; t < max_T; ++t) STATUS_TRY(run_iteration(s));
         return IRTPS_OK;
     };
     (void)resident_trace_blocks();  // device queries stay outside any capture
@@ -263,7 +273,7 @@ int batch_layout(int32_t n, const irtps_problem* problems, size_t* tables, std::
     size_t tiles = 0;
     for (int j = 0; j < n; ++j) {
         if (!dims_ok(problems[j].width, problems[j].height)) return IRTPS_ERR_INVALID_ARG;
-        tiles += (size_t)((problems[j].width + 15) / 16) * ((problems[j].height + 15) / 16);
+        tiles += (size_t)eng::max_tracer_tiles(problems[j].width, problems[j].height);
     }
     *tables = eng::table_bytes(n, (int)tiles);
     size_t off = *tables;
@@ -305,10 +315,10 @@ int irtps_batch_solve(int32_t n, const irtps_problem* problems, const irtps_para
         STATUS_TRY(eng::fill_job(jobs[j], problems[j], params[j], outputs[j], base + offsets[j]));
     eng::Batch b;
     b.build(jobs);
-    b.place(base);
+    STATUS_TRY(b.place(base, tables));
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     STATUS_TRY(b.upload_tables(st));
-    return b.run_all(st, (options & IRTPS_BATCH_GRAPH) != 0, g_ready_batch);
+    return b.run_all(st, (options & IRTPS_BATCH_GRAPH) != 0);
 }
 
 }  // extern "C"

@@ -20,6 +20,9 @@ int fill_job(kern::JobDesc& J, const irtps_problem& pr, const irtps_params& pa, 
              char* region);
 // Device bytes of the tables of a batch of n jobs with `tiles` tracer tiles.
 size_t table_bytes(int n, int tiles);
+// Tracer tiles a W x H job can need under any schedule (table space is sized
+// for this, so a schedule change between sizing and solving cannot overflow).
+int max_tracer_tiles(int W, int H);
 
 struct Batch {
     std::vector<kern::JobDesc> jobs;
@@ -32,11 +35,12 @@ struct Batch {
     unsigned* d_queue = nullptr;
 
     void build(const std::vector<kern::JobDesc>& js);
-    int place(char* table_dev);         // carve the tables at table_dev (table_bytes)
+    // carve the tables at table_dev; IRTPS_ERR_WORKSPACE if they need more than capacity
+    int place(char* table_dev, size_t capacity);
     int upload_tables(hipStream_t st);  // job descriptors and tile lists
     int run_init(hipStream_t st) const;                    // t = 0: PS of I0, cold integration
-    int run_iteration(hipStream_t st, int ready_batch) const;  // one IRT iteration of every job
-    int run_all(hipStream_t st, bool use_graph, int ready_batch);
+    int run_iteration(hipStream_t st) const;  // one IRT iteration of every job
+    int run_all(hipStream_t st, bool use_graph);
 };
 
 }  // namespace eng

@@ -101,7 +101,9 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
         ta.key0 = (uint32_t)pa->seed;
         ta.key1 = (uint32_t)(pa->seed >> 32);
-        ta.ready_batch = g_ready_batch;
+        const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
+        ta.ready_batch = sched.ready_batch;
+        ta.tile_shift = sched.tile_shift;
         HIP_TRY(traced(ta, st));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
@@ -194,7 +196,9 @@ int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_d
     ta.flags = flags;
     ta.key0 = (uint32_t)seed;
     ta.key1 = (uint32_t)(seed >> 32);
-    ta.ready_batch = g_ready_batch;
+    const Schedule sched = schedule_for(W, H, C, K, B);
+    ta.ready_batch = sched.ready_batch;
+    ta.tile_shift = sched.tile_shift;
     HIP_TRY(traced(ta, reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
@@ -259,19 +263,15 @@ int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_
     ta.flags = 0;
     ta.key0 = (uint32_t)seed;
     ta.key1 = (uint32_t)(seed >> 32);
-    ta.ready_batch = g_ready_batch;
+    const Schedule sched = schedule_for(W, H, C, K, B);
+    ta.ready_batch = sched.ready_batch;
+    ta.tile_shift = sched.tile_shift;
     HIP_TRY(traced(ta, st));
     HIP_TRY(kern::compose((int)npx, C, K, albedo_dev, S, G, images_dev, st));
     return IRTPS_OK;
 }
 
-int irtps_set_ready_batch(int32_t lanes) {
-    if (lanes < 1 || lanes > 64) return IRTPS_ERR_INVALID_ARG;
-    g_ready_batch = lanes;
-    return IRTPS_OK;
-}
 
-int irtps_get_ready_batch(void) { return g_ready_batch; }
 
 int irtps_profile_begin(void) {
     for (auto& pr : g_prof.ev) {

@@ -37,9 +37,15 @@ inline int hip_fail(hipError_t e) {
 
 constexpr size_t kAlign = 256;
 
-// Lanes that must hold a finished segment before a tracer wave shades them
-// (set by the autotuner; any value gives the same bits).
-inline int g_ready_batch = 32;
+// The tracer's schedule: tile width 2^tile_shift and the lanes that must hold a
+// finished segment before a wave shades them.  Any schedule gives the same
+// bits.  Forced values (irtps_set_schedule) win over the tuning table, which
+// wins over the default 16 x 16 tiles, 32 lanes (tune.cpp).
+struct Schedule {
+    int tile_shift;
+    int ready_batch;
+};
+Schedule schedule_for(int W, int H, int C, int K, int B);
 
 // Event pairs around tracer launches while profiling is on (per thread).
 struct Profiler {

@@ -379,7 +379,7 @@ __device__ __forceinline__ void min_key_block(const float* __restrict__ X, int v
 
 // ---------------------------------------------------------------------------
 // Eq.5-7: per pixel, spp cosine-weighted paths of up to B segments, for one
-// 16 x 16 tile of pixels (one 256-thread block).
+// tile of 2^tile_shift x (256 >> tile_shift) pixels (one 256-thread block).
 // One lane owns one pixel.  Its K x C hit sums live in that pixel's row of the
 // pixel-major output G[p][k][c] (only this lane touches it); the C environment
 // sums stay in registers.  Each lane runs its own sequence of segments: the
@@ -389,9 +389,10 @@ __device__ __forceinline__ void min_key_block(const float* __restrict__ X, int v
 // ones.  A lane's segments are summed in (sample, bounce) order.
 template <int C>
 __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
-    const int tiles_x = (a.sa.W + 15) / 16;
-    const int i = (tile % tiles_x) * 16 + (threadIdx.x & 15);
-    const int j = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
+    const int tw = 1 << a.tile_shift;
+    const int tiles_x = (a.sa.W + tw - 1) >> a.tile_shift;
+    const int i = (tile % tiles_x) * tw + ((int)threadIdx.x & (tw - 1));
+    const int j = (tile / tiles_x) * (kTileThreads >> a.tile_shift) + ((int)threadIdx.x >> a.tile_shift);
     const bool live = i < a.sa.W && j < a.sa.Hh;
     const int npx = a.sa.W * a.sa.Hh;
     const int p = live ? j * a.sa.W + i : 0;
@@ -549,7 +550,7 @@ template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(a.sa.off, a.sa.wc, s_lvl);
-    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
+    const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= tiles) return;
     const Surface S = make_surface(a.sa, s_lvl);
@@ -674,7 +675,7 @@ __device__ __forceinline__ bool participates(const JobDesc& J, int init) {
     return init ? J.active != 0 : iterating(J);
 }
 
-__device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, int ready_batch) {
+__device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
     TraceArgs a;
     a.sa.H = J.depth;
     a.sa.pyr = J.pyr;
@@ -702,7 +703,8 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, i
     a.t = J.t;
     a.tag = tag;
     a.flags = J.flags & (kFlagQuadrature | kFlagFlat);
-    a.ready_batch = ready_batch;
+    a.ready_batch = J.ready_batch;
+    a.tile_shift = J.tile_shift;
     a.key0 = J.key0;
     a.key1 = J.key1;
     return a;
@@ -712,7 +714,7 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag, i
 template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace_multi(const JobDesc* __restrict__ jobs,
                                                      const int2* __restrict__ tiles, int ntiles,
-                                                     unsigned* queue, int tag, int ready_batch) {
+                                                     unsigned* queue, int tag) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     __shared__ int s_item;
     for (;;) {
@@ -724,7 +726,7 @@ __global__ void IRTPS_TRACER_OCCUPANCY k_trace_multi(const JobDesc* __restrict__
         const int2 jt = tiles[item];
         const JobDesc& J = jobs[jt.x];
         if (!iterating(J)) continue;  // uniform per block; s_item was read above
-        const TraceArgs a = job_trace_args(J, tag, ready_batch);
+        const TraceArgs a = job_trace_args(J, tag);
         load_level_table(a.sa.off, a.sa.wc, s_lvl);
         const Surface S = make_surface(a.sa, s_lvl);
         trace_tile<C>(a, S, jt.y);
@@ -961,7 +963,7 @@ hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int 
 }
 
 hipError_t trace(TraceArgs a, hipStream_t st) {
-    const int tiles = ((a.sa.W + 15) / 16) * ((a.sa.Hh + 15) / 16);
+    const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
     const int grid = (tiles + 7) / 8 * 8;
     if (a.C == 1) hipLaunchKernelGGL(k_trace<1>, dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_trace<3>, dim3(grid), dim3(256), 0, st, a);
@@ -1066,18 +1068,16 @@ hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st) {
 
 // ---- multi-job ----
 hipError_t trace_multi(const JobDesc* jobs, int C, const int2* tiles, int ntiles, unsigned* queue,
-                       int tag, int ready_batch, int resident_blocks, hipStream_t st) {
+                       int tag, int resident_blocks, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, queue, 0u, 1);
     // enough resident blocks to fill every CU several times over; the queue balances them
     int grid = resident_blocks;
     if (grid > ntiles) grid = ntiles;
     if (C == 1)
-        hipLaunchKernelGGL(k_trace_multi<1>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag,
-                           ready_batch);
+        hipLaunchKernelGGL(k_trace_multi<1>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag);
     else
-        hipLaunchKernelGGL(k_trace_multi<3>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag,
-                           ready_batch);
+        hipLaunchKernelGGL(k_trace_multi<3>, dim3(grid), dim3(256), 0, st, jobs, tiles, ntiles, queue, tag);
     return hipGetLastError();
 }
 

@@ -10,6 +10,13 @@ namespace irtps {
 namespace kern {
 
 constexpr int kMaxLights = 64;
+// Tracer tiles: one 256-thread block covers tile_w x (256 / tile_w) pixels.
+constexpr int kTileThreads = 256;
+__host__ __device__ inline int tile_rows(int tile_w) { return kTileThreads / tile_w; }
+__host__ __device__ inline int tiles_for(int W, int H, int tile_w) {
+    const int th = tile_rows(tile_w);
+    return ((W + tile_w - 1) / tile_w) * ((H + th - 1) / th);
+}
 constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
@@ -49,6 +56,7 @@ struct TraceArgs {
     int C, K;
     int spp, B, t, tag, flags;
     int ready_batch;   // lanes that must have a result before the wave shades
+    int tile_shift;    // tile width 2^tile_shift (8..64 pixels), 256 / width rows
     uint32_t key0, key1;
 };
 
@@ -68,6 +76,7 @@ struct JobDesc {
     int rho_mode, flags, cycles_cold, cycles_warm;
     uint32_t key0, key1;
     int active;         // 0: skipped by every multi-job kernel
+    int tile_shift, ready_batch;  // the tracer's schedule for this job
     int pyr_levels, quad_off;
     int pyr_wc[trv::kMaxLevels], pyr_hc[trv::kMaxLevels], pyr_off[trv::kMaxLevels];
     MgPlan mg;
@@ -122,7 +131,7 @@ hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st);
 // ---- multi-job launches: grid.y walks the job table, the tracer a tile queue ----
 // Persistent tracer over (job, tile) pairs; `queue` (one uint32) is cleared here.
 hipError_t trace_multi(const JobDesc* jobs, int C, const int2* tiles, int ntiles, unsigned* queue,
-                       int tag, int ready_batch, int resident_blocks, hipStream_t st);
+                       int tag, int resident_blocks, hipStream_t st);
 // t = 0, counters and E cleared.
 hipError_t batch_begin(const JobDesc* jobs, const BatchShape& bs, hipStream_t st);
 hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t st);

@@ -227,17 +227,17 @@ bool irtps_server::step() {
         if (!fresh.empty()) {
             eng::Batch b;
             b.build(fresh);
-            b.place(base);
-            rc = b.upload_tables(stream);
+            rc = b.place(base, table_bytes);
+            if (rc == IRTPS_OK) rc = b.upload_tables(stream);
             if (rc == IRTPS_OK) rc = b.run_init(stream);
         }
         // jobs admitted this round also run their first iteration now
         if (rc == IRTPS_OK && !running.empty()) {
             eng::Batch b;
             b.build(running);
-            b.place(base);
-            rc = b.upload_tables(stream);
-            if (rc == IRTPS_OK) rc = b.run_iteration(stream, g_ready_batch);
+            rc = b.place(base, table_bytes);
+            if (rc == IRTPS_OK) rc = b.upload_tables(stream);
+            if (rc == IRTPS_OK) rc = b.run_iteration(stream);
         }
         if (rc == IRTPS_OK) {
             const hipError_t e = hipStreamSynchronize(stream);
@@ -324,7 +324,7 @@ int irtps_server_submit(irtps_server* s, const irtps_problem* problem, const irt
         STATUS_TRY(make_psmatrix(K, J.pr.light_dirs_host, J.pr.light_intensity_host, M));
     }
     J.bytes = align_up(eng::job_region_bytes(J.pr));
-    J.tiles = ((problem->width + 15) / 16) * ((problem->height + 15) / 16);
+    J.tiles = eng::max_tracer_tiles(problem->width, problem->height);
     // a job that could never be resident, even alone, is refused now
     if (J.bytes > s->pool_bytes || eng::table_bytes(1, J.tiles) > s->table_bytes) return IRTPS_ERR_OOM;
     std::lock_guard<std::mutex> lock(s->mu);

@@ -9,6 +9,7 @@ fallback path.
 from __future__ import annotations
 
 import ctypes as ct
+import glob
 import os
 
 import numpy as np
@@ -54,6 +55,13 @@ class Params(ct.Structure):
 class Outputs(ct.Structure):
     _fields_ = [("normals_dev", _vp), ("albedo_dev", _vp), ("depth_dev", _vp),
                 ("indirect_dev", _vp), ("counters_dev", _vp)]
+
+
+class Schedule(ct.Structure):
+    _fields_ = [("tile_w", _i32), ("ready_batch", _i32)]
+
+
+TUNE_CANDIDATES = 16
 
 
 class ServerCfg(ct.Structure):
@@ -110,6 +118,11 @@ def lib():
             "irtps_batch_workspace_bytes": [_i32, _vp, _vp, P(_sz)],
             "irtps_batch_solve": [_i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp],
             "irtps_set_ready_batch": [_i32],
+            "irtps_set_schedule": [_i32, _i32],
+            "irtps_get_schedule": [_i32] * 5 + [P(Schedule)],
+            "irtps_autotune": [P(Problem), P(Params), P(Outputs), _vp, _sz, _vp, P(Schedule), P(ct.c_float)],
+            "irtps_tuning_save": [ct.c_char_p],
+            "irtps_tuning_load": [ct.c_char_p, P(_i32)],
             "irtps_server_create": [P(ServerCfg), _vp, _sz, P(_vp)],
             "irtps_server_submit": [_vp, P(Problem), P(Params), P(Outputs), P(_u64)],
             "irtps_server_poll": [_vp, _u64, P(JobStatus)],
@@ -130,6 +143,7 @@ def lib():
             fn.argtypes = args
             fn.restype = ct.c_int
         _LIB = L
+        load_shipped_tuning()
     return _LIB
 
 
@@ -450,11 +464,70 @@ class Server:
 
 
 def set_ready_batch(lanes):
+    """Force the tracer's rays-per-wave batch (0: tuning table / default)."""
     _check("irtps_set_ready_batch", lib().irtps_set_ready_batch(lanes))
 
 
 def get_ready_batch():
     return lib().irtps_get_ready_batch()
+
+
+def set_schedule(tile_w=0, ready_batch=0):
+    """Force the tracer's tile width and/or rays-per-wave batch (0: automatic)."""
+    _check("irtps_set_schedule", lib().irtps_set_schedule(tile_w, ready_batch))
+
+
+def get_schedule(W, H, C, K, B):
+    sc = Schedule()
+    _check("irtps_get_schedule", lib().irtps_get_schedule(W, H, C, K, B, ct.byref(sc)))
+    return {"tile_w": sc.tile_w, "ready_batch": sc.ready_batch}
+
+
+def autotune(job, outs=None, workspace=None, stream=None):
+    """Time the tracer's schedules on this job (arguments of solve()); the fastest
+    enters the process's tuning table.  Returns (best, {(tile_w, ready_batch): ms})."""
+    dev = job["images"].device
+    if outs is None:
+        outs = _outputs_for(job["images"], dev)
+    probs, pars, o, keep = _batch_structs([job], [outs])
+    if workspace is None:
+        workspace = _alloc_ws(workspace_bytes(**job), dev)
+    best = Schedule()
+    ms = (ct.c_float * TUNE_CANDIDATES)()
+    _check("irtps_autotune", lib().irtps_autotune(ct.byref(probs[0]), ct.byref(pars[0]), ct.byref(o[0]),
+                                                  ct.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                                  _stream(stream), ct.byref(best), ms))
+    cands = [(tw, rb) for tw in (8, 16, 32, 64) for rb in (16, 24, 32, 48)]
+    return {"tile_w": best.tile_w, "ready_batch": best.ready_batch}, dict(zip(cands, list(ms)))
+
+
+def tuning_save(path):
+    _check("irtps_tuning_save", lib().irtps_tuning_save(str(path).encode()))
+
+
+def tuning_load(path):
+    n = _i32()
+    _check("irtps_tuning_load", lib().irtps_tuning_load(str(path).encode(), ct.byref(n)))
+    return n.value
+
+
+def load_shipped_tuning():
+    """Merge the tuning tables shipped next to the library; only the one written
+    on this device's architecture loads.  Returns the entries loaded."""
+    total = 0
+    for f in sorted(glob.glob(os.path.join(os.path.dirname(LIB_PATH), "tuning_*.json"))):
+        n = _i32()
+        if lib().irtps_tuning_load(f.encode(), ct.byref(n)) == OK:
+            total += n.value
+    return total
+
+
+def tuning_clear():
+    _check("irtps_tuning_clear", lib().irtps_tuning_clear())
+
+
+def tuning_entries():
+    return lib().irtps_tuning_entries()
 
 
 def profile_begin():

@@ -412,17 +412,64 @@ def test_batch_graph_and_ready_batch_invariance(dev):
             for k in range(len(jobs)):
                 for key in ("normals", "albedo", "depth", "indirect", "counters"):
                     assert np.array_equal(H(outs[k][key]), ref[k][key]), (rep, k, key)
-    old = irtps.get_ready_batch()
     try:
-        for lanes in (8, 64):
-            irtps.set_ready_batch(lanes)
+        for tile_w, lanes in ((16, 8), (16, 64), (8, 24), (64, 48), (32, 1)):
+            irtps.set_schedule(tile_w, lanes)
             outs = irtps.batch_solve(jobs)
             for k in range(len(jobs)):
-                assert np.array_equal(H(outs[k]["indirect"]), ref[k]["indirect"]), (lanes, k)
+                assert np.array_equal(H(outs[k]["indirect"]), ref[k]["indirect"]), (tile_w, lanes, k)
+                assert np.array_equal(H(outs[k]["counters"]), ref[k]["counters"]), (tile_w, lanes, k)
             alone = irtps.solve(**jobs[0])
             assert np.array_equal(H(alone["normals"]), ref[0]["normals"])
     finally:
-        irtps.set_ready_batch(old)
+        irtps.set_schedule(0, 0)
+
+
+def test_batch_tables_fit_every_tile_shape(dev):
+    """A 129 x 129 job needs 81 tiles of 16 x 16 but 99 of 64 x 4: the batch's
+    tables are sized for the largest count any schedule can need."""
+    say("case: batch of 129^2 jobs under 64-wide and 8-wide tiles")
+    jobs = []
+    for k in range(3):
+        sc = scenes.fbm_terrain(seed=20 + k, size=129, channels=1 + 2 * (k == 1), num_lights=7 + k,
+                                env_shape=(8, 16), ptp=16.0)
+        I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 4, 1,
+                         seed=k)
+        jobs.append(dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+                         env=T(sc.env, dev), spp=4, bounces=2, iterations=2, seed=50 + k))
+    ref = [{k: H(v) for k, v in irtps.solve(**j).items()} for j in jobs]
+    try:
+        for tile_w in (64, 8):
+            irtps.set_schedule(tile_w, 0)
+            outs = irtps.batch_solve(jobs)
+            for k in range(len(jobs)):
+                for key in ("normals", "depth", "indirect", "counters"):
+                    assert np.array_equal(H(outs[k][key]), ref[k][key]), (tile_w, k, key)
+    finally:
+        irtps.set_schedule(0, 0)
+
+
+def test_autotune_picks_a_schedule_and_changes_no_bits(dev):
+    say("case: autotuner on one job, then solves under the tuned and forced schedules")
+    jobs = _batch_jobs(dev)
+    job = jobs[1]
+    ref = {k: H(v) for k, v in irtps.solve(**job).items()}
+    irtps.tuning_clear()
+    try:
+        best, ms = irtps.autotune(job)
+        say(f"  best {best}; times {({k: round(v, 3) for k, v in ms.items()})}")
+        assert best["tile_w"] in (8, 16, 32, 64) and best["ready_batch"] in (16, 24, 32, 48)
+        assert len(ms) == irtps.TUNE_CANDIDATES and all(v > 0 for v in ms.values())
+        assert ms[(best["tile_w"], best["ready_batch"])] == min(ms.values())
+        K, C, Hh, W = job["images"].shape
+        assert irtps.get_schedule(W, Hh, C, K, job["bounces"]) == best
+        assert irtps.tuning_entries() == 1
+        got = irtps.solve(**job)
+        for key in ("normals", "albedo", "depth", "indirect", "counters"):
+            assert np.array_equal(H(got[key]), ref[key]), key
+    finally:
+        irtps.tuning_clear()
+        irtps.load_shipped_tuning()
 
 
 def test_batch_against_oracle(dev):
