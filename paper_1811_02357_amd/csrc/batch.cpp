@@ -142,6 +142,8 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
         shape.max_cycles_cold = std::max(shape.max_cycles_cold, J.cycles_cold);
         shape.max_cycles_warm = std::max(shape.max_cycles_warm, J.cycles_warm);
         shape.max_KCnpx = std::max(shape.max_KCnpx, J.K * J.C * J.W * J.Hh);
+        if (J.C == 1) shape.max_K1 = std::max(shape.max_K1, J.K);
+        else shape.max_K3 = std::max(shape.max_K3, J.K);
         max_T = std::max(max_T, J.T);
     }
 }

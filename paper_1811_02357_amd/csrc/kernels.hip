@@ -128,11 +128,12 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     }
 }
 
-// Stage 5 (G is pixel-major [p][k][c], images and E are [k][c][p]).
+// Stage 5 for one pixel p: Grow[k C + c] and Srow[k] are that pixel's gathered
+// and direct values (images and E are [k][c][p]).
 template <int C>
 __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, int cumulative,
                                            const float* __restrict__ I0, const float* __restrict__ Aprev,
-                                           const float* __restrict__ G, const float* __restrict__ S,
+                                           const float* Grow, const float* Srow,
                                            const float* __restrict__ rho, float* __restrict__ E,
                                            float* __restrict__ Anext) {
 #pragma unroll
@@ -142,7 +143,7 @@ __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, 
             float num = 0.0f, den = 0.0f;
             for (int k = 0; k < K; ++k) {
                 const size_t x = ((size_t)k * C + c) * npx + p;
-                const float v = S[(size_t)p * K + k] + G[((size_t)p * K + k) * C + c];
+                const float v = Srow[k] + Grow[k * C + c];
                 num = fmaf(I0[x], v, num);
                 den = fmaf(v, v, den);
             }
@@ -152,12 +153,26 @@ __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, 
         }
         for (int k = 0; k < K; ++k) {
             const size_t x = ((size_t)k * C + c) * npx + p;
-            const float e = rt * G[((size_t)p * K + k) * C + c];
+            const float e = rt * Grow[k * C + c];
             if (E) E[x] = e;
             Anext[x] = (cumulative ? Aprev[x] : I0[x]) - e;
         }
     }
 }
+
+// Rows of a pixel-major array (w floats per pixel, rows r0.. r0+n-1 contiguous
+// from src) into LDS with a row stride of w + 1 (odd: lanes reading their own
+// rows hit distinct banks).  Loads are coalesced across the block.
+__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int n, int w, float* dst) {
+    const unsigned magic = 0xFFFFFFFFu / (unsigned)w + 1u;  // x / w = umulhi(x, magic) for x < 2^32 / w
+    for (int x = threadIdx.x; x < n * w; x += blockDim.x) {
+        const int r = (int)__umulhi((unsigned)x, magic);
+        dst[r * (w + 1) + (x - r * w)] = src[x];
+    }
+}
+
+// Pixels per correction block: 64 when both staged rows fit 64 KB of LDS.
+__host__ __device__ inline int correct_rows(int K, int C) { return 64 * (K * C + K + 2) <= 16384 ? 64 : 32; }
 
 // Forward render: images = albedo (S + G).
 template <int C>
@@ -366,15 +381,28 @@ __device__ __forceinline__ float order_val(unsigned k) {
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-// Minimum of X + 0 over a block's nodes into *key (one atomic per wave).
-__device__ __forceinline__ void min_key_block(const float* __restrict__ X, int v, int n, unsigned* key) {
+// Minimum of X + 0 over the nodes v = start, start + stride, ... below n into
+// *key: each thread strides, the block reduces (wave shuffles, then LDS) and
+// issues one atomic.  The minimum does not depend on the order.
+__device__ __forceinline__ void min_key_strided(const float* __restrict__ X, long long start, long long stride,
+                                                int n, unsigned* key) {
+    __shared__ unsigned s_min[4];  // one per wave of a 256-thread block
     unsigned k = 0xffffffffu;
-    if (v < n) k = order_key(X[v] + 0.0f);  // +0.0f: one zero
+    for (long long v = start; v < n; v += stride) {
+        const unsigned o = order_key(X[v] + 0.0f);  // +0.0f: one zero
+        k = o < k ? o : k;
+    }
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned other = __shfl_xor(k, o);
         k = other < k ? other : k;
     }
-    if ((threadIdx.x & 63) == 0) atomicMin(key, k);
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = s_min[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = s_min[w] < m ? s_min[w] : m;
+        atomicMin(key, m);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -558,14 +586,24 @@ __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
 }
 
 template <int C>
-__global__ void __launch_bounds__(256) k_correct(int npx, int K, int rho_mode, int cumulative,
-                                                 const float* __restrict__ I0, const float* __restrict__ Aprev,
-                                                 const float* __restrict__ G, const float* __restrict__ S,
-                                                 const float* __restrict__ rho, float* __restrict__ E,
-                                                 float* __restrict__ Anext) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npx) return;
-    correct_px<C>(p, npx, K, rho_mode, cumulative, I0, Aprev, G, S, rho, E, Anext);
+__global__ void __launch_bounds__(64) k_correct(int npx, int K, int rho_mode, int cumulative,
+                                                const float* __restrict__ I0, const float* __restrict__ Aprev,
+                                                const float* __restrict__ G, const float* __restrict__ S,
+                                                const float* __restrict__ rho, float* __restrict__ E,
+                                                float* __restrict__ Anext) {
+    extern __shared__ float sm[];
+    const int KC = K * C, rows = correct_rows(K, C);
+    const int p0 = blockIdx.x * rows;
+    const int n = npx - p0 < rows ? npx - p0 : rows;
+    float* sG = sm;
+    float* sS = sm + rows * (KC + 1);
+    stage_rows(G + (size_t)p0 * KC, n, KC, sG);
+    stage_rows(S + (size_t)p0 * K, n, K, sS);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < n)
+        correct_px<C>(p0 + t, npx, K, rho_mode, cumulative, I0, Aprev, sG + t * (KC + 1), sS + t * (K + 1), rho, E,
+                      Anext);
 }
 
 template <int C>
@@ -655,7 +693,7 @@ __global__ void k_copy_f32(float* __restrict__ dst, const float* __restrict__ sr
 }
 
 __global__ void __launch_bounds__(256) k_min_key(const float* __restrict__ X, int n, unsigned* key) {
-    min_key_block(X, blockIdx.x * blockDim.x + threadIdx.x, n, key);
+    min_key_strided(X, (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x, n, key);
 }
 
 __global__ void __launch_bounds__(256) k_anchor(const float* __restrict__ X, int n, const unsigned* key,
@@ -772,15 +810,25 @@ __global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict_
 }
 
 template <int C>
-__global__ void __launch_bounds__(256) k_correct_multi(const JobDesc* __restrict__ jobs) {
+__global__ void __launch_bounds__(64) k_correct_multi(const JobDesc* __restrict__ jobs) {
+    extern __shared__ float sm[];
     const JobDesc& J = jobs[blockIdx.y];
     const int npx = J.W * J.Hh;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!iterating(J) || J.C != C || p >= npx) return;
+    const int K = J.K, KC = J.K * C, rows = correct_rows(K, C);
+    const int p0 = blockIdx.x * rows;
+    if (!iterating(J) || J.C != C || p0 >= npx) return;  // uniform per block
+    const int n = npx - p0 < rows ? npx - p0 : rows;
+    float* sG = sm;
+    float* sS = sm + rows * (KC + 1);
+    stage_rows(J.G + (size_t)p0 * KC, n, KC, sG);
+    stage_rows(J.S + (size_t)p0 * K, n, K, sS);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= n) return;
     const bool cumulative = (J.flags & 2) != 0;
     float* E = (J.t == J.T - 1) ? J.E : nullptr;
-    correct_px<C>(p, npx, J.K, J.rho_mode, cumulative ? 1 : 0, J.I0, (cumulative && J.t > 0) ? J.A : J.I0,
-                  J.G, J.S, J.rho, E, J.A);
+    correct_px<C>(p0 + t, npx, K, J.rho_mode, cumulative ? 1 : 0, J.I0, (cumulative && J.t > 0) ? J.A : J.I0,
+                  sG + t * (KC + 1), sS + t * (K + 1), J.rho, E, J.A);
 }
 
 __global__ void __launch_bounds__(256) k_pyr0_multi(const JobDesc* __restrict__ jobs) {
@@ -880,9 +928,8 @@ __global__ void __launch_bounds__(256) k_min_key_multi(const JobDesc* __restrict
         return;
     }
     const int n = J.W * J.Hh;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int)(blockIdx.x * blockDim.x) >= n) return;  // whole block past the end
-    min_key_block(J.mg_ws + J.mg.xoff[0], v, n, key);
+    min_key_strided(J.mg_ws + J.mg.xoff[0], (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                    (long long)gridDim.x * blockDim.x, n, key);
 }
 
 __global__ void __launch_bounds__(256) k_anchor_multi(const JobDesc* __restrict__ jobs, int cold) {
@@ -973,13 +1020,15 @@ hipError_t trace(TraceArgs a, hipStream_t st) {
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
                    const float* Aprev, const float* G, const float* S, const float* rho, float* E,
                    float* Anext, hipStream_t st) {
-    const unsigned g = blocks_for(npx, 256);
+    const int rows = correct_rows(K, C);
+    const unsigned g = blocks_for(npx, rows);
+    const size_t lds = sizeof(float) * rows * (K * C + 1 + K + 1);
     if (C == 1)
-        hipLaunchKernelGGL(k_correct<1>, dim3(g), dim3(256), 0, st, npx, K, rho_mode, cumulative, I0,
-                           Aprev, G, S, rho, E, Anext);
+        hipLaunchKernelGGL(k_correct<1>, dim3(g), dim3(64), lds, st, npx, K, rho_mode, cumulative, I0, Aprev, G, S,
+                           rho, E, Anext);
     else
-        hipLaunchKernelGGL(k_correct<3>, dim3(g), dim3(256), 0, st, npx, K, rho_mode, cumulative, I0,
-                           Aprev, G, S, rho, E, Anext);
+        hipLaunchKernelGGL(k_correct<3>, dim3(g), dim3(64), lds, st, npx, K, rho_mode, cumulative, I0, Aprev, G, S,
+                           rho, E, Anext);
     return hipGetLastError();
 }
 
@@ -1006,6 +1055,9 @@ hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, f
                            P.hc[l]);
     return hipGetLastError();
 }
+
+// Blocks of the anchor's minimum reduction (each strides over the grid).
+constexpr unsigned kMinKeyBlocks = 512;
 
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
                      float* ws, hipStream_t st) {
@@ -1050,7 +1102,8 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
         }
     }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, key, 0xffffffffu, 1);
-    hipLaunchKernelGGL(k_min_key, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key);
+    const unsigned gm = blocks_for(npx, 256) < kMinKeyBlocks ? blocks_for(npx, 256) : kMinKeyBlocks;
+    hipLaunchKernelGGL(k_min_key, dim3(gm), dim3(256), 0, st, X[0], npx, key);
     hipLaunchKernelGGL(k_anchor, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key, Hout);
     return hipGetLastError();
 }
@@ -1119,9 +1172,21 @@ hipError_t batch_direct(const JobDesc* jobs, const BatchShape& bs, hipStream_t s
 }
 
 hipError_t batch_correct(const JobDesc* jobs, const BatchShape& bs, int /*last_only*/, hipStream_t st) {
-    const dim3 g(blocks_for(bs.max_npx, 256), bs.njobs);
-    hipLaunchKernelGGL(k_correct_multi<1>, g, dim3(256), 0, st, jobs);
-    hipLaunchKernelGGL(k_correct_multi<3>, g, dim3(256), 0, st, jobs);
+    // LDS for the largest light count of each channel count; rows per block
+    // never exceed what that allows (correct_rows shrinks with K C)
+    for (int C = 1; C <= 3; C += 2) {
+        const int K = C == 1 ? bs.max_K1 : bs.max_K3;
+        if (K == 0) continue;
+        int need = 0;  // the largest staging area any job of this channel count uses
+        for (int k = 1; k <= K; ++k) {
+            const int r = correct_rows(k, C) * (k * C + 1 + k + 1);
+            need = r > need ? r : need;
+        }
+        const dim3 g(blocks_for(bs.max_npx, 32), bs.njobs);  // enough blocks for 32-row jobs too
+        const size_t lds = sizeof(float) * need;
+        if (C == 1) hipLaunchKernelGGL(k_correct_multi<1>, g, dim3(64), lds, st, jobs);
+        else hipLaunchKernelGGL(k_correct_multi<3>, g, dim3(64), lds, st, jobs);
+    }
     return hipGetLastError();
 }
 
@@ -1151,7 +1216,8 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
         }
     }
     hipLaunchKernelGGL(k_min_key_multi, dim3(1, nj), dim3(64), 0, st, jobs, 1, cold);
-    hipLaunchKernelGGL(k_min_key_multi, gpx, dim3(256), 0, st, jobs, 0, cold);
+    const unsigned gm = gpx.x < kMinKeyBlocks ? gpx.x : kMinKeyBlocks;
+    hipLaunchKernelGGL(k_min_key_multi, dim3(gm, nj), dim3(256), 0, st, jobs, 0, cold);
     hipLaunchKernelGGL(k_anchor_multi, gpx, dim3(256), 0, st, jobs, cold);
     return hipGetLastError();
 }

@@ -109,6 +109,7 @@ struct BatchShape {
     int max_mg_nodes[kMaxMgLevels];
     int max_cycles_cold, max_cycles_warm;
     int max_KCnpx;           // largest K * C * W * H
+    int max_K1, max_K3;      // largest light count of the grey and of the colour jobs (0: none)
 };
 
 hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, float* n, float* rho,

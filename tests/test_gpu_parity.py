@@ -265,19 +265,20 @@ def test_trace_stage(dev, case):
 def test_correct_stage(dev, mode, flags):
     say(f"case: correct mode={mode} flags={flags}")
     rng = np.random.default_rng(21)
-    K, C, Hh, W = 7, 3, 30, 41
-    I0 = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
-    G = rng.uniform(0, 0.5, (K, C, Hh, W)).astype(F32)
-    S = rng.uniform(0, 1, (Hh, W, K)).astype(F32)
-    S[S < 0.2] = 0
-    S[0, 0, :] = 0
-    G[:, :, 0, 0] = 0
-    rho = rng.uniform(0.2, 1, (C, Hh, W)).astype(F32)
-    Ap = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
-    E, A = irtps.correct(T(I0, dev), T(np.transpose(G, (2, 3, 0, 1)), dev), T(S, dev), T(rho, dev), mode, flags,
-                         T(Ap, dev) if flags else None)
-    rE, rA = O.correct(I0, G, S, rho, mode, flags, Ap if flags else None)
-    assert np.array_equal(H(E), rE) and np.array_equal(H(A), rA)
+    # (K, C, H, W): ragged blocks, the 32-pixel blocks of K = 64 RGB, one-row images
+    for K, C, Hh, W in ((7, 3, 30, 41), (64, 3, 9, 23), (64, 1, 17, 5), (3, 1, 2, 70), (16, 3, 8, 8)):
+        I0 = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
+        G = rng.uniform(0, 0.5, (K, C, Hh, W)).astype(F32)
+        S = rng.uniform(0, 1, (Hh, W, K)).astype(F32)
+        S[S < 0.2] = 0
+        S[0, 0, :] = 0
+        G[:, :, 0, 0] = 0
+        rho = rng.uniform(0.2, 1, (C, Hh, W)).astype(F32)
+        Ap = rng.uniform(0, 2, (K, C, Hh, W)).astype(F32)
+        E, A = irtps.correct(T(I0, dev), T(np.transpose(G, (2, 3, 0, 1)), dev), T(S, dev), T(rho, dev), mode,
+                             flags, T(Ap, dev) if flags else None)
+        rE, rA = O.correct(I0, G, S, rho, mode, flags, Ap if flags else None)
+        assert np.array_equal(H(E), rE) and np.array_equal(H(A), rA), (K, C, Hh, W)
 
 
 def test_render_stage(dev):
