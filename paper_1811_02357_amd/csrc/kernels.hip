@@ -415,6 +415,8 @@ __device__ __forceinline__ void min_key_strided(const float* __restrict__ X, lon
 // until at least ready_batch lanes (or all that still have work) have finished
 // theirs, with a phase that shades the finished segments and starts the next
 // ones.  A lane's segments are summed in (sample, bounce) order.
+constexpr int kStepsPerVote = 3;
+
 template <int C>
 __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
     const int tw = 1 << a.tile_shift;
@@ -478,9 +480,14 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
         if (__all(finished)) break;
         // traversal phase
         for (;;) {
-            if (!finished && !ready) {
-                res = trv::walker_step(w, S, qi, qj);
-                ready = res != trv::kGoOn;
+            // a few walker steps per pair of ballots: a lane that finishes early
+            // waits out the remaining steps, but the wave votes less often
+#pragma unroll
+            for (int u = 0; u < kStepsPerVote; ++u) {
+                if (!finished && !ready) {
+                    res = trv::walker_step(w, S, qi, qj);
+                    ready = res != trv::kGoOn;
+                }
             }
             const int n_act = __popcll(__ballot(!finished));
             const int n_rdy = __popcll(__ballot(!finished && ready));
