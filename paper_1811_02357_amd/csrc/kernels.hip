@@ -417,6 +417,37 @@ __device__ __forceinline__ void min_key_strided(const float* __restrict__ X, lon
 // ones.  A lane's segments are summed in (sample, bounce) order.
 constexpr int kStepsPerVote = 3;
 
+// One hit's share: g[k C + c] = fma(wgt[c], Sq[k], g[k C + c]) for every light
+// and channel, in that order per element.  With vec4, four lights at a time
+// through float4 loads and stores of S and G (same arithmetic).
+template <int C>
+__device__ __forceinline__ void accumulate_hit(float* __restrict__ g, const float* __restrict__ Sq,
+                                               const float (&wgt)[C], int K, bool vec4) {
+    if (vec4) {
+        for (int m = 0; m < K; m += 4) {
+            const float4 s4 = *reinterpret_cast<const float4*>(Sq + m);
+            const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+            float4* g4 = reinterpret_cast<float4*>(g + m * C);
+            // the 4C elements of these four lights are C float4s of G: element
+            // e = 4x + i is light e / C, channel e % C
+#pragma unroll
+            for (int x = 0; x < C; ++x) {
+                const float4 t = g4[x];
+                float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) tv[i] = fmaf(wgt[(4 * x + i) % C], sv[(4 * x + i) / C], tv[i]);
+                g4[x] = make_float4(tv[0], tv[1], tv[2], tv[3]);
+            }
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const float sq = Sq[k];
+#pragma unroll
+            for (int c = 0; c < C; ++c) g[k * C + c] = fmaf(wgt[c], sq, g[k * C + c]);
+        }
+    }
+}
+
 template <int C>
 __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
     const int tw = 1 << a.tile_shift;
@@ -431,6 +462,9 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     const int KC = K * C;
     const int batch = a.ready_batch;
     float* __restrict__ gp = a.G + (size_t)p * KC;  // this pixel's sums
+    // whole float4 rows of S and G when K is a multiple of 4 and G is 16-byte aligned
+    const bool vec4 = (K & 3) == 0 && (reinterpret_cast<uintptr_t>(a.G) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0;
 
     if (live)
         for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
@@ -513,12 +547,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                 float wgt[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[c * npx + q];
-                const float* __restrict__ Sq = a.S + (size_t)q * K;
-                for (int k = 0; k < K; ++k) {
-                    const float sq = Sq[k];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) gp[k * C + c] = fmaf(wgt[c], sq, gp[k * C + c]);
-                }
+                accumulate_hit<C>(gp, a.S + (size_t)q * K, wgt, K, vec4);
                 if (b < a.B) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) beta[c] = wgt[c];
