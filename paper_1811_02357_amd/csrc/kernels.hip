@@ -40,12 +40,14 @@ __device__ __forceinline__ Surface make_surface(const float* H, const float* pyr
     Surface S;
     S.H = H;
     S.pyr = pyr;
-    S.quad = pyr + quad_off;
     S.lvl = s_lvl;
     S.W = W;
     S.Hh = Hh;
     S.QW = trv::quad_cells(W);
     S.QH = trv::quad_cells(Hh);
+    const float* tab = pyr + quad_off;
+    S.esc = reinterpret_cast<const float4*>(tab);
+    S.quad = tab + 25 * trv::block_plane4(S.QW, S.QH);
     S.top = levels - 1;
     S.hmax = S.quad[0];  // quadrant (+x, +y) of block (0, 0): every sample
     return S;
@@ -222,15 +224,33 @@ __device__ __forceinline__ void pyr_reduce_cell(int c, const float* __restrict__
     out[c] = m;
 }
 
-// Quadrant maxima over 8 x 8 sample blocks: quad[q][by][bx] = max of H over
-// samples (x', y') with x' >= 8 bx (sx > 0) or x' <= 8 bx + 7 (sx < 0), and the
-// same along y, q = (sx < 0) + 2 (sy < 0).  Block maxima go to plane 3 first;
-// the rows then fill planes 0 (suffix along x) and 1 (prefix); the columns fill
-// planes 2 and 3 (prefix along y of planes 0 and 1) and finish 0 and 1
-// (suffix along y) in place.
-__device__ __forceinline__ void quad_block(int b, int W, int Hh, const float* __restrict__ H, int QW, int QH,
-                                           float* __restrict__ quad) {
-    const int bx = b % QW, by = b / QW;
+// The block tables (layout in traverse.hpp), from the block maxima of H.
+struct BlockTables {
+    float4* esc;
+    float* bmax;
+    float* rowmax;
+    float* quad;
+    int QW, QH;
+    long long plane;  // QW QH
+};
+
+__device__ __forceinline__ BlockTables block_tables(float* tab, int W, int Hh) {
+    BlockTables t;
+    t.QW = trv::quad_cells(W);
+    t.QH = trv::quad_cells(Hh);
+    t.plane = (long long)t.QW * t.QH;
+    const long long p4 = trv::block_plane4(t.QW, t.QH);
+    t.esc = reinterpret_cast<float4*>(tab);
+    t.bmax = tab + 16 * p4;
+    t.rowmax = tab + 17 * p4;
+    t.quad = tab + 25 * p4;
+    return t;
+}
+
+// Block maxima of H over 8 x 8 sample blocks.
+__device__ __forceinline__ void quad_block(int b, int W, int Hh, const float* __restrict__ H,
+                                           const BlockTables& t) {
+    const int bx = b % t.QW, by = b / t.QW;
     const int x0 = bx << trv::kQuadShift, y0 = by << trv::kQuadShift;
     const int x1 = min(x0 + (1 << trv::kQuadShift), W), y1 = min(y0 + (1 << trv::kQuadShift), Hh);
     float m = H[(size_t)y0 * W + x0];
@@ -239,33 +259,37 @@ __device__ __forceinline__ void quad_block(int b, int W, int Hh, const float* __
             const float v = H[(size_t)y * W + x];
             m = v > m ? v : m;
         }
-    quad[(size_t)3 * QW * QH + b] = m;
+    t.bmax[b] = m;
 }
 
-__device__ __forceinline__ void quad_row(int j, int QW, int QH, float* __restrict__ quad) {
-    const size_t plane = (size_t)QW * QH;
-    const float* row = quad + 3 * plane + (size_t)j * QW;
-    float* suf = quad + (size_t)j * QW;
-    float* pre = quad + plane + (size_t)j * QW;
-    float m = row[QW - 1];
-    for (int x = QW - 1; x >= 0; --x) {
+// Quadrant maxima over blocks: quad[q][by][bx] = max of H over samples (x, y)
+// with x >= 8 bx (sx > 0) or x <= 8 bx + 7 (sx < 0), and the same along y,
+// q = (sx < 0) + 2 (sy < 0).  Rows fill planes 0 (suffix along x) and 1
+// (prefix); columns fill planes 2 and 3 (prefix along y of planes 0 and 1) and
+// finish 0 and 1 (suffix along y) in place.
+__device__ __forceinline__ void quad_row(int j, const BlockTables& t) {
+    const float* row = t.bmax + (size_t)j * t.QW;
+    float* suf = t.quad + (size_t)j * t.QW;
+    float* pre = t.quad + t.plane + (size_t)j * t.QW;
+    float m = row[t.QW - 1];
+    for (int x = t.QW - 1; x >= 0; --x) {
         const float v = row[x];
         m = v > m ? v : m;
         suf[x] = m;
     }
     m = row[0];
-    for (int x = 0; x < QW; ++x) {
+    for (int x = 0; x < t.QW; ++x) {
         const float v = row[x];
         m = v > m ? v : m;
         pre[x] = m;
     }
 }
 
-__device__ __forceinline__ void quad_col(int i, int QW, int QH, float* __restrict__ quad) {
-    const size_t plane = (size_t)QW * QH;
+__device__ __forceinline__ void quad_col(int i, const BlockTables& t) {
+    const int QW = t.QW, QH = t.QH;
     for (int h = 0; h < 2; ++h) {
-        float* src = quad + h * plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
-        float* pre = quad + (h + 2) * plane;  // sy = -1
+        float* src = t.quad + h * t.plane;        // sx = +1 (h = 0) or -1 (h = 1), rows done
+        float* pre = t.quad + (h + 2) * t.plane;  // sy = -1
         float m = src[i];
         for (int y = 0; y < QH; ++y) {
             const float v = src[(size_t)y * QW + i];
@@ -278,6 +302,56 @@ __device__ __forceinline__ void quad_col(int i, int QW, int QH, float* __restric
             m = v > m ? v : m;
             src[(size_t)y * QW + i] = m;
         }
+    }
+}
+
+// Block range of escape window k along one axis for travel direction s: a
+// ray in block c can read samples from one before the block to scale + 9
+// past its start going +, mirrored going -, i.e. blocks [c - 1, c + scale/8 + 1]
+// or [c - scale/8 - 1, c + 1], clamped to the grid.
+__device__ __forceinline__ void escape_range(int c, int k, bool forward, int n, int& lo, int& hi) {
+    const int reach = (trv::escape_scale(k) >> trv::kQuadShift) + 1;
+    lo = forward ? c - 1 : c - reach;
+    hi = forward ? c + reach : c + 1;
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > n - 1 ? n - 1 : hi;
+}
+
+// Row pass: rowmax[xdir][k][by][bx] = max of the block maxima of row by over
+// the x-range of window k (xdir 0: +x, 1: -x).
+__device__ __forceinline__ void escape_row(int b, const BlockTables& t) {
+    const int bx = b % t.QW, by = b / t.QW;
+    const float* row = t.bmax + (size_t)by * t.QW;
+    for (int xd = 0; xd < 2; ++xd)
+        for (int k = 0; k < trv::kEscapeScales; ++k) {
+            int lo, hi;
+            escape_range(bx, k, xd == 0, t.QW, lo, hi);
+            float m = row[lo];
+            for (int x = lo + 1; x <= hi; ++x) m = row[x] > m ? row[x] : m;
+            t.rowmax[(xd * trv::kEscapeScales + k) * t.plane + b] = m;
+        }
+}
+
+// Column pass: esc[q][by][bx] = (max of rowmax[xdir(q)][k] over the y-range of
+// window k, k = 0..2; quadrant maximum), each with the escape margin.  Runs
+// after the quadrant maxima.
+__device__ __forceinline__ void escape_col(int b, const BlockTables& t) {
+    const int bx = b % t.QW, by = b / t.QW;
+    for (int q = 0; q < 4; ++q) {
+        float m[trv::kEscapeScales + 1];
+        for (int k = 0; k < trv::kEscapeScales; ++k) {
+            int lo, hi;
+            escape_range(by, k, (q & 2) == 0, t.QH, lo, hi);
+            const float* col = t.rowmax + ((q & 1) * trv::kEscapeScales + k) * t.plane + bx;
+            float v = col[(size_t)lo * t.QW];
+            for (int y = lo + 1; y <= hi; ++y) {
+                const float u = col[(size_t)y * t.QW];
+                v = u > v ? u : v;
+            }
+            m[k] = trv::escape_margin(v);
+        }
+        m[3] = trv::escape_margin(t.quad[q * t.plane + b]);
+        t.esc[q * t.plane + b] = make_float4(m[0], m[1], m[2], m[3]);
     }
 }
 
@@ -666,20 +740,34 @@ __global__ void __launch_bounds__(256) k_pyr_reduce(const float* __restrict__ in
 }
 
 __global__ void __launch_bounds__(256) k_quad_blocks(int W, int Hh, const float* __restrict__ H,
-                                                    float* __restrict__ quad) {
-    const int QW = trv::quad_cells(W), QH = trv::quad_cells(Hh);
+                                                    float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < QW * QH) quad_block(b, W, Hh, H, QW, QH, quad);
+    if (b < t.plane) quad_block(b, W, Hh, H, t);
 }
 
-__global__ void __launch_bounds__(64) k_quad_rows(int QW, int QH, float* __restrict__ quad) {
+__global__ void __launch_bounds__(64) k_quad_rows(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < QH) quad_row(j, QW, QH, quad);
+    if (j < t.QH) quad_row(j, t);
 }
 
-__global__ void __launch_bounds__(64) k_quad_cols(int QW, int QH, float* __restrict__ quad) {
+__global__ void __launch_bounds__(64) k_quad_cols(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < QW) quad_col(i, QW, QH, quad);
+    if (i < t.QW) quad_col(i, t);
+}
+
+__global__ void __launch_bounds__(256) k_escape_rows(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < t.plane) escape_row(b, t);
+}
+
+__global__ void __launch_bounds__(256) k_escape_cols(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < t.plane) escape_col(b, t);
 }
 
 __global__ void __launch_bounds__(256) k_mg_rhs(int W, int Hh, const float* __restrict__ n,
@@ -884,23 +972,37 @@ __global__ void __launch_bounds__(256) k_pyr_reduce_multi(const JobDesc* __restr
 
 __global__ void __launch_bounds__(256) k_quad_blocks_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
-    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (iterating(J) && b < QW * QH) quad_block(b, J.W, J.Hh, J.depth, QW, QH, J.pyr + J.quad_off);
+    if (iterating(J) && b < t.plane) quad_block(b, J.W, J.Hh, J.depth, t);
 }
 
 __global__ void __launch_bounds__(64) k_quad_rows_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
-    if (iterating(J) && j < QH) quad_row(j, QW, QH, J.pyr + J.quad_off);
+    if (iterating(J) && j < t.QH) quad_row(j, t);
 }
 
 __global__ void __launch_bounds__(64) k_quad_cols_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int QW = trv::quad_cells(J.W), QH = trv::quad_cells(J.Hh);
-    if (iterating(J) && i < QW) quad_col(i, QW, QH, J.pyr + J.quad_off);
+    if (iterating(J) && i < t.QW) quad_col(i, t);
+}
+
+__global__ void __launch_bounds__(256) k_escape_rows_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && b < t.plane) escape_row(b, t);
+}
+
+__global__ void __launch_bounds__(256) k_escape_cols_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && b < t.plane) escape_col(b, t);
 }
 
 __global__ void __launch_bounds__(256) k_mg_rhs_multi(const JobDesc* __restrict__ jobs, int cold) {
@@ -1078,11 +1180,14 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st) {
-    float* quad = pyr + quad_off;
+    float* tab = pyr + quad_off;
     const int QW = trv::quad_cells(W), QH = trv::quad_cells(Hh);
-    hipLaunchKernelGGL(k_quad_blocks, dim3(blocks_for((long long)QW * QH, 256)), dim3(256), 0, st, W, Hh, H, quad);
-    hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(QH, 64)), dim3(64), 0, st, QW, QH, quad);
-    hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(QW, 64)), dim3(64), 0, st, QW, QH, quad);
+    const unsigned gb = blocks_for((long long)QW * QH, 256);
+    hipLaunchKernelGGL(k_quad_blocks, dim3(gb), dim3(256), 0, st, W, Hh, H, tab);
+    hipLaunchKernelGGL(k_quad_rows, dim3(blocks_for(QH, 64)), dim3(64), 0, st, W, Hh, tab);
+    hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(QW, 64)), dim3(64), 0, st, W, Hh, tab);
+    hipLaunchKernelGGL(k_escape_rows, dim3(gb), dim3(256), 0, st, W, Hh, tab);
+    hipLaunchKernelGGL(k_escape_cols, dim3(gb), dim3(256), 0, st, W, Hh, tab);
     hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
                        st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
     for (int l = 1; l < P.levels; ++l)
@@ -1194,6 +1299,8 @@ hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t 
                        st, jobs);
     hipLaunchKernelGGL(k_quad_cols_multi, dim3(blocks_for(trv::quad_cells(bs.max_cols), 64), bs.njobs), dim3(64), 0,
                        st, jobs);
+    hipLaunchKernelGGL(k_escape_rows_multi, dim3(blocks_for(qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_escape_cols_multi, dim3(blocks_for(qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
     hipLaunchKernelGGL(k_pyr0_multi, dim3(blocks_for(bs.max_pyr_cells[0], 256), bs.njobs), dim3(256), 0, st,
                        jobs);
     for (int l = 1; l < bs.max_pyr_levels; ++l)

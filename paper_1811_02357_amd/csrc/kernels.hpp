@@ -39,7 +39,7 @@ struct SurfaceArgs {
     const float* pyr;  // apron-max levels, then the four quadrant maxima
     int W, Hh;
     int levels;
-    int quad_off;      // floats from pyr to the quadrant tables
+    int quad_off;      // floats from pyr to the block tables (escape windows, quadrant maxima)
     int off[trv::kMaxLevels];
     int wc[trv::kMaxLevels];  // cells per row of every level
 };
@@ -122,7 +122,7 @@ hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const fl
                    float* Anext, hipStream_t st);
 hipError_t compose(int npx, int C, int K, const float* rho, const float* S, const float* G, float* I,
                    hipStream_t st);
-// Apron-max levels of P at pyr, then the quadrant maxima at pyr + quad_off.
+// Apron-max levels of P at pyr, then the block tables at pyr + quad_off.
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st);
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,

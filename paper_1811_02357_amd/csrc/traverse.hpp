@@ -28,6 +28,27 @@ constexpr int kMaxLevels = 16;
 constexpr int kQuadShift = 3;
 __host__ __device__ inline int quad_cells(int n) { return (n + (1 << kQuadShift) - 1) >> kQuadShift; }
 
+// Escape windows: per block and quadrant of travel, the maxima over the
+// samples a ray starting in the block can read within 16, 64 and 256 samples of
+// horizontal travel (escape_scale(k)), and the quadrant maximum; each is raised
+// by 2e-3 + 2e-6 |max| so that a test against it survives the rounding of the
+// ray's heights.
+constexpr int kEscapeScales = 3;
+__host__ __device__ inline int escape_scale(int k) { return 16 << (2 * k); }
+__host__ __device__ inline float escape_margin(float m) { return fmaf(2e-6f, fabsf(m), m + 2e-3f); }
+
+// The block tables that follow the pyramid levels, in floats from their start
+// (which is 64-float aligned), for a QW x QH block grid with plane p4 =
+// QW QH rounded up to a multiple of 4:
+//   escape windows  float4 [4 quadrants][QH][QW]      at 0
+//   block maxima    [QH][QW]                          at 16 p4
+//   row-window maxima [2 x-directions][3 scales][QH][QW] at 17 p4
+//   quadrant maxima [4 quadrants][QH][QW]             at 25 p4 (the end)
+__host__ __device__ inline long long block_plane4(int QW, int QH) { return ((long long)QW * QH + 3) / 4 * 4; }
+__host__ __device__ inline long long block_tables_floats(int QW, int QH) {
+    return 25 * block_plane4(QW, QH) + 4LL * QW * QH;
+}
+
 // Apron-max pyramid.  Level l has cells (cx, cy), cx < wc[l], cy < hc[l];
 // cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l].
 struct Pyramid {
@@ -46,6 +67,7 @@ struct Surface {
     const float* H;      // [Hh][W]
     const float* pyr;    // apron maxima, levels concatenated
     const float* quad;   // 4 quadrant maxima [q][QH][QW] over blocks, q = (dx < 0) + 2 (dy < 0)
+    const float4* esc;   // escape windows [q][QH][QW]: maxima within escape_scale(0..2), quadrant max
     const int2* lvl;     // LDS copy of (offset, cells per row) of every level
     int W, Hh;
     int QW, QH;          // blocks of the quadrant tables
@@ -58,6 +80,7 @@ struct Surface {
 // origin (i0, j0).
 struct Ray {
     float nx0, ny0, oz, dx, dy, dz;
+    float slope;           // rise per unit of horizontal travel, rounded down (0 if not rising)
     float ainv_x, ainv_y;  // |1/dx|, |1/dy| (+inf for a zero component)
     int i0, j0, sx, sy;
 };
@@ -82,6 +105,10 @@ __device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float 
     r.ny0 = (float)j0 + (float)r.sy * kNudge;
     r.ainv_x = fabsf(1.0f / dx);
     r.ainv_y = fabsf(1.0f / dy);
+    // dz / |(dx, dy)| from the hardware reciprocal square root (within a few ulp),
+    // shrunk by 1e-5 so that it never exceeds the exact slope
+    const float hd2 = fmaf(dx, dx, dy * dy);
+    r.slope = (dz > 0.0f && hd2 > 0.0f) ? dz * __builtin_amdgcn_rsqf(hd2) * 0.99999f : 0.0f;
     return r;
 }
 
@@ -123,6 +150,17 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
     }
     if (z >= S.hmax && r.dz >= 0.0f) return kMiss;
     return kGoOn;
+}
+
+// A rising ray at height z in a block escapes when, over each stretch of
+// horizontal travel, its lowest height clears the highest sample it can read
+// there: z clears the first window; after escape_scale(k) of travel it has
+// risen at least slope escape_scale(k) and clears the next window; after the
+// last scale, the quadrant maximum (win.w).  z grows with t exactly as the
+// crossings compute it (fma, monotone); the windows carry the rounding margin.
+__device__ __forceinline__ bool escapes(float z, float slope, const float4& win) {
+    return z >= win.x && fmaf(slope, (float)escape_scale(0), z) >= win.y &&
+           fmaf(slope, (float)escape_scale(1), z) >= win.z && fmaf(slope, (float)escape_scale(2), z) >= win.w;
 }
 
 // Smallest crossing index m >= 1 whose t (same formula as the walk) is >= t_lim.
@@ -182,22 +220,19 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
         if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
             const int l = w.level;
             const int ix = (int)px, iy = (int)py;  // px, py > 0: truncation is floor
-            // Every sample a later crossing can read lies in the quadrant ahead of
-            // the ray's position: at most one sample behind floor(x) going +x, two
-            // ahead of it going -x (a lerp reads the next sample), and the nudge
-            // moves floor by at most one.  The table's block quadrant containing
-            // that corner covers it.  If the ray is not descending and is at or
-            // above the maximum there, nothing ahead can hit.
-            const int qx = r.sx > 0 ? ix - 2 : (ix + 3 < S.W ? ix + 3 : S.W - 1);
-            const int qy = r.sy > 0 ? iy - 2 : (iy + 3 < S.Hh ? iy + 3 : S.Hh - 1);
+            // Escape windows of the block holding the (nudged) position: every
+            // sample a later crossing can read within escape_scale(k) of travel
+            // lies in window k (one sample behind the block going +, the lerp's
+            // second sample and the nudge included), and everything ahead in the
+            // block-aligned quadrant.
             const int quadrant = (r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0);
-            const float qmax = S.quad[(quadrant * S.QH + (qy >> kQuadShift)) * S.QW + (qx >> kQuadShift)];
+            const float4 win = S.esc[(quadrant * S.QH + (iy >> kQuadShift)) * S.QW + (ix >> kQuadShift)];
             const int cx = ix >> l;
             const int cy = iy >> l;
             const int2 lv = S.lvl[l];
             const float cmax = S.pyr[lv.x + cy * lv.y + cx];  // +inf near the border
             // both loads are issued before either result is tested (one wait)
-            __asm__ volatile("" : : "v"(qmax), "v"(cmax));
+            __asm__ volatile("" : : "v"(cmax), "v"(win.x), "v"(win.y), "v"(win.z), "v"(win.w));
             // exit of the cell along the ray (computed while the loads are in flight)
             const int size = 1 << l;
             const int mxe = (cx << l) + (r.sx > 0 ? size : 0) - r.i0;
@@ -207,7 +242,7 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             const float tye = mya >= 1 ? t_y(r, mya) : __builtin_inff();
             const float t_exit = txe <= tye ? txe : tye;
             const float z_exit = fmaf(t_exit, r.dz, r.oz);
-            if (z_now >= qmax && rising) return kMiss;
+            if (rising && escapes(z_now, r.slope, win)) return kMiss;
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
             // the ray is at or above its maximum over that range
             if (z_now >= cmax && t_exit > t_now && !isinf(t_exit) && z_exit >= cmax) {

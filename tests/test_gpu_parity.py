@@ -16,6 +16,7 @@ import torch
 
 from oracle import oracle as O
 from paper_1811_02357_amd import irtps, scenes
+from tests.fp32 import fmaf
 
 pytestmark = pytest.mark.gpu
 
@@ -365,6 +366,51 @@ def test_quadrant_maxima(dev):
                 xs = slice(8 * bx, W) if sx > 0 else slice(0, 8 * bx + 8)
                 ys = slice(8 * by, Hh) if sy > 0 else slice(0, 8 * by + 8)
                 assert quad[q, by, bx] == Hf[ys, xs].max(), (q, by, bx)
+
+
+def test_escape_windows(dev):
+    """Escape windows per 8 x 8 block and quadrant of travel: the maxima over the
+    block ranges that cover what a ray reads within 16, 64 and 256 samples of
+    travel, then the quadrant maximum, each raised by the rounding margin
+    fma(2e-6, |m|, m + 2e-3)."""
+    say("case: escape windows in the pyramid buffer")
+    rng = np.random.default_rng(5)
+    margin = lambda m: fmaf(np.float32(2e-6), np.abs(np.float32(m)), np.float32(m) + np.float32(2e-3))
+    for Hh, W in ((45, 70), (300, 133), (9, 1030)):
+        Hf = rng.uniform(-5, 5, (Hh, W)).astype(F32)
+        pyr = H(irtps.build_pyramid(T(Hf, dev)))
+        wc, hc, lv = W - 1, Hh - 1, 0
+        while True:  # pyramid levels, then the block tables (64-float aligned)
+            lv += wc * hc
+            if wc == 1 and hc == 1:
+                break
+            wc, hc = (wc + 1) // 2, (hc + 1) // 2
+        tab = (lv + 63) // 64 * 64
+        QH, QW = (Hh + 7) // 8, (W + 7) // 8
+        esc = pyr[tab:tab + 16 * QW * QH].reshape(4, QH, QW, 4)
+        quad = pyr[pyr.size - 4 * QW * QH:].reshape(4, QH, QW)
+        bmax = np.full((QH, QW), -np.inf, np.float32)
+        for by in range(QH):
+            for bx in range(QW):
+                bmax[by, bx] = Hf[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].max()
+        for q in range(4):
+            for by in range(0, QH, max(1, QH // 7)):
+                for bx in range(0, QW, max(1, QW // 7)):
+                    assert esc[q, by, bx, 3] == margin(quad[q, by, bx])
+                    for k, D in enumerate((16, 64, 256)):
+                        reach = D // 8 + 1
+                        xl, xh = (bx - 1, bx + reach) if not q & 1 else (bx - reach, bx + 1)
+                        yl, yh = (by - 1, by + reach) if not q & 2 else (by - reach, by + 1)
+                        xl, yl, xh, yh = max(xl, 0), max(yl, 0), min(xh, QW - 1), min(yh, QH - 1)
+                        want = bmax[yl:yh + 1, xl:xh + 1].max()
+                        assert esc[q, by, bx, k] == margin(want), (Hh, W, q, by, bx, k)
+                        # it covers every sample a ray from the block reads within D of travel
+                        sx0 = 8 * bx - 2 if not q & 1 else 8 * bx - D - 2
+                        sx1 = 8 * bx + 7 + D + 2 if not q & 1 else 8 * bx + 9
+                        sy0 = 8 * by - 2 if not q & 2 else 8 * by - D - 2
+                        sy1 = 8 * by + 7 + D + 2 if not q & 2 else 8 * by + 9
+                        win = Hf[max(sy0, 0):min(sy1, Hh - 1) + 1, max(sx0, 0):min(sx1, W - 1) + 1]
+                        assert esc[q, by, bx, k] > win.max()
 
 
 # ---------------------------------------------------------------------------
