@@ -680,9 +680,9 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
     direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
 }
 
-// The tracer is issue- and latency-bound: ask for eight waves per SIMD (at most
-// 64 VGPRs), which measures faster than seven with more registers.
-#define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// The tracer is issue- and latency-bound: ask for seven waves per SIMD (at most
+// 72 VGPRs); eight forces spills to scratch, six measure slower.
+#define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7)))
 
 template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
