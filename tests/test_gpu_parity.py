@@ -368,6 +368,19 @@ def test_quadrant_maxima(dev):
                 assert quad[q, by, bx] == Hf[ys, xs].max(), (q, by, bx)
 
 
+def test_solve_is_deterministic(dev):
+    say("case: the same solve twice, and again after other work on the device")
+    sc = scenes.fbm_terrain(seed=7, size=160, channels=3, num_lights=10, env_shape=(16, 32), ptp=24.0)
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 2, seed=1)
+    args = dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+                env=T(sc.env, dev), spp=16, bounces=3, iterations=3, seed=99)
+    first = {k: H(v) for k, v in irtps.solve(**args).items()}
+    irtps.solve(**dict(args, seed=5))  # unrelated work in between
+    second = {k: H(v) for k, v in irtps.solve(**args).items()}
+    for k in first:
+        assert np.array_equal(first[k], second[k]), k
+
+
 def test_escape_windows(dev):
     """Escape windows per 8 x 8 block and quadrant of travel: the maxima over the
     block ranges that cover what a ray reads within 16, 64 and 256 samples of

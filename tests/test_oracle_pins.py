@@ -62,6 +62,38 @@ def test_philox_is_a_bijection_on_a_counter_slice():
     assert np.unique(packed).size == 1 << 16
 
 
+def _philox_reference(ctr, key):
+    """Philox4x32-10 written here from its definition (Salmon, Moraes, Dror and
+    Shaw, SC'11): ten rounds of two 32x32 -> 64 multiplications by the round
+    multipliers, the high halves mixed with the other counter words and the key,
+    the key bumped by the Weyl constants between rounds.  Independent of the
+    oracle's C code; plain Python integers."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    mask = 0xFFFFFFFF
+    x0, x1, x2, x3 = (int(v) & mask for v in ctr)
+    k0, k1 = (int(v) & mask for v in key)
+    for r in range(10):
+        p0 = M0 * x0
+        p1 = M1 * x2
+        x0, x1, x2, x3 = (((p1 >> 32) ^ x1 ^ k0) & mask, p1 & mask, ((p0 >> 32) ^ x3 ^ k1) & mask, p0 & mask)
+        k0, k1 = (k0 + W0) & mask, (k1 + W1) & mask
+    return [x0, x1, x2, x3]
+
+
+def test_philox_matches_an_independent_implementation():
+    rng = np.random.default_rng(17)
+    ctrs = rng.integers(0, 1 << 32, size=(300, 4), dtype=np.uint64).astype(np.uint32)
+    keys = rng.integers(0, 1 << 32, size=(300, 2), dtype=np.uint64).astype(np.uint32)
+    ctrs[:4] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [1, 2, 3, 4], [0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344]]
+    keys[:4] = [[0, 0], [0xFFFFFFFF] * 2, [5, 6], [0xA4093822, 0x299F31D0]]
+    for c, k in zip(ctrs, keys):
+        assert list(O.philox(c.tolist(), k.tolist())) == _philox_reference(c, k), (c, k)
+    # the batch entry point draws the same words
+    out = O.philox_n(ctrs, (int(keys[2, 0]), int(keys[2, 1])))
+    for c, o in zip(ctrs[:20], out[:20]):
+        assert o.tolist() == _philox_reference(c, keys[2])
+
+
 # ---------------------------------------------------------------------------
 # Polynomials standing in for transcendentals.
 def test_sincos_quarter_exhaustive():
