@@ -120,8 +120,10 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     };
     start();
     while (k < K) {
+        // two steps per pass halve the divergent branch back to the loop head
         int qi, qj;
-        const int res = trv::walker_step(w, S, qi, qj);
+        int res = trv::walker_step(w, S, qi, qj);
+        if (res == trv::kGoOn) res = trv::walker_step(w, S, qi, qj);
         if (res != trv::kGoOn) {
             out[k] = res == trv::kHit ? 0.0f : s[k] * c;
             ++k;

@@ -75,6 +75,14 @@ struct Surface {
     float hmax;          // highest sample
 };
 
+// Loads through a 32-bit byte offset from a wave-uniform base, so that the
+// address is one scalar base plus one vector offset.  Every table a walk reads
+// (samples, pyramid, escape windows) is below 2^32 bytes: W H <= 2^28.
+template <class T>
+__device__ __forceinline__ T ld32(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 // Per-ray state shared by both walks.  The cell search uses the origin nudged
 // by kNudge along the travel direction (nx0, ny0); crossings use the exact
 // origin (i0, j0).
@@ -83,6 +91,7 @@ struct Ray {
     float slope;           // rise per unit of horizontal travel, rounded down (0 if not rising)
     float ainv_x, ainv_y;  // |1/dx|, |1/dy| (+inf for a zero component)
     int i0, j0, sx, sy;
+    int qrow;              // first block row of the ray's quadrant in the escape windows
 };
 
 // Cells are chosen at the ray's position nudged this far along the travel
@@ -95,12 +104,13 @@ __device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float 
     Ray r;
     r.i0 = i0;
     r.j0 = j0;
-    r.oz = S.H[j0 * S.W + i0];
+    r.oz = ld32(S.H, (unsigned)(j0 * S.W + i0));
     r.dx = dx;
     r.dy = dy;
     r.dz = dz;
     r.sx = signbit(dx) ? -1 : 1;
     r.sy = signbit(dy) ? -1 : 1;
+    r.qrow = ((r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0)) * S.QH;
     r.nx0 = (float)i0 + (float)r.sx * kNudge;
     r.ny0 = (float)j0 + (float)r.sy * kNudge;
     r.ainv_x = fabsf(1.0f / dx);
@@ -119,39 +129,6 @@ __device__ __forceinline__ float t_y(const Ray& r, int m) { return (float)m * r.
 
 enum : int { kMiss = 0, kHit = 1, kGoOn = 2 };
 
-// Evaluate one crossing; returns kHit (q set), kMiss (escaped) or kGoOn.
-__device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xline, float t,
-                                        int mx, int my, int& qi, int& qj) {
-    const int major = xline ? r.i0 + r.sx * mx : r.j0 + r.sy * my;
-    const int n_major = xline ? S.W : S.Hh;
-    const int n_minor = xline ? S.Hh : S.W;
-    if (major < 0 || major > n_major - 1) return kMiss;
-    const float minor = fmaf(t, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
-    if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
-    const int m0 = (int)floorf(minor);
-    const float f = minor - (float)m0;
-    const int idx0 = xline ? m0 * S.W + major : major * S.W + m0;
-    const float h0 = S.H[idx0];
-    float h = h0;
-    if (f != 0.0f) {
-        const float h1 = S.H[idx0 + (xline ? S.W : 1)];
-        h = fmaf(f, h1 - h0, h0);
-        const float lo = h0 < h1 ? h0 : h1;
-        const float hi = h0 < h1 ? h1 : h0;
-        h = h < lo ? lo : h;
-        h = h > hi ? hi : h;
-    }
-    const float z = fmaf(t, r.dz, r.oz);
-    if (z < h) {
-        const int qm = f < 0.5f ? m0 : m0 + 1;
-        qi = xline ? major : qm;
-        qj = xline ? qm : major;
-        return kHit;
-    }
-    if (z >= S.hmax && r.dz >= 0.0f) return kMiss;
-    return kGoOn;
-}
-
 // A rising ray at height z in a block escapes when, over each stretch of
 // horizontal travel, its lowest height clears the highest sample it can read
 // there: z clears the first window; after escape_scale(k) of travel it has
@@ -159,57 +136,61 @@ __device__ __forceinline__ int crossing(const Surface& S, const Ray& r, bool xli
 // last scale, the quadrant maximum (win.w).  z grows with t exactly as the
 // crossings compute it (fma, monotone); the windows carry the rounding margin.
 __device__ __forceinline__ bool escapes(float z, float slope, const float4& win) {
-    return z >= win.x && fmaf(slope, (float)escape_scale(0), z) >= win.y &&
-           fmaf(slope, (float)escape_scale(1), z) >= win.z && fmaf(slope, (float)escape_scale(2), z) >= win.w;
+    // all four tests, without short-circuit branches
+    return (z >= win.x) & (fmaf(slope, (float)escape_scale(0), z) >= win.y) &
+           (fmaf(slope, (float)escape_scale(1), z) >= win.z) & (fmaf(slope, (float)escape_scale(2), z) >= win.w);
 }
 
-// Smallest crossing index m >= 1 whose t (same formula as the walk) is >= t_lim.
-__device__ __forceinline__ int first_index_at_or_after(const Ray& r, bool xline, float t_lim) {
-    const float d_abs = xline ? fabsf(r.dx) : fabsf(r.dy);
-    const float est = ceilf(t_lim * d_abs);
-    int m = est > 2.0e9f ? 2000000000 : (est < 1.0f ? 1 : (int)est);
-    const float ainv = xline ? r.ainv_x : r.ainv_y;
-    // the estimate is almost always exact or one off: keep the loops rolled
-#pragma unroll 1
-    while (m > 1 && (float)(m - 1) * ainv >= t_lim) --m;
-#pragma unroll 1
-    while ((float)m * ainv < t_lim) ++m;
-    return m;
+// Smallest crossing index m >= 1 whose t = m ainv (the walk's own product) is
+// >= t_lim, with that t.  The answer is within one of ceil(t_lim |d|): ainv and
+// each product round to within 2^-24 relative, so with t_lim |d| (the travel
+// along the axis, at most the domain's side, < 2^15) the exact threshold moves
+// by less than 2^-8 of an index, and the rounded estimate by less than 2^-9;
+// both ceilings therefore differ by at most one.  For ainv = inf (no travel
+// along the axis) the result is m = 1, t = inf.
+__device__ __forceinline__ int first_index_at_or_after(float ainv, float d_abs, float t_lim, float& t_m) {
+    const float est = fmaxf(ceilf(t_lim * d_abs), 1.0f);
+    const float lo = est - 1.0f, hi = est + 1.0f;
+    const float t_lo = lo * ainv, t_est = est * ainv, t_hi = hi * ainv;
+    const bool take_lo = lo >= 1.0f && t_lo >= t_lim;
+    const bool take_est = t_est >= t_lim;
+    t_m = take_lo ? t_lo : (take_est ? t_est : t_hi);
+    return (int)(take_lo ? lo : (take_est ? est : hi));
 }
 
 // Finest pyramid level the walker tries to skip (cells of 4 x 4 sample gaps).
 constexpr int kMinSkipLevel = 2;
-// Resumable walk.  Every crossing with t < t_cur has been evaluated or lies in
-// a skipped cell.  In fine mode (mx, my, tX, tY) name the next crossing of each
-// family; in coarse mode only t_cur (the exit of the last skipped cell) is kept
-// and both families are rebuilt from it when the walker drops to crossing
-// evaluation.  level < 0 walks every crossing.
+// Resumable walk.  (mx, tX) and (my, tY) name the next crossing of each family;
+// every crossing before min(tX, tY) has been evaluated or lies in a skipped
+// cell.  level < 0 walks every crossing.
 struct Walker {
     Ray r;
-    float t_cur, tX, tY;
+    float tX, tY;
     int mx, my, level;
-    bool fine;
 };
 
 __device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0, int j0, float dx,
                                             float dy, float dz, bool flat) {
     w.r = make_ray(S, i0, j0, dx, dy, dz);
-    w.t_cur = 0.0f;
     w.mx = 1;
     w.my = 1;
     w.level = flat ? -1 : kMinSkipLevel;
-    w.fine = true;
     // a ray along z has no crossings: t = inf on both families ends the walk
     const bool vertical = dx == 0.0f && dy == 0.0f;
     w.tX = vertical ? __builtin_inff() : t_x(w.r, 1);
     w.tY = vertical ? __builtin_inff() : t_y(w.r, 1);
 }
 
-// Returns kGoOn, kHit (qi, qj set) or kMiss.
+// One step: a pyramid cell test (skip it, climb, descend or give up to crossing
+// evaluation), or the evaluation of the next crossing.  Returns kGoOn, kHit
+// (qi, qj set) or kMiss.
 __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi, int& qj) {
     const Ray& r = w.r;
-    if (w.fine && isinf(w.tX) && isinf(w.tY)) return kMiss;
-    const float t_now = w.fine ? (w.tX <= w.tY ? w.tX : w.tY) : w.t_cur;
+    const bool xline = w.tX <= w.tY;  // the next crossing is on an x-line (first on a tie)
+    // t_now = inf (no crossing left: a ray along z) ends the walk in this step:
+    // z_now is +inf (caught just below), or -inf or NaN, and then the position
+    // is not interior and the crossing's minor coordinate is not in the domain
+    const float t_now = xline ? w.tX : w.tY;
     const float z_now = fmaf(t_now, r.dz, r.oz);
     const bool rising = r.dz >= 0.0f;
     // at or above every sample and not descending: no crossing ahead can hit
@@ -219,35 +200,45 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
         const float py = fmaf(t_now, r.dy, r.ny0);
         if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
             const int l = w.level;
-            const int ix = (int)px, iy = (int)py;  // px, py > 0: truncation is floor
+            const unsigned ix = (unsigned)px, iy = (unsigned)py;  // px, py > 0: truncation is floor
             // Escape windows of the block holding the (nudged) position: every
             // sample a later crossing can read within escape_scale(k) of travel
             // lies in window k (one sample behind the block going +, the lerp's
             // second sample and the nudge included), and everything ahead in the
             // block-aligned quadrant.
-            const int quadrant = (r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0);
-            const float4 win = S.esc[(quadrant * S.QH + (iy >> kQuadShift)) * S.QW + (ix >> kQuadShift)];
-            const int cx = ix >> l;
-            const int cy = iy >> l;
+            const float4 win = ld32(S.esc, __umul24((unsigned)r.qrow + (iy >> kQuadShift), (unsigned)S.QW) +
+                                               (ix >> kQuadShift));
+            const unsigned cx = ix >> l, cy = iy >> l;
             const int2 lv = S.lvl[l];
-            const float cmax = S.pyr[lv.x + cy * lv.y + cx];  // +inf near the border
+            const float cmax = ld32(S.pyr, (unsigned)lv.x + __umul24(cy, (unsigned)lv.y) + cx);  // +inf near the border
             // both loads are issued before either result is tested (one wait)
             __asm__ volatile("" : : "v"(cmax), "v"(win.x), "v"(win.y), "v"(win.z), "v"(win.w));
-            // exit of the cell along the ray (computed while the loads are in flight)
+            // exit of the cell along the ray (computed while the loads are in
+            // flight): the crossing index of its far edge in x and in y, >= 1
+            // because the nudged position lies beyond the origin's lines
             const int size = 1 << l;
-            const int mxe = (cx << l) + (r.sx > 0 ? size : 0) - r.i0;
-            const int mye = (cy << l) + (r.sy > 0 ? size : 0) - r.j0;
-            const int mxa = r.sx > 0 ? mxe : -mxe, mya = r.sy > 0 ? mye : -mye;
-            const float txe = mxa >= 1 ? t_x(r, mxa) : __builtin_inff();
-            const float tye = mya >= 1 ? t_y(r, mya) : __builtin_inff();
-            const float t_exit = txe <= tye ? txe : tye;
+            const int ex = (int)(cx << l) - r.i0, ey = (int)(cy << l) - r.j0;
+            const int mxa = r.sx > 0 ? ex + size : -ex;
+            const int mya = r.sy > 0 ? ey + size : -ey;
+            const float txe = t_x(r, mxa), tye = t_y(r, mya);
+            const bool x_exit = txe <= tye;
+            const float t_exit = x_exit ? txe : tye;
             const float z_exit = fmaf(t_exit, r.dz, r.oz);
             if (rising && escapes(z_now, r.slope, win)) return kMiss;
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
-            // the ray is at or above its maximum over that range
-            if (z_now >= cmax && t_exit > t_now && !isinf(t_exit) && z_exit >= cmax) {
-                w.t_cur = t_exit;
-                w.fine = false;
+            // the ray is at or above its maximum over that range (t_exit is finite:
+            // a ray with no travel along either axis never gets here)
+            if ((z_now >= cmax) & (z_exit >= cmax) & (t_exit > t_now)) {
+                // Resume at the first crossing of each family at or after t_exit:
+                // the exit line itself for the family the ray leaves through (t is
+                // strictly increasing in the index), a search for the other.
+                float t_o;
+                const int m_o = first_index_at_or_after(x_exit ? r.ainv_y : r.ainv_x,
+                                                        fabsf(x_exit ? r.dy : r.dx), t_exit, t_o);
+                w.mx = x_exit ? mxa : m_o;
+                w.tX = x_exit ? t_exit : t_o;
+                w.my = x_exit ? m_o : mya;
+                w.tY = x_exit ? t_o : t_exit;
                 if (l < S.top) w.level = l + 1;
                 return kGoOn;
             }
@@ -257,32 +248,45 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             }
         }
     }
-    if (!w.fine) {
-        // back to crossing-by-crossing: each family's first crossing at or
-        // after t_cur
-        if (!isinf(r.ainv_x)) {
-            w.mx = first_index_at_or_after(r, true, w.t_cur);
-            w.tX = t_x(r, w.mx);
-        }
-        if (!isinf(r.ainv_y)) {
-            w.my = first_index_at_or_after(r, false, w.t_cur);
-            w.tY = t_y(r, w.my);
-        }
-        w.fine = true;
-        if (isinf(w.tX) && isinf(w.tY)) return kMiss;
+    // Evaluate the nearer crossing at t = t_now and height z_now.  It hits when
+    // the ray is strictly below the surface there; the shading sample is the
+    // nearer end of that grid segment.
+    const int m = xline ? w.mx : w.my;
+    const int o_major = xline ? r.i0 : r.j0;
+    const int major = (xline ? r.sx > 0 : r.sy > 0) ? o_major + m : o_major - m;
+    const int n_major = xline ? S.W : S.Hh;
+    if ((unsigned)major > (unsigned)(n_major - 1)) return kMiss;
+    const int n_minor = xline ? S.Hh : S.W;
+    const float minor = fmaf(t_now, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
+    if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
+    const float fm = floorf(minor);
+    const int m0 = (int)fm;
+    const float f = minor - fm;
+    const unsigned idx0 = xline ? __umul24((unsigned)m0, (unsigned)S.W) + (unsigned)major
+                                : __umul24((unsigned)major, (unsigned)S.W) + (unsigned)m0;
+    // the segment's second sample (the first again when the crossing is on a
+    // sample: then the lerp below returns h0 without reading past the border)
+    const unsigned step1 = f != 0.0f ? (xline ? (unsigned)S.W : 1u) : 0u;
+    const float h0 = ld32(S.H, idx0);
+    const float h1 = ld32(S.H, idx0 + step1);
+    // h0 + f (h1 - h0), clamped to the segment's range (the median of the three)
+    const float h = __builtin_amdgcn_fmed3f(fmaf(f, h1 - h0, h0), h0, h1);
+    if (z_now < h) {
+        const int qm = f < 0.5f ? m0 : m0 + 1;
+        qi = xline ? major : qm;
+        qj = xline ? qm : major;
+        return kHit;
     }
-    const bool xline = w.tX <= w.tY;
-    const int res = crossing(S, r, xline, xline ? w.tX : w.tY, w.mx, w.my, qi, qj);
-    if (res == kGoOn) {
-        if (xline) {
-            ++w.mx;
-            w.tX = t_x(r, w.mx);
-        } else {
-            ++w.my;
-            w.tY = t_y(r, w.my);
-        }
+    const int m1 = m + 1;
+    const float t1 = (float)m1 * (xline ? r.ainv_x : r.ainv_y);
+    if (xline) {
+        w.mx = m1;
+        w.tX = t1;
+    } else {
+        w.my = m1;
+        w.tY = t1;
     }
-    return res;
+    return kGoOn;
 }
 
 // Whole walk in one call (shadow rays, probes).
