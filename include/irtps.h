@@ -157,10 +157,23 @@ int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes);
 /* Per level l, cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l]
  * and stores the max over that box grown by one sample on each side, or +inf
  * when the box comes within two samples of the border (cx 2^l < 2 or
- * (cx+1) 2^l > W - 3, likewise in y).  Four quadrant tables follow the levels, one per
- * sign pair (sx, sy) of a ray's travel, q = (sx < 0) + 2 (sy < 0), each
- * ceil(H/8) x ceil(W/8): entry (by, bx) is the max over the samples (x, y) with
- * x >= 8 bx (sx > 0) or x <= 8 bx + 7 (sx < 0), and likewise along y. */
+ * (cx+1) 2^l > W - 3, likewise in y).  Block tables follow the levels (from the
+ * next multiple of 64 floats), over 8 x 8 sample blocks, QW = ceil(W/8),
+ * QH = ceil(H/8), p4 = QW QH rounded up to a multiple of 4, s4 = the count of
+ * 64 x 64 super-blocks rounded up likewise; q = (sx < 0) + 2 (sy < 0) names
+ * the sign pair of a ray's travel.  In floats from the tables' start:
+ *   0       escape windows float4 [4][QH][QW]
+ *   16 p4   block maxima [QH][QW]
+ *   17 p4   window row maxima [2][3][QH][QW] (build scratch)
+ *   25 p4   quadrant maxima [4][QH][QW]: max over samples with x >= 8 bx
+ *           (sx > 0) or x <= 8 bx + 7 (sx < 0), likewise along y
+ *   29 p4   block minima [QH][QW]
+ *   30 p4   horizon chords float4 [4][QH][QW] (a_mid, k_mid, a_far, k_far)
+ *   46 p4   super-block maxima
+ *   46 p4 + s4   near horizons float4 [H][W] (the four quadrants of a sample)
+ * A rising ray from a sample whose slope (rise per unit of horizontal travel)
+ * is at least the sample's near horizon for its quadrant and both chords
+ * a + k h at the sample's height h cannot hit anything. */
 int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyramid_dev,
                         void* stream);
 

@@ -105,7 +105,7 @@ inline long long pyramid_level_floats(const trv::Pyramid& P) {
 
 // Apron-max levels followed by the four quadrant-maximum planes.
 inline long long pyramid_floats(int W, int H) {
-    return pyramid_level_floats(pyramid_plan(W, H)) + trv::block_tables_floats(trv::quad_cells(W), trv::quad_cells(H));
+    return pyramid_level_floats(pyramid_plan(W, H)) + trv::block_tables_floats(W, H);
 }
 
 inline kern::MgPlan mg_plan(int W, int H) {

@@ -46,8 +46,11 @@ __device__ __forceinline__ Surface make_surface(const float* H, const float* pyr
     S.QW = trv::quad_cells(W);
     S.QH = trv::quad_cells(Hh);
     const float* tab = pyr + quad_off;
+    const long long p4 = trv::block_plane4(S.QW, S.QH);
     S.esc = reinterpret_cast<const float4*>(tab);
-    S.quad = tab + 25 * trv::block_plane4(S.QW, S.QH);
+    S.quad = tab + 25 * p4;
+    S.hzb = reinterpret_cast<const float4*>(tab + 30 * p4);
+    S.nearh = tab + trv::near_horizon_offset(W, Hh);
     S.top = levels - 1;
     S.hmax = S.quad[0];  // quadrant (+x, +y) of block (0, 0): every sample
     return S;
@@ -106,7 +109,9 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     int k = 0;
     float c = 0.0f;
     trv::Walker w;
-    // move to the next light facing the sample (the others give 0)
+    // move to the next light facing the sample (the others give 0).  Shadow
+    // rays skip the horizon test: its loads cost more here than the steps it
+    // saves, since a wave waits for its slowest lane's lights anyway.
     auto start = [&]() {
         for (; k < K; ++k) {
             const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
@@ -232,7 +237,12 @@ struct BlockTables {
     float* bmax;
     float* rowmax;
     float* quad;
+    float* bmin;
+    float4* hzb;
+    float* smax;
+    float4* nearh;
     int QW, QH;
+    int SW, SH;       // super-blocks
     long long plane;  // QW QH
 };
 
@@ -246,22 +256,211 @@ __device__ __forceinline__ BlockTables block_tables(float* tab, int W, int Hh) {
     t.bmax = tab + 16 * p4;
     t.rowmax = tab + 17 * p4;
     t.quad = tab + 25 * p4;
+    t.bmin = tab + 29 * p4;
+    t.hzb = reinterpret_cast<float4*>(tab + 30 * p4);
+    t.smax = tab + 46 * p4;
+    t.nearh = reinterpret_cast<float4*>(tab + trv::near_horizon_offset(W, Hh));
+    t.SW = trv::super_cells(W);
+    t.SH = trv::super_cells(Hh);
     return t;
 }
 
-// Block maxima of H over 8 x 8 sample blocks.
+// Block maxima and minima of H over 8 x 8 sample blocks.
 __device__ __forceinline__ void quad_block(int b, int W, int Hh, const float* __restrict__ H,
                                            const BlockTables& t) {
     const int bx = b % t.QW, by = b / t.QW;
     const int x0 = bx << trv::kQuadShift, y0 = by << trv::kQuadShift;
     const int x1 = min(x0 + (1 << trv::kQuadShift), W), y1 = min(y0 + (1 << trv::kQuadShift), Hh);
-    float m = H[(size_t)y0 * W + x0];
+    float m = H[(size_t)y0 * W + x0], n = m;
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) {
             const float v = H[(size_t)y * W + x];
             m = v > m ? v : m;
+            n = v < n ? v : n;
         }
     t.bmax[b] = m;
+    t.bmin[b] = n;
+}
+
+// Super-block maxima: the largest block maximum of each 64 x 64 super-block.
+__device__ __forceinline__ void super_block(int c, const BlockTables& t) {
+    constexpr int kBlocks = 1 << (trv::kSuperShift - trv::kQuadShift);
+    const int sx = c % t.SW, sy = c / t.SW;
+    const int bx0 = sx * kBlocks, by0 = sy * kBlocks;
+    const int bx1 = min(bx0 + kBlocks, t.QW), by1 = min(by0 + kBlocks, t.QH);
+    float m = t.bmax[(size_t)by0 * t.QW + bx0];
+    for (int y = by0; y < by1; ++y)
+        for (int x = bx0; x < bx1; ++x) {
+            const float v = t.bmax[(size_t)y * t.QW + x];
+            m = v > m ? v : m;
+        }
+    t.smax[c] = m;
+}
+
+// A bound computed in binary32 raised above every rounding of its terms.
+__device__ __forceinline__ float raise_bound(float m) { return isinf(m) ? m : m + fabsf(m) * 1e-5f + 1e-7f; }
+
+// Square root at compile time (Newton's iteration in binary64; the tables
+// built with it keep a relative slack far above its error).
+constexpr double ce_sqrt(double x) {
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+// 1 / d for the mid bound between a block and the block (ca, cb) blocks ahead:
+// d = max(kHorizonReach, gap - 1.5), gap the least distance between their
+// samples; rounded up to binary32.
+struct MidInverse {
+    float v[trv::kMidBlocks + 2][trv::kMidBlocks + 2];
+};
+constexpr MidInverse mid_inverse() {
+    MidInverse t{};
+    constexpr int kBS = 1 << trv::kQuadShift;
+    for (int cb = 0; cb < trv::kMidBlocks + 2; ++cb)
+        for (int ca = 0; ca < trv::kMidBlocks + 2; ++ca) {
+            const double gx = ca * kBS - (kBS - 1) > 0 ? ca * kBS - (kBS - 1) : 0;
+            const double gy = cb * kBS - (kBS - 1) > 0 ? cb * kBS - (kBS - 1) : 0;
+            double d = ce_sqrt(gx * gx + gy * gy) * (1.0 - 1e-9) - 1.5;
+            d = d > (double)trv::kHorizonReach ? d : (double)trv::kHorizonReach;
+            t.v[cb][ca] = (float)(1.0 / d * (1.0 + 1e-7));
+        }
+    return t;
+}
+__constant__ MidInverse k_mid_inv = mid_inverse();
+
+// Mid and far horizon bounds of block b for quadrant q (run after the block,
+// super-block and quadrant maxima).  For each far region R with maximum M_R at
+// least d_R of travel away, the slope needed from a sample of height h is
+// (escape_margin(M_R) - h) / d_R; the maximum over the regions is convex in h,
+// so its chord between the block's lowest and highest sample bounds it there.
+__device__ __forceinline__ void horizon_block(int b, int q, const BlockTables& t) {
+    const int bx = b % t.QW, by = b / t.QW;
+    const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+    const float lo = t.bmin[b], hi = t.bmax[b];
+    constexpr int kBS = 1 << trv::kQuadShift;
+    float mid_lo = -__builtin_inff(), mid_hi = -__builtin_inff();
+    for (int cb = 0; cb <= trv::kMidBlocks + 1; ++cb) {
+        const int cy = by + sy * cb;
+        if (cy < 0 || cy >= t.QH) break;
+        for (int ca = 0; ca <= trv::kMidBlocks + 1; ++ca) {
+            const int cx = bx + sx * ca;
+            if (cx < 0 || cx >= t.QW) break;
+            const float inv = k_mid_inv.v[cb][ca];
+            const float M = trv::escape_margin(t.bmax[(size_t)cy * t.QW + cx]);
+            mid_lo = fmaxf(mid_lo, (M - lo) * inv);
+            mid_hi = fmaxf(mid_hi, (M - hi) * inv);
+        }
+    }
+    // far: super-blocks ahead of the block (the one holding it included), then
+    // everything else in the quadrant at kFarQuadrantTravel or more
+    constexpr int kSS = 1 << trv::kSuperShift;
+    const int X0 = bx * kBS, Y0 = by * kBS;
+    const int hx = X0 >> trv::kSuperShift, hy = Y0 >> trv::kSuperShift;
+    const float mid_floor = (float)(trv::kMidBlocks * kBS);
+    const float Mq = trv::escape_margin(t.quad[q * t.plane + b]);
+    float far_lo = (Mq - lo) / trv::kFarQuadrantTravel, far_hi = (Mq - hi) / trv::kFarQuadrantTravel;
+    for (int cb = 0; cb <= trv::kFarSupers + 1; ++cb) {
+        const int cy = hy + sy * cb;
+        if (cy < 0 || cy >= t.SH) break;
+        const int y0 = cy * kSS, y1 = y0 + kSS - 1;
+        const float gy = (float)max(0, max(y0 - (Y0 + kBS - 1), Y0 - y1));
+        for (int ca = 0; ca <= trv::kFarSupers + 1; ++ca) {
+            const int cx = hx + sx * ca;
+            if (cx < 0 || cx >= t.SW) break;
+            const int x0 = cx * kSS, x1 = x0 + kSS - 1;
+            const float gx = (float)max(0, max(x0 - (X0 + kBS - 1), X0 - x1));
+            // hardware square root and reciprocal (within 1 ulp each), the
+            // distance lowered and its inverse raised by far more than that
+            float d = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy)) * (1.0f - 1e-6f) - 1.5f;
+            d = d > mid_floor ? d : mid_floor;
+            const float inv = __builtin_amdgcn_rcpf(d) * (1.0f + 1e-6f);
+            const float M = trv::escape_margin(t.smax[(size_t)cy * t.SW + cx]);
+            far_lo = fmaxf(far_lo, (M - lo) * inv);
+            far_hi = fmaxf(far_hi, (M - hi) * inv);
+        }
+    }
+    // chords a + k h through (lo, f(lo)) and (hi, f(hi)), evaluated in binary64
+    // and raised by more than the rounding of a, k and of fma(k, h, a)
+    auto chord = [&](float f_lo, float f_hi, float& a_out, float& k_out) {
+        const double flo = raise_bound(f_lo), fhi = raise_bound(f_hi);
+        const double k = hi > lo ? (fhi - flo) / ((double)hi - (double)lo) : 0.0;
+        const double a = flo - k * (double)lo;
+        const double hm = fabs((double)lo) > fabs((double)hi) ? fabs((double)lo) : fabs((double)hi);
+        const double slack = 0x1p-21 * (fabs(a) + fabs(k) * hm) + 1e-7;
+        a_out = (float)(a + slack);
+        k_out = (float)k;
+    };
+    float am, km, af, kf;
+    chord(mid_lo, mid_hi, am, km);
+    chord(far_lo, far_hi, af, kf);
+    t.hzb[q * t.plane + b] = make_float4(am, km, af, kf);
+}
+
+// Near horizons of a 16 x 16 tile of samples, from an LDS copy of
+// escape_margin(H) with an apron of kHorizonReach + 1 (-inf outside the domain).
+constexpr int kNearTile = 16;
+constexpr int kNearApron = trv::kHorizonReach + 1;
+constexpr int kNearSpan = kNearTile + 2 * kNearApron;
+constexpr int kNearOff = kNearApron + 1;  // offsets 0 .. kNearApron along each axis
+
+// 1 / tmin(a, b) with tmin lowered by 0.01 per minor offset and 1e-6 relative
+// (the rounding of crossing positions), 0 where tmin exceeds kHorizonReach; and
+// per row b the last a with a weight (tmin grows with a).  Computed at compile
+// time in binary64 and rounded up to binary32.
+struct NearWeights {
+    float w[kNearOff][kNearOff];
+    int last[kNearOff];
+};
+constexpr NearWeights near_weights() {
+    NearWeights t{};
+    for (int b = 0; b < kNearOff; ++b) {
+        t.last[b] = -1;
+        for (int a = 0; a < kNearOff; ++a) {
+            const double am = a - 1.01 > 0.0 ? a - 1.01 : 0.0, bm = b - 1.01 > 0.0 ? b - 1.01 : 0.0;
+            const double tx = a >= 1 ? ce_sqrt((double)a * a + bm * bm) : 1e300;
+            const double ty = b >= 1 ? ce_sqrt(am * am + (double)b * b) : 1e300;
+            const double tt = (tx < ty ? tx : ty) * (1.0 - 1e-6);
+            t.w[b][a] = tt <= (double)trv::kHorizonReach ? (float)(1.0 / tt * (1.0 + 1e-7)) : 0.0f;
+            if (t.w[b][a] > 0.0f) t.last[b] = a;
+        }
+    }
+    return t;
+}
+__constant__ NearWeights k_near_w = near_weights();
+
+__device__ __forceinline__ void near_tile(int W, int Hh, const float* __restrict__ H, int tile_x, int tile_y,
+                                          float4* __restrict__ nearh, float* s_e) {
+    const int X0 = tile_x * kNearTile - kNearApron, Y0 = tile_y * kNearTile - kNearApron;
+    for (int k = threadIdx.x; k < kNearSpan * kNearSpan; k += blockDim.x) {
+        const int x = X0 + k % kNearSpan, y = Y0 + k / kNearSpan;
+        s_e[k] = (x >= 0 && x < W && y >= 0 && y < Hh) ? trv::escape_margin(H[(size_t)y * W + x]) : -__builtin_inff();
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kNearTile, ty = threadIdx.x / kNearTile;
+    const int x = tile_x * kNearTile + tx, y = tile_y * kNearTile + ty;
+    if (x >= W || y >= Hh) return;
+    const float hp = H[(size_t)y * W + x];
+    // the four quadrants together (q = (dx < 0) + 2 (dy < 0)): one weight
+    // serves four independent terms
+    const float* c = s_e + (ty + kNearApron) * kNearSpan + (tx + kNearApron);
+    float m0 = -__builtin_inff(), m1 = m0, m2 = m0, m3 = m0;
+#pragma unroll 1
+    for (int b = 0; b < kNearOff; ++b) {
+        const float* up = c + b * kNearSpan;  // dy >= 0
+        const float* dn = c - b * kNearSpan;  // dy < 0
+        const int last = k_near_w.last[b];
+#pragma unroll 2
+        for (int a = b == 0 ? 1 : 0; a <= last; ++a) {  // (0, 0) is the sample itself
+            const float w = k_near_w.w[b][a];
+            m0 = fmaxf(m0, (up[a] - hp) * w);
+            m1 = fmaxf(m1, (up[-a] - hp) * w);
+            m2 = fmaxf(m2, (dn[a] - hp) * w);
+            m3 = fmaxf(m3, (dn[-a] - hp) * w);
+        }
+    }
+    const float m[4] = {raise_bound(m0), raise_bound(m1), raise_bound(m2), raise_bound(m3)};
+    nearh[(size_t)y * W + x] = make_float4(m[0], m[1], m[2], m[3]);
 }
 
 // Quadrant maxima over blocks: quad[q][by][bx] = max of H over samples (x, y)
@@ -492,6 +691,8 @@ __device__ __forceinline__ void min_key_strided(const float* __restrict__ X, lon
 // theirs, with a phase that shades the finished segments and starts the next
 // ones.  A lane's segments are summed in (sample, bounce) order.
 constexpr int kStepsPerVote = 3;
+// Shading rounds in a row for segments the horizon bounds let go at once.
+constexpr int kEscapeRounds = 3;
 
 // One hit's share: g[k C + c] = fma(wgt[c], Sq[k], g[k C + c]) for every light
 // and channel, in that order per element.  With vec4, four lights at a time
@@ -567,6 +768,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     int ci = i, cj = j;  // sample the current segment starts from
     trv::Walker w;
     bool need_setup = !finished;
+    int chain = 0;  // shading rounds since the last traversal phase
 
     for (;;) {
         n_seg += __popcll(__ballot(need_setup));
@@ -584,10 +786,18 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             const float* nq = a.n + 3 * (cj * a.sa.W + ci);
             const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
             trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
+            // a segment the horizon bounds let go is ready at once (an escape)
+            ready = trv::leaves_at_once(w, S);
+            res = trv::kMiss;
             need_setup = false;
-            ready = false;
         }
         if (__all(finished)) break;
+        // Segments let go at once are shaded (and replaced) straight away, for a
+        // few rounds, so that their lanes do not sit out a traversal phase.
+        if (chain < kEscapeRounds && __any(!finished && ready)) {
+            ++chain;
+        } else {
+        chain = 0;
         // traversal phase
         for (;;) {
             // a few walker steps per pair of ballots: a lane that finishes early
@@ -602,6 +812,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             const int n_act = __popcll(__ballot(!finished));
             const int n_rdy = __popcll(__ballot(!finished && ready));
             if (n_rdy >= (n_act < batch ? n_act : batch)) break;
+        }
         }
         // shading phase
         {
@@ -746,6 +957,25 @@ __global__ void __launch_bounds__(256) k_quad_blocks(int W, int Hh, const float*
     const BlockTables t = block_tables(tab, W, Hh);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < t.plane) quad_block(b, W, Hh, H, t);
+}
+
+__global__ void __launch_bounds__(256) k_super_blocks(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < t.SW * t.SH) super_block(c, t);
+}
+
+__global__ void __launch_bounds__(256) k_horizon_blocks(int W, int Hh, float* __restrict__ tab) {
+    const BlockTables t = block_tables(tab, W, Hh);
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < 4 * t.plane) horizon_block((int)(v >> 2), (int)(v & 3), t);
+}
+
+__global__ void __launch_bounds__(256) k_horizon_near(int W, int Hh, const float* __restrict__ H,
+                                                      float* __restrict__ tab) {
+    __shared__ float s_e[kNearSpan * kNearSpan];
+    const BlockTables t = block_tables(tab, W, Hh);
+    near_tile(W, Hh, H, blockIdx.x, blockIdx.y, t.nearh, s_e);
 }
 
 __global__ void __launch_bounds__(64) k_quad_rows(int W, int Hh, float* __restrict__ tab) {
@@ -979,6 +1209,30 @@ __global__ void __launch_bounds__(256) k_quad_blocks_multi(const JobDesc* __rest
     if (iterating(J) && b < t.plane) quad_block(b, J.W, J.Hh, J.depth, t);
 }
 
+__global__ void __launch_bounds__(256) k_super_blocks_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && c < t.SW * t.SH) super_block(c, t);
+}
+
+__global__ void __launch_bounds__(256) k_horizon_blocks_multi(const JobDesc* __restrict__ jobs) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (iterating(J) && v < 4 * t.plane) horizon_block((int)(v >> 2), (int)(v & 3), t);
+}
+
+// grid.x walks the tiles of the largest job; each job uses its own tile grid
+__global__ void __launch_bounds__(256) k_horizon_near_multi(const JobDesc* __restrict__ jobs) {
+    __shared__ float s_e[kNearSpan * kNearSpan];
+    const JobDesc& J = jobs[blockIdx.y];
+    const int tiles_x = (J.W + kNearTile - 1) / kNearTile, tiles_y = (J.Hh + kNearTile - 1) / kNearTile;
+    if (!iterating(J) || (int)blockIdx.x >= tiles_x * tiles_y) return;  // uniform per block
+    const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
+    near_tile(J.W, J.Hh, J.depth, (int)blockIdx.x % tiles_x, (int)blockIdx.x / tiles_x, t.nearh, s_e);
+}
+
 __global__ void __launch_bounds__(64) k_quad_rows_multi(const JobDesc* __restrict__ jobs) {
     const JobDesc& J = jobs[blockIdx.y];
     const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
@@ -1190,6 +1444,11 @@ hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, f
     hipLaunchKernelGGL(k_quad_cols, dim3(blocks_for(QW, 64)), dim3(64), 0, st, W, Hh, tab);
     hipLaunchKernelGGL(k_escape_rows, dim3(gb), dim3(256), 0, st, W, Hh, tab);
     hipLaunchKernelGGL(k_escape_cols, dim3(gb), dim3(256), 0, st, W, Hh, tab);
+    const long long supers = (long long)trv::super_cells(W) * trv::super_cells(Hh);
+    hipLaunchKernelGGL(k_super_blocks, dim3(blocks_for(supers, 256)), dim3(256), 0, st, W, Hh, tab);
+    hipLaunchKernelGGL(k_horizon_blocks, dim3(blocks_for(4LL * QW * QH, 256)), dim3(256), 0, st, W, Hh, tab);
+    hipLaunchKernelGGL(k_horizon_near, dim3(blocks_for(W, kNearTile), blocks_for(Hh, kNearTile)), dim3(256), 0, st,
+                       W, Hh, H, tab);
     hipLaunchKernelGGL(k_pyr_level0, dim3(blocks_for((long long)P.wc[0] * P.hc[0], 256)), dim3(256), 0,
                        st, W, Hh, H, pyr + P.off[0], P.wc[0], P.hc[0]);
     for (int l = 1; l < P.levels; ++l)
@@ -1303,6 +1562,11 @@ hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t 
                        st, jobs);
     hipLaunchKernelGGL(k_escape_rows_multi, dim3(blocks_for(qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
     hipLaunchKernelGGL(k_escape_cols_multi, dim3(blocks_for(qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
+    const long long supers = (long long)trv::super_cells(bs.max_cols) * trv::super_cells(bs.max_rows);
+    hipLaunchKernelGGL(k_super_blocks_multi, dim3(blocks_for(supers, 256), bs.njobs), dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_horizon_blocks_multi, dim3(blocks_for(4 * qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
+    const long long near_tiles = (long long)blocks_for(bs.max_cols, kNearTile) * blocks_for(bs.max_rows, kNearTile);
+    hipLaunchKernelGGL(k_horizon_near_multi, dim3((unsigned)near_tiles, bs.njobs), dim3(256), 0, st, jobs);
     hipLaunchKernelGGL(k_pyr0_multi, dim3(blocks_for(bs.max_pyr_cells[0], 256), bs.njobs), dim3(256), 0, st,
                        jobs);
     for (int l = 1; l < bs.max_pyr_levels; ++l)

@@ -37,16 +37,51 @@ constexpr int kEscapeScales = 3;
 __host__ __device__ inline int escape_scale(int k) { return 16 << (2 * k); }
 __host__ __device__ inline float escape_margin(float m) { return fmaf(2e-6f, fabsf(m), m + 2e-3f); }
 
+// Horizon bounds, which let most rising rays leave at their first step.  From
+// sample p, a crossing can read a sample r (offsets a, b >= 0 along the travel
+// quadrant) only after at least tmin(a, b) of horizontal travel: an x-line
+// crossing at column a reads rows within one of the ray's, so after
+// sqrt(a^2 + (b-1)^2) at least, and a y-line crossing after sqrt((a-1)^2 + b^2).
+// A ray of slope s (rise per unit of horizontal travel) stays at or above
+// escape_margin(h_r) at every such crossing when s >= (escape_margin(h_r) - h_p)
+// / tmin(a, b).  Three bounds on that slope, each conservative:
+//   near: per sample and quadrant, the exact maximum over the samples read
+//     within kHorizonReach of travel;
+//   mid: per block and quadrant, over the blocks up to kMidBlocks blocks ahead,
+//     with the block-to-block distance less 1.5 (>= kHorizonReach) and the
+//     block's lowest sample for h_p;
+//   far: the same over 64 x 64 super-blocks up to kFarSupers ahead (distance >=
+//     kMidBlocks blocks) and the quadrant maximum at 2048 samples.
+// The mid and far maxima are convex in h_p; each is stored as its chord over the
+// block's height range, a + k h_p, raised to cover rounding.
+constexpr int kHorizonReach = 24;
+constexpr int kMidBlocks = 32;
+constexpr int kSuperShift = 6;
+constexpr int kFarSupers = 32;
+constexpr float kFarQuadrantTravel = 2048.0f;
+__host__ __device__ inline int super_cells(int n) { return (n + (1 << kSuperShift) - 1) >> kSuperShift; }
+
 // The block tables that follow the pyramid levels, in floats from their start
 // (which is 64-float aligned), for a QW x QH block grid with plane p4 =
-// QW QH rounded up to a multiple of 4:
+// QW QH rounded up to a multiple of 4, and s4 = the super-block count rounded
+// up to a multiple of 4:
 //   escape windows  float4 [4 quadrants][QH][QW]      at 0
 //   block maxima    [QH][QW]                          at 16 p4
 //   row-window maxima [2 x-directions][3 scales][QH][QW] at 17 p4
-//   quadrant maxima [4 quadrants][QH][QW]             at 25 p4 (the end)
+//   quadrant maxima [4 quadrants][QH][QW]             at 25 p4
+//   block minima    [QH][QW]                          at 29 p4
+//   horizon bounds  float4 [4 quadrants][QH][QW]      at 30 p4: (a_mid, k_mid, a_far, k_far)
+//   super-block maxima [SH][SW]                       at 46 p4
+//   near horizons   float4 [Hh][W]                    at 46 p4 + s4: the four quadrants of a sample
 __host__ __device__ inline long long block_plane4(int QW, int QH) { return ((long long)QW * QH + 3) / 4 * 4; }
-__host__ __device__ inline long long block_tables_floats(int QW, int QH) {
-    return 25 * block_plane4(QW, QH) + 4LL * QW * QH;
+__host__ __device__ inline long long super_plane4(int W, int Hh) {
+    return ((long long)super_cells(W) * super_cells(Hh) + 3) / 4 * 4;
+}
+__host__ __device__ inline long long near_horizon_offset(int W, int Hh) {
+    return 46 * block_plane4(quad_cells(W), quad_cells(Hh)) + super_plane4(W, Hh);
+}
+__host__ __device__ inline long long block_tables_floats(int W, int Hh) {
+    return near_horizon_offset(W, Hh) + 4LL * W * Hh;
 }
 
 // Apron-max pyramid.  Level l has cells (cx, cy), cx < wc[l], cy < hc[l];
@@ -68,6 +103,8 @@ struct Surface {
     const float* pyr;    // apron maxima, levels concatenated
     const float* quad;   // 4 quadrant maxima [q][QH][QW] over blocks, q = (dx < 0) + 2 (dy < 0)
     const float4* esc;   // escape windows [q][QH][QW]: maxima within escape_scale(0..2), quadrant max
+    const float4* hzb;   // horizon bounds [q][QH][QW]: (a_mid, k_mid, a_far, k_far)
+    const float* nearh;  // near horizons [Hh][W][q]
     const int2* lvl;     // LDS copy of (offset, cells per row) of every level
     int W, Hh;
     int QW, QH;          // blocks of the quadrant tables
@@ -179,6 +216,29 @@ __device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0,
     const bool vertical = dx == 0.0f && dy == 0.0f;
     w.tX = vertical ? __builtin_inff() : t_x(w.r, 1);
     w.tY = vertical ? __builtin_inff() : t_y(w.r, 1);
+}
+
+// Quadrant index of a ray: 0..3 = (dx < 0) + 2 (dy < 0).
+__device__ __forceinline__ unsigned quadrant(const Ray& r) { return (r.sx < 0 ? 1u : 0u) + (r.sy < 0 ? 2u : 0u); }
+
+// True when the start sample's horizon bounds for the ray's quadrant (near
+// bound hn, block bounds hb) prove that no crossing can hit: the walk's result
+// is then kMiss and no step is needed.  A ray that descends is never let go.
+__device__ __forceinline__ bool leaves_at_once(const Ray& r, float hn, const float4& hb) {
+    // not descending: its height at travel T is at least oz + slope T
+    const float s = r.slope;
+    return (r.dz >= 0.0f) & (s >= hn) & (s >= fmaf(hb.y, r.oz, hb.x)) & (s >= fmaf(hb.w, r.oz, hb.z));
+}
+
+// The same, reading the bounds of the ray's start sample (never in a flat walk).
+__device__ __forceinline__ bool leaves_at_once(const Walker& w, const Surface& S) {
+    const Ray& r = w.r;
+    if (w.level < 0) return false;
+    const unsigned q = quadrant(r);
+    const float hn = ld32(S.nearh, (unsigned)(r.j0 * S.W + r.i0) * 4u + q);
+    const float4 hb = ld32(S.hzb, __umul24((unsigned)r.qrow + ((unsigned)r.j0 >> kQuadShift), (unsigned)S.QW) +
+                                      ((unsigned)r.i0 >> kQuadShift));
+    return leaves_at_once(r, hn, hb);
 }
 
 // One step: a pyramid cell test (skip it, climb, descend or give up to crossing
@@ -294,6 +354,7 @@ __device__ __forceinline__ bool walk(const Surface& S, bool flat, int i0, int j0
                                      float dz, int& qi, int& qj) {
     Walker w;
     walker_init(w, S, i0, j0, dx, dy, dz, flat);
+    if (leaves_at_once(w, S)) return false;
     for (;;) {
         const int res = walker_step(w, S, qi, qj);
         if (res != kGoOn) return res == kHit;

@@ -350,6 +350,31 @@ def test_solve_T0_is_plain_ps(dev):
     assert (got["indirect"] == 0).all()
 
 
+def _block_tables(pyr, W, Hh):
+    """Views of the block tables that follow the pyramid levels (layout of the
+    pyramid buffer as include/irtps.h documents it)."""
+    wc, hc, lv = W - 1, Hh - 1, 0
+    while True:  # pyramid levels, then the block tables (64-float aligned)
+        lv += wc * hc
+        if wc == 1 and hc == 1:
+            break
+        wc, hc = (wc + 1) // 2, (hc + 1) // 2
+    tab = (lv + 63) // 64 * 64
+    QH, QW = (Hh + 7) // 8, (W + 7) // 8
+    SH, SW = (Hh + 63) // 64, (W + 63) // 64
+    p4 = (QW * QH + 3) // 4 * 4
+    s4 = (SW * SH + 3) // 4 * 4
+    t = pyr[tab:]
+    near0 = 46 * p4 + s4
+    assert t.size == near0 + 4 * W * Hh
+    return dict(esc=t[:16 * QW * QH].reshape(4, QH, QW, 4), bmax=t[16 * p4:16 * p4 + QW * QH].reshape(QH, QW),
+                quad=t[25 * p4:25 * p4 + 4 * QW * QH].reshape(4, QH, QW),
+                bmin=t[29 * p4:29 * p4 + QW * QH].reshape(QH, QW),
+                hzb=t[30 * p4:30 * p4 + 16 * QW * QH].reshape(4, QH, QW, 4),
+                smax=t[46 * p4:46 * p4 + SW * SH].reshape(SH, SW),
+                near=t[near0:].reshape(Hh, W, 4))
+
+
 def test_quadrant_maxima(dev):
     say("case: quadrant maxima in the pyramid buffer")
     rng = np.random.default_rng(4)
@@ -357,7 +382,7 @@ def test_quadrant_maxima(dev):
     Hh, W = Hf.shape
     pyr = H(irtps.build_pyramid(T(Hf, dev)))
     QH, QW = (Hh + 7) // 8, (W + 7) // 8
-    quad = pyr[pyr.size - 4 * QW * QH:].reshape(4, QH, QW)
+    quad = _block_tables(pyr, W, Hh)["quad"]
     for q in range(4):
         sx = -1 if q & 1 else 1
         sy = -1 if q & 2 else 1
@@ -392,16 +417,9 @@ def test_escape_windows(dev):
     for Hh, W in ((45, 70), (300, 133), (9, 1030)):
         Hf = rng.uniform(-5, 5, (Hh, W)).astype(F32)
         pyr = H(irtps.build_pyramid(T(Hf, dev)))
-        wc, hc, lv = W - 1, Hh - 1, 0
-        while True:  # pyramid levels, then the block tables (64-float aligned)
-            lv += wc * hc
-            if wc == 1 and hc == 1:
-                break
-            wc, hc = (wc + 1) // 2, (hc + 1) // 2
-        tab = (lv + 63) // 64 * 64
         QH, QW = (Hh + 7) // 8, (W + 7) // 8
-        esc = pyr[tab:tab + 16 * QW * QH].reshape(4, QH, QW, 4)
-        quad = pyr[pyr.size - 4 * QW * QH:].reshape(4, QH, QW)
+        tabs = _block_tables(pyr, W, Hh)
+        esc, quad = tabs["esc"], tabs["quad"]
         bmax = np.full((QH, QW), -np.inf, np.float32)
         for by in range(QH):
             for bx in range(QW):
@@ -424,6 +442,104 @@ def test_escape_windows(dev):
                         sy1 = 8 * by + 7 + D + 2 if not q & 2 else 8 * by + 9
                         win = Hf[max(sy0, 0):min(sy1, Hh - 1) + 1, max(sx0, 0):min(sx1, W - 1) + 1]
                         assert esc[q, by, bx, k] > win.max()
+
+
+REACH = 24  # samples of travel the per-sample (near) horizon bound covers
+
+
+def _tmin(a, b, slack):
+    """Least horizontal travel at which a crossing can read the sample at
+    offsets (a, b) along the travel quadrant (slack lowers each minor offset)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    tx = np.where(a >= 1, np.sqrt(a * a + np.maximum(b - 1 - slack, 0) ** 2), np.inf)
+    ty = np.where(b >= 1, np.sqrt(np.maximum(a - 1 - slack, 0) ** 2 + b * b), np.inf)
+    return np.minimum(tx, ty)
+
+
+@pytest.mark.parametrize("shape,ptp", [((97, 150), 20.0), ((45, 70), 10.0), ((9, 1030), 4.0), ((300, 277), 40.0)])
+def test_horizon_bounds(dev, shape, ptp):
+    """The horizon tables bound, from above, the slope a ray from a sample needs
+    to clear every sample its crossings can read (escape margin included): the
+    near bound per sample and quadrant over REACH samples of travel, the mid and
+    far chords per block over the block and super-block maxima beyond (a bound
+    below 0 only has to stay below 0: a rising ray's slope is never negative).
+    They are also no looser than the slack they are built with."""
+    say(f"case: horizon bounds on {shape}")
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    Hf = scenes.fbm_heights(max(shape), 0.7, ptp, rng)[:shape[0], :shape[1]].astype(F32)
+    Hh, W = Hf.shape
+    tabs = _block_tables(H(irtps.build_pyramid(T(Hf, dev))), W, Hh)
+    em = fmaf(np.float32(2e-6), np.abs(Hf), Hf + np.float32(2e-3)).astype(np.float64)
+    QH, QW = (Hh + 7) // 8, (W + 7) // 8
+    pad = np.full((QH * 8, QW * 8), np.nan)
+    pad[:Hh, :W] = Hf
+    bmin = np.nanmin(pad.reshape(QH, 8, QW, 8), axis=(1, 3)).astype(F32)
+    bmax = np.nanmax(pad.reshape(QH, 8, QW, 8), axis=(1, 3)).astype(F32)
+    assert np.array_equal(tabs["bmin"], bmin) and np.array_equal(tabs["bmax"], bmax)
+    SH, SW = (QH + 7) // 8, (QW + 7) // 8
+    padb = np.full((SH * 8, SW * 8), -np.inf, np.float32)
+    padb[:QH, :QW] = bmax
+    assert np.array_equal(tabs["smax"], padb.reshape(SH, 8, SW, 8).max(axis=(1, 3)))
+    # near: exact maximum (true tmin, every sample within 32) <= table <= the
+    # same with the builder's slack
+    A = np.arange(REACH + 3)
+    aa, bb = np.meshgrid(A, A)
+    t_true, t_slack = _tmin(aa, bb, 0.0), _tmin(aa, bb, 0.01) * (1 - 1e-6)
+    near = tabs["near"]
+    for n in range(400):
+        i, j = rng.integers(0, W), rng.integers(0, Hh)
+        for q in range(4):
+            sx, sy = (-1 if q & 1 else 1), (-1 if q & 2 else 1)
+            x, y = i + sx * aa, j + sy * bb
+            ok = (x >= 0) & (x < W) & (y >= 0) & (y < Hh)
+            e = np.where(ok, em[np.clip(y, 0, Hh - 1), np.clip(x, 0, W - 1)], -np.inf) - float(Hf[j, i])
+            lo_set = ok & (t_true <= REACH)
+            hi_set = ok & (t_slack <= REACH)
+            lo = (e[lo_set] / t_true[lo_set]).max(initial=-np.inf)
+            hi = (e[hi_set] / t_slack[hi_set]).max(initial=-np.inf)
+            v = float(near[j, i, q])
+            # (slopes are >= 0: below 0 only the sign matters)
+            assert max(v, 0.0) >= max(lo, 0.0), (i, j, q, v, lo)
+            if np.isfinite(hi):
+                assert v <= hi + abs(hi) * 1e-4 + 1e-6, (i, j, q, v, hi)
+            else:  # nothing ahead within reach (a corner of the domain)
+                assert v == -np.inf, (i, j, q, v)
+    # mid and far chords over each sampled block's height range
+    hz = tabs["hzb"].astype(np.float64)
+    quad = tabs["quad"]
+    off = np.arange(34)
+    for n in range(120):
+        bx, by = rng.integers(0, QW), rng.integers(0, QH)
+        hs = Hf[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].astype(np.float64).ravel()
+        for q in range(4):
+            sx, sy = (-1 if q & 1 else 1), (-1 if q & 2 else 1)
+            ca, cb = np.meshgrid(off, off)
+            cx, cy = bx + sx * ca, by + sy * cb
+            ok = (cx >= 0) & (cx < QW) & (cy >= 0) & (cy < QH)
+            gap = np.hypot(np.maximum(0, ca * 8 - 7), np.maximum(0, cb * 8 - 7))
+            d = np.maximum(float(REACH), gap - 1.5)[ok]
+            M = fmaf(np.float32(2e-6), np.abs(bmax), bmax + np.float32(2e-3)).astype(np.float64)[cy[ok], cx[ok]]
+            need_mid = ((M[None, :] - hs[:, None]) / d[None, :]).max(1)
+            mid = hz[q, by, bx, 0] + hz[q, by, bx, 1] * hs
+            assert (mid >= need_mid).all(), (shape, bx, by, q)
+            assert (mid <= need_mid.max() + abs(need_mid.max()) * 1e-4 + 1e-4).all(), (shape, bx, by, q)
+            # far: super-blocks ahead, floor 256, and the quadrant maximum at 2048
+            X0, Y0 = 8 * bx, 8 * by
+            hx, hy = X0 // 64, Y0 // 64
+            sa, sb = np.meshgrid(off, off)
+            ux, uy = hx + sx * sa, hy + sy * sb
+            ok = (ux >= 0) & (ux < SW) & (uy >= 0) & (uy < SH)
+            gx = np.maximum(0, np.maximum(ux * 64 - (X0 + 7), X0 - (ux * 64 + 63)))
+            gy = np.maximum(0, np.maximum(uy * 64 - (Y0 + 7), Y0 - (uy * 64 + 63)))
+            d = np.maximum(256.0, np.hypot(gx, gy) - 1.5)[ok]
+            smax = tabs["smax"]
+            M = fmaf(np.float32(2e-6), np.abs(smax), smax + np.float32(2e-3)).astype(np.float64)[uy[ok], ux[ok]]
+            Mq = float(fmaf(np.float32(2e-6), np.abs(quad[q, by, bx]), quad[q, by, bx] + np.float32(2e-3)))
+            need_far = np.maximum(((M[None, :] - hs[:, None]) / d[None, :]).max(1), (Mq - hs) / 2048.0)
+            far = hz[q, by, bx, 2] + hz[q, by, bx, 3] * hs
+            assert (far >= need_far).all(), (shape, bx, by, q)
+            assert (far <= need_far.max() + abs(need_far.max()) * 1e-4 + 1e-4).all(), (shape, bx, by, q)
 
 
 # ---------------------------------------------------------------------------
