@@ -118,6 +118,8 @@ inline kern::MgPlan mg_plan(int W, int H) {
         m.H[m.levels] = (m.H[m.levels - 1] + 1) / 2;
         ++m.levels;
     }
+    m.tail = 0;
+    while ((long long)m.W[m.tail] * m.H[m.tail] > kern::kMgTailNodes) ++m.tail;
     long long off = 0;
     for (int l = 0; l < m.levels; ++l) {
         const long long n = (long long)m.W[l] * m.H[l];

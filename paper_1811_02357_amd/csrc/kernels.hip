@@ -638,13 +638,50 @@ __device__ __forceinline__ void mg_prolong_node(int v, int Wf, float* __restrict
     Xf[v] = Xf[v] + 2.0f * Xc[(size_t)(J / 2) * Wc + I / 2];
 }
 
-// The coarsest grid (at most 4 x 4): 16 red-black sweeps by one thread, in the
-// same colour order as the parallel sweeps (nodes of one colour are independent).
-__device__ __forceinline__ void mg_coarse(int Wl, int Hl, int shift, int W0, int H0, float* X,
-                                          const float* b) {
-    for (int sw = 0; sw < 16; ++sw)
-        for (int colour = 0; colour < 2; ++colour)
-            for (int v = 0; v < Wl * Hl; ++v) mg_smooth_node(v, Wl, Hl, shift, W0, H0, X, b, colour);
+// The V-cycle's small levels, from plan.tail to the coarsest, by one block:
+// the same node updates in the same colour and level order as the per-level
+// launches (nodes of one colour are independent), with a block barrier
+// between passes.  The coarsest grid (at most 4 x 4) gets 16 red-black sweeps.
+// The levels' X and b live in LDS for the duration (s_mg, mg_tail_floats(m)
+// floats): X and b of level tail come in, X of level tail goes back.
+__host__ __device__ inline long long mg_tail_floats(const MgPlan& m) { return m.keyoff - m.xoff[m.tail]; }
+constexpr int kMgTailThreads = 1024;
+
+__device__ __forceinline__ void mg_tail(const MgPlan& m, int W0, int H0, float* ws, float* s_mg) {
+    const int top = m.levels - 1;
+    const long long base = m.xoff[m.tail];
+    auto X = [&](int l) { return s_mg + (m.xoff[l] - base); };
+    auto B = [&](int l) { return s_mg + (m.boff[l] - base); };
+    const int n0 = m.W[m.tail] * m.H[m.tail];
+    for (int v = threadIdx.x; v < n0; v += blockDim.x) {
+        X(m.tail)[v] = ws[m.xoff[m.tail] + v];
+        B(m.tail)[v] = ws[m.boff[m.tail] + v];
+    }
+    __syncthreads();
+    auto smooth = [&](int l, int sweeps) {
+        const int n = m.W[l] * m.H[l];
+        for (int sw = 0; sw < sweeps; ++sw)
+            for (int colour = 0; colour < 2; ++colour) {
+                for (int v = threadIdx.x; v < n; v += blockDim.x)
+                    mg_smooth_node(v, m.W[l], m.H[l], l, W0, H0, X(l), B(l), colour);
+                __syncthreads();
+            }
+    };
+    for (int l = m.tail; l < top; ++l) {
+        smooth(l, 2);
+        const int nc = m.W[l + 1] * m.H[l + 1];
+        for (int v = threadIdx.x; v < nc; v += blockDim.x)
+            mg_restrict_node(v, m.W[l], m.H[l], l, W0, H0, X(l), B(l), m.W[l + 1], B(l + 1), X(l + 1));
+        __syncthreads();
+    }
+    smooth(top, 16);
+    for (int l = top - 1; l >= m.tail; --l) {
+        const int n = m.W[l] * m.H[l];
+        for (int v = threadIdx.x; v < n; v += blockDim.x) mg_prolong_node(v, m.W[l], X(l), m.W[l + 1], X(l + 1));
+        __syncthreads();
+        smooth(l, 2);
+    }
+    for (int v = threadIdx.x; v < n0; v += blockDim.x) ws[m.xoff[m.tail] + v] = X(m.tail)[v];
 }
 
 // Order-preserving map of binary32 (no NaN) to uint32.
@@ -1029,8 +1066,9 @@ __global__ void __launch_bounds__(256) k_mg_prolong(int Wf, int Hf, float* __res
     if (v < Wf * Hf) mg_prolong_node(v, Wf, Xf, Wc, Xc);
 }
 
-__global__ void k_mg_coarse(int Wl, int Hl, int shift, int W0, int H0, float* X, const float* b) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) mg_coarse(Wl, Hl, shift, W0, H0, X, b);
+__global__ void __launch_bounds__(kMgTailThreads) k_mg_tail(MgPlan m, int W0, int H0, float* ws) {
+    extern __shared__ float s_mg[];
+    mg_tail(m, W0, H0, ws, s_mg);
 }
 
 __global__ void k_fill_u32(unsigned* p, unsigned v, int n) {
@@ -1284,7 +1322,7 @@ __global__ void __launch_bounds__(256) k_mg_smooth_multi(const JobDesc* __restri
                                                          int c, int cold) {
     const JobDesc& J = jobs[blockIdx.y];
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l] * J.mg.H[l]) return;
+    if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l] * J.mg.H[l]) return;
     mg_smooth_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
                    colour);
 }
@@ -1293,23 +1331,23 @@ __global__ void __launch_bounds__(256) k_mg_restrict_multi(const JobDesc* __rest
                                                            int cold) {
     const JobDesc& J = jobs[blockIdx.y];
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l + 1] * J.mg.H[l + 1]) return;
+    if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l + 1] * J.mg.H[l + 1]) return;
     mg_restrict_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
                      J.mg.W[l + 1], J.mg_ws + J.mg.boff[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
 }
 
-__global__ void k_mg_coarse_multi(const JobDesc* __restrict__ jobs, int c, int cold) {
+__global__ void __launch_bounds__(kMgTailThreads) k_mg_tail_multi(const JobDesc* __restrict__ jobs, int c, int cold) {
+    extern __shared__ float s_mg[];
     const JobDesc& J = jobs[blockIdx.y];
-    if (!in_cycle(J, c, cold) || threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int l = J.mg.levels - 1;
-    mg_coarse(J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l]);
+    if (!in_cycle(J, c, cold)) return;  // uniform per block
+    mg_tail(J.mg, J.W, J.Hh, J.mg_ws, s_mg);
 }
 
 __global__ void __launch_bounds__(256) k_mg_prolong_multi(const JobDesc* __restrict__ jobs, int l, int c,
                                                           int cold) {
     const JobDesc& J = jobs[blockIdx.y];
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!in_cycle(J, c, cold) || l >= J.mg.levels - 1 || v >= J.mg.W[l] * J.mg.H[l]) return;
+    if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l] * J.mg.H[l]) return;
     mg_prolong_node(v, J.mg.W[l], J.mg_ws + J.mg.xoff[l], J.mg.W[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
 }
 
@@ -1486,18 +1524,17 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
                 hipLaunchKernelGGL(k_mg_smooth, dim3(blocks_for(nl, 256)), dim3(256), 0, st, plan.W[l],
                                    plan.H[l], l, W0, H0, X[l], b[l], colour);
     };
-    const int top = plan.levels - 1;
     for (int c = 0; c < cycles; ++c) {
-        for (int l = 0; l < top; ++l) {
+        for (int l = 0; l < plan.tail; ++l) {
             smooth(l, 2);
             const int nc = plan.W[l + 1] * plan.H[l + 1];
             hipLaunchKernelGGL(k_mg_restrict, dim3(blocks_for(nc, 256)), dim3(256), 0, st, plan.W[l],
                                plan.H[l], l, W0, H0, X[l], b[l], plan.W[l + 1], plan.H[l + 1], b[l + 1],
                                X[l + 1]);
         }
-        hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(64), 0, st, plan.W[top], plan.H[top], top, W0, H0,
-                           X[top], b[top]);
-        for (int l = top - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kMgTailThreads), sizeof(float) * mg_tail_floats(plan), st,
+                           plan, W0, H0, ws);
+        for (int l = plan.tail - 1; l >= 0; --l) {
             hipLaunchKernelGGL(k_mg_prolong, dim3(blocks_for(plan.W[l] * plan.H[l], 256)), dim3(256), 0,
                                st, plan.W[l], plan.H[l], X[l], plan.W[l + 1], X[l + 1]);
             smooth(l, 2);
@@ -1605,9 +1642,9 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     hipLaunchKernelGGL(k_mg_rhs_multi, gpx, dim3(256), 0, st, jobs, cold);
     hipLaunchKernelGGL(k_mg_init_multi, gpx, dim3(256), 0, st, jobs, cold);
     const int cycles = cold ? bs.max_cycles_cold : bs.max_cycles_warm;
-    const int L = bs.max_mg_levels;
+    const int L = bs.max_mg_tail;  // every job's per-level part
     for (int c = 0; c < cycles; ++c) {
-        for (int l = 0; l < L - 1; ++l) {
+        for (int l = 0; l < L; ++l) {
             const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
             for (int s = 0; s < 2; ++s)
                 for (int colour = 0; colour < 2; ++colour)
@@ -1615,8 +1652,9 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
             hipLaunchKernelGGL(k_mg_restrict_multi, dim3(blocks_for(bs.max_mg_nodes[l + 1], 256), nj), dim3(256),
                                0, st, jobs, l, c, cold);
         }
-        hipLaunchKernelGGL(k_mg_coarse_multi, dim3(1, nj), dim3(64), 0, st, jobs, c, cold);
-        for (int l = L - 2; l >= 0; --l) {
+        hipLaunchKernelGGL(k_mg_tail_multi, dim3(1, nj), dim3(kMgTailThreads), sizeof(float) * bs.max_mg_tail_floats,
+                           st, jobs, c, cold);
+        for (int l = L - 1; l >= 0; --l) {
             const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
             hipLaunchKernelGGL(k_mg_prolong_multi, g, dim3(256), 0, st, jobs, l, c, cold);
             for (int s = 0; s < 2; ++s)

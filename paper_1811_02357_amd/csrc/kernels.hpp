@@ -61,8 +61,12 @@ struct TraceArgs {
 };
 
 // Multigrid levels of a W x H grid, offsets (in floats) into the workspace.
+// Levels of at most kMgTailNodes nodes (from `tail` to the coarsest) run in one
+// single-block launch per V-cycle.
+constexpr int kMgTailNodes = 4096;
 struct MgPlan {
     int levels;
+    int tail;  // first level with at most kMgTailNodes nodes
     int W[kMaxMgLevels], H[kMaxMgLevels];
     long long xoff[kMaxMgLevels], boff[kMaxMgLevels];
     long long keyoff;  // one uint32 for the anchor's minimum
@@ -106,6 +110,8 @@ struct BatchShape {
     int max_pyr_levels;
     int max_rows, max_cols;  // largest H, W
     int max_mg_levels;
+    int max_mg_tail;         // largest first tail level
+    long long max_mg_tail_floats;  // largest LDS need of the tail levels
     int max_mg_nodes[kMaxMgLevels];
     int max_cycles_cold, max_cycles_warm;
     int max_KCnpx;           // largest K * C * W * H
