@@ -67,18 +67,31 @@ def tracer_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(workload):
-    """HBM bytes per tracer launch from the committed FETCH_SIZE / WRITE_SIZE
-    profile (copy-calibrated), or None when the profile is missing, is for
-    another workload, or was taken on other tracer sources."""
+def profiled_values(workload):
+    """The values the committed tracer counter profile hands to this script
+    (HBM bytes per launch from copy-calibrated FETCH_SIZE / WRITE_SIZE, VALU
+    wave instructions per launch, lane utilisation), or None when the profile
+    is missing, is for another workload, or was taken on other tracer sources."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             kv = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
         if kv.get("workload") != workload or kv.get("tracer_sources_sha256") != tracer_digest():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return {"traffic": float(kv["traffic_bytes_per_launch"]),
+                "valu": float(kv["valu_wave_instructions_per_launch"]),
+                "lanes": float(kv["valu_lane_utilisation"])}
     except (OSError, KeyError, ValueError):
         return None
+
+
+def profiled_traffic(workload):
+    v = profiled_values(workload)
+    return None if v is None else v["traffic"]
+
+
+# VALU issue rate: 256 CUs x 4 SIMDs, one wave64 VALU instruction per 4 cycles
+# each at 2.4 GHz (non-packed FP32: the kernels are built without packed ops)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def algorithmic_bytes(cnt, npx, K, C):
@@ -347,6 +360,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if args.flat else profiled_traffic(args.workload)},
     }
+    prof = None if args.flat else profiled_values(args.workload)
+    if prof is not None:
+        # the binding limit: VALU issue (counted instructions of the profiled
+        # kernel over this run's launch time)
+        line["valu_issue"] = {"wave_instructions_per_launch": prof["valu"],
+                              "per_s": prof["valu"] / (per_launch_ms / 1e3), "peak_per_s": VALU_ISSUE_PEAK,
+                              "frac": prof["valu"] / (per_launch_ms / 1e3) / VALU_ISSUE_PEAK,
+                              "lane_utilisation": prof["lanes"],
+                              "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
     del ws, out, I0
     torch.cuda.empty_cache()
     if args.mode in ("all", "batched"):
