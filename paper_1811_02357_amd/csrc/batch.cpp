@@ -129,6 +129,18 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
     }
     std::memset(&shape, 0, sizeof(shape));
     shape.njobs = (int)jobs.size();
+    // flattened grids: each job's blocks follow the previous job's
+    for (kern::JobDesc& J : jobs) {
+        for (int l = 0; l < kern::kMaxMgLevels; ++l) {
+            const bool own = l < J.mg.tail;
+            J.mg_bstart[l] = shape.mg_blocks[l];
+            J.rs_bstart[l] = shape.rs_blocks[l];
+            shape.mg_blocks[l] += own ? kern::flat_blocks((long long)J.mg.W[l] * J.mg.H[l]) : 0;
+            shape.rs_blocks[l] += own ? kern::flat_blocks((long long)J.mg.W[l + 1] * J.mg.H[l + 1]) : 0;
+        }
+        J.near_bstart = shape.near_blocks;
+        shape.near_blocks += kern::near_tiles(J.W, J.Hh);
+    }
     for (const kern::JobDesc& J : jobs) {
         shape.max_npx = std::max(shape.max_npx, J.W * J.Hh);
         shape.max_rows = std::max(shape.max_rows, J.Hh);

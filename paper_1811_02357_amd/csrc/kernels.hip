@@ -399,7 +399,6 @@ __device__ __forceinline__ void horizon_block(int b, int q, const BlockTables& t
 
 // Near horizons of a 16 x 16 tile of samples, from an LDS copy of
 // escape_margin(H) with an apron of kHorizonReach + 1 (-inf outside the domain).
-constexpr int kNearTile = 16;
 constexpr int kNearApron = trv::kHorizonReach + 1;
 constexpr int kNearSpan = kNearTile + 2 * kNearApron;
 constexpr int kNearOff = kNearApron + 1;  // offsets 0 .. kNearApron along each axis
@@ -1103,6 +1102,19 @@ __global__ void __launch_bounds__(256) k_anchor(const float* __restrict__ X, int
 // A job takes part in the iteration steps while t < T; the t = 0 steps (PS of
 // I0, cold integration) run for every active job.
 __device__ __forceinline__ bool iterating(const JobDesc& J) { return J.active && J.t < J.T; }
+
+// The job that owns block b of a flattened grid: the last job whose first
+// block (start(J)) is <= b (starts are non-decreasing in table order).
+template <class Start>
+__device__ __forceinline__ int job_of_block(const JobDesc* __restrict__ jobs, int njobs, int b, Start start) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start(jobs[mid]) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 __device__ __forceinline__ bool participates(const JobDesc& J, int init) {
     return init ? J.active != 0 : iterating(J);
 }
@@ -1261,14 +1273,16 @@ __global__ void __launch_bounds__(256) k_horizon_blocks_multi(const JobDesc* __r
     if (iterating(J) && v < 4 * t.plane) horizon_block((int)(v >> 2), (int)(v & 3), t);
 }
 
-// grid.x walks the tiles of the largest job; each job uses its own tile grid
-__global__ void __launch_bounds__(256) k_horizon_near_multi(const JobDesc* __restrict__ jobs) {
+// the flattened grid holds each job's near-horizon tiles
+__global__ void __launch_bounds__(256) k_horizon_near_multi(const JobDesc* __restrict__ jobs, int njobs) {
     __shared__ float s_e[kNearSpan * kNearSpan];
-    const JobDesc& J = jobs[blockIdx.y];
-    const int tiles_x = (J.W + kNearTile - 1) / kNearTile, tiles_y = (J.Hh + kNearTile - 1) / kNearTile;
-    if (!iterating(J) || (int)blockIdx.x >= tiles_x * tiles_y) return;  // uniform per block
+    const int jb = job_of_block(jobs, njobs, blockIdx.x, [](const JobDesc& J) { return J.near_bstart; });
+    const JobDesc& J = jobs[jb];
+    const int tiles_x = (J.W + kNearTile - 1) / kNearTile;
+    const int tile = (int)blockIdx.x - J.near_bstart;
+    if (!iterating(J) || tile >= near_tiles(J.W, J.Hh)) return;  // uniform per block
     const BlockTables t = block_tables(J.pyr + J.quad_off, J.W, J.Hh);
-    near_tile(J.W, J.Hh, J.depth, (int)blockIdx.x % tiles_x, (int)blockIdx.x / tiles_x, t.nearh, s_e);
+    near_tile(J.W, J.Hh, J.depth, tile % tiles_x, tile / tiles_x, t.nearh, s_e);
 }
 
 __global__ void __launch_bounds__(64) k_quad_rows_multi(const JobDesc* __restrict__ jobs) {
@@ -1318,19 +1332,21 @@ __device__ __forceinline__ bool in_cycle(const JobDesc& J, int c, int cold) {
     return participates(J, cold) && c < (cold ? J.cycles_cold : J.cycles_warm);
 }
 
-__global__ void __launch_bounds__(256) k_mg_smooth_multi(const JobDesc* __restrict__ jobs, int l, int colour,
-                                                         int c, int cold) {
-    const JobDesc& J = jobs[blockIdx.y];
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mg_smooth_multi(const JobDesc* __restrict__ jobs, int njobs, int l,
+                                                         int colour, int c, int cold) {
+    const int jb = job_of_block(jobs, njobs, blockIdx.x, [l](const JobDesc& J) { return J.mg_bstart[l]; });
+    const JobDesc& J = jobs[jb];
+    const int v = (blockIdx.x - J.mg_bstart[l]) * blockDim.x + threadIdx.x;
     if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l] * J.mg.H[l]) return;
     mg_smooth_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
                    colour);
 }
 
-__global__ void __launch_bounds__(256) k_mg_restrict_multi(const JobDesc* __restrict__ jobs, int l, int c,
-                                                           int cold) {
-    const JobDesc& J = jobs[blockIdx.y];
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mg_restrict_multi(const JobDesc* __restrict__ jobs, int njobs, int l,
+                                                           int c, int cold) {
+    const int jb = job_of_block(jobs, njobs, blockIdx.x, [l](const JobDesc& J) { return J.rs_bstart[l]; });
+    const JobDesc& J = jobs[jb];
+    const int v = (blockIdx.x - J.rs_bstart[l]) * blockDim.x + threadIdx.x;
     if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l + 1] * J.mg.H[l + 1]) return;
     mg_restrict_node(v, J.mg.W[l], J.mg.H[l], l, J.W, J.Hh, J.mg_ws + J.mg.xoff[l], J.mg_ws + J.mg.boff[l],
                      J.mg.W[l + 1], J.mg_ws + J.mg.boff[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
@@ -1343,10 +1359,11 @@ __global__ void __launch_bounds__(kMgTailThreads) k_mg_tail_multi(const JobDesc*
     mg_tail(J.mg, J.W, J.Hh, J.mg_ws, s_mg);
 }
 
-__global__ void __launch_bounds__(256) k_mg_prolong_multi(const JobDesc* __restrict__ jobs, int l, int c,
-                                                          int cold) {
-    const JobDesc& J = jobs[blockIdx.y];
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mg_prolong_multi(const JobDesc* __restrict__ jobs, int njobs, int l,
+                                                          int c, int cold) {
+    const int jb = job_of_block(jobs, njobs, blockIdx.x, [l](const JobDesc& J) { return J.mg_bstart[l]; });
+    const JobDesc& J = jobs[jb];
+    const int v = (blockIdx.x - J.mg_bstart[l]) * blockDim.x + threadIdx.x;
     if (!in_cycle(J, c, cold) || l >= J.mg.tail || v >= J.mg.W[l] * J.mg.H[l]) return;
     mg_prolong_node(v, J.mg.W[l], J.mg_ws + J.mg.xoff[l], J.mg.W[l + 1], J.mg_ws + J.mg.xoff[l + 1]);
 }
@@ -1602,8 +1619,8 @@ hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t 
     const long long supers = (long long)trv::super_cells(bs.max_cols) * trv::super_cells(bs.max_rows);
     hipLaunchKernelGGL(k_super_blocks_multi, dim3(blocks_for(supers, 256), bs.njobs), dim3(256), 0, st, jobs);
     hipLaunchKernelGGL(k_horizon_blocks_multi, dim3(blocks_for(4 * qcells, 256), bs.njobs), dim3(256), 0, st, jobs);
-    const long long near_tiles = (long long)blocks_for(bs.max_cols, kNearTile) * blocks_for(bs.max_rows, kNearTile);
-    hipLaunchKernelGGL(k_horizon_near_multi, dim3((unsigned)near_tiles, bs.njobs), dim3(256), 0, st, jobs);
+    if (bs.near_blocks > 0)
+        hipLaunchKernelGGL(k_horizon_near_multi, dim3(bs.near_blocks), dim3(256), 0, st, jobs, bs.njobs);
     hipLaunchKernelGGL(k_pyr0_multi, dim3(blocks_for(bs.max_pyr_cells[0], 256), bs.njobs), dim3(256), 0, st,
                        jobs);
     for (int l = 1; l < bs.max_pyr_levels; ++l)
@@ -1645,21 +1662,20 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     const int L = bs.max_mg_tail;  // every job's per-level part
     for (int c = 0; c < cycles; ++c) {
         for (int l = 0; l < L; ++l) {
-            const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
             for (int s = 0; s < 2; ++s)
                 for (int colour = 0; colour < 2; ++colour)
-                    hipLaunchKernelGGL(k_mg_smooth_multi, g, dim3(256), 0, st, jobs, l, colour, c, cold);
-            hipLaunchKernelGGL(k_mg_restrict_multi, dim3(blocks_for(bs.max_mg_nodes[l + 1], 256), nj), dim3(256),
-                               0, st, jobs, l, c, cold);
+                    hipLaunchKernelGGL(k_mg_smooth_multi, dim3(bs.mg_blocks[l]), dim3(256), 0, st, jobs, nj, l,
+                                       colour, c, cold);
+            hipLaunchKernelGGL(k_mg_restrict_multi, dim3(bs.rs_blocks[l]), dim3(256), 0, st, jobs, nj, l, c, cold);
         }
         hipLaunchKernelGGL(k_mg_tail_multi, dim3(1, nj), dim3(kMgTailThreads), sizeof(float) * bs.max_mg_tail_floats,
                            st, jobs, c, cold);
         for (int l = L - 1; l >= 0; --l) {
-            const dim3 g(blocks_for(bs.max_mg_nodes[l], 256), nj);
-            hipLaunchKernelGGL(k_mg_prolong_multi, g, dim3(256), 0, st, jobs, l, c, cold);
+            hipLaunchKernelGGL(k_mg_prolong_multi, dim3(bs.mg_blocks[l]), dim3(256), 0, st, jobs, nj, l, c, cold);
             for (int s = 0; s < 2; ++s)
                 for (int colour = 0; colour < 2; ++colour)
-                    hipLaunchKernelGGL(k_mg_smooth_multi, g, dim3(256), 0, st, jobs, l, colour, c, cold);
+                    hipLaunchKernelGGL(k_mg_smooth_multi, dim3(bs.mg_blocks[l]), dim3(256), 0, st, jobs, nj, l,
+                                       colour, c, cold);
         }
     }
     hipLaunchKernelGGL(k_min_key_multi, dim3(1, nj), dim3(64), 0, st, jobs, 1, cold);

@@ -64,6 +64,13 @@ struct TraceArgs {
 // Levels of at most kMgTailNodes nodes (from `tail` to the coarsest) run in one
 // single-block launch per V-cycle.
 constexpr int kMgTailNodes = 4096;
+// Blocks of 256 threads for n elements, and near-horizon tiles (16 x 16) of a
+// W x H surface: the units of the flattened multi-job grids.
+constexpr int kNearTile = 16;
+__host__ __device__ inline int flat_blocks(long long n) { return (int)((n + 255) / 256); }
+__host__ __device__ inline int near_tiles(int W, int H) {
+    return ((W + kNearTile - 1) / kNearTile) * ((H + kNearTile - 1) / kNearTile);
+}
 struct MgPlan {
     int levels;
     int tail;  // first level with at most kMgTailNodes nodes
@@ -84,6 +91,11 @@ struct JobDesc {
     int pyr_levels, quad_off;
     int pyr_wc[trv::kMaxLevels], pyr_hc[trv::kMaxLevels], pyr_off[trv::kMaxLevels];
     MgPlan mg;
+    // First block of this job in the flattened grids of the batch (jobs in
+    // table order, each with only the blocks it needs): multigrid level l
+    // (smoothing, prolongation; 0 blocks from the tail level on), restriction
+    // l -> l+1, and the near-horizon tiles.
+    int mg_bstart[kMaxMgLevels], rs_bstart[kMaxMgLevels], near_bstart;
     const float* I0;     // [K][C][H][W]
     const float* env;    // [He][We][C]
     int env_h, env_w;
@@ -113,6 +125,7 @@ struct BatchShape {
     int max_mg_tail;         // largest first tail level
     long long max_mg_tail_floats;  // largest LDS need of the tail levels
     int max_mg_nodes[kMaxMgLevels];
+    int mg_blocks[kMaxMgLevels], rs_blocks[kMaxMgLevels], near_blocks;  // flattened grid sizes
     int max_cycles_cold, max_cycles_warm;
     int max_KCnpx;           // largest K * C * W * H
     int max_K1, max_K3;      // largest light count of the grey and of the colour jobs (0: none)
