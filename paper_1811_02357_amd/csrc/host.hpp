@@ -118,8 +118,6 @@ inline kern::MgPlan mg_plan(int W, int H) {
         m.H[m.levels] = (m.H[m.levels - 1] + 1) / 2;
         ++m.levels;
     }
-    m.tail = 0;
-    while ((long long)m.W[m.tail] * m.H[m.tail] > kern::kMgTailNodes) ++m.tail;
     long long off = 0;
     for (int l = 0; l < m.levels; ++l) {
         const long long n = (long long)m.W[l] * m.H[l];
@@ -131,6 +129,12 @@ inline kern::MgPlan mg_plan(int W, int H) {
     m.keyoff = off;
     off += 64;
     m.total = off;
+    // the tail: the first level of at most kMgTailNodes nodes whose X and b,
+    // with those of every coarser level, fit the tail kernel's LDS
+    m.tail = 0;
+    while ((long long)m.W[m.tail] * m.H[m.tail] > kern::kMgTailNodes ||
+           (long long)sizeof(float) * (m.keyoff - m.xoff[m.tail]) > kern::kMgTailLdsBytes)
+        ++m.tail;
     return m;
 }
 

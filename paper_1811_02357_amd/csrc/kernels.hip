@@ -1541,6 +1541,8 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
                 hipLaunchKernelGGL(k_mg_smooth, dim3(blocks_for(nl, 256)), dim3(256), 0, st, plan.W[l],
                                    plan.H[l], l, W0, H0, X[l], b[l], colour);
     };
+    // the plan chose the tail so that its levels fit the default 64 KiB of LDS
+    if ((long long)sizeof(float) * mg_tail_floats(plan) > kMgTailLdsBytes) return hipErrorInvalidValue;
     for (int c = 0; c < cycles; ++c) {
         for (int l = 0; l < plan.tail; ++l) {
             smooth(l, 2);
@@ -1659,6 +1661,7 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     hipLaunchKernelGGL(k_mg_rhs_multi, gpx, dim3(256), 0, st, jobs, cold);
     hipLaunchKernelGGL(k_mg_init_multi, gpx, dim3(256), 0, st, jobs, cold);
     const int cycles = cold ? bs.max_cycles_cold : bs.max_cycles_warm;
+    if ((long long)sizeof(float) * bs.max_mg_tail_floats > kMgTailLdsBytes) return hipErrorInvalidValue;
     const int L = bs.max_mg_tail;  // every job's per-level part
     for (int c = 0; c < cycles; ++c) {
         for (int l = 0; l < L; ++l) {

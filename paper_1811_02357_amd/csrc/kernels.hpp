@@ -64,6 +64,7 @@ struct TraceArgs {
 // Levels of at most kMgTailNodes nodes (from `tail` to the coarsest) run in one
 // single-block launch per V-cycle.
 constexpr int kMgTailNodes = 4096;
+constexpr long long kMgTailLdsBytes = 65536;
 // Blocks of 256 threads for n elements, and near-horizon tiles (16 x 16) of a
 // W x H surface: the units of the flattened multi-job grids.
 constexpr int kNearTile = 16;

@@ -16,6 +16,8 @@
 // cell can read after binary32 rounding of its minor coordinate (off by far
 // less than a sample).  Cells touching the domain border are never skipped, so
 // the escape test is always taken at the same crossing as in the flat walk.
+// Escape windows and horizon bounds end a pyramid walk early only when no
+// crossing ahead can hit, which is the flat walk's result too.
 #pragma once
 
 #include "device_math.hpp"
@@ -114,7 +116,8 @@ struct Surface {
 
 // Loads through a 32-bit byte offset from a wave-uniform base, so that the
 // address is one scalar base plus one vector offset.  Every table a walk reads
-// (samples, pyramid, escape windows) is below 2^32 bytes: W H <= 2^28.
+// (samples, pyramid, escape windows, horizons) is below 2^32 bytes: W H <= 2^28
+// (the largest, four near horizons per sample, ends 16 bytes short of it).
 template <class T>
 __device__ __forceinline__ T ld32(const T* base, unsigned idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));

@@ -200,7 +200,7 @@ def test_ps_solve_stage(dev, C, K, shape):
     assert np.array_equal(H(n), rn) and np.array_equal(H(rho), rr)
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (37, 61), (3, 200), (2, 2), (257, 129), (2, 5000)])
+@pytest.mark.parametrize("shape", [(64, 64), (37, 61), (3, 200), (2, 2), (257, 129), (2, 5000), (2, 16384)])
 def test_integrate_stage(dev, shape):
     say(f"case: integrate {shape}")
     rng = np.random.default_rng(shape[0] * 7 + shape[1])
