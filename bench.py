@@ -30,6 +30,7 @@ Both legs require every job's outputs to be bit-identical to the plain path.
 import argparse
 import json
 import os
+import struct
 import sys
 import time
 
@@ -52,19 +53,55 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-TRACER_SOURCES = ("kernels.hip", "kernels.hpp", "traverse.hpp", "device_math.hpp")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_fbm2048_rgb_counters.md")
+TRACER_SYMBOL = "_ZN5irtps4kern7k_traceILi3EEEvNS0_9TraceArgsE"  # k_trace<3>
+
+
+def _elf_sections(data):
+    shoff = struct.unpack_from("<Q", data, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3a)
+    secs = []
+    for i in range(shnum):
+        name, typ, _flags, addr, offset, size, link, _info, _align, _ent = struct.unpack_from(
+            "<IIQQQQIIQQ", data, shoff + i * shentsize)
+        secs.append({"name": name, "type": typ, "addr": addr, "offset": offset, "size": size, "link": link})
+    names = secs[shstrndx]
+    for sec in secs:
+        raw = data[names["offset"] + sec["name"]:]
+        sec["name"] = raw[:raw.index(b"\0")].decode()
+    return secs
 
 
 def tracer_digest():
-    """sha256 over the tracer's sources: a byte-counter profile is only quoted
-    for the kernel it was taken on."""
+    """sha256 of the machine code of k_trace<3> in the built library (the
+    gfx950 code object of its offload bundle): a counter profile is only quoted
+    for the kernel it was taken on.  None if the library cannot be read."""
     import hashlib
-    h = hashlib.sha256()
-    for name in TRACER_SOURCES:
-        with open(os.path.join(ROOT, "paper_1811_02357_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    try:
+        with open(os.path.join(ROOT, "paper_1811_02357_amd", "libirtps.so"), "rb") as f:
+            data = f.read()
+        fat = next(s for s in _elf_sections(data) if s["name"] == ".hip_fatbin")
+        bundle = data[fat["offset"]:fat["offset"] + fat["size"]]
+        if bundle[:24] != b"__CLANG_OFFLOAD_BUNDLE__":
+            return None
+        code, p = None, 32
+        for _ in range(struct.unpack_from("<Q", bundle, 24)[0]):
+            off, size, tlen = struct.unpack_from("<QQQ", bundle, p)
+            if b"gfx950" in bundle[p + 24:p + 24 + tlen]:
+                code = bundle[off:off + size]
+            p += 24 + tlen
+        secs = _elf_sections(code)
+        symtab = next(s for s in secs if s["type"] == 2)
+        strs, text = secs[symtab["link"]], next(s for s in secs if s["name"] == ".text")
+        for k in range(symtab["size"] // 24):
+            st_name, st_info, _o, _x, st_value, st_size = struct.unpack_from("<IBBHQQ", code, symtab["offset"] + 24 * k)
+            raw = code[strs["offset"] + st_name:]
+            if raw[:raw.index(b"\0")].decode() == TRACER_SYMBOL and (st_info & 0xf) == 2:
+                fo = text["offset"] + (st_value - text["addr"])
+                return hashlib.sha256(code[fo:fo + st_size]).hexdigest()
+    except (OSError, StopIteration, struct.error, ValueError, TypeError):
+        return None
+    return None
 
 
 def profiled_values(workload):
@@ -75,7 +112,8 @@ def profiled_values(workload):
     try:
         with open(TRAFFIC_PROFILE) as f:
             kv = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
-        if kv.get("workload") != workload or kv.get("tracer_sources_sha256") != tracer_digest():
+        digest = tracer_digest()
+        if kv.get("workload") != workload or digest is None or kv.get("tracer_code_sha256") != digest:
             return None
         return {"traffic": float(kv["traffic_bytes_per_launch"]),
                 "valu": float(kv["valu_wave_instructions_per_launch"]),

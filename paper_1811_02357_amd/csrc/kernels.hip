@@ -96,6 +96,9 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
     n[3 * (size_t)p + 2] = nz;
 }
 
+// Walker steps per pass of the shadow-ray loop.
+constexpr int kDirectSteps = 4;
+
 // Eq.2 without albedo, with cast shadows: K any-hit walks from sample p.  Each
 // lane runs through its own lights: when one shadow ray ends it starts the next
 // at once, so a wave waits for its slowest lane's total, not for the slowest
@@ -125,10 +128,12 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     };
     start();
     while (k < K) {
-        // two steps per pass halve the divergent branch back to the loop head
+        // several steps per pass: fewer divergent branches back to the loop head
         int qi, qj;
         int res = trv::walker_step(w, S, qi, qj);
-        if (res == trv::kGoOn) res = trv::walker_step(w, S, qi, qj);
+#pragma unroll
+        for (int u = 1; u < kDirectSteps; ++u)
+            if (res == trv::kGoOn) res = trv::walker_step(w, S, qi, qj);
         if (res != trv::kGoOn) {
             out[k] = res == trv::kHit ? 0.0f : s[k] * c;
             ++k;
