@@ -148,11 +148,8 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
         shape.max_pyr_levels = std::max(shape.max_pyr_levels, J.pyr_levels);
         for (int l = 0; l < J.pyr_levels; ++l)
             shape.max_pyr_cells[l] = std::max(shape.max_pyr_cells[l], J.pyr_wc[l] * J.pyr_hc[l]);
-        shape.max_mg_levels = std::max(shape.max_mg_levels, J.mg.levels);
         shape.max_mg_tail = std::max(shape.max_mg_tail, J.mg.tail);
         shape.max_mg_tail_floats = std::max(shape.max_mg_tail_floats, J.mg.keyoff - J.mg.xoff[J.mg.tail]);
-        for (int l = 0; l < J.mg.levels; ++l)
-            shape.max_mg_nodes[l] = std::max(shape.max_mg_nodes[l], J.mg.W[l] * J.mg.H[l]);
         shape.max_cycles_cold = std::max(shape.max_cycles_cold, J.cycles_cold);
         shape.max_cycles_warm = std::max(shape.max_cycles_warm, J.cycles_warm);
         shape.max_KCnpx = std::max(shape.max_KCnpx, J.K * J.C * J.W * J.Hh);

@@ -122,10 +122,8 @@ struct BatchShape {
     int max_pyr_cells[trv::kMaxLevels];
     int max_pyr_levels;
     int max_rows, max_cols;  // largest H, W
-    int max_mg_levels;
     int max_mg_tail;         // largest first tail level
     long long max_mg_tail_floats;  // largest LDS need of the tail levels
-    int max_mg_nodes[kMaxMgLevels];
     int mg_blocks[kMaxMgLevels], rs_blocks[kMaxMgLevels], near_blocks;  // flattened grid sizes
     int max_cycles_cold, max_cycles_warm;
     int max_KCnpx;           // largest K * C * W * H
