@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define IRTPS_ABI_VERSION 1
+#define IRTPS_ABI_VERSION 2
 
 typedef enum irtps_status {
     IRTPS_OK = 0,
@@ -76,10 +76,11 @@ enum {
 /* Sample-stream tags (word 3 of the Philox counter). */
 enum { IRTPS_TAG_SOLVE = 0, IRTPS_TAG_RENDER = 1 };
 
-/* Counters of traced segments, accumulated by the trace kernels into a device
- * array of four uint64: [0] segments, [1] surface hits, [2] escapes to the
- * environment, [3] continuations (hits that start another segment). */
-#define IRTPS_NUM_COUNTERS 4
+/* Counters, a device array of five uint64: [0] segments, [1] surface hits,
+ * [2] escapes to the environment, [3] continuations (hits that start another
+ * segment), accumulated by the trace kernels; [4] IRT iterations run (the
+ * solves: T, or fewer with stop_tol). */
+#define IRTPS_NUM_COUNTERS 5
 
 typedef struct irtps_problem {
     int32_t width, height, channels, num_lights; /* W, H, C in {1,3}, K in 3..64 */
@@ -98,7 +99,9 @@ typedef struct irtps_params {
     int32_t flags;          /* IRTPS_FLAG_* */
     int32_t mg_cycles_cold; /* V-cycles of the first integration (0 = 8) */
     int32_t mg_cycles_warm; /* V-cycles of each warm-started integration (0 = 4) */
-    int32_t reserved;       /* must be 0 */
+    float stop_tol;         /* 0: run all T iterations; > 0: stop after the first iteration whose
+                               surface change D_H = max_p |H_{t+1}(p) - H_t(p)| (pixel units) is
+                               below stop_tol (last paragraph of Sec. IV); must be finite, >= 0 */
     uint64_t seed;          /* Philox key */
 } irtps_params;
 
@@ -106,7 +109,7 @@ typedef struct irtps_outputs {
     float* normals_dev;   /* [H][W][3] n_T */
     float* albedo_dev;    /* [C][H][W] rho_T */
     float* depth_dev;     /* [H][W] H_T, pixel units, min(H_T) = 0 */
-    float* indirect_dev;  /* [K][C][H][W] E_{T-1} (zeros for T = 0), or NULL */
+    float* indirect_dev;  /* [K][C][H][W] E of the last iteration run (zeros for T = 0), or NULL */
     uint64_t* counters_dev; /* IRTPS_NUM_COUNTERS uint64 accumulated over the solve, or NULL */
 } irtps_outputs;
 

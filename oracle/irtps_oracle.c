@@ -784,7 +784,7 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
 int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
              const float* s, const float* env, int He, int We, int spp, int B,
              int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
-             int cycles_warm, float* n, float* rho, float* H, float* E,
+             int cycles_warm, float stop_tol, float* n, float* rho, float* H, float* E,
              or_counters* cnt) {
     const size_t npx = (size_t)W * Hh;
     float* M = (float*)malloc(sizeof(float) * 3 * K);
@@ -809,7 +809,15 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
         float* tmp = A; A = A2; A2 = tmp;
         or_ps_solve(W, Hh, C, K, M, A, n, rho);
         or_integrate(W, Hh, n, H, cycles_warm, Hn);
+        /* D_H: the largest change of the surface in this iteration */
+        float dh = 0.0f;
+        for (size_t p = 0; p < npx; ++p) {
+            const float d = fabsf(Hn[p] - H[p]);
+            if (d > dh) dh = d;
+        }
         memcpy(H, Hn, sizeof(float) * npx);
+        if (cnt) cnt->v[4] += 1;
+        if (stop_tol > 0.0f && dh < stop_tol) break;
     }
     free(M);
     free(A);

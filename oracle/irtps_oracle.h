@@ -37,7 +37,8 @@ enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2 };
 enum { OR_MISS = 0, OR_HIT = 1 };
 
 /* counters of one trace: [0] segments, [1] hits, [2] escapes, [3] continuations */
-typedef struct { uint64_t v[4]; } or_counters;
+/* segments, surface hits, escapes, continuations, IRT iterations run */
+typedef struct { uint64_t v[5]; } or_counters;
 
 /* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -98,11 +99,14 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
               const float* rho, const float* l, const float* s, const float* env,
               int He, int We, int spp, int B, uint64_t seed, float* I0, or_counters* cnt);
 
-/* The whole IRT-PS loop.  Returns 0 or -1 (singular lights). */
+/* The whole IRT-PS loop (Sec. IV): T iterations, or fewer when stop_tol > 0
+ * and an iteration changes the surface by less than stop_tol, D_H =
+ * max_p |H_{t+1}(p) - H_t(p)| < stop_tol (last paragraph of Sec. IV).
+ * Returns 0 or -1 (singular lights). */
 int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
              const float* s, const float* env, int He, int We, int spp, int B,
              int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
-             int cycles_warm, float* n, float* rho, float* H, float* E,
+             int cycles_warm, float stop_tol, float* n, float* rho, float* H, float* E,
              or_counters* cnt);
 
 /* Element-wise batch forms (independent calls), used by the exhaustive checks. */

@@ -24,11 +24,11 @@ _i = ct.POINTER(ct.c_int)
 
 
 class Counters(ct.Structure):
-    _fields_ = [("v", ct.c_uint64 * 4)]
+    _fields_ = [("v", ct.c_uint64 * 5)]
 
     def as_dict(self):
         return {"segments": self.v[0], "hits": self.v[1], "escapes": self.v[2],
-                "continuations": self.v[3]}
+                "continuations": self.v[3], "iterations": self.v[4]}
 
 
 def lib():
@@ -65,7 +65,7 @@ def lib():
                                 + [_f, ct.POINTER(Counters)])
         L.or_render.restype = ct.c_int
         L.or_solve.argtypes = ([ct.c_int] * 4 + [_f] * 4 + [ct.c_int] * 5 + [ct.c_uint64]
-                               + [ct.c_int] * 4 + [_f] * 4 + [ct.POINTER(Counters)])
+                               + [ct.c_int] * 4 + [ct.c_float] + [_f] * 4 + [ct.POINTER(Counters)])
         L.or_solve.restype = ct.c_int
         L.or_num_threads.restype = ct.c_int
         _ll = ct.c_longlong
@@ -303,7 +303,7 @@ def render_scene(sc):
 
 
 def solve(I0, l, s, env, spp, B, T, seed=0, rho_mode=RHO_FIT, flags=0,
-          cycles_cold=8, cycles_warm=4):
+          cycles_cold=8, cycles_warm=4, stop_tol=0.0):
     I0, l, s, env = map(_f32, (I0, l, s, env))
     K, C, Hh, W = I0.shape
     n = np.zeros((Hh, W, 3), np.float32)
@@ -313,7 +313,7 @@ def solve(I0, l, s, env, spp, B, T, seed=0, rho_mode=RHO_FIT, flags=0,
     cnt = Counters()
     rc = lib().or_solve(W, Hh, C, K, _p(I0), _p(l), _p(s), _p(env), env.shape[0], env.shape[1],
                         spp, B, T, int(seed), rho_mode, flags, cycles_cold, cycles_warm,
-                        _p(n), _p(rho), _p(H), _p(E), ct.byref(cnt))
+                        float(stop_tol), _p(n), _p(rho), _p(H), _p(E), ct.byref(cnt))
     if rc != 0:
         raise ValueError("singular light configuration")
     return {"normals": n, "albedo": rho, "depth": H, "indirect": E, "counters": cnt.as_dict()}

@@ -59,6 +59,7 @@ int fill_job(kern::JobDesc& J, const irtps_problem& pr, const irtps_params& pa, 
     J.B = pa.bounces;
     J.t = 0;
     J.T = pa.iterations;
+    J.stop_tol = pa.stop_tol;
     J.rho_mode = pa.rho_mode;
     J.flags = pa.flags;
     J.cycles_cold = pa.mg_cycles_cold ? pa.mg_cycles_cold : 8;

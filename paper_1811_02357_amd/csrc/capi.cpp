@@ -16,6 +16,8 @@ using namespace irtps::host;
 
 extern "C" {
 
+static_assert(kern::kNumCounters == IRTPS_NUM_COUNTERS, "counter count");
+
 int irtps_abi_version(void) { return IRTPS_ABI_VERSION; }
 
 const char* irtps_status_string(int status) {
@@ -79,6 +81,8 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
     if (out->indirect_dev) HIP_TRY(kern::fill_f32(out->indirect_dev, 0.0f, (long long)npx * K * C, st));
 
     const kern::SurfaceArgs sa = surface(W, H, out->depth_dev, pyr);
+    const bool stop = pa->stop_tol > 0.0f;
+    int run = 0;  // IRT iterations run
     for (int t = 0; t < pa->iterations; ++t) {
         HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
         HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
@@ -107,12 +111,24 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         HIP_TRY(traced(ta, st));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
-        float* E = (t == pa->iterations - 1) ? out->indirect_dev : nullptr;
+        // the last iteration writes E; with a stop rule any iteration may be the last
+        float* E = (t == pa->iterations - 1 || stop) ? out->indirect_dev : nullptr;
         HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
                               out->albedo_dev, E, A, st));
         HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
-        HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st));
+        HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st, stop));
+        ++run;
+        if (stop) {
+            // the paper's stop rule: D_H = max |H_{t+1} - H_t| below the tolerance
+            unsigned bits = 0;
+            HIP_TRY(hipMemcpyAsync(&bits, kern::change_key_of(lay.plan, mg), sizeof(bits), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            float dh;
+            std::memcpy(&dh, &bits, sizeof(dh));
+            if (dh < pa->stop_tol) break;
+        }
     }
+    if (cnt) HIP_TRY(kern::add_u64(cnt + 4, (unsigned long long)run, st));
     return IRTPS_OK;
 }
 

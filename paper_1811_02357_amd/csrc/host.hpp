@@ -246,7 +246,8 @@ inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
         return IRTPS_ERR_INVALID_ARG;
     if (pa->spp < 1 || pa->bounces < 0 || pa->bounces > 8 || pa->iterations < 0 ||
         pa->iterations > 1000 || (pa->rho_mode != IRTPS_RHO_FIT && pa->rho_mode != IRTPS_RHO_PREV) ||
-        pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || pa->reserved != 0 ||
+        pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || !(pa->stop_tol >= 0.0f) ||
+        !(pa->stop_tol <= 3.0e38f) ||
         (pa->flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_LITERAL_CUMULATIVE | IRTPS_FLAG_FLAT_TRAVERSAL)))
         return IRTPS_ERR_INVALID_ARG;
     return IRTPS_OK;

@@ -1094,10 +1094,36 @@ __global__ void __launch_bounds__(256) k_min_key(const float* __restrict__ X, in
     min_key_strided(X, (long long)blockIdx.x * blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x, n, key);
 }
 
+// Largest of d >= 0 over a 256-thread block, one atomic per block into *key
+// (float bits of non-negative values order as unsigned integers).
+__device__ __forceinline__ void block_max_into(float d, unsigned* key) {
+    __shared__ unsigned s_max[4];
+    unsigned k = __float_as_uint(d);
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned other = __shfl_xor(k, o);
+        k = other > k ? other : k;
+    }
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = s_max[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = s_max[w] > m ? s_max[w] : m;
+        atomicMax(key, m);
+    }
+}
+
+// H = X - min(X); with change_key, also the largest |H_new - H_old| where out
+// holds H_old on entry (D_H of the paper's stop rule).
 __global__ void __launch_bounds__(256) k_anchor(const float* __restrict__ X, int n, const unsigned* key,
-                                                float* __restrict__ out) {
+                                                float* __restrict__ out, unsigned* change_key) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) out[v] = X[v] - order_val(*key);
+    float d = 0.0f;
+    if (v < n) {
+        const float h = X[v] - order_val(*key);
+        if (change_key) d = fabsf(h - out[v]);
+        out[v] = h;
+    }
+    if (change_key) block_max_into(d, change_key);
 }
 
 // ===========================================================================
@@ -1187,7 +1213,7 @@ __global__ void __launch_bounds__(256) k_begin_multi(JobDesc* jobs) {
     JobDesc& J = jobs[blockIdx.y];
     if (blockIdx.x == 0 && threadIdx.x == 0) J.t = 0;
     if (!J.active) return;
-    if (J.counters && blockIdx.x == 0 && threadIdx.x < 4) J.counters[threadIdx.x] = 0ull;
+    if (J.counters && blockIdx.x == 0 && threadIdx.x < kNumCounters) J.counters[threadIdx.x] = 0ull;
     if (J.E) {
         const long long n = (long long)J.K * J.C * J.W * J.Hh;
         for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
@@ -1198,7 +1224,10 @@ __global__ void __launch_bounds__(256) k_begin_multi(JobDesc* jobs) {
 
 __global__ void k_advance_multi(JobDesc* jobs, int njobs) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < njobs && iterating(jobs[j])) jobs[j].t += 1;
+    if (j < njobs && iterating(jobs[j])) {
+        jobs[j].t += 1;
+        if (jobs[j].counters) jobs[j].counters[4] += 1ull;  // IRT iterations run
+    }
 }
 
 template <int C>
@@ -1237,7 +1266,8 @@ __global__ void __launch_bounds__(64) k_correct_multi(const JobDesc* __restrict_
     const int t = threadIdx.x;
     if (t >= n) return;
     const bool cumulative = (J.flags & 2) != 0;
-    float* E = (J.t == J.T - 1) ? J.E : nullptr;
+    // the last iteration writes E; with a stop rule any iteration may be the last
+    float* E = (J.t == J.T - 1 || J.stop_tol > 0.0f) ? J.E : nullptr;
     correct_px<C>(p0 + t, npx, K, J.rho_mode, cumulative ? 1 : 0, J.I0, (cumulative && J.t > 0) ? J.A : J.I0,
                   sG + t * (KC + 1), sS + t * (K + 1), J.rho, E, J.A);
 }
@@ -1378,7 +1408,10 @@ __global__ void __launch_bounds__(256) k_min_key_multi(const JobDesc* __restrict
     if (!participates(J, cold)) return;
     unsigned* key = reinterpret_cast<unsigned*>(J.mg_ws + J.mg.keyoff);
     if (init) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *key = 0xffffffffu;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            key[0] = 0xffffffffu;
+            key[1] = 0u;  // D_H
+        }
         return;
     }
     const int n = J.W * J.Hh;
@@ -1389,9 +1422,27 @@ __global__ void __launch_bounds__(256) k_min_key_multi(const JobDesc* __restrict
 __global__ void __launch_bounds__(256) k_anchor_multi(const JobDesc* __restrict__ jobs, int cold) {
     const JobDesc& J = jobs[blockIdx.y];
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!participates(J, cold) || v >= J.W * J.Hh) return;
+    if (!participates(J, cold)) return;  // uniform per block
+    unsigned* key = reinterpret_cast<unsigned*>(J.mg_ws + J.mg.keyoff);
+    const bool measure = !cold && J.stop_tol > 0.0f;  // uniform per block
+    float d = 0.0f;
+    if (v < J.W * J.Hh) {
+        const float h = J.mg_ws[J.mg.xoff[0] + v] - order_val(key[0]);
+        if (measure) d = fabsf(h - J.depth[v]);
+        J.depth[v] = h;
+    }
+    if (measure) block_max_into(d, key + 1);
+}
+
+// The paper's stop rule: a job whose surface changed by less than stop_tol in
+// this iteration ends with it (T lowered to t + 1; t advances afterwards).
+__global__ void k_stop_multi(JobDesc* jobs, int njobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    JobDesc& J = jobs[j];
+    if (!iterating(J) || !(J.stop_tol > 0.0f)) return;
     const unsigned* key = reinterpret_cast<const unsigned*>(J.mg_ws + J.mg.keyoff);
-    J.depth[v] = J.mg_ws[J.mg.xoff[0] + v] - order_val(*key);
+    if (__uint_as_float(key[1]) < J.stop_tol) J.T = J.t + 1;
 }
 
 // ===========================================================================
@@ -1522,7 +1573,8 @@ hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, f
 constexpr unsigned kMinKeyBlocks = 512;
 
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
-                     float* ws, hipStream_t st) {
+                     float* ws, hipStream_t st, bool measure_change) {
+    if (measure_change && Hinit != Hout) return hipErrorInvalidValue;
     const int W0 = plan.W[0], H0 = plan.H[0];
     const int npx = W0 * H0;
     float* X[kMaxMgLevels];
@@ -1565,9 +1617,11 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
         }
     }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, key, 0xffffffffu, 1);
+    unsigned* change = measure_change ? change_key_of(plan, ws) : nullptr;
+    if (change) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, change, 0u, 1);
     const unsigned gm = blocks_for(npx, 256) < kMinKeyBlocks ? blocks_for(npx, 256) : kMinKeyBlocks;
     hipLaunchKernelGGL(k_min_key, dim3(gm), dim3(256), 0, st, X[0], npx, key);
-    hipLaunchKernelGGL(k_anchor, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key, Hout);
+    hipLaunchKernelGGL(k_anchor, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key, Hout, change);
     return hipGetLastError();
 }
 
@@ -1579,6 +1633,15 @@ hipError_t fill_f32(float* p, float v, long long n, hipStream_t st) {
 
 hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(p), 0u, 2 * n);
+    return hipGetLastError();
+}
+
+__global__ void k_add_u64(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) *p += v;
+}
+
+hipError_t add_u64(unsigned long long* p, unsigned long long v, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, st, p, v);
     return hipGetLastError();
 }
 
@@ -1690,6 +1753,8 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     const unsigned gm = gpx.x < kMinKeyBlocks ? gpx.x : kMinKeyBlocks;
     hipLaunchKernelGGL(k_min_key_multi, dim3(gm, nj), dim3(256), 0, st, jobs, 0, cold);
     hipLaunchKernelGGL(k_anchor_multi, gpx, dim3(256), 0, st, jobs, cold);
+    if (!cold)
+        hipLaunchKernelGGL(k_stop_multi, dim3(blocks_for(nj, 64)), dim3(64), 0, st, const_cast<JobDesc*>(jobs), nj);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ namespace irtps {
 namespace kern {
 
 constexpr int kMaxLights = 64;
+constexpr int kNumCounters = 5;  // IRTPS_NUM_COUNTERS
 // Tracer tiles: one 256-thread block covers tile_w x (256 / tile_w) pixels.
 constexpr int kTileThreads = 256;
 __host__ __device__ inline int tile_rows(int tile_w) { return kTileThreads / tile_w; }
@@ -77,7 +78,7 @@ struct MgPlan {
     int tail;  // first level with at most kMgTailNodes nodes
     int W[kMaxMgLevels], H[kMaxMgLevels];
     long long xoff[kMaxMgLevels], boff[kMaxMgLevels];
-    long long keyoff;  // one uint32 for the anchor's minimum
+    long long keyoff;  // uint32s: [0] the anchor's minimum, [1] the largest surface change (D_H)
     long long total;   // floats
 };
 
@@ -86,6 +87,7 @@ struct JobDesc {
     int W, Hh, C, K;
     int spp, B, t, T;
     int rho_mode, flags, cycles_cold, cycles_warm;
+    float stop_tol;     // > 0: the iteration whose D_H is below it is the last (T lowered to t + 1)
     uint32_t key0, key1;
     int active;         // 0: skipped by every multi-job kernel
     int tile_shift, ready_batch;  // the tracer's schedule for this job
@@ -143,10 +145,17 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 // Apron-max levels of P at pyr, then the block tables at pyr + quad_off.
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st);
+// With measure_change (Hinit == Hout), the largest |H_new - H_old| over the
+// nodes is left, as float bits, in uint32 [1] of the key area of ws
+// (change_key_of(plan, ws)).
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
-                     float* ws, hipStream_t st);
+                     float* ws, hipStream_t st, bool measure_change = false);
+inline unsigned* change_key_of(const MgPlan& plan, float* ws) {
+    return reinterpret_cast<unsigned*>(ws + plan.keyoff) + 1;
+}
 hipError_t fill_f32(float* p, float v, long long n, hipStream_t st);
 hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st);
+hipError_t add_u64(unsigned long long* p, unsigned long long v, hipStream_t st);
 // ---- multi-job launches: grid.y walks the job table, the tracer a tile queue ----
 // Persistent tracer over (job, tile) pairs; `queue` (one uint32) is cleared here.
 hipError_t trace_multi(const JobDesc* jobs, int C, const int2* tiles, int ntiles, unsigned* queue,

@@ -45,6 +45,7 @@ struct Job {
     int state = IRTPS_JOB_QUEUED;
     int status = IRTPS_OK;
     int t = 0;
+    int t_last = 0;                     // iterations to run: T, lowered by the stop rule
     int tiles = 0;                      // tracer tiles (table space while resident)
     bool admitted = false;
     bool initialised = false;
@@ -146,6 +147,7 @@ void finish(irtps_server* s, Job& J, int state, int status) {
 bool irtps_server::step() {
     std::vector<kern::JobDesc> fresh, running;
     std::vector<uint64_t> fresh_ids, running_ids;
+    std::vector<int> running_T;  // each running job's T after its iteration
     {
         std::unique_lock<std::mutex> lock(mu);
         // cancellations take effect at the iteration boundary
@@ -195,7 +197,7 @@ bool irtps_server::step() {
                 fresh.push_back(D);
                 fresh_ids.push_back(id);
             }
-            if (J.t < J.pa.iterations) {
+            if (J.t < J.t_last) {
                 D.t = J.t;
                 running.push_back(D);
                 running_ids.push_back(id);
@@ -210,7 +212,7 @@ bool irtps_server::step() {
                     finish(this, J, IRTPS_JOB_FAILED, J.status);
                     it = resident.erase(it);
                     any = true;
-                } else if (J.initialised && J.t >= J.pa.iterations) {
+                } else if (J.initialised && J.t >= J.t_last) {
                     finish(this, J, IRTPS_JOB_DONE, IRTPS_OK);
                     it = resident.erase(it);
                     any = true;
@@ -238,6 +240,14 @@ bool irtps_server::step() {
             rc = b.place(base, table_bytes);
             if (rc == IRTPS_OK) rc = b.upload_tables(stream);
             if (rc == IRTPS_OK) rc = b.run_iteration(stream);
+            // the stop rule may have lowered a job's T on the device
+            if (rc == IRTPS_OK) {
+                std::vector<kern::JobDesc> after(running.size());
+                const hipError_t e = hipMemcpyAsync(after.data(), b.d_jobs, sizeof(kern::JobDesc) * after.size(),
+                                                    hipMemcpyDeviceToHost, stream);
+                if (e != hipSuccess) rc = hip_fail(e);
+                for (size_t k = 0; k < after.size(); ++k) running_T.push_back(after[k].T);
+            }
         }
         if (rc == IRTPS_OK) {
             const hipError_t e = hipStreamSynchronize(stream);
@@ -250,13 +260,17 @@ bool irtps_server::step() {
     std::unique_lock<std::mutex> lock(mu);
     ++iterations;
     for (uint64_t id : fresh_ids) jobs[id].initialised = true;
-    for (uint64_t id : running_ids) jobs[id].t += 1;
+    for (size_t k = 0; k < running_ids.size(); ++k) {
+        Job& J = jobs[running_ids[k]];
+        J.t += 1;
+        if (k < running_T.size() && running_T[k] < J.t_last) J.t_last = running_T[k];
+    }
     for (auto it = resident.begin(); it != resident.end();) {
         Job& J = jobs[*it];
         if (rc != IRTPS_OK || J.status != IRTPS_OK) {
             finish(this, J, IRTPS_JOB_FAILED, rc != IRTPS_OK ? rc : J.status);
             it = resident.erase(it);
-        } else if (J.initialised && J.t >= J.pa.iterations) {
+        } else if (J.initialised && J.t >= J.t_last) {
             finish(this, J, IRTPS_JOB_DONE, IRTPS_OK);
             it = resident.erase(it);
         } else {
@@ -312,6 +326,7 @@ int irtps_server_submit(irtps_server* s, const irtps_problem* problem, const irt
     Job J;
     J.pr = *problem;
     J.pa = *params;
+    J.t_last = params->iterations;
     J.out = *outputs;
     const int K = problem->num_lights;
     J.lights.assign(problem->light_dirs_host, problem->light_dirs_host + 3 * K);

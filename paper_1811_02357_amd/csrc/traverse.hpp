@@ -177,8 +177,9 @@ enum : int { kMiss = 0, kHit = 1, kGoOn = 2 };
 // crossings compute it (fma, monotone); the windows carry the rounding margin.
 __device__ __forceinline__ bool escapes(float z, float slope, const float4& win) {
     // all four tests, without short-circuit branches
-    return (z >= win.x) & (fmaf(slope, (float)escape_scale(0), z) >= win.y) &
-           (fmaf(slope, (float)escape_scale(1), z) >= win.z) & (fmaf(slope, (float)escape_scale(2), z) >= win.w);
+    return ((int)(z >= win.x) & (int)(fmaf(slope, (float)escape_scale(0), z) >= win.y) &
+            (int)(fmaf(slope, (float)escape_scale(1), z) >= win.z) &
+            (int)(fmaf(slope, (float)escape_scale(2), z) >= win.w)) != 0;
 }
 
 // Smallest crossing index m >= 1 whose t = m ainv (the walk's own product) is
@@ -230,7 +231,8 @@ __device__ __forceinline__ unsigned quadrant(const Ray& r) { return (r.sx < 0 ? 
 __device__ __forceinline__ bool leaves_at_once(const Ray& r, float hn, const float4& hb) {
     // not descending: its height at travel T is at least oz + slope T
     const float s = r.slope;
-    return (r.dz >= 0.0f) & (s >= hn) & (s >= fmaf(hb.y, r.oz, hb.x)) & (s >= fmaf(hb.w, r.oz, hb.z));
+    return ((int)(r.dz >= 0.0f) & (int)(s >= hn) & (int)(s >= fmaf(hb.y, r.oz, hb.x)) &
+            (int)(s >= fmaf(hb.w, r.oz, hb.z))) != 0;
 }
 
 // The same, reading the bounds of the ray's start sample (never in a flat walk).
@@ -291,7 +293,7 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
             // the ray is at or above its maximum over that range (t_exit is finite:
             // a ray with no travel along either axis never gets here)
-            if ((z_now >= cmax) & (z_exit >= cmax) & (t_exit > t_now)) {
+            if (((int)(z_now >= cmax) & (int)(z_exit >= cmax) & (int)(t_exit > t_now)) != 0) {
                 // Resume at the first crossing of each family at or after t_exit:
                 // the exit line itself for the family the ray leaves through (t is
                 // strictly increasing in the index), a search for the other.

@@ -22,7 +22,7 @@ OK = 0
 RHO_FIT, RHO_PREV = 0, 1
 FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL = 1, 2, 4
 TAG_SOLVE, TAG_RENDER = 0, 1
-NUM_COUNTERS = 4
+NUM_COUNTERS = 5  # segments, hits, escapes, continuations, IRT iterations run
 
 _vp = ct.c_void_p
 _i32 = ct.c_int32
@@ -49,7 +49,7 @@ class Problem(ct.Structure):
 class Params(ct.Structure):
     _fields_ = [("spp", _i32), ("bounces", _i32), ("iterations", _i32), ("rho_mode", _i32),
                 ("flags", _i32), ("mg_cycles_cold", _i32), ("mg_cycles_warm", _i32),
-                ("reserved", _i32), ("seed", _u64)]
+                ("stop_tol", ct.c_float), ("seed", _u64)]
 
 
 class Outputs(ct.Structure):
@@ -206,13 +206,15 @@ def _problem(images, light_dirs, light_intensity, env):
 
 def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
           rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None,
-          workspace=None, stream=None):
+          workspace=None, stream=None, stop_tol=0.0):
     """The whole IRT-PS loop.  images [K][C][H][W], env [He][We][C] on the device.
+    stop_tol > 0 ends the loop after the first iteration that moves the surface
+    by less than stop_tol (pixel units) everywhere.
     Returns a dict of device tensors: normals, albedo, depth, indirect, counters."""
     K, C, H, W = images.shape
     dev = images.device
     pr, keep = _problem(images, light_dirs, light_intensity, env)
-    pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, 0, seed)
+    pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, float(stop_tol), seed)
     if out is None:
         out = {"normals": torch.empty((H, W, 3), device=dev),
                "albedo": torch.empty((C, H, W), device=dev),
@@ -235,9 +237,9 @@ def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, se
 
 
 def workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
-                    rho_mode=RHO_FIT, flags=0):
+                    rho_mode=RHO_FIT, flags=0, stop_tol=0.0):
     pr, keep = _problem(images, light_dirs, light_intensity, env)
-    pa = Params(spp, bounces, iterations, rho_mode, flags, 0, 0, 0, seed)
+    pa = Params(spp, bounces, iterations, rho_mode, flags, 0, 0, float(stop_tol), seed)
     n = _sz()
     _check("irtps_workspace_bytes", lib().irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n)))
     return n.value
@@ -359,8 +361,8 @@ def _batch_structs(jobs, outs):
         keep.append(k)
         probs[j] = pr
         pars[j] = Params(job["spp"], job["bounces"], job["iterations"], job.get("rho_mode", RHO_FIT),
-                         job.get("flags", 0), job.get("mg_cycles_cold", 0), job.get("mg_cycles_warm", 0), 0,
-                         job.get("seed", 0))
+                         job.get("flags", 0), job.get("mg_cycles_cold", 0), job.get("mg_cycles_warm", 0),
+                         float(job.get("stop_tol", 0.0)), job.get("seed", 0))
         if outs is not None:
             K, C, H, W = job["images"].shape
             out = outs[j]

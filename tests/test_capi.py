@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 20
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    assert L.irtps_abi_version() == 1
+    assert L.irtps_abi_version() == 2
     assert L.irtps_status_string(0) == b"ok"
     assert L.irtps_status_string(2) == b"singular light configuration"
 
@@ -64,6 +64,11 @@ def test_invalid_arguments_rejected_on_host():
     assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(bad), ct.byref(n)) == 1
     bad = irtps.Params(16, 1, 3, 2, 0, 0, 0, 0, 0)     # unknown albedo mode
     assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(bad), ct.byref(n)) == 1
+    for tol in (-1.0, float("nan"), float("inf")):     # stop tolerance: finite, >= 0
+        bad = irtps.Params(16, 1, 3, 0, 0, 0, 0, tol, 0)
+        assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(bad), ct.byref(n)) == 1
+    ok = irtps.Params(16, 1, 3, 0, 0, 0, 0, 0.25, 0)
+    assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(ok), ct.byref(n)) == 0
     # a workspace that is too small is refused before any device work
     o = irtps.Outputs(ct.c_void_p(256), ct.c_void_p(256), ct.c_void_p(256), None, None)
     assert L.irtps_solve(ct.byref(pr), ct.byref(pa), ct.byref(o), ct.c_void_p(256), 16, None) == 3

@@ -252,12 +252,12 @@ def test_trace_stage(dev, case):
     seed = 0x1234_5678_9ABC
     ref, rc = O.trace(Hf, n, rho, S, env, spp, B, seed, t=t, tag=tag,
                       flags=flags & irtps.FLAG_QUADRATURE)
-    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(irtps.NUM_COUNTERS, dtype=torch.int64, device=dev)
     G = irtps.trace(T(Hf, dev), T(n, dev), T(rho, dev), T(S, dev), T(env, dev), spp, B, seed, t=t,
                     tag=tag, flags=flags, counters=cnt)
     ref = np.transpose(ref, (2, 3, 0, 1))  # oracle [K][C][H][W] -> library [H][W][K][C]
     assert_radiance(H(G), ref, name)
-    assert H(cnt).tolist() == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"]]
+    assert H(cnt).tolist() == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"], 0]
     assert np.array_equal(H(G), ref)
 
 
@@ -294,15 +294,15 @@ def test_render_stage(dev):
 
 # ---------------------------------------------------------------------------
 # The whole loop.
-def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None):
+def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None, stop_tol=0.0):
     if I0 is None:
         I0, _ = O.render_scene(sc)
     Tn = sc.iterations if T_ is None else T_
     ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, Tn,
                   seed=sc.seed, rho_mode=rho_mode,
-                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE))
+                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE), stop_tol=stop_tol)
     out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
-                      sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags)
+                      sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
     return ref, {k: H(v) for k, v in out.items()}
 
 
@@ -312,7 +312,8 @@ def _compare_solve(ref, got, name):
     assert_depth(got["depth"], ref["depth"], name + " depth")
     assert_radiance(got["indirect"], ref["indirect"], name + " indirect")
     c = ref["counters"]
-    assert got["counters"].tolist() == [c["segments"], c["hits"], c["escapes"], c["continuations"]]
+    assert got["counters"].tolist() == [c["segments"], c["hits"], c["escapes"], c["continuations"],
+                                        c["iterations"]]
 
 
 @pytest.mark.parametrize("rho_mode,flags", [(irtps.RHO_FIT, 0), (irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE),
@@ -322,6 +323,23 @@ def test_solve_bowl64(dev, rho_mode, flags):
     sc = scenes.bowl_64()
     ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags)
     _compare_solve(ref, got, "bowl64")
+
+
+def test_solve_stop_rule(dev):
+    """The optional stop of Sec. IV: tolerances from the oracle's own surface
+    changes stop the GPU solve after the same iteration, with the same outputs
+    and iteration count."""
+    say("case: solve bowl64 with the D_H stop rule")
+    sc = scenes.bowl_64()
+    I0, _ = O.render_scene(sc)
+    args = (I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces)
+    d = [O.solve(*args, T_, seed=sc.seed)["depth"] for T_ in range(3)]
+    D0, D1 = (float(np.abs(d[t + 1].astype(np.float64) - d[t]).max()) for t in range(2))
+    for tol, want in ((np.nextafter(F32(D0), F32(np.inf)), 1), (F32(0.5 * (D0 + D1)), 2), (F32(1e-30), 3)):
+        ref, got = _solve_both(sc, dev, I0=I0, T_=3, stop_tol=float(tol))
+        assert ref["counters"]["iterations"] == want, (tol, D0, D1)
+        _compare_solve(ref, got, f"bowl64 stop {tol}")
+        assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
 
 
 def test_solve_groove512(dev):
@@ -559,7 +577,8 @@ def _batch_jobs(dev):
                          seed=k)  # inputs come from the oracle, never from the GPU
         jobs.append(dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
                          env=T(sc.env, dev), spp=spp, bounces=B, iterations=Tn, seed=100 + k,
-                         rho_mode=mode, flags=flags))
+                         rho_mode=mode, flags=flags,
+                         stop_tol=1e30 if k == 2 else 0.0))  # job 2 stops after its first iteration
         scs.append(sc)
     return jobs
 
@@ -652,11 +671,11 @@ def test_batch_against_oracle(dev):
     say("case: batched job against the oracle")
     jobs = _batch_jobs(dev)
     outs = irtps.batch_solve(jobs)
-    for k in (1, 3):
+    for k in (1, 2, 3):
         job = jobs[k]
         ref = O.solve(H(job["images"]), job["light_dirs"], job["light_intensity"], H(job["env"]), job["spp"],
                       job["bounces"], job["iterations"], seed=job["seed"], rho_mode=job["rho_mode"],
-                      flags=job["flags"] & irtps.FLAG_LITERAL_CUMULATIVE)
+                      flags=job["flags"] & irtps.FLAG_LITERAL_CUMULATIVE, stop_tol=job["stop_tol"])
         got = {kk: H(v) for kk, v in outs[k].items()}
         _compare_solve(ref, got, f"batch job {k}")
 

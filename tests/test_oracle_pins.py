@@ -703,6 +703,33 @@ def test_loop_improves_bowl_and_is_deterministic():
     assert r3["counters"]["segments"] == 3 * 64 * 64 * 16
 
 
+def test_loop_stop_rule():
+    """The optional stop of Sec. IV (last paragraph): the loop ends after the
+    first iteration whose surface change D_H = max |H_{t+1} - H_t| is below the
+    tolerance.  D_H is measured here from separate fixed-T runs; a tolerance just
+    above D_1 stops after one iteration and one between D_2 and D_1 after two,
+    each run equal bit for bit to the fixed-T run of that length (the indirect
+    images included); 0 runs all T."""
+    sc = scenes.bowl_64()
+    I0, _ = O.render_scene(sc)
+    args = (I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces)
+    runs = [O.solve(*args, T) for T in range(4)]
+    D = [float(np.abs(runs[t + 1]["depth"].astype(np.float64) - runs[t]["depth"]).max()) for t in range(3)]
+    assert D[1] < D[0] and D[2] < D[0]
+    full = O.solve(*args, 3, stop_tol=0.0)
+    assert full["counters"]["iterations"] == 3
+    assert np.array_equal(full["depth"], runs[3]["depth"])
+    for stop_after, tol in ((1, np.nextafter(F32(D[0]), F32(np.inf))),
+                            (2, F32(0.5 * (D[0] + D[1])) if D[1] < D[0] else None)):
+        r = O.solve(*args, 3, stop_tol=float(tol))
+        assert r["counters"]["iterations"] == stop_after, (stop_after, tol, D)
+        for k in ("normals", "albedo", "depth", "indirect"):
+            assert np.array_equal(r[k], runs[stop_after][k]), (stop_after, k)
+    # a tolerance at D_1 itself does not stop (the change must be below it)
+    r = O.solve(*args, 3, stop_tol=float(F32(D[0])))
+    assert r["counters"]["iterations"] >= 2
+
+
 def test_gather_paths_rebuilt_from_the_estimator():
     """The gather rebuilt path by path from Eq.7 and the colour products of
     Fig. 5: the same Philox stream and rays (pinned above), the path weight is
