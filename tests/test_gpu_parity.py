@@ -475,7 +475,8 @@ def _tmin(a, b, slack):
     return np.minimum(tx, ty)
 
 
-@pytest.mark.parametrize("shape,ptp", [((97, 150), 20.0), ((45, 70), 10.0), ((9, 1030), 4.0), ((300, 277), 40.0)])
+@pytest.mark.parametrize("shape,ptp", [((97, 150), 20.0), ((45, 70), 10.0), ((9, 1030), 4.0), ((300, 277), 40.0),
+                                       ((700, 1100), 90.0)])
 def test_horizon_bounds(dev, shape, ptp):
     """The horizon tables bound, from above, the slope a ray from a sample needs
     to clear every sample its crossings can read (escape margin included): the
