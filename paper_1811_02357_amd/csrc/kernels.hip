@@ -130,10 +130,10 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     while (k < K) {
         // several steps per pass: fewer divergent branches back to the loop head
         int qi, qj;
-        int res = trv::walker_step(w, S, qi, qj);
+        int res = trv::walker_step<true>(w, S, qi, qj);
 #pragma unroll
         for (int u = 1; u < kDirectSteps; ++u)
-            if (res == trv::kGoOn) res = trv::walker_step(w, S, qi, qj);
+            if (res == trv::kGoOn) res = trv::walker_step<true>(w, S, qi, qj);
         if (res != trv::kGoOn) {
             out[k] = res == trv::kHit ? 0.0f : s[k] * c;
             ++k;
@@ -846,7 +846,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
 #pragma unroll
             for (int u = 0; u < kStepsPerVote; ++u) {
                 if (!finished && !ready) {
-                    res = trv::walker_step(w, S, qi, qj);
+                    res = trv::walker_step<false>(w, S, qi, qj);
                     ready = res != trv::kGoOn;
                 }
             }

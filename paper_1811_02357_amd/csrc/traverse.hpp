@@ -248,7 +248,10 @@ __device__ __forceinline__ bool leaves_at_once(const Walker& w, const Surface& S
 
 // One step: a pyramid cell test (skip it, climb, descend or give up to crossing
 // evaluation), or the evaluation of the next crossing.  Returns kGoOn, kHit
-// (qi, qj set) or kMiss.
+// (qi, qj set) or kMiss.  kEscapeWindows adds the escape-window test to every
+// cell test; walks whose rays were already offered the horizon test at their
+// start (the tracer's) do better without it.
+template <bool kEscapeWindows>
 __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi, int& qj) {
     const Ray& r = w.r;
     const bool xline = w.tX <= w.tY;  // the next crossing is on an x-line (first on a tie)
@@ -271,13 +274,14 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             // lies in window k (one sample behind the block going +, the lerp's
             // second sample and the nudge included), and everything ahead in the
             // block-aligned quadrant.
-            const float4 win = ld32(S.esc, __umul24((unsigned)r.qrow + (iy >> kQuadShift), (unsigned)S.QW) +
-                                               (ix >> kQuadShift));
+            float4 win = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (kEscapeWindows)
+                win = ld32(S.esc, __umul24((unsigned)r.qrow + (iy >> kQuadShift), (unsigned)S.QW) + (ix >> kQuadShift));
             const unsigned cx = ix >> l, cy = iy >> l;
             const int2 lv = S.lvl[l];
             const float cmax = ld32(S.pyr, (unsigned)lv.x + __umul24(cy, (unsigned)lv.y) + cx);  // +inf near the border
             // both loads are issued before either result is tested (one wait)
-            __asm__ volatile("" : : "v"(cmax), "v"(win.x), "v"(win.y), "v"(win.z), "v"(win.w));
+            if (kEscapeWindows) __asm__ volatile("" : : "v"(cmax), "v"(win.x), "v"(win.y), "v"(win.z), "v"(win.w));
             // exit of the cell along the ray (computed while the loads are in
             // flight): the crossing index of its far edge in x and in y, >= 1
             // because the nudged position lies beyond the origin's lines
@@ -289,7 +293,7 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             const bool x_exit = txe <= tye;
             const float t_exit = x_exit ? txe : tye;
             const float z_exit = fmaf(t_exit, r.dz, r.oz);
-            if (rising && escapes(z_now, r.slope, win)) return kMiss;
+            if (kEscapeWindows && rising && escapes(z_now, r.slope, win)) return kMiss;
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
             // the ray is at or above its maximum over that range (t_exit is finite:
             // a ray with no travel along either axis never gets here)
@@ -361,7 +365,7 @@ __device__ __forceinline__ bool walk(const Surface& S, bool flat, int i0, int j0
     walker_init(w, S, i0, j0, dx, dy, dz, flat);
     if (leaves_at_once(w, S)) return false;
     for (;;) {
-        const int res = walker_step(w, S, qi, qj);
+        const int res = walker_step<true>(w, S, qi, qj);
         if (res != kGoOn) return res == kHit;
     }
 }
