@@ -155,6 +155,9 @@ __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, 
         float rt;
         if (rho_mode == 0) {
             float num = 0.0f, den = 0.0f;
+            // unrolled so that several image loads are in flight (the sums
+            // still run over k in order)
+#pragma unroll 16
             for (int k = 0; k < K; ++k) {
                 const size_t x = ((size_t)k * C + c) * npx + p;
                 const float v = Srow[k] + Grow[k * C + c];
@@ -165,6 +168,7 @@ __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, 
         } else {
             rt = rho[(size_t)c * npx + p];
         }
+#pragma unroll 16
         for (int k = 0; k < K; ++k) {
             const size_t x = ((size_t)k * C + c) * npx + p;
             const float e = rt * Grow[k * C + c];
@@ -176,12 +180,28 @@ __device__ __forceinline__ void correct_px(int p, int npx, int K, int rho_mode, 
 
 // Rows of a pixel-major array (w floats per pixel, rows r0.. r0+n-1 contiguous
 // from src) into LDS with a row stride of w + 1 (odd: lanes reading their own
-// rows hit distinct banks).  Loads are coalesced across the block.
+// rows hit distinct banks).  Loads are coalesced across the block, and each
+// lane issues kStageBatch of them before it stores any, so that a wave keeps
+// that many in flight (LDS, not registers, limits these blocks per CU).
+constexpr int kStageBatch = 32;
 __device__ __forceinline__ void stage_rows(const float* __restrict__ src, int n, int w, float* dst) {
     const unsigned magic = 0xFFFFFFFFu / (unsigned)w + 1u;  // x / w = umulhi(x, magic) for x < 2^32 / w
-    for (int x = threadIdx.x; x < n * w; x += blockDim.x) {
-        const int r = (int)__umulhi((unsigned)x, magic);
-        dst[r * (w + 1) + (x - r * w)] = src[x];
+    const int total = n * w, nt = (int)blockDim.x;
+    for (int base = (int)threadIdx.x; base < total; base += kStageBatch * nt) {
+        float v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int x = base + u * nt;
+            v[u] = x < total ? src[x] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int x = base + u * nt;
+            if (x < total) {
+                const int r = (int)__umulhi((unsigned)x, magic);
+                dst[r * (w + 1) + (x - r * w)] = v[u];
+            }
+        }
     }
 }
 
