@@ -73,6 +73,8 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        // unrolled so that several image loads are in flight (sums in k order)
+#pragma unroll 16
         for (int k = 0; k < K; ++k) {
             const float a = A[((size_t)k * C + c) * npx + p];
             g0 = fmaf(M[k], a, g0);
