@@ -144,6 +144,7 @@ void Batch::build(const std::vector<kern::JobDesc>& js) {
     }
     for (const kern::JobDesc& J : jobs) {
         shape.max_npx = std::max(shape.max_npx, J.W * J.Hh);
+        shape.max_direct_tiles = std::max(shape.max_direct_tiles, kern::tiles_for(J.W, J.Hh, kern::kDirectTileW));
         shape.max_rows = std::max(shape.max_rows, J.Hh);
         shape.max_cols = std::max(shape.max_cols, J.W);
         shape.max_pyr_levels = std::max(shape.max_pyr_levels, J.pyr_levels);

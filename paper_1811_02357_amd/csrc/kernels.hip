@@ -144,6 +144,20 @@ __device__ __forceinline__ void direct_px(const Surface& S, int p, const float* 
     }
 }
 
+// The pixel a direct-shading thread takes: block b of nb covers a tile of
+// kDirectTileW x (256 / kDirectTileW) samples (XCD-aware order), or -1 past the
+// image.  Shadow rays of nearby samples cross similar terrain, so compact tiles
+// keep a wave's walks alike in length.
+__device__ __forceinline__ int direct_pixel(int W, int Hh, int b, int nb) {
+    const int th = tile_rows(kDirectTileW);
+    const int tiles_x = (W + kDirectTileW - 1) / kDirectTileW;
+    const int tile = xcd_tile(b, nb);
+    if (tile >= tiles_x * ((Hh + th - 1) / th)) return -1;
+    const int i = (tile % tiles_x) * kDirectTileW + ((int)threadIdx.x % kDirectTileW);
+    const int j = (tile / tiles_x) * th + ((int)threadIdx.x / kDirectTileW);
+    return (i < W && j < Hh) ? j * W + i : -1;
+}
+
 // Stage 5 for one pixel p: Grow[k C + c] and Srow[k] are that pixel's gathered
 // and direct values (images and E are [k][c][p]).
 template <int C>
@@ -950,8 +964,8 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
                                                 int flat, float* __restrict__ S_out) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(sa.off, sa.wc, s_lvl);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= sa.W * sa.Hh) return;
+    const int p = direct_pixel(sa.W, sa.Hh, blockIdx.x, gridDim.x);
+    if (p < 0) return;
     const Surface S = make_surface(sa, s_lvl);
     direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
 }
@@ -1265,8 +1279,8 @@ __global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict_
     __shared__ int2 s_lvl[trv::kMaxLevels];
     const JobDesc& J = jobs[blockIdx.y];
     load_level_table(J.pyr_off, J.pyr_wc, s_lvl);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!iterating(J) || p >= J.W * J.Hh) return;
+    const int p = direct_pixel(J.W, J.Hh, blockIdx.x, gridDim.x);
+    if (!iterating(J) || p < 0) return;
     const Surface S = make_surface(J.depth, J.pyr, J.W, J.Hh, J.pyr_levels, J.quad_off, s_lvl);
     direct_px(S, p, J.n, J.K, &J.L[0][0], J.s, (J.flags & kFlagFlat) != 0, J.S);
 }
@@ -1531,8 +1545,8 @@ hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, fl
 
 hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_direct, dim3(blocks_for((long long)sa.W * sa.Hh, 256)), dim3(256), 0, st,
-                       sa, n, L, flat, S);
+    const int tiles = tiles_for(sa.W, sa.Hh, kDirectTileW);
+    hipLaunchKernelGGL(k_direct, dim3((tiles + 7) / 8 * 8), dim3(256), 0, st, sa, n, L, flat, S);
     return hipGetLastError();
 }
 
@@ -1722,7 +1736,8 @@ hipError_t batch_pyramid(const JobDesc* jobs, const BatchShape& bs, hipStream_t 
 }
 
 hipError_t batch_direct(const JobDesc* jobs, const BatchShape& bs, hipStream_t st) {
-    hipLaunchKernelGGL(k_direct_multi, dim3(blocks_for(bs.max_npx, 256), bs.njobs), dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_direct_multi, dim3((bs.max_direct_tiles + 7) / 8 * 8, bs.njobs), dim3(256), 0, st,
+                       jobs);
     return hipGetLastError();
 }
 

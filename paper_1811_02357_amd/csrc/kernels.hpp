@@ -14,6 +14,8 @@ constexpr int kNumCounters = 5;  // IRTPS_NUM_COUNTERS
 // Tracer tiles: one 256-thread block covers tile_w x (256 / tile_w) pixels.
 constexpr int kTileThreads = 256;
 __host__ __device__ inline int tile_rows(int tile_w) { return kTileThreads / tile_w; }
+// Tile width of the direct-shading kernels (tiles of 8 x 32 samples).
+constexpr int kDirectTileW = 8;
 __host__ __device__ inline int tiles_for(int W, int H, int tile_w) {
     const int th = tile_rows(tile_w);
     return ((W + tile_w - 1) / tile_w) * ((H + th - 1) / th);
@@ -121,6 +123,7 @@ struct JobDesc {
 struct BatchShape {
     int njobs;
     int max_npx;             // largest W * H
+    int max_direct_tiles;    // largest tiles_for(W, H, kDirectTileW)
     int max_pyr_cells[trv::kMaxLevels];
     int max_pyr_levels;
     int max_rows, max_cols;  // largest H, W
