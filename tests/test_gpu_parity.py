@@ -215,7 +215,8 @@ def test_integrate_stage(dev, shape):
     assert np.array_equal(H(warm), O.integrate(n, ref, 3))
 
 
-@pytest.mark.parametrize("name,make", SURFACES[1:4], ids=[s[0] for s in SURFACES[1:4]])
+# ragged against the 8 x 32 tiles of the direct kernel: 61 x 37, 277 x 300, 53 x 97
+@pytest.mark.parametrize("name,make", SURFACES[1:], ids=[s[0] for s in SURFACES[1:]])
 def test_direct_stage(dev, name, make):
     say(f"case: direct {name}")
     rng = np.random.default_rng(11)
