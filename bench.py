@@ -227,6 +227,47 @@ def batched_leg(args, dev):
             "speedup": tp / tb, "repeats": args.mode_reps}
 
 
+def small_leg(args, dev):
+    """The 64 x 64 bowl (8 lights, grey, spp 16, B 1, T 3), a solve short enough
+    to be bound by launches: timed call by call through the plain solve (kernels
+    launched one by one on the stream) and through a one-job batched solve whose
+    iterations replay a captured HIP graph."""
+    import numpy as np
+    import torch
+    from paper_1811_02357_amd import irtps, scenes
+    n = args.small_reps
+    log(f"bench: small leg, bowl 64x64, {n} solves each way")
+    job = _job(scenes.bowl_64(), dev, irtps, torch, np)
+    stream = torch.cuda.current_stream()
+
+    def each(fn):
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return np.array(ts)
+
+    ws = torch.empty(irtps.workspace_bytes(**job), dtype=torch.uint8, device=dev)
+    out = irtps.solve(**job, workspace=ws)  # warm-up and reference
+    plain = each(lambda: irtps.solve(**job, out=out, workspace=ws))
+    bws = torch.empty(irtps.batch_workspace_bytes([job]), dtype=torch.uint8, device=dev)
+    bout = [irtps._outputs_for(job["images"], dev)]
+    irtps.batch_solve([job], graph=True, outs=bout, workspace=bws)  # warm-up, graph capture
+    graph = each(lambda: irtps.batch_solve([job], graph=True, outs=bout, workspace=bws))
+    torch.cuda.synchronize()
+    same = _same(out, bout[0], torch)
+    log(f"bench: small solve {np.median(plain):.3f} ms plain vs {np.median(graph):.3f} ms graph-replayed")
+    stats = lambda t: {"median_ms": float(np.median(t)), "p99_ms": float(np.quantile(t, 0.99)),
+                       "reconstructions_per_s": 1e3 / float(np.median(t))}
+    return {"workload": "bowl64: 64x64 bowl, K 8, grey, env 2x4 uniform; spp 16, bounces 1, iterations 3",
+            "repeats": n, "equal_to_plain": bool(same), "plain": stats(plain), "graph": stats(graph),
+            "speedup": float(np.median(plain) / np.median(graph))}
+
+
 def served_leg(args, dev):
     """A truncated Poisson arrival trace through a FIFO loop over the plain
     solve and through the continuous-batching server."""
@@ -299,8 +340,9 @@ def main():
     ap.add_argument("--flat", action="store_true", help="walk every crossing (no pyramid skips)")
     ap.add_argument("--cpu-tile", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="all", choices=["all", "plain", "batched", "served"],
-                    help="plain: the main workload only; batched/served: the main workload and that leg")
+    ap.add_argument("--mode", default="all", choices=["all", "plain", "small", "batched", "served"],
+                    help="plain: the main workload only; small/batched/served: the main workload and that leg")
+    ap.add_argument("--small-reps", type=int, default=200)
     ap.add_argument("--batched-jobs", type=int, default=64)
     ap.add_argument("--served-jobs", type=int, default=24)
     ap.add_argument("--served-budget-gib", type=float, default=96.0)
@@ -409,6 +451,8 @@ def main():
                               "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
     del ws, out, I0
     torch.cuda.empty_cache()
+    if args.mode in ("all", "small"):
+        line["small"] = small_leg(args, dev)
     if args.mode in ("all", "batched"):
         line["batched"] = batched_leg(args, dev)
         torch.cuda.empty_cache()
