@@ -68,6 +68,8 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
     float* G = reinterpret_cast<float*>(base + lay.G);
     float* pyr = reinterpret_cast<float*>(base + lay.pyr);
     float* mg = reinterpret_cast<float*>(base + lay.mg);
+    unsigned* tile_cost = reinterpret_cast<unsigned*>(base + lay.tile_cost);
+    int* tile_order = reinterpret_cast<int*>(base + lay.tile_order);
     const int npx = W * H;
     const int cold = pa->mg_cycles_cold ? pa->mg_cycles_cold : 8;
     const int warm = pa->mg_cycles_warm ? pa->mg_cycles_warm : 4;
@@ -108,6 +110,15 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
         ta.ready_batch = sched.ready_batch;
         ta.tile_shift = sched.tile_shift;
+        // Each launch records its blocks' times per tile; from the second
+        // iteration on, the tiles go out heaviest first by the previous
+        // iteration's times, so that the launch ends on short blocks (the
+        // surface changes little between iterations).
+        ta.tile_cost = tile_cost;
+        if (t > 0) {
+            HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
+            ta.order = tile_order;
+        }
         HIP_TRY(traced(ta, st));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;

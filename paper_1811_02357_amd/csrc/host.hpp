@@ -215,7 +215,7 @@ inline kern::SurfaceArgs surface(int W, int H, const float* depth, const float* 
 
 // Workspace layout of one solve (byte offsets, each 256-aligned).
 struct SolveLayout {
-    size_t A, S, G, pyr, mg, total;
+    size_t A, S, G, pyr, mg, tile_cost, tile_order, total;
     kern::MgPlan plan;
 };
 
@@ -234,6 +234,10 @@ inline SolveLayout solve_layout(int W, int H, int C, int K) {
     L.plan = mg_plan(W, H);
     L.mg = off;
     off = align_up(off + sizeof(float) * (size_t)L.plan.total);
+    L.tile_cost = off;
+    off = align_up(off + sizeof(unsigned) * (size_t)kern::max_trace_tiles(W, H));
+    L.tile_order = off;
+    off = align_up(off + sizeof(int) * (size_t)kern::max_trace_tiles(W, H));
     L.total = off;
     return L;
 }

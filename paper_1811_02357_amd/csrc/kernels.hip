@@ -974,15 +974,87 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
 // 72 VGPRs); eight forces spills to scratch, six measure slower.
 #define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7)))
 
+// Blocks take their tiles in XCD order, or in the given order (a permutation of
+// the tiles: block b < tiles takes order[b]).  With tile_cost, each block
+// records its time (wall clock, its slowest wave's) under its tile.
 template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(a.sa.off, a.sa.wc, s_lvl);
     const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= tiles) return;
+    int tile;
+    if (a.order) {
+        if ((int)blockIdx.x >= tiles) return;
+        tile = a.order[blockIdx.x];
+    } else {
+        tile = xcd_tile(blockIdx.x, gridDim.x);
+        if (tile >= tiles) return;
+    }
     const Surface S = make_surface(a.sa, s_lvl);
+    const unsigned long long t0 = wall_clock64();
     trace_tile<C>(a, S, tile);
+    if (a.tile_cost) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long dt = wall_clock64() - t0;
+            a.tile_cost[tile] = dt < 0xFFFFFFFFull ? (unsigned)dt : 0xFFFFFFFFu;
+        }
+    }
+}
+
+// Tiles by descending cost: a counting sort over kOrderBuckets cost classes in
+// one block (classes of 2^s ticks, s the least shift that fits the largest
+// cost).  Slots within a class go by LDS atomics, so ties fall in any order;
+// the trace does not depend on the order.
+constexpr int kOrderBuckets = 4096;
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) k_order_tiles(const unsigned* __restrict__ cost, int tiles,
+                                                                int* __restrict__ order) {
+    __shared__ unsigned s_cnt[kOrderBuckets];
+    __shared__ unsigned s_part[kOrderThreads];
+    const int tid = (int)threadIdx.x;
+    unsigned mx = 0;
+    for (int t = tid; t < tiles; t += kOrderThreads) mx = cost[t] > mx ? cost[t] : mx;
+    s_part[tid] = mx;
+    for (int b = tid; b < kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0u;
+    __syncthreads();
+    for (int h = kOrderThreads / 2; h > 0; h >>= 1) {
+        if (tid < h && s_part[tid + h] > s_part[tid]) s_part[tid] = s_part[tid + h];
+        __syncthreads();
+    }
+    mx = s_part[0];
+    int sh = 0;
+    while ((mx >> sh) >= (unsigned)kOrderBuckets) ++sh;
+    __syncthreads();  // every thread has read s_part[0]
+    // class k = kOrderBuckets - 1 - (cost >> sh): the heaviest tiles come first
+    for (int t = tid; t < tiles; t += kOrderThreads) atomicAdd(&s_cnt[kOrderBuckets - 1 - (cost[t] >> sh)], 1u);
+    __syncthreads();
+    // exclusive scan of the counts: each thread sums its 4 classes, the block
+    // scans the partial sums, then each thread writes its classes' starts
+    constexpr int per = kOrderBuckets / kOrderThreads;
+    unsigned loc = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) loc += s_cnt[tid * per + i];
+    s_part[tid] = loc;
+    __syncthreads();
+    for (int h = 1; h < kOrderThreads; h <<= 1) {
+        const unsigned v = tid >= h ? s_part[tid - h] : 0u;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    unsigned start = s_part[tid] - loc;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        const unsigned c = s_cnt[tid * per + i];
+        s_cnt[tid * per + i] = start;
+        start += c;
+    }
+    __syncthreads();
+    for (int t = tid; t < tiles; t += kOrderThreads) {
+        const unsigned slot = atomicAdd(&s_cnt[kOrderBuckets - 1 - (cost[t] >> sh)], 1u);
+        order[slot] = t;
+    }
 }
 
 template <int C>
@@ -1205,6 +1277,8 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
     a.env = J.env;
     a.G = J.G;
     a.counters = J.counters;
+    a.order = nullptr;
+    a.tile_cost = nullptr;
     a.env_h = J.env_h;
     a.env_w = J.env_w;
     a.C = J.C;
@@ -1547,6 +1621,11 @@ hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int 
                   hipStream_t st) {
     const int tiles = tiles_for(sa.W, sa.Hh, kDirectTileW);
     hipLaunchKernelGGL(k_direct, dim3((tiles + 7) / 8 * 8), dim3(256), 0, st, sa, n, L, flat, S);
+    return hipGetLastError();
+}
+
+hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t st) {
+    hipLaunchKernelGGL(k_order_tiles, dim3(1), dim3(kOrderThreads), 0, st, cost, tiles, order);
     return hipGetLastError();
 }
 

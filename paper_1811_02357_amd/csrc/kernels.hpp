@@ -20,6 +20,12 @@ __host__ __device__ inline int tiles_for(int W, int H, int tile_w) {
     const int th = tile_rows(tile_w);
     return ((W + tile_w - 1) / tile_w) * ((H + th - 1) / th);
 }
+// Most tracer tiles over the schedule's tile widths (8..64).
+__host__ __device__ inline int max_trace_tiles(int W, int H) {
+    int m = 0;
+    for (int tw = 8; tw <= 64; tw *= 2) m = tiles_for(W, H, tw) > m ? tiles_for(W, H, tw) : m;
+    return m;
+}
 constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
@@ -61,6 +67,8 @@ struct TraceArgs {
     int ready_batch;   // lanes that must have a result before the wave shades
     int tile_shift;    // tile width 2^tile_shift (8..64 pixels), 256 / width rows
     uint32_t key0, key1;
+    const int* order;     // tile of each block (a permutation of the tiles), or null: XCD order
+    unsigned* tile_cost;  // per tile, the block's time in wall-clock ticks (written), or null
 };
 
 // Multigrid levels of a W x H grid, offsets (in floats) into the workspace.
@@ -140,6 +148,8 @@ hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, fl
 hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
                   hipStream_t st);
 hipError_t trace(TraceArgs a, hipStream_t st);
+// order[0..tiles) = the tiles by descending cost (ties in any order).
+hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t st);
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
                    const float* Aprev, const float* G, const float* S, const float* rho, float* E,
                    float* Anext, hipStream_t st);
