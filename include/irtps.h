@@ -133,7 +133,9 @@ int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* para
 /* t = 0: PS of I0 (Eq.4) and integration; then T times: trace the current
  * surface (Eq.5-7), subtract the indirect estimate (stage 5), PS and integrate
  * warm-started from H_t.  ws_dev must hold irtps_workspace_bytes() bytes,
- * 256-byte aligned. */
+ * 256-byte aligned; it needs no initialisation and carries nothing between
+ * calls (besides the loop's buffers it keeps each tracer tile's launch time,
+ * which orders the next iteration's tiles and never changes a result). */
 int irtps_solve(const irtps_problem* problem, const irtps_params* params,
                 const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
                 void* stream);
