@@ -75,3 +75,30 @@ def test_invalid_arguments_rejected_on_host():
     assert L.irtps_trace(64, 64, 2, 8, *([ct.c_void_p(256)] * 5), 2, 4, ct.c_void_p(256), 16, 1, 0,
                          0, 0, 0, ct.c_void_p(256), None, None) == 1  # C = 2
     assert L.irtps_probe_philox(-1, None, 0, None, None) == 1
+
+
+def test_size_limits_on_host():
+    """Sizes at the documented limits are accepted and sized without overflow;
+    one past them is refused (no device work)."""
+    L = irtps.lib()
+    n = ct.c_size_t()
+    pa = irtps.Params(16, 1, 3, 0, 0, 0, 0, 0, 0)
+    l = np.zeros((64, 3), np.float32)
+    lp = l.ctypes.data_as(ct.c_void_p)
+
+    def ws(W, H, C, K):
+        pr = irtps.Problem(W, H, C, K, ct.c_void_p(256), lp, None, ct.c_void_p(256), 2, 4)
+        return L.irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n))
+
+    # the largest surface: 16384 x 16384 samples (W H = 2^28), 64 lights, RGB
+    assert ws(16384, 16384, 3, 64) == 0
+    images = 4 * 16384 * 16384 * 64 * 3
+    assert n.value > 2 * images  # A and G at least, computed in 64-bit
+    assert ws(2, 2, 1, 3) == 0 and n.value > 0
+    for W, H, C, K in ((16385, 2, 1, 8), (2, 16385, 1, 8), (1, 64, 1, 8), (64, 1, 1, 8),
+                       (64, 64, 2, 8), (64, 64, 1, 2), (64, 64, 1, 65)):
+        assert ws(W, H, C, K) == 1, (W, H, C, K)
+    b = ct.c_size_t()
+    assert L.irtps_pyramid_bytes(16384, 16384, ct.byref(b)) == 0 and b.value > 4 * 16384 * 16384
+    assert L.irtps_pyramid_bytes(16385, 16384, ct.byref(b)) == 1
+    assert L.irtps_integrate_workspace_bytes(16384, 16384, ct.byref(b)) == 0 and b.value > 4 * 16384 * 16384
