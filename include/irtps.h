@@ -110,7 +110,8 @@ typedef struct irtps_outputs {
     float* albedo_dev;    /* [C][H][W] rho_T */
     float* depth_dev;     /* [H][W] H_T, pixel units, min(H_T) = 0 */
     float* indirect_dev;  /* [K][C][H][W] E of the last iteration run (zeros for T = 0), or NULL */
-    uint64_t* counters_dev; /* IRTPS_NUM_COUNTERS uint64 accumulated over the solve, or NULL */
+    uint64_t* counters_dev; /* IRTPS_NUM_COUNTERS uint64 accumulated over the solve (zeroed at
+                               its start), or NULL */
 } irtps_outputs;
 
 /* ---- library ------------------------------------------------------------ */

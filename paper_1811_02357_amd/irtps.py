@@ -220,7 +220,7 @@ def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, se
                "albedo": torch.empty((C, H, W), device=dev),
                "depth": torch.empty((H, W), device=dev),
                "indirect": torch.empty((K, C, H, W), device=dev),
-               "counters": torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=dev)}
+               "counters": torch.empty(NUM_COUNTERS, dtype=torch.int64, device=dev)}  # zeroed by the solve
     o = Outputs(_dev(out["normals"], shape=(H, W, 3), name="normals"),
                 _dev(out["albedo"], shape=(C, H, W), name="albedo"),
                 _dev(out["depth"], shape=(H, W), name="depth"),
@@ -347,7 +347,9 @@ def _outputs_for(images, dev):
             "albedo": torch.empty((C, H, W), device=dev),
             "depth": torch.empty((H, W), device=dev),
             "indirect": torch.empty((K, C, H, W), device=dev),
-            "counters": torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=dev)}
+            # the batched and served solves zero the counters themselves; no fill
+            # kernel here, so a submit does not wait behind running work
+            "counters": torch.empty(NUM_COUNTERS, dtype=torch.int64, device=dev)}
 
 
 def _batch_structs(jobs, outs):
