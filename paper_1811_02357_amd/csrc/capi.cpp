@@ -46,7 +46,8 @@ int irtps_ps_matrix(int32_t K, const float* light_dirs_host, const float* light_
 int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* params, size_t* bytes) {
     STATUS_TRY(check_problem(problem, params));
     if (!bytes) return IRTPS_ERR_INVALID_ARG;
-    *bytes = solve_layout(problem->width, problem->height, problem->channels, problem->num_lights).total;
+    *bytes = solve_workspace_bytes(problem->width, problem->height, problem->channels, problem->num_lights,
+                                   params->spp, params->bounces);
     return IRTPS_OK;
 }
 
@@ -56,7 +57,9 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
     if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
     const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
     const SolveLayout lay = solve_layout(W, H, C, K);
-    if (!ws || ws_bytes < lay.total || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return IRTPS_ERR_WORKSPACE;
+    const size_t rec_bytes = split_bytes(W, H, C, pa->spp, pa->bounces);
+    if (!ws || ws_bytes < lay.total + rec_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign))
+        return IRTPS_ERR_WORKSPACE;
     kern::PsMatrix M;
     kern::LightSet Ls;
     STATUS_TRY(make_psmatrix(K, pr->light_dirs_host, pr->light_intensity_host, M));
@@ -115,7 +118,9 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         // iteration's times, so that the launch ends on short blocks (the
         // surface changes little between iterations).
         ta.tile_cost = tile_cost;
-        if (t > 0) {
+        // a small problem traces one path per (pixel, sample) lane instead
+        ta.records = rec_bytes ? reinterpret_cast<float*>(base + lay.total) : nullptr;
+        if (t > 0 && !ta.records) {
             HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
             ta.order = tile_order;
         }

@@ -242,6 +242,15 @@ inline SolveLayout solve_layout(int W, int H, int C, int K) {
     return L;
 }
 
+// The solve's workspace: the layout above, then (small problems) the per-path
+// tracer's segment records.
+inline size_t split_bytes(int W, int H, int C, int spp, int B) {
+    return align_up((size_t)kern::split_record_bytes((long long)W * H, C, spp, B));
+}
+inline size_t solve_workspace_bytes(int W, int H, int C, int K, int spp, int B) {
+    return solve_layout(W, H, C, K).total + split_bytes(W, H, C, spp, B);
+}
+
 inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
     if (!pr || !pa) return IRTPS_ERR_INVALID_ARG;
     if (!dims_ok(pr->width, pr->height) || !channels_ok(pr->channels) || !lights_ok(pr->num_lights))

@@ -974,6 +974,130 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
 // 72 VGPRs); eight forces spills to scratch, six measure slower.
 #define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7)))
 
+// Per-path mode, first pass: lane (s, p) traces sample s of pixel p (Eq.5-7, the
+// same segment arithmetic as trace_tile) and records every segment: code q for
+// a hit at sample q with weights beta albedo(q), or -(texel + 1) for an escape
+// with weights beta.  Records are planes [1 + C][B][spp][npx].
+template <int C>
+__global__ void IRTPS_TRACER_OCCUPANCY k_trace_paths(TraceArgs a) {
+    __shared__ int2 s_lvl[trv::kMaxLevels];
+    load_level_table(a.sa.off, a.sa.wc, s_lvl);
+    const int W = a.sa.W, npx = W * a.sa.Hh;
+    const int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const bool live = idx < npx * a.spp;
+    const int s = live ? idx / npx : 0;
+    const int p = live ? idx - s * npx : 0;
+    const Surface S = make_surface(a.sa, s_lvl);
+    unsigned cnt[4] = {0u, 0u, 0u, 0u};  // segments, hits, escapes, continuations
+    if (live) {
+        const bool flat = (a.flags & kFlagFlat) != 0;
+        int M = 0;
+        if (a.flags & kFlagQuadrature) {
+            M = 1;
+            while (M * M < a.spp) ++M;
+        }
+        const size_t plane = (size_t)npx * a.spp * a.B;
+        int ci = p % W, cj = p / W;
+        float beta[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+        for (int b = 1; b <= a.B; ++b) {
+            ++cnt[0];
+            float u1, u2;
+            if (M > 0 && b == 1) {
+                u1 = ((float)(s / M) + 0.5f) / (float)M;
+                u2 = ((float)(s % M) + 0.5f) / (float)M;
+            } else {
+                const dm::U4 r = dm::philox((uint32_t)p, (uint32_t)s, (uint32_t)a.t * 256u + (uint32_t)b,
+                                            (uint32_t)a.tag, a.key0, a.key1);
+                u1 = dm::unit24(r.x);
+                u2 = dm::unit24(r.y);
+            }
+            const float* nq = a.n + 3 * (cj * W + ci);
+            const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
+            trv::Walker w;
+            trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
+            int res = trv::kMiss, qi = 0, qj = 0;
+            if (!trv::leaves_at_once(w, S)) {
+                do {
+                    res = trv::walker_step<false>(w, S, qi, qj);
+                } while (res == trv::kGoOn);
+            }
+            const size_t r = ((size_t)(b - 1) * a.spp + s) * npx + p;
+            if (res == trv::kMiss) {
+                ++cnt[2];
+                int er, ec;
+                dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
+                a.records[r] = __int_as_float(-(er * a.env_w + ec) - 1);
+#pragma unroll
+                for (int c = 0; c < C; ++c) a.records[(1 + c) * plane + r] = beta[c];
+                break;
+            }
+            ++cnt[1];
+            const int q = qj * W + qi;
+            float wgt[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[c * npx + q];
+            a.records[r] = __int_as_float(q);
+#pragma unroll
+            for (int c = 0; c < C; ++c) a.records[(1 + c) * plane + r] = wgt[c];
+            if (b >= a.B) break;
+            ++cnt[3];
+#pragma unroll
+            for (int c = 0; c < C; ++c) beta[c] = wgt[c];
+            ci = qi;
+            cj = qj;
+        }
+    }
+    if (a.counters) {
+        // one atomic per wave and counter
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            unsigned x = cnt[i];
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+            if ((threadIdx.x & 63) == 0 && x) atomicAdd(&a.counters[i], (unsigned long long)x);
+        }
+    }
+}
+
+// Per-path mode, second pass: pixel p's records in (sample, segment) order,
+// summed exactly as trace_tile sums them, then the means.
+template <int C>
+__global__ void __launch_bounds__(256) k_gather_paths(TraceArgs a) {
+    const int npx = a.sa.W * a.sa.Hh;
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= npx) return;
+    const int K = a.K, KC = K * C;
+    float* __restrict__ gp = a.G + (size_t)p * KC;
+    const bool vec4 = (K & 3) == 0 && (reinterpret_cast<uintptr_t>(a.G) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0;
+    for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
+    float eacc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) eacc[c] = 0.0f;
+    const size_t plane = (size_t)npx * a.spp * a.B;
+    for (int s = 0; s < a.spp; ++s)
+        for (int b = 1; b <= a.B; ++b) {
+            const size_t r = ((size_t)(b - 1) * a.spp + s) * npx + p;
+            const int code = __float_as_int(a.records[r]);
+            float w[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) w[c] = a.records[(1 + c) * plane + r];
+            if (code < 0) {
+                const float* L = a.env + (size_t)(-code - 1) * C;
+#pragma unroll
+                for (int c = 0; c < C; ++c) eacc[c] = fmaf(w[c], dm::kPi * L[c], eacc[c]);
+                break;
+            }
+            accumulate_hit<C>(gp, a.S + (size_t)code * K, w, K, vec4);
+        }
+    const float fspp = (float)a.spp;
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
+    }
+}
+
 // Blocks take their tiles in XCD order, or in the given order (a permutation of
 // the tiles: block b < tiles takes order[b]).  With tile_cost, each block
 // records its time (wall clock, its slowest wave's) under its tile.
@@ -1279,6 +1403,7 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
     a.counters = J.counters;
     a.order = nullptr;
     a.tile_cost = nullptr;
+    a.records = nullptr;
     a.env_h = J.env_h;
     a.env_w = J.env_w;
     a.C = J.C;
@@ -1630,6 +1755,19 @@ hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t 
 }
 
 hipError_t trace(TraceArgs a, hipStream_t st) {
+    if (a.records) {
+        const int npx = a.sa.W * a.sa.Hh;
+        if (split_record_bytes(npx, a.C, a.spp, a.B) == 0) return hipErrorInvalidValue;
+        const unsigned g1 = blocks_for((long long)npx * a.spp, 256), g2 = blocks_for(npx, 256);
+        if (a.C == 1) {
+            hipLaunchKernelGGL(k_trace_paths<1>, dim3(g1), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_gather_paths<1>, dim3(g2), dim3(256), 0, st, a);
+        } else {
+            hipLaunchKernelGGL(k_trace_paths<3>, dim3(g1), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_gather_paths<3>, dim3(g2), dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
+    }
     const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
     const int grid = (tiles + 7) / 8 * 8;
     if (a.C == 1) hipLaunchKernelGGL(k_trace<1>, dim3(grid), dim3(256), 0, st, a);

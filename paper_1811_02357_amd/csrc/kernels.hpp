@@ -69,7 +69,21 @@ struct TraceArgs {
     uint32_t key0, key1;
     const int* order;     // tile of each block (a permutation of the tiles), or null: XCD order
     unsigned* tile_cost;  // per tile, the block's time in wall-clock ticks (written), or null
+    float* records;       // per-path mode: segment records (split_record_bytes), or null
 };
+
+// Small problems can trace one path per (pixel, sample) lane: each lane records
+// its segments' outcomes (code: the hit sample q, or -(texel + 1) for an escape;
+// then C weights), and a second pass adds them into G pixel by pixel in (sample,
+// segment) order -- the same sums as the per-pixel tracer, with spp times the
+// lanes.  Bytes of the records, or 0 where the mode does not apply.
+constexpr long long kSplitMaxPixels = 65536;
+constexpr long long kSplitMaxBytes = 64LL << 20;
+__host__ __device__ inline long long split_record_bytes(long long npx, int C, int spp, int B) {
+    if (npx > kSplitMaxPixels || B < 1 || spp < 1) return 0;
+    const long long b = npx * spp * B * (1 + C) * 4;
+    return b <= kSplitMaxBytes ? b : 0;
+}
 
 // Multigrid levels of a W x H grid, offsets (in floats) into the workspace.
 // Levels of at most kMgTailNodes nodes (from `tail` to the coarsest) run in one

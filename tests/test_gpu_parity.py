@@ -317,8 +317,10 @@ def _compare_solve(ref, got, name):
                                         c["iterations"]]
 
 
+# 64 x 64 with 16 spp takes the per-path tracer (one lane per pixel and sample)
 @pytest.mark.parametrize("rho_mode,flags", [(irtps.RHO_FIT, 0), (irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE),
-                                            (irtps.RHO_FIT, irtps.FLAG_FLAT_TRAVERSAL)])
+                                            (irtps.RHO_FIT, irtps.FLAG_FLAT_TRAVERSAL),
+                                            (irtps.RHO_FIT, irtps.FLAG_QUADRATURE)])
 def test_solve_bowl64(dev, rho_mode, flags):
     say(f"case: solve bowl64 rho_mode={rho_mode} flags={flags}")
     sc = scenes.bowl_64()
