@@ -687,6 +687,16 @@ __device__ __forceinline__ void mg_prolong_node(int v, int Wf, float* __restrict
 __host__ __device__ inline long long mg_tail_floats(const MgPlan& m) { return m.keyoff - m.xoff[m.tail]; }
 constexpr int kMgTailThreads = 1024;
 
+// Passes over levels of at most 64 nodes run in the first wave alone: its lanes
+// see each other's LDS writes in program order, so a compiler fence replaces the
+// block barrier between passes.
+constexpr int kMgWaveNodes = 64;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void mg_tail(const MgPlan& m, int W0, int H0, float* ws, float* s_mg) {
     const int top = m.levels - 1;
     const long long base = m.xoff[m.tail];
@@ -698,28 +708,52 @@ __device__ __forceinline__ void mg_tail(const MgPlan& m, int W0, int H0, float* 
         B(m.tail)[v] = ws[m.boff[m.tail] + v];
     }
     __syncthreads();
-    auto smooth = [&](int l, int sweeps) {
+    // one pass of `body` over level l's nodes: the whole block, or wave 0 alone
+    auto pass = [&](int n, bool wave, auto body) {
+        if (wave) {
+            for (int v = threadIdx.x; v < n; v += 64) body(v);
+            wave_sync();
+        } else {
+            for (int v = threadIdx.x; v < n; v += blockDim.x) body(v);
+            __syncthreads();
+        }
+    };
+    auto smooth = [&](int l, int sweeps, bool wave) {
         const int n = m.W[l] * m.H[l];
         for (int sw = 0; sw < sweeps; ++sw)
-            for (int colour = 0; colour < 2; ++colour) {
-                for (int v = threadIdx.x; v < n; v += blockDim.x)
-                    mg_smooth_node(v, m.W[l], m.H[l], l, W0, H0, X(l), B(l), colour);
-                __syncthreads();
-            }
+            for (int colour = 0; colour < 2; ++colour)
+                pass(n, wave, [&](int v) { mg_smooth_node(v, m.W[l], m.H[l], l, W0, H0, X(l), B(l), colour); });
     };
-    for (int l = m.tail; l < top; ++l) {
-        smooth(l, 2);
-        const int nc = m.W[l + 1] * m.H[l + 1];
-        for (int v = threadIdx.x; v < nc; v += blockDim.x)
+    auto restrict_to = [&](int l, bool wave) {  // level l -> l + 1
+        pass(m.W[l + 1] * m.H[l + 1], wave, [&](int v) {
             mg_restrict_node(v, m.W[l], m.H[l], l, W0, H0, X(l), B(l), m.W[l + 1], B(l + 1), X(l + 1));
-        __syncthreads();
+        });
+    };
+    auto prolong_from = [&](int l, bool wave) {  // level l + 1 -> l
+        pass(m.W[l] * m.H[l], wave, [&](int v) { mg_prolong_node(v, m.W[l], X(l), m.W[l + 1], X(l + 1)); });
+    };
+    // levels from lw on have at most kMgWaveNodes nodes (the coarsest always does)
+    int lw = top;
+    while (lw > m.tail && m.W[lw - 1] * m.H[lw - 1] <= kMgWaveNodes) --lw;
+    for (int l = m.tail; l < lw; ++l) {
+        smooth(l, 2, false);
+        restrict_to(l, false);
     }
-    smooth(top, 16);
-    for (int l = top - 1; l >= m.tail; --l) {
-        const int n = m.W[l] * m.H[l];
-        for (int v = threadIdx.x; v < n; v += blockDim.x) mg_prolong_node(v, m.W[l], X(l), m.W[l + 1], X(l + 1));
-        __syncthreads();
-        smooth(l, 2);
+    if (threadIdx.x < 64) {
+        for (int l = lw; l < top; ++l) {
+            smooth(l, 2, true);
+            restrict_to(l, true);
+        }
+        smooth(top, 16, true);
+        for (int l = top - 1; l >= lw; --l) {
+            prolong_from(l, true);
+            smooth(l, 2, true);
+        }
+    }
+    __syncthreads();
+    for (int l = lw - 1; l >= m.tail; --l) {
+        prolong_from(l, false);
+        smooth(l, 2, false);
     }
     for (int v = threadIdx.x; v < n0; v += blockDim.x) ws[m.xoff[m.tail] + v] = X(m.tail)[v];
 }
