@@ -136,7 +136,7 @@ int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* para
  * warm-started from H_t.  ws_dev must hold irtps_workspace_bytes() bytes,
  * 256-byte aligned; it needs no initialisation and carries nothing between
  * calls (besides the loop's buffers it keeps each tracer tile's launch time,
- * which orders the next iteration's tiles, and for problems of at most 65536
+ * which orders the next iteration's tiles, and for problems of at most 16384
  * pixels the per-path tracer's segment records; neither changes a result). */
 int irtps_solve(const irtps_problem* problem, const irtps_params* params,
                 const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
