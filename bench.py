@@ -353,7 +353,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent jobs would shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
