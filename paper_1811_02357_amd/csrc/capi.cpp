@@ -124,13 +124,23 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
             HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
             ta.order = tile_order;
         }
-        HIP_TRY(traced(ta, st));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
         // the last iteration writes E; with a stop rule any iteration may be the last
         float* E = (t == pa->iterations - 1 || stop) ? out->indirect_dev : nullptr;
-        HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
-                              out->albedo_dev, E, A, st));
+        if (!ta.records) {
+            // the per-pixel tracer corrects each pixel as soon as its G is final
+            ta.I0 = pr->images_dev;
+            ta.Aprev = Aprev;
+            ta.Anext = A;
+            ta.E = E;
+            ta.rho_mode = pa->rho_mode;
+            ta.cumulative = cumulative ? 1 : 0;
+        }
+        HIP_TRY(traced(ta, st));
+        if (ta.records)
+            HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
+                                  out->albedo_dev, E, A, st));
         HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
         HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st, stop));
         ++run;

@@ -836,6 +836,16 @@ __device__ __forceinline__ void accumulate_hit(float* __restrict__ g, const floa
     }
 }
 
+// Kept out of line: inlined, its unrolled loops would raise the register budget
+// of the whole tracer.
+template <int C>
+__device__ __attribute__((noinline)) void fused_correct(int p, int npx, int K, int rho_mode, int cumulative,
+                                                        const float* I0, const float* Aprev, const float* gp,
+                                                        const float* Srow, const float* rho, float* E,
+                                                        float* Anext) {
+    correct_px<C>(p, npx, K, rho_mode, cumulative, I0, Aprev, gp, Srow, rho, E, Anext);
+}
+
 template <int C>
 __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
     const int tw = 1 << a.tile_shift;
@@ -973,6 +983,9 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
 #pragma unroll
             for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
         }
+        if (a.Anext)
+            fused_correct<C>(p, npx, K, a.rho_mode, a.cumulative, a.I0, a.Aprev, gp, a.S + (size_t)p * K, a.rho,
+                             a.E, a.Anext);
     }
     if (a.counters && (threadIdx.x & 63) == 0) {
         // one atomic per wave and counter
@@ -1438,6 +1451,12 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
     a.order = nullptr;
     a.tile_cost = nullptr;
     a.records = nullptr;
+    a.I0 = nullptr;
+    a.Aprev = nullptr;
+    a.Anext = nullptr;
+    a.E = nullptr;
+    a.rho_mode = 0;
+    a.cumulative = 0;
     a.env_h = J.env_h;
     a.env_w = J.env_w;
     a.C = J.C;

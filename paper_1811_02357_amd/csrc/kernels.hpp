@@ -70,6 +70,14 @@ struct TraceArgs {
     const int* order;     // tile of each block (a permutation of the tiles), or null: XCD order
     unsigned* tile_cost;  // per tile, the block's time in wall-clock ticks (written), or null
     float* records;       // per-path mode: segment records (split_record_bytes), or null
+    // Stage 5 fused into the per-pixel tracer: with Anext set, each lane corrects
+    // its pixel as soon as its G is final (E too when set); the trace reads none
+    // of these, so no lane can see another's correction.
+    const float* I0;      // [K][C][H][W]
+    const float* Aprev;   // [K][C][H][W]
+    float* Anext;         // [K][C][H][W], or null: no fused correction
+    float* E;             // [K][C][H][W] or null
+    int rho_mode, cumulative;
 };
 
 // Small problems can trace one path per (pixel, sample) lane: each lane records
