@@ -132,14 +132,20 @@ def profiled_traffic(workload):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def algorithmic_bytes(cnt, npx, K, C):
-    """Bytes the gather must move per the tracer's yardstick: a hit reads the
-    direct radiance of every light and channel at the hit sample (4 K C), a
-    continuation also reads albedo and normal there (4 C + 12), an escape reads
-    one environment texel (4 C); per pixel the origin's normal and albedo
-    (12 + 4 C) are read and the K C gathered values written."""
+def algorithmic_bytes(cnt, npx, K, C, iterations):
+    """Bytes the tracer launches of one solve must move, by the tracer's
+    yardstick: a hit reads the direct radiance of every light and channel at
+    the hit sample (4 K C), a continuation also reads albedo and normal there
+    (4 C + 12), an escape reads one environment texel (4 C); per pixel the
+    origin's normal and albedo (12 + 4 C) are read and the K C gathered values
+    written.  The launches also correct each pixel (stage 5 with the fitted
+    albedo): per pixel and iteration the K C input values and the direct row
+    (4 K C + 4 K) are read and the K C corrected values written, plus the K C
+    values of E in the last iteration."""
     hits, esc, cont = cnt[1], cnt[2], cnt[3]
-    return (hits * 4 * K * C + cont * (4 * C + 12) + esc * 4 * C + npx * (12 + 4 * C + 4 * K * C))
+    gather = hits * 4 * K * C + cont * (4 * C + 12) + esc * 4 * C + iterations * npx * (12 + 4 * C + 4 * K * C)
+    correction = iterations * npx * (8 * K * C + 4 * K) + npx * 4 * K * C
+    return gather + correction
 
 
 def cpu_baseline(sc, args):
@@ -419,7 +425,7 @@ def main():
     seg_per_step = cnt[0]
     value = seg_per_step * args.steps / (sum(step_ms) / 1e3)
     per_launch_ms = trace_ms / max(launches, 1)
-    bytes_per_launch = algorithmic_bytes(cnt, npx, K, C) / sc.iterations
+    bytes_per_launch = algorithmic_bytes(cnt, npx, K, C, sc.iterations) / sc.iterations
     achieved = bytes_per_launch / (per_launch_ms / 1e3) / 1e9
     line = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
