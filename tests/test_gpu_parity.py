@@ -363,6 +363,22 @@ def test_solve_rgb_ragged(dev):
     _compare_solve(ref, got, "fbm150x97")
 
 
+# 160 x 120 = 19200 pixels: the per-pixel tracer, which corrects each pixel itself
+@pytest.mark.parametrize("rho_mode,flags,stop_tol", [(irtps.RHO_FIT, 0, 0.0), (irtps.RHO_PREV, 0, 0.0),
+                                                     (irtps.RHO_FIT, irtps.FLAG_LITERAL_CUMULATIVE, 0.0),
+                                                     (irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE, 1e-30)])
+def test_solve_fused_correction_modes(dev, rho_mode, flags, stop_tol):
+    say(f"case: solve RGB fbm 160x120 rho_mode={rho_mode} flags={flags} stop_tol={stop_tol}")
+    sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=8, env_shape=(16, 32),
+                            ptp=16.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+    sc.heights = np.ascontiguousarray(sc.heights[:120])
+    sc.normals = np.ascontiguousarray(sc.normals[:120])
+    sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
+    _compare_solve(ref, got, "fbm160x120")
+    assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
+
+
 def test_solve_T0_is_plain_ps(dev):
     say("case: solve T=0")
     sc = scenes.bowl_64()
