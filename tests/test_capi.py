@@ -102,3 +102,27 @@ def test_size_limits_on_host():
     assert L.irtps_pyramid_bytes(16384, 16384, ct.byref(b)) == 0 and b.value > 4 * 16384 * 16384
     assert L.irtps_pyramid_bytes(16385, 16384, ct.byref(b)) == 1
     assert L.irtps_integrate_workspace_bytes(16384, 16384, ct.byref(b)) == 0 and b.value > 4 * 16384 * 16384
+
+
+def test_workspace_holds_small_problem_records():
+    """Up to 16384 pixels (and 64 MiB of records) the solve workspace carries the
+    per-path tracer's segment records, (1 + C) floats per pixel, sample and
+    segment; beyond that it does not."""
+    L = irtps.lib()
+    n = ct.c_size_t()
+    l = np.zeros((8, 3), np.float32)
+    lp = l.ctypes.data_as(ct.c_void_p)
+
+    def ws(W, H, C, spp, B):
+        pr = irtps.Problem(W, H, C, 8, ct.c_void_p(256), lp, None, ct.c_void_p(256), 2, 4)
+        pa = irtps.Params(spp, B, 3, 0, 0, 0, 0, 0, 0)
+        assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n)) == 0
+        return n.value
+
+    def align(x):
+        return (x + 255) // 256 * 256
+
+    assert ws(64, 64, 1, 16, 1) - ws(64, 64, 1, 16, 0) == align(64 * 64 * 16 * 1 * 2 * 4)
+    assert ws(128, 128, 3, 32, 3) - ws(128, 128, 3, 32, 0) == align(128 * 128 * 32 * 3 * 4 * 4)
+    assert ws(129, 128, 1, 16, 1) == ws(129, 128, 1, 16, 0)       # more than 16384 pixels
+    assert ws(128, 128, 3, 128, 3) == ws(128, 128, 3, 128, 0)     # records above 64 MiB
