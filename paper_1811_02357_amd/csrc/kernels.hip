@@ -101,48 +101,68 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
 // Walker steps per pass of the shadow-ray loop.
 constexpr int kDirectSteps = 4;
 
-// Eq.2 without albedo, with cast shadows: K any-hit walks from sample p.  Each
-// lane runs through its own lights: when one shadow ray ends it starts the next
-// at once, so a wave waits for its slowest lane's total, not for the slowest
-// lane of every light in turn.
-__device__ __forceinline__ void direct_px(const Surface& S, int p, const float* __restrict__ n, int K,
-                                          const float* __restrict__ L, const float* __restrict__ s,
-                                          bool flat, float* __restrict__ S_out) {
-    const int i = p % S.W, j = p / S.W;
-    const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
-    float* __restrict__ out = S_out + (size_t)p * K;
-    int k = 0;
+// Eq.2 without albedo, with cast shadows: an any-hit walk from sample p towards
+// each light k facing it.  The wave's (pixel, light) walks are dealt to lanes as
+// they free up (item 64 k + j is light k of lane j's pixel, p_self of lane j, -1
+// for none), so the wave waits for its mean lane's work plus one walk rather
+// than for its slowest pixel's lights.  Each S value depends on its pixel and
+// light only.
+__device__ __forceinline__ void direct_wave(const Surface& S, int p_self, const float* __restrict__ n, int K,
+                                            const float* __restrict__ L, const float* __restrict__ s, bool flat,
+                                            float* __restrict__ S_out) {
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int total = 64 * K;
+    int cur = lane, next = 64, p = -1, k = 0;
+    bool fresh = true, have = false, done = false;
     float c = 0.0f;
     trv::Walker w;
-    // move to the next light facing the sample (the others give 0).  Shadow
-    // rays skip the horizon test: its loads cost more here than the steps it
-    // saves, since a wave waits for its slowest lane's lights anyway.
-    auto start = [&]() {
-        for (; k < K; ++k) {
-            const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
-            c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
-            if (c > 0.0f) {
-                trv::walker_init(w, S, i, j, lx, ly, lz, flat);
-                return;
+    for (;;) {
+        for (;;) {
+            const bool want = !have && !done && !fresh;
+            const unsigned long long m = __ballot(want);
+            if (want) {
+                cur = next + __popcll(m & below);
+                fresh = true;
             }
-            out[k] = 0.0f;
+            next += __popcll(m);
+            const int pj = __shfl(p_self, cur & 63);
+            if (fresh) {
+                fresh = false;
+                if (cur >= total) {
+                    done = true;
+                } else if (pj >= 0) {
+                    p = pj;
+                    k = cur >> 6;
+                    const int i = p % S.W, j = p / S.W;
+                    const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
+                    const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
+                    c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
+                    if (c > 0.0f) {
+                        trv::walker_init(w, S, i, j, lx, ly, lz, flat);
+                        have = true;
+                    } else {
+                        S_out[(size_t)p * K + k] = 0.0f;
+                    }
+                }
+            }
+            if (!__any(!have && !done)) break;
         }
-    };
-    start();
-    while (k < K) {
-        // several steps per pass: fewer divergent branches back to the loop head
-        int qi, qj;
-        int res = trv::walker_step<true>(w, S, qi, qj);
+        if (__all(done)) break;
+        if (have) {
+            int qi, qj;
+            int res = trv::walker_step<true>(w, S, qi, qj);
 #pragma unroll
-        for (int u = 1; u < kDirectSteps; ++u)
-            if (res == trv::kGoOn) res = trv::walker_step<true>(w, S, qi, qj);
-        if (res != trv::kGoOn) {
-            out[k] = res == trv::kHit ? 0.0f : s[k] * c;
-            ++k;
-            start();
+            for (int u = 1; u < kDirectSteps; ++u)
+                if (res == trv::kGoOn) res = trv::walker_step<true>(w, S, qi, qj);
+            if (res != trv::kGoOn) {
+                S_out[(size_t)p * K + k] = res == trv::kHit ? 0.0f : s[k] * c;
+                have = false;
+            }
         }
     }
 }
+
 
 // The pixel a direct-shading thread takes: block b of nb covers a tile of
 // kDirectTileW x (256 / kDirectTileW) samples (XCD-aware order), or -1 past the
@@ -1007,14 +1027,14 @@ __global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, co
     ps_px<C>(p, npx, K, &M.m[0][0], A, n, rho);
 }
 
+
 __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
                                                 int flat, float* __restrict__ S_out) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(sa.off, sa.wc, s_lvl);
     const int p = direct_pixel(sa.W, sa.Hh, blockIdx.x, gridDim.x);
-    if (p < 0) return;
     const Surface S = make_surface(sa, s_lvl);
-    direct_px(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
+    direct_wave(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
 }
 
 // The tracer is issue- and latency-bound: ask for seven waves per SIMD (at most
@@ -1532,9 +1552,9 @@ __global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict_
     const JobDesc& J = jobs[blockIdx.y];
     load_level_table(J.pyr_off, J.pyr_wc, s_lvl);
     const int p = direct_pixel(J.W, J.Hh, blockIdx.x, gridDim.x);
-    if (!iterating(J) || p < 0) return;
+    if (!iterating(J)) return;  // uniform per block
     const Surface S = make_surface(J.depth, J.pyr, J.W, J.Hh, J.pyr_levels, J.quad_off, s_lvl);
-    direct_px(S, p, J.n, J.K, &J.L[0][0], J.s, (J.flags & kFlagFlat) != 0, J.S);
+    direct_wave(S, p, J.n, J.K, &J.L[0][0], J.s, (J.flags & kFlagFlat) != 0, J.S);
 }
 
 template <int C>
