@@ -99,7 +99,7 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
 }
 
 // Walker steps per pass of the shadow-ray loop.
-constexpr int kDirectSteps = 4;
+constexpr int kDirectSteps = 8;
 
 // Eq.2 without albedo, with cast shadows: an any-hit walk from sample p towards
 // each light k facing it.  The wave's (pixel, light) walks are dealt to lanes as
