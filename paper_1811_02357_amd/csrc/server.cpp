@@ -150,12 +150,15 @@ bool irtps_server::step() {
     std::vector<int> running_T;  // each running job's T after its iteration
     {
         std::unique_lock<std::mutex> lock(mu);
-        // cancellations take effect at the iteration boundary
+        // cancellations take effect at the iteration boundary; a job whose state
+        // changes here wakes its waiters even if nothing else runs this round
+        bool changed = false;
         for (auto it = resident.begin(); it != resident.end();) {
             Job& J = jobs[*it];
             if (J.cancel) {
                 finish(this, J, IRTPS_JOB_CANCELLED, IRTPS_ERR_CANCELLED);
                 it = resident.erase(it);
+                changed = true;
             } else {
                 ++it;
             }
@@ -169,6 +172,7 @@ bool irtps_server::step() {
                 J.t_end = now_s();
                 ++cancelled;
                 queue.pop_front();
+                changed = true;
                 continue;
             }
             if (cfg.max_resident_jobs > 0 && (int)resident.size() >= cfg.max_resident_jobs) break;
@@ -205,7 +209,7 @@ bool irtps_server::step() {
         }
         if (fresh.empty() && running.empty()) {
             // jobs with T = 0 that are initialised, or nothing resident
-            bool any = false;
+            bool any = changed;
             for (auto it = resident.begin(); it != resident.end();) {
                 Job& J = jobs[*it];
                 if (J.status != IRTPS_OK) {
@@ -225,6 +229,9 @@ bool irtps_server::step() {
         }
     }
     int rc = IRTPS_OK;
+    // the job table after the iteration (the stop rule may lower a job's T on the
+    // device); read only once the stream has been synchronised
+    std::vector<kern::JobDesc> after;
     if (cfg.dry_run == 0) {
         if (!fresh.empty()) {
             eng::Batch b;
@@ -242,17 +249,21 @@ bool irtps_server::step() {
             if (rc == IRTPS_OK) rc = b.run_iteration(stream);
             // the stop rule may have lowered a job's T on the device
             if (rc == IRTPS_OK) {
-                std::vector<kern::JobDesc> after(running.size());
+                after.resize(running.size());
                 const hipError_t e = hipMemcpyAsync(after.data(), b.d_jobs, sizeof(kern::JobDesc) * after.size(),
                                                     hipMemcpyDeviceToHost, stream);
-                if (e != hipSuccess) rc = hip_fail(e);
-                for (size_t k = 0; k < after.size(); ++k) running_T.push_back(after[k].T);
+                if (e != hipSuccess) {
+                    rc = hip_fail(e);
+                    after.clear();
+                }
             }
         }
         if (rc == IRTPS_OK) {
             const hipError_t e = hipStreamSynchronize(stream);
             if (e != hipSuccess) rc = hip_fail(e);
         }
+        if (rc == IRTPS_OK)
+            for (size_t k = 0; k < after.size(); ++k) running_T.push_back(after[k].T);
     } else {
         // scheduler-only mode: no kernel runs, no output is written
         std::this_thread::sleep_for(std::chrono::microseconds(200 * (int)(fresh.size() + running.size())));

@@ -9,6 +9,7 @@ fallback path.
 from __future__ import annotations
 
 import ctypes as ct
+import functools
 import glob
 import os
 
@@ -182,6 +183,19 @@ def _alloc_ws(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _on_stream(fn):
+    """Run a call with an explicit `stream` as if that stream were current, so
+    that the workspace and outputs it allocates belong to the stream its kernels
+    run on (the caching allocator then never hands them out while they run)."""
+    @functools.wraps(fn)
+    def call(*args, stream=None, **kw):
+        if stream is None:
+            return fn(*args, **kw)
+        with torch.cuda.stream(stream):
+            return fn(*args, **kw)
+    return call
+
+
 # ---------------------------------------------------------------------------
 def ps_matrix(light_dirs, light_intensity=None):
     """Eq.4 solve matrix M = (L^T L)^-1 L^T, [3][K] (host computation)."""
@@ -204,6 +218,7 @@ def _problem(images, light_dirs, light_intensity, env):
     return pr, (l, s)
 
 
+@_on_stream
 def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
           rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None,
           workspace=None, stream=None, stop_tol=0.0):
@@ -245,6 +260,7 @@ def workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iter
     return n.value
 
 
+@_on_stream
 def ps_solve(A, light_dirs, light_intensity=None, stream=None):
     K, C, H, W = A.shape
     l, lp = _host_f32(light_dirs, (K, 3), "light_dirs")
@@ -256,6 +272,7 @@ def ps_solve(A, light_dirs, light_intensity=None, stream=None):
     return n, rho
 
 
+@_on_stream
 def integrate(normals, depth_init=None, cycles=8, stream=None):
     H, W = normals.shape[:2]
     nb = _sz()
@@ -269,6 +286,7 @@ def integrate(normals, depth_init=None, cycles=8, stream=None):
     return depth
 
 
+@_on_stream
 def build_pyramid(depth, stream=None):
     H, W = depth.shape
     nb = _sz()
@@ -279,6 +297,7 @@ def build_pyramid(depth, stream=None):
     return pyr
 
 
+@_on_stream
 def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, stream=None):
     H, W = depth.shape
     l, lp = _host_f32(light_dirs, name="light_dirs")
@@ -292,6 +311,7 @@ def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, strea
     return S
 
 
+@_on_stream
 def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOLVE, flags=0,
           pyramid=None, counters=None, stream=None):
     """Gathered radiance G, pixel-major [H][W][K][C]."""
@@ -309,6 +329,7 @@ def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOL
     return G
 
 
+@_on_stream
 def correct(I0, G, S, albedo, rho_mode=RHO_FIT, flags=0, A_prev=None, want_E=True, stream=None):
     """Stage 5: I0, A_prev [K][C][H][W]; G [H][W][K][C] (as irtps_trace returns it)."""
     K, C, H, W = I0.shape
@@ -320,6 +341,7 @@ def correct(I0, G, S, albedo, rho_mode=RHO_FIT, flags=0, A_prev=None, want_E=Tru
     return E, A
 
 
+@_on_stream
 def render(depth, normals, albedo, light_dirs, light_intensity, env, spp, bounces, seed=0,
            stream=None):
     H, W = depth.shape
@@ -383,6 +405,7 @@ def batch_workspace_bytes(jobs):
     return nb.value
 
 
+@_on_stream
 def batch_solve(jobs, graph=False, outs=None, workspace=None, stream=None):
     """Many reconstructions in one set of launches.  `jobs` is a list of dicts
     with the arguments of solve() (images, light_dirs, light_intensity, env,
@@ -487,6 +510,7 @@ def get_schedule(W, H, C, K, B):
     return {"tile_w": sc.tile_w, "ready_batch": sc.ready_batch}
 
 
+@_on_stream
 def autotune(job, outs=None, workspace=None, stream=None):
     """Time the tracer's schedules on this job (arguments of solve()); the fastest
     enters the process's tuning table.  Returns (best, {(tile_w, ready_batch): ms})."""

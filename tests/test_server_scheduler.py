@@ -131,3 +131,41 @@ def test_invalid_server_arguments():
         assert L.irtps_server_poll(srv.h, 12345, ct.byref(st)) == 7
     finally:
         srv.close()
+
+
+def test_cancel_of_only_job_wakes_its_waiter():
+    """Cancelling every resident job leaves the scheduler idle: the round that
+    retires them launches nothing, and it must still wake the jobs' waiters (a
+    waiter that re-checked its job between the cancel call and that round would
+    otherwise sleep until its time-out).  The window is a few microseconds wide,
+    so this exercises the path rather than forcing the race."""
+    srv = irtps.Server(256 << 20, dry_run=True)
+    try:
+        ids = []
+        for _ in range(40):
+            rc, jid = _submit_dry(srv, 64, T=1000)
+            assert rc == 0
+            ids.append(jid)
+        t0 = time.monotonic()
+        while srv.stats()["resident"] < 40:
+            assert time.monotonic() - t0 < 20.0
+            time.sleep(0.001)
+        got = {}
+
+        def waiter():
+            t1 = time.monotonic()
+            got["st"] = srv.wait(ids[0], 20.0)
+            got["s"] = time.monotonic() - t1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        time.sleep(0.03)  # the waiter is asleep while the jobs run
+        for j in ids:
+            srv.cancel(j)
+        th.join(30.0)
+        assert not th.is_alive()
+        assert got["st"].state == irtps.JOB_CANCELLED
+        assert got["s"] < 10.0  # woken by the cancellation, not by the time-out
+        assert srv.stats()["cancelled"] == 40
+    finally:
+        srv.close()
