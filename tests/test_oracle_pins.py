@@ -789,3 +789,160 @@ def test_subset_entry_points_match_full_stages():
     assert np.array_equal(Ga, G.reshape(5, 3, -1)[:, :, pix].transpose(2, 0, 1))
     _, call = O.trace_at(sc.heights, sc.normals, sc.albedo, S, sc.env, 16, 3, 99, np.arange(480), t=1)
     assert call == c
+
+
+# ---------------------------------------------------------------------------
+# Pins of the parts a shadow-free or hit-free scene cannot see.
+def _step_surface(W, Hh, X0, h):
+    """Floor at height 0 for columns i < X0, a plateau of height h from X0 on;
+    long in y, so that every row sees the same step."""
+    H = np.zeros((Hh, W), F32)
+    H[:, X0:] = F32(h)
+    return H
+
+
+def test_direct_cast_shadow_of_a_step():
+    """Eq.2 with cast shadows: a light in the x-z plane at elevation e on the
+    plateau side shines on a floor sample at distance d = X0 - i from the step's
+    face only if the shadow ray has climbed to the plateau's height h when it
+    reaches the face, d tan e >= h (the crossing of column X0 is the first sample
+    of height h it meets; with dy = 0 there are no other crossings).  Lit samples
+    read s (n . l) = s l_z exactly (n = e_z); shadowed ones 0.  Lights pointing
+    away from the step, and the plateau itself, are never shadowed.  Elevations
+    and h are chosen so that no floor sample lies within 1e-3 of a tie."""
+    W, Hh, X0, h = 48, 6, 30, 10.3
+    H = _step_surface(W, Hh, X0, h)
+    n = np.zeros((Hh, W, 3), F32)
+    n[..., 2] = 1
+    elev = np.radians([20.0, 33.0, 47.0, 61.0, 75.0, 40.0])
+    toward = np.array([1, 1, 1, 1, 1, -1])            # +1: towards the step
+    l = np.stack([toward * np.cos(elev), np.zeros_like(elev), np.sin(elev)], -1).astype(F32)
+    s = np.array([1.0, 0.5, 2.0, 1.25, 0.75, 1.5], F32)
+    S = O.direct(H, n, l, s)
+    lz = l[:, 2]
+    for k in range(len(elev)):
+        tan_e = float(np.float64(lz[k]) / abs(np.float64(l[k, 0])))
+        for i in range(W):
+            if i < X0 and toward[k] > 0:
+                margin = (X0 - i) * tan_e - h
+                assert abs(margin) > 1e-3
+                lit = margin > 0
+            else:
+                lit = True
+            want = F32(s[k]) * lz[k] if lit else F32(0)
+            assert (S[:, i, k] == want).all(), (k, i, S[0, i, k], want)
+    # the scene really casts shadows, and not everywhere
+    assert (S[:, :X0, :5] == 0).any() and (S[:, :X0, :5] > 0).any()
+
+
+def test_cumulative_subtraction_flat_region():
+    """Stage 5 as written, A_{t+1} = A_t - E_t (LITERAL_CUMULATIVE), on the P14
+    flat region (45 deg ring lights, uniform L = 0.2, albedo 0.8, no hits, so
+    G = pi L and Eq.4 gives rho = sqrt(2) a for a uniform image a).
+    With the previous albedo rho_t: A_{t+1} = A_t - rho_t pi L, hence
+    rho_{t+1} = rho_t (1 - sqrt(2) pi L) and rho_t = sqrt(2) I (1 - sqrt(2) pi L)^t.
+    With the fitted albedo, 0.8 exactly while the normal is e_z, every step
+    removes the same 0.8 pi L: A_t = 0.8 (sin45 - (t - 1) pi L) and
+    rho_t = 0.8 |1 - (t - 1) sqrt(2) pi L| (A_3 < 0: the normal flips to -e_z,
+    rho is still |g|).  Using I0 instead of A_t as the base gives 1.361274
+    resp. 0.8 at t = 2."""
+    sc = _flat_scene(W=16)
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity,
+                     sc.env, 64, 1)
+    I = 0.8 * (math.sin(math.radians(45)) + math.pi * 0.2)
+    q = 1 - math.sqrt(2) * math.pi * 0.2
+    want_prev = {1: 0.16834532, 2: 0.018757610, 3: 0.0020900369}
+    want_fit = {1: 0.8, 2: 0.089138730, 3: 0.62172254}
+    for T in (1, 2, 3):
+        assert abs(math.sqrt(2) * I * q ** T / want_prev[T] - 1) < 5e-6
+        assert abs(0.8 * abs(1 - (T - 1) * (1 - q)) / want_fit[T] - 1) < 5e-6
+        # each step cancels about 8/9 of the image, so binary32 error grows ~9x per step
+        tol = 2e-6 * 9 ** T
+        rp = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, 16, 1, T, rho_mode=O.RHO_PREV,
+                     flags=O.FLAG_LITERAL_CUMULATIVE)
+        assert np.abs(rp["albedo"] / want_prev[T] - 1).max() < tol, (T, rp["albedo"].mean())
+        rf = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, 16, 1, T, rho_mode=O.RHO_FIT,
+                     flags=O.FLAG_LITERAL_CUMULATIVE)
+        assert np.abs(rf["albedo"] / want_fit[T] - 1).max() < tol, (T, rf["albedo"].mean())
+
+
+def _step_view_factor(d, h):
+    """Cosine-weighted fraction of the hemisphere of an up-facing point that an
+    infinitely long step of height h at distance d blocks: the 2-D view factor
+    1/2 (sin 90 - sin atan(d/h)) = 1/2 (1 - d / sqrt(d^2 + h^2))."""
+    return 0.5 * (1.0 - d / math.hypot(d, h))
+
+
+def test_gather_hit_weight_against_step_view_factor():
+    """Eq.5-7 with a surface hit, B = 1: floor samples at distance d from a step
+    of height h (long in y), n = e_z everywhere, uniform S_p, albedo rho_p and
+    environment L.  A path that hits adds rho_p S_p to every light's sum, one that
+    escapes pi L; so G = F rho_p S_p + (1 - F) pi L with F the blocked fraction.
+    The surface is linear along grid lines, so the step's face is a one-sample
+    ramp from column X0 - 1 to X0 and F lies between the view factors of a wall
+    at d and at d - 1.  Checked: the hit fraction against that bracket (4 sigma),
+    and G against hits rho_p S_p + escapes pi L (the estimator's own sum)."""
+    W, Hh, X0, h, d = 64, 1025, 40, 32.0, 16
+    H = _step_surface(W, Hh, X0, h)
+    n = np.zeros((Hh, W, 3), F32)
+    n[..., 2] = 1
+    K, rho_p, S_p, L = 3, 0.3, 2.0, 0.05
+    S = np.full((Hh, W, K), S_p, F32)
+    S[..., 1] *= F32(0.5)
+    rho = np.full((1, Hh, W), rho_p, F32)
+    env = np.full((2, 4, 1), L, F32)
+    rows = np.arange(256, 768)
+    pix = rows * W + (X0 - d)
+    spp = 512
+    Gs, cnt = O.trace_at(H, n, rho, S, env, spp, 1, seed=21, pix=pix)
+    assert cnt["segments"] == rows.size * spp == cnt["hits"] + cnt["escapes"]
+    F_hat = cnt["hits"] / cnt["segments"]
+    lo, hi = _step_view_factor(d, h), _step_view_factor(d - 1, h)
+    sig = math.sqrt(hi * (1 - lo) / cnt["segments"])
+    assert lo - 4 * sig < F_hat < hi + 4 * sig, (lo, F_hat, hi)
+    # per pixel: G = (hits rho_p S_p[k] + escapes pi L) / spp, recomputed from
+    # each pixel's own counts
+    piL = float(F32(3.14159274) * F32(L))
+    for m in range(0, rows.size, 37):
+        _, c1 = O.trace_at(H, n, rho, S, env, spp, 1, seed=21, pix=pix[m:m + 1])
+        for k in range(K):
+            want = (c1["hits"] * float(F32(rho_p) * S[0, 0, k]) + c1["escapes"] * piL) / spp
+            assert abs(Gs[m, k, 0] / want - 1) < 2 * spp * 2.0 ** -24, (m, k, Gs[m, k, 0], want)
+    # and the mean over the rows lies in the bracket of the closed form
+    Gm = Gs[:, 0, 0].astype(np.float64).mean()
+    g = lambda F: F * rho_p * S_p + (1 - F) * math.pi * L
+    assert g(lo) - 4 * sig * (rho_p * S_p - math.pi * L) < Gm < g(hi) + 4 * sig * (rho_p * S_p - math.pi * L)
+
+
+def test_gather_second_bounce_weight_is_the_albedo_product():
+    """Eq.5-7 with B = 2 on the step: a second segment starts at the first hit q
+    with weight beta = rho(q) (Fig. 5's colour product), so with uniform
+    rho_p, S_p and L every path adds one of rho_p S_p + rho_p^2 S_p,
+    rho_p S_p + rho_p pi L, or pi L.  The counters split the segments: first
+    hits = continuations c, second hits = hits - c, second escapes = 2c - hits,
+    first escapes = escapes - (2c - hits); G must equal the sum they give.  A
+    weight without the albedo product (rho_p S_p for a second hit) misses it."""
+    W, Hh, X0, h, d = 40, 64, 24, 12.0, 3
+    H = _step_surface(W, Hh, X0, h)
+    n = np.zeros((Hh, W, 3), F32)
+    n[..., 2] = 1
+    rho_p, S_p, L = F32(0.6), F32(1.5), F32(0.1)
+    S = np.full((Hh, W, 1), S_p, F32)
+    rho = np.full((1, Hh, W), rho_p, F32)
+    env = np.full((2, 4, 1), L, F32)
+    spp = 256
+    piL = float(F32(3.14159274) * L)
+    two_hits = 0
+    for j in range(8, 56, 6):
+        p = j * W + (X0 - d)
+        G, c = O.trace_at(H, n, rho, S, env, spp, 2, seed=3, pix=[p])
+        cont, hits, esc = c["continuations"], c["hits"], c["escapes"]
+        h2 = hits - cont
+        e2 = 2 * cont - hits
+        e1 = esc - e2
+        assert min(h2, e2, e1) >= 0 and cont + e1 == spp
+        want = (cont * float(rho_p * S_p) + e1 * piL + h2 * float(F32(rho_p * rho_p) * S_p)
+                + e2 * float(rho_p * F32(piL))) / spp
+        assert abs(G[0, 0, 0] / want - 1) < 4 * spp * 2.0 ** -24, (j, G[0, 0, 0], want)
+        two_hits += h2
+    assert two_hits > 0  # some second segments hit (from the ramp's floor end)
