@@ -375,6 +375,103 @@ void or_ps_solve(int W, int Hh, int C, int K, const float* M, const float* A,
     }
 }
 
+/* Eq.4 restricted, per pixel, to the lights that reach it (the paper's shadow
+ * condition: at least three lights are needed for the solve).  A light is kept
+ * at pixel p when its direct irradiance S[p][k] = s_k max(0, n_t . l_k) V_k(H_t)
+ * is positive, i.e. it faces the current normal and its shadow ray escapes the
+ * current surface.  With at least three kept lights whose 3x3 normal matrix
+ * passes the same conditioning test as or_ps_matrix, the pixel's own solve
+ * matrix M_p = (L_p^T L_p)^-1 L_p^T is built in binary64 from the kept rows (in
+ * light order), rounded to binary32, and applied like M; otherwise the pixel
+ * takes the all-light M.  The normal and albedo then follow as in or_ps_solve. */
+static int masked_matrix(int K, const float* l, const float* s, const float* Sp, float* Mp) {
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    int kept = 0;
+    for (int k = 0; k < K; ++k) {
+        if (!(Sp[k] > 0.0f)) continue;
+        ++kept;
+        const double sk = s ? (double)s[k] : 1.0;
+        double Lk[3];
+        for (int a = 0; a < 3; ++a) Lk[a] = sk * (double)l[3 * k + a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + Lk[a] * Lk[b];
+    }
+    if (kept < 3) return -1;
+    double cof[3][3];
+    cof[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    cof[0][1] = -(A[1][0] * A[2][2] - A[1][2] * A[2][0]);
+    cof[0][2] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    cof[1][0] = -(A[0][1] * A[2][2] - A[0][2] * A[2][1]);
+    cof[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+    cof[1][2] = -(A[0][0] * A[2][1] - A[0][1] * A[2][0]);
+    cof[2][0] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+    cof[2][1] = -(A[0][0] * A[1][2] - A[0][2] * A[1][0]);
+    cof[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const double det = A[0][0] * cof[0][0] + A[0][1] * cof[0][1] + A[0][2] * cof[0][2];
+    const double tr3 = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+    if (!(det > 1e-7 * tr3 * tr3 * tr3)) return -1;
+    double inv[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) inv[a][b] = cof[b][a] / det;
+    for (int k = 0; k < K; ++k) {
+        if (!(Sp[k] > 0.0f)) {
+            Mp[0 * K + k] = Mp[1 * K + k] = Mp[2 * K + k] = 0.0f;
+            continue;
+        }
+        const double sk = s ? (double)s[k] : 1.0;
+        double Lk[3];
+        for (int a = 0; a < 3; ++a) Lk[a] = sk * (double)l[3 * k + a];
+        for (int a = 0; a < 3; ++a)
+            Mp[(size_t)a * K + k] = (float)(inv[a][0] * Lk[0] + inv[a][1] * Lk[1] + inv[a][2] * Lk[2]);
+    }
+    return 0;
+}
+
+int or_ps_solve_masked(int W, int Hh, int C, int K, const float* l, const float* s, const float* A,
+                       const float* S, float* n, float* rho) {
+    const size_t npx = (size_t)W * Hh;
+    float* M = (float*)malloc(sizeof(float) * 3 * K);
+    float* Mp = (float*)malloc(sizeof(float) * 3 * K);
+    if (or_ps_matrix(K, l, s, M) != 0) {
+        free(M);
+        free(Mp);
+        return -1;
+    }
+    for (size_t p = 0; p < npx; ++p) {
+        const float* Sp = S + p * K;
+        const int own = masked_matrix(K, l, s, Sp, Mp) == 0;
+        const float* Mu = own ? Mp : M;
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+        for (int c = 0; c < C; ++c) {
+            float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+            for (int k = 0; k < K; ++k) {
+                if (own && !(Sp[k] > 0.0f)) continue; /* a dropped light adds nothing */
+                const float a = A[((size_t)k * C + c) * npx + p];
+                g0 = fmaf(Mu[0 * K + k], a, g0);
+                g1 = fmaf(Mu[1 * K + k], a, g1);
+                g2 = fmaf(Mu[2 * K + k], a, g2);
+            }
+            rho[(size_t)c * npx + p] = sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2)));
+            sx = sx + g0;
+            sy = sy + g1;
+            sz = sz + g2;
+        }
+        const float len = sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
+        if (len > 0.0f) {
+            n[3 * p + 0] = sx / len;
+            n[3 * p + 1] = sy / len;
+            n[3 * p + 2] = sz / len;
+        } else {
+            n[3 * p + 0] = 0.0f;
+            n[3 * p + 1] = 0.0f;
+            n[3 * p + 2] = 1.0f;
+        }
+    }
+    free(M);
+    free(Mp);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Eq.2 at every sample without the albedo: the irradiance from light k, zero
  * where the sample faces away or a shadow ray towards the light hits the
@@ -807,7 +904,10 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
                  flags & OR_FLAG_QUADRATURE, G, cnt);
         or_correct(W, Hh, C, K, rho_mode, flags, I0, A, G, S, rho, E, A2);
         float* tmp = A; A = A2; A2 = tmp;
-        or_ps_solve(W, Hh, C, K, M, A, n, rho);
+        if (flags & OR_FLAG_SHADOW_AWARE_PS)
+            or_ps_solve_masked(W, Hh, C, K, l, s, A, S, n, rho);
+        else
+            or_ps_solve(W, Hh, C, K, M, A, n, rho);
         or_integrate(W, Hh, n, H, cycles_warm, Hn);
         /* D_H: the largest change of the surface in this iteration */
         float dh = 0.0f;

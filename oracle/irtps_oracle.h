@@ -33,7 +33,7 @@ extern "C" {
 
 enum { OR_TAG_SOLVE = 0, OR_TAG_RENDER = 1 };
 enum { OR_RHO_FIT = 0, OR_RHO_PREV = 1 };
-enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2 };
+enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2, OR_FLAG_SHADOW_AWARE_PS = 8 };
 enum { OR_MISS = 0, OR_HIT = 1 };
 
 /* counters of one trace: [0] segments, [1] hits, [2] escapes, [3] continuations */
@@ -68,6 +68,14 @@ int or_ps_matrix(int K, const float* l, const float* s, float* M);
 void or_ps_solve(int W, int Hh, int C, int K, const float* M, const float* A,
                  float* n, float* rho);
 
+/* Eq.4 per pixel over the lights that reach it: light k is kept at pixel p
+ * when S[p][k] > 0 (it faces n_t and its shadow ray escapes H_t); with at least
+ * three kept, well-conditioned lights the pixel's own binary64 solve matrix is
+ * used, else the all-light one.  S is [Hh][W][K] from or_direct.  Returns 0, or
+ * -1 if the all-light matrix is singular. */
+int or_ps_solve_masked(int W, int Hh, int C, int K, const float* l, const float* s, const float* A,
+                       const float* S, float* n, float* rho);
+
 /* Direct irradiance S[q][k] = s_k max(0, n(q).l_k) V_k(q) (Eq.2 without albedo). */
 void or_direct(int W, int Hh, int K, const float* H, const float* n,
                const float* l, const float* s, float* S);
@@ -101,8 +109,11 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
 
 /* The whole IRT-PS loop (Sec. IV): T iterations, or fewer when stop_tol > 0
  * and an iteration changes the surface by less than stop_tol, D_H =
- * max_p |H_{t+1}(p) - H_t(p)| < stop_tol (last paragraph of Sec. IV).
- * Returns 0 or -1 (singular lights). */
+ * max_p |H_{t+1}(p) - H_t(p)| < stop_tol (last paragraph of Sec. IV).  With
+ * OR_FLAG_SHADOW_AWARE_PS the PS after each correction keeps, per pixel, only
+ * the lights that reach it (or_ps_solve_masked with that iteration's S); the
+ * first PS of the input images uses every light.  Returns 0 or -1 (singular
+ * lights). */
 int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
              const float* s, const float* env, int He, int We, int spp, int B,
              int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,

@@ -16,7 +16,7 @@ _LIB = None
 
 TAG_SOLVE, TAG_RENDER = 0, 1
 RHO_FIT, RHO_PREV = 0, 1
-FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE = 1, 2
+FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_SHADOW_AWARE_PS = 1, 2, 8
 
 _f = ct.POINTER(ct.c_float)
 _u32 = ct.POINTER(ct.c_uint32)
@@ -53,6 +53,8 @@ def lib():
         L.or_ps_matrix.restype = ct.c_int
         L.or_ps_solve.argtypes = [ct.c_int] * 4 + [_f, _f, _f, _f]
         L.or_direct.argtypes = [ct.c_int] * 3 + [_f, _f, _f, _f, _f]
+        L.or_ps_solve_masked.argtypes = [ct.c_int] * 4 + [_f] * 6
+        L.or_ps_solve_masked.restype = ct.c_int
         L.or_trace.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
                                + [ct.c_int] * 3 + [_f, ct.POINTER(Counters)])
         L.or_correct.argtypes = [ct.c_int] * 6 + [_f] * 7
@@ -206,6 +208,19 @@ def ps_solve(M, A):
     n = np.zeros((Hh, W, 3), np.float32)
     rho = np.zeros((C, Hh, W), np.float32)
     lib().or_ps_solve(W, Hh, C, K, _p(M), _p(A), _p(n), _p(rho))
+    return n, rho
+
+
+def ps_solve_masked(l, s, A, S):
+    """Eq.4 per pixel over the lights with S[p][k] > 0 (at least three), else
+    all lights.  A: [K][C][H][W], S: [H][W][K] -> normals, albedo."""
+    l, s, A, S = _f32(l), _f32(s), _f32(A), _f32(S)
+    K, C, Hh, W = A.shape
+    assert S.shape == (Hh, W, K)
+    n = np.zeros((Hh, W, 3), np.float32)
+    rho = np.zeros((C, Hh, W), np.float32)
+    if lib().or_ps_solve_masked(W, Hh, C, K, _p(l), _p(s), _p(A), _p(S), _p(n), _p(rho)) != 0:
+        raise ValueError("singular light configuration")
     return n, rho
 
 

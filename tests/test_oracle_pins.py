@@ -946,3 +946,59 @@ def test_gather_second_bounce_weight_is_the_albedo_product():
         assert abs(G[0, 0, 0] / want - 1) < 4 * spp * 2.0 ** -24, (j, G[0, 0, 0], want)
         two_hits += h2
     assert two_hits > 0  # some second segments hit (from the ramp's floor end)
+
+
+# ---------------------------------------------------------------------------
+# Shadow-aware PS (Eq.4 over the lights that reach a pixel).
+def _shadowed_scene():
+    """A floor with a step (plateau of height 10 from column 30) cut by a
+    narrow trench, and a paraboloid hill; 12 Fibonacci lights (elevations down
+    to 2.4 deg): attached shadows on the hill's far sides, cast shadows in
+    front of the step and behind the hill, almost none in the trench."""
+    W, Hh = 48, 40
+    yy, xx = np.mgrid[0:Hh, 0:W].astype(np.float64)
+    h = np.where(xx >= 30, 10.0, 0.0)
+    r2 = (xx - 14.0) ** 2 + (yy - 20.0) ** 2
+    h = h + np.where(r2 < 64.0, 4.0 * (1 - r2 / 64.0), 0.0)
+    # a narrow trench in the plateau: its floor sees fewer than three lights
+    h = np.where((xx >= 39) & (xx <= 41) & (yy >= 6) & (yy <= 33), -12.0, h)
+    rng = np.random.default_rng(4)
+    rho = rng.uniform(0.3, 0.9, (3, Hh, W))
+    K = 12
+    s = np.linspace(0.8, 1.3, K)
+    return scenes._scene("step_hill", h, rho, scenes.fibonacci_lights(K), s, np.zeros((2, 4, 3)))
+
+
+def test_shadow_aware_ps_recovers_normals_where_three_lights_remain():
+    """Images with no indirect light (B = 0, no environment) are I = rho S with
+    S = s max(0, n.l) V.  At a pixel whose kept lights (S > 0) number at least
+    three and are well conditioned, Eq.4 over those lights alone is exact: it
+    returns n and rho.  Plain Eq.4 over all lights is wrong wherever a light is
+    shadowed; where fewer than three lights remain the masked solve is the
+    plain one, bit for bit."""
+    sc = _shadowed_scene()
+    I0, cnt = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity,
+                       sc.env, spp=1, B=0)
+    S = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity)
+    l = sc.light_dirs.astype(np.float64) * sc.light_intensity.astype(np.float64)[:, None]
+    kept = S > 0
+    ok = np.zeros(kept.shape[:2], bool)
+    for j in range(kept.shape[0]):
+        for i in range(kept.shape[1]):
+            Lp = l[kept[j, i]]
+            if Lp.shape[0] >= 3:
+                N = Lp.T @ Lp
+                ok[j, i] = np.linalg.det(N) > 1e-7 * (np.trace(N) / 3) ** 3
+    shadowed = ~kept.all(-1)
+    assert shadowed.mean() > 0.2 and (ok & shadowed).sum() > 200
+    n, rho = O.ps_solve_masked(sc.light_dirs, sc.light_intensity, I0, S)
+    assert angle_deg(n[ok], sc.normals[ok]).max() < 1e-3
+    assert np.abs(rho[:, ok] / sc.albedo[:, ok] - 1).max() < 1e-5
+    n0, rho0 = O.ps_solve(O.ps_matrix(sc.light_dirs, sc.light_intensity), I0)
+    assert angle_deg(n0[ok & shadowed], sc.normals[ok & shadowed]).max() > 1.0
+    assert (~ok).any()
+    assert (n[~ok] == n0[~ok]).all() and (rho[:, ~ok] == rho0[:, ~ok]).all()
+    # unshadowed pixels: the kept rows are all rows; the same solve up to the
+    # rounding of the per-pixel matrix
+    full = kept.all(-1)
+    assert angle_deg(n[full], n0[full]).max() < 1e-3
