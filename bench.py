@@ -235,16 +235,18 @@ def batched_leg(args, dev):
 
 def small_leg(args, dev):
     """The 64 x 64 bowl (8 lights, grey, spp 16, B 1, T 3), a solve short enough
-    to be bound by launches: timed call by call through the plain solve (kernels
-    launched one by one on the stream) and through a one-job batched solve whose
-    iterations replay a captured HIP graph."""
+    that launches matter: timed call by call through the plain solve (kernels
+    launched one by one on the stream), through the plain solve replayed from a
+    captured HIP graph (IRTPS_FLAG_GRAPH), and through a one-job batched solve
+    whose iterations replay a captured HIP graph."""
     import numpy as np
     import torch
     from paper_1811_02357_amd import irtps, scenes
     n = args.small_reps
     log(f"bench: small leg, bowl 64x64, {n} solves each way")
+    stream = torch.cuda.Stream()  # graphs need a stream other than the legacy default one
+    torch.cuda.set_stream(stream)
     job = _job(scenes.bowl_64(), dev, irtps, torch, np)
-    stream = torch.cuda.current_stream()
 
     def each(fn):
         ts = []
@@ -260,18 +262,24 @@ def small_leg(args, dev):
     ws = torch.empty(irtps.workspace_bytes(**job), dtype=torch.uint8, device=dev)
     out = irtps.solve(**job, workspace=ws)  # warm-up and reference
     plain = each(lambda: irtps.solve(**job, out=out, workspace=ws))
+    gout = irtps._outputs_for(job["images"], dev)
+    gws = torch.empty(irtps.workspace_bytes(**job), dtype=torch.uint8, device=dev)
+    irtps.solve(**job, flags=irtps.FLAG_GRAPH, out=gout, workspace=gws)  # warm-up, graph capture
+    solve_graph = each(lambda: irtps.solve(**job, flags=irtps.FLAG_GRAPH, out=gout, workspace=gws))
     bws = torch.empty(irtps.batch_workspace_bytes([job]), dtype=torch.uint8, device=dev)
     bout = [irtps._outputs_for(job["images"], dev)]
     irtps.batch_solve([job], graph=True, outs=bout, workspace=bws)  # warm-up, graph capture
     graph = each(lambda: irtps.batch_solve([job], graph=True, outs=bout, workspace=bws))
     torch.cuda.synchronize()
-    same = _same(out, bout[0], torch)
-    log(f"bench: small solve {np.median(plain):.3f} ms plain vs {np.median(graph):.3f} ms graph-replayed")
+    same = _same(out, bout[0], torch) and _same(out, gout, torch)
+    torch.cuda.set_stream(torch.cuda.default_stream(dev))
+    log(f"bench: small solve {np.median(plain):.3f} ms plain, {np.median(solve_graph):.3f} ms graph-replayed "
+        f"solve, {np.median(graph):.3f} ms graph-replayed one-job batch")
     stats = lambda t: {"median_ms": float(np.median(t)), "p99_ms": float(np.quantile(t, 0.99)),
                        "reconstructions_per_s": 1e3 / float(np.median(t))}
     return {"workload": "bowl64: 64x64 bowl, K 8, grey, env 2x4 uniform; spp 16, bounces 1, iterations 3",
-            "repeats": n, "equal_to_plain": bool(same), "plain": stats(plain), "graph": stats(graph),
-            "speedup": float(np.median(plain) / np.median(graph))}
+            "repeats": n, "equal_to_plain": bool(same), "plain": stats(plain), "graph": stats(solve_graph),
+            "batch_graph": stats(graph), "speedup": float(np.median(plain) / np.median(solve_graph))}
 
 
 def served_leg(args, dev):
@@ -355,6 +363,10 @@ def main():
     ap.add_argument("--mode-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device to device three times (calibrates byte counters) and exit")
+    ap.add_argument("--valu-probe", type=int, default=0, metavar="ITERS",
+                    help="only launch the VALU issue-rate probe (ITERS rounds of 16 integer instructions "
+                         "per lane, 8 waves per SIMD) three times each with 64, 32, 16 and 1 active lanes "
+                         "per wave, print the fastest launch times and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -377,6 +389,28 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
+        return
+    if args.valu_probe:
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        blocks = cus * 8  # 256-thread blocks: 8 waves per SIMD
+        stream = torch.cuda.current_stream()
+        irtps.probe_valu(blocks, 16)  # warm-up
+        res = {}
+        for active in (64, 32, 16, 1):
+            ms = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                irtps.probe_valu(blocks, args.valu_probe, active)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            res[str(active)] = min(ms)
+        waves = blocks * 4
+        loop = waves * 16 * args.valu_probe
+        print(json.dumps({"valu_probe": {"cus": cus, "blocks": blocks, "iters": args.valu_probe,
+                                         "min_ms_by_active_lanes": res, "loop_wave_instructions": loop,
+                                         "loop_rate_per_s": loop / (res["64"] / 1e3)}}), flush=True)
         return
     wl = WORKLOADS[args.workload]
     log(f"bench: building scene {args.workload}")

@@ -70,7 +70,15 @@ enum {
 enum {
     IRTPS_FLAG_QUADRATURE = 1,         /* first segment on sqrt(spp)^2 stratum midpoints */
     IRTPS_FLAG_LITERAL_CUMULATIVE = 2, /* A_{t+1} = A_t - E_t instead of I0 - E_t */
-    IRTPS_FLAG_FLAT_TRAVERSAL = 4      /* walk every grid-line crossing (no pyramid skips) */
+    IRTPS_FLAG_FLAT_TRAVERSAL = 4,     /* walk every grid-line crossing (no pyramid skips) */
+    IRTPS_FLAG_SHADOW_AWARE_PS = 8,    /* the PS after each correction keeps, per pixel, only the
+                                          lights that reach it (irtps_ps_solve_masked with that
+                                          iteration's direct irradiance); the first PS uses all */
+    IRTPS_FLAG_GRAPH = 16              /* irtps_solve only: capture the solve's launches in a
+                                          hipGraph the first time, replay it on later calls with
+                                          identical arguments (same pointers, lights, schedule);
+                                          needs stop_tol = 0 and a stream other than the legacy
+                                          default one; changes no result */
 };
 
 /* Sample-stream tags (word 3 of the Philox counter). */
@@ -148,6 +156,21 @@ int irtps_solve(const irtps_problem* problem, const irtps_params* params,
 int irtps_ps_solve(int32_t W, int32_t H, int32_t C, int32_t K,
                    const float* light_dirs_host, const float* light_intensity_host,
                    const float* A_dev, float* normals_dev, float* albedo_dev, void* stream);
+
+/* Eq.4 restricted per pixel to the lights that reach it (Sec. III: the solve
+ * needs at least three lights; a light whose direct irradiance is zero carries
+ * no shading).  Light k is kept at pixel p when S_dev[p][k] > 0, S_dev being
+ * the [H][W][K] direct irradiance s_k max(0, n.l_k) V_k of irtps_direct.  With
+ * at least three kept lights whose normal matrix L_p^T L_p passes the test of
+ * irtps_ps_matrix (det > 1e-7 (trace/3)^3), the pixel's own matrix
+ * (L_p^T L_p)^-1 L_p^T is built in binary64 from the kept rows (3x3 adjugate),
+ * rounded to float and applied over the kept lights in light order; other
+ * pixels use the all-light matrix.  Normals and albedo then as irtps_ps_solve.
+ * Returns IRTPS_ERR_SINGULAR_LIGHTS when the all-light matrix is singular. */
+int irtps_ps_solve_masked(int32_t W, int32_t H, int32_t C, int32_t K,
+                          const float* light_dirs_host, const float* light_intensity_host,
+                          const float* A_dev, const float* S_dev, float* normals_dev,
+                          float* albedo_dev, void* stream);
 
 /* Bytes of workspace for irtps_integrate. */
 int irtps_integrate_workspace_bytes(int32_t W, int32_t H, size_t* bytes);
@@ -361,6 +384,13 @@ int irtps_profile_begin(void);
 int irtps_profile_end(double* trace_ms, int64_t* launches);
 
 /* ---- probes of the device arithmetic (parity checks) -------------------- */
+/* Issue-rate calibration (not part of the method): `blocks` blocks of 256
+ * threads, each lane running `iters` rounds of 16 independent 32-bit integer
+ * VALU instructions; only lanes below active_lanes (1..64) of each wave do the
+ * work, the others are masked off.  out_dev receives blocks x 256 uint32 (the
+ * chains' values, so that the work is kept).  A counted and timed launch
+ * measures the VALU instruction rate the tracer's is compared with. */
+int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, uint32_t* out_dev, void* stream);
 /* Philox4x32-10 of count counters [count][4] under key (seed lo, hi) -> out [count][4]. */
 int irtps_probe_philox(int64_t count, const uint32_t* ctr_dev, uint64_t seed,
                        uint32_t* out_dev, void* stream);

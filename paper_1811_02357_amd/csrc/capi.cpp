@@ -6,6 +6,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <list>
+#include <mutex>
+#include <vector>
 
 #include "host.hpp"
 #include "kernels.hpp"
@@ -51,20 +54,16 @@ int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* para
     return IRTPS_OK;
 }
 
-int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
-                size_t ws_bytes, void* stream) {
-    STATUS_TRY(check_problem(pr, pa));
-    if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// The solve's launches for one (problem, params, outputs, workspace), on st.
+int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
+                   const kern::PsMatrix& M, const kern::LightSet& Ls, hipStream_t st) {
     const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
     const SolveLayout lay = solve_layout(W, H, C, K);
     const size_t rec_bytes = split_bytes(W, H, C, pa->spp, pa->bounces);
-    if (!ws || ws_bytes < lay.total + rec_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign))
-        return IRTPS_ERR_WORKSPACE;
-    kern::PsMatrix M;
-    kern::LightSet Ls;
-    STATUS_TRY(make_psmatrix(K, pr->light_dirs_host, pr->light_intensity_host, M));
-    STATUS_TRY(make_lights(K, pr->light_dirs_host, pr->light_intensity_host, Ls));
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     float* A = reinterpret_cast<float*>(base + lay.A);
     float* S = reinterpret_cast<float*>(base + lay.S);
@@ -141,7 +140,10 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
         if (ta.records)
             HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
                                   out->albedo_dev, E, A, st));
-        HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
+        if (pa->flags & IRTPS_FLAG_SHADOW_AWARE_PS)  // per pixel, the lights that reach it (S of H_t, n_t)
+            HIP_TRY(kern::ps_solve_masked(npx, C, K, M, Ls, A, S, out->normals_dev, out->albedo_dev, st));
+        else
+            HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
         HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st, stop));
         ++run;
         if (stop) {
@@ -158,6 +160,105 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
     return IRTPS_OK;
 }
 
+// ---- hipGraph cache of whole solves ----------------------------------------
+// A solve with IRTPS_FLAG_GRAPH is captured once into a graph keyed by every
+// value its launches depend on (the problem, params, output and workspace
+// pointers, the lights and the tracer schedule); a later call with the same key
+// replays it.  Most recent first, at most kMaxSolveGraphs.
+struct SolveGraph {
+    std::vector<char> key;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_solve_graph_mu;
+std::list<SolveGraph> g_solve_graphs;
+constexpr size_t kMaxSolveGraphs = 8;
+
+template <class T>
+void put(std::vector<char>& k, const T& v) {
+    const char* p = reinterpret_cast<const char*>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
+std::vector<char> solve_key(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
+                            const kern::PsMatrix& M, const kern::LightSet& Ls) {
+    std::vector<char> k;
+    put(k, *pr);
+    put(k, *pa);
+    put(k, *out);
+    put(k, ws);
+    put(k, M);
+    put(k, Ls);
+    const Schedule sc = schedule_for(pr->width, pr->height, pr->channels, pr->num_lights, pa->bounces);
+    put(k, sc.tile_shift);
+    put(k, sc.ready_batch);
+    return k;
+}
+
+int solve_graphed(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
+                  const kern::PsMatrix& M, const kern::LightSet& Ls, hipStream_t st) {
+    std::vector<char> key = solve_key(pr, pa, out, ws, M, Ls);
+    std::lock_guard<std::mutex> lock(g_solve_graph_mu);
+    for (auto it = g_solve_graphs.begin(); it != g_solve_graphs.end(); ++it) {
+        if (it->key == key) {
+            g_solve_graphs.splice(g_solve_graphs.begin(), g_solve_graphs, it);
+            HIP_TRY(hipGraphLaunch(g_solve_graphs.front().exec, st));
+            return IRTPS_OK;
+        }
+    }
+    // the tracer's timing events are not captured
+    const bool prof = g_prof.on;
+    g_prof.on = false;
+    hipGraph_t graph = nullptr;
+    hipError_t eb = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+        g_prof.on = prof;
+        return hip_fail(eb);
+    }
+    const int rc = solve_launches(pr, pa, out, ws, M, Ls, st);
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    g_prof.on = prof;
+    if (rc != IRTPS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess) return hip_fail(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei);
+    g_solve_graphs.push_front(SolveGraph{std::move(key), exec});
+    while (g_solve_graphs.size() > kMaxSolveGraphs) {
+        (void)hipGraphExecDestroy(g_solve_graphs.back().exec);
+        g_solve_graphs.pop_back();
+    }
+    HIP_TRY(hipGraphLaunch(exec, st));
+    return IRTPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_outputs* out, void* ws,
+                size_t ws_bytes, void* stream) {
+    STATUS_TRY(check_problem(pr, pa));
+    if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
+    const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
+    const SolveLayout lay = solve_layout(W, H, C, K);
+    const size_t rec_bytes = split_bytes(W, H, C, pa->spp, pa->bounces);
+    if (!ws || ws_bytes < lay.total + rec_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign))
+        return IRTPS_ERR_WORKSPACE;
+    const bool graph = (pa->flags & IRTPS_FLAG_GRAPH) != 0;
+    // a graph cannot hold the stop rule's read-back, nor run on the legacy stream
+    if (graph && (pa->stop_tol > 0.0f || stream == nullptr)) return IRTPS_ERR_INVALID_ARG;
+    kern::PsMatrix M;
+    kern::LightSet Ls;
+    STATUS_TRY(make_psmatrix(K, pr->light_dirs_host, pr->light_intensity_host, M));
+    STATUS_TRY(make_lights(K, pr->light_dirs_host, pr->light_intensity_host, Ls));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return graph ? solve_graphed(pr, pa, out, ws, M, Ls, st) : solve_launches(pr, pa, out, ws, M, Ls, st);
+}
+
 int irtps_ps_solve(int32_t W, int32_t H, int32_t C, int32_t K, const float* light_dirs_host,
                    const float* light_intensity_host, const float* A_dev, float* normals_dev,
                    float* albedo_dev, void* stream) {
@@ -165,6 +266,20 @@ int irtps_ps_solve(int32_t W, int32_t H, int32_t C, int32_t K, const float* ligh
     kern::PsMatrix M;
     STATUS_TRY(make_psmatrix(K, light_dirs_host, light_intensity_host, M));
     HIP_TRY(kern::ps_solve(W * H, C, K, M, A_dev, normals_dev, albedo_dev, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_ps_solve_masked(int32_t W, int32_t H, int32_t C, int32_t K, const float* light_dirs_host,
+                          const float* light_intensity_host, const float* A_dev, const float* S_dev,
+                          float* normals_dev, float* albedo_dev, void* stream) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !A_dev || !S_dev || !normals_dev || !albedo_dev)
+        return IRTPS_ERR_INVALID_ARG;
+    kern::PsMatrix M;
+    kern::LightSet Ls;
+    STATUS_TRY(make_psmatrix(K, light_dirs_host, light_intensity_host, M));
+    STATUS_TRY(make_lights(K, light_dirs_host, light_intensity_host, Ls));
+    HIP_TRY(kern::ps_solve_masked(W * H, C, K, M, Ls, A_dev, S_dev, normals_dev, albedo_dev,
+                                  reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
 
@@ -345,6 +460,13 @@ int irtps_profile_end(double* trace_ms, int64_t* launches) {
     if (trace_ms) *trace_ms = total;
     if (launches) *launches = n;
     if (err != hipSuccess) return hip_fail(err);
+    return IRTPS_OK;
+}
+
+int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, uint32_t* out_dev, void* stream) {
+    if (blocks < 1 || blocks > (1 << 24) || iters < 0 || active_lanes < 1 || active_lanes > 64 || !out_dev)
+        return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::probe_valu(blocks, iters, active_lanes, out_dev, reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
 

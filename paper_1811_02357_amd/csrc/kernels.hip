@@ -98,6 +98,101 @@ __device__ __forceinline__ void ps_px(int p, int npx, int K, const float* __rest
     n[3 * (size_t)p + 2] = nz;
 }
 
+// Eq.4 over the lights that reach pixel p: light k is kept when its direct
+// irradiance S[p][k] = s_k max(0, n_t . l_k) V_k(H_t) is positive.  With at
+// least three kept lights whose 3x3 normal matrix passes the conditioning test
+// of the all-light matrix (det > 1e-7 (trace/3)^3), the pixel's own solve
+// matrix (L_p^T L_p)^-1 L_p^T is built in binary64 from the kept rows in light
+// order (adjugate over determinant) and rounded to binary32, one column per
+// kept light as the sums reach it; dropped lights add nothing.  Otherwise the
+// all-light M.  The sums per channel and component still run in light order.
+template <int C>
+__device__ __forceinline__ void ps_px_masked(int p, int npx, int K, const float* __restrict__ M,
+                                             const float* __restrict__ l, const float* __restrict__ s,
+                                             const float* __restrict__ A, const float* __restrict__ Srow,
+                                             float* __restrict__ n, float* __restrict__ rho) {
+    unsigned long long kept = 0ull;
+    int nkept = 0;
+    // normal matrix of the kept rows (symmetric: six sums; a product is the
+    // same in either operand order)
+    double a00 = 0.0, a01 = 0.0, a02 = 0.0, a11 = 0.0, a12 = 0.0, a22 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (!(Srow[k] > 0.0f)) continue;
+        kept |= 1ull << k;
+        ++nkept;
+        const double sk = (double)s[k];
+        const double x = sk * (double)l[3 * k], y = sk * (double)l[3 * k + 1], z = sk * (double)l[3 * k + 2];
+        a00 = a00 + x * x;
+        a01 = a01 + x * y;
+        a02 = a02 + x * z;
+        a11 = a11 + y * y;
+        a12 = a12 + y * z;
+        a22 = a22 + z * z;
+    }
+    // adjugate (cofactor c_ab of entry (a, b)), determinant, inverse = c_ba / det
+    const double c00 = a11 * a22 - a12 * a12;
+    const double c01 = -(a01 * a22 - a12 * a02);
+    const double c02 = a01 * a12 - a11 * a02;
+    const double c10 = -(a01 * a22 - a02 * a12);
+    const double c11 = a00 * a22 - a02 * a02;
+    const double c12 = -(a00 * a12 - a01 * a02);
+    const double c20 = a01 * a12 - a02 * a11;
+    const double c21 = -(a00 * a12 - a02 * a01);
+    const double c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double tr3 = (a00 + a11 + a22) / 3.0;
+    const bool own = nkept >= 3 && det > 1e-7 * tr3 * tr3 * tr3;
+    double i00 = 0, i01 = 0, i02 = 0, i10 = 0, i11 = 0, i12 = 0, i20 = 0, i21 = 0, i22 = 0;
+    if (own) {
+        i00 = c00 / det; i01 = c10 / det; i02 = c20 / det;
+        i10 = c01 / det; i11 = c11 / det; i12 = c21 / det;
+        i20 = c02 / det; i21 = c12 / det; i22 = c22 / det;
+    }
+    float g[C][3];
+#pragma unroll
+    for (int c = 0; c < C; ++c) g[c][0] = g[c][1] = g[c][2] = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        float m0, m1, m2;
+        if (own) {
+            if (!((kept >> k) & 1ull)) continue;
+            const double sk = (double)s[k];
+            const double x = sk * (double)l[3 * k], y = sk * (double)l[3 * k + 1], z = sk * (double)l[3 * k + 2];
+            m0 = (float)(i00 * x + i01 * y + i02 * z);
+            m1 = (float)(i10 * x + i11 * y + i12 * z);
+            m2 = (float)(i20 * x + i21 * y + i22 * z);
+        } else {
+            m0 = M[k];
+            m1 = M[kMaxLights + k];
+            m2 = M[2 * kMaxLights + k];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float a = A[((size_t)k * C + c) * npx + p];
+            g[c][0] = fmaf(m0, a, g[c][0]);
+            g[c][1] = fmaf(m1, a, g[c][1]);
+            g[c][2] = fmaf(m2, a, g[c][2]);
+        }
+    }
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[(size_t)c * npx + p] = sqrtf(fmaf(g[c][0], g[c][0], fmaf(g[c][1], g[c][1], g[c][2] * g[c][2])));
+        sx = sx + g[c][0];
+        sy = sy + g[c][1];
+        sz = sz + g[c][2];
+    }
+    const float len = sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
+    float nx = 0.0f, ny = 0.0f, nz = 1.0f;
+    if (len > 0.0f) {
+        nx = sx / len;
+        ny = sy / len;
+        nz = sz / len;
+    }
+    n[3 * (size_t)p + 0] = nx;
+    n[3 * (size_t)p + 1] = ny;
+    n[3 * (size_t)p + 2] = nz;
+}
+
 // Walker steps per pass of the shadow-ray loop.
 constexpr int kDirectSteps = 8;
 
@@ -1028,6 +1123,15 @@ __global__ void __launch_bounds__(256) k_ps_solve(int npx, int K, PsMatrix M, co
 }
 
 
+template <int C>
+__global__ void __launch_bounds__(256) k_ps_solve_masked(int npx, int K, PsMatrix M, LightSet L,
+                                                         const float* __restrict__ A, const float* __restrict__ S,
+                                                         float* __restrict__ n, float* __restrict__ rho) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npx) return;
+    ps_px_masked<C>(p, npx, K, &M.m[0][0], &L.l[0][0], L.s, A, S + (size_t)p * K, n, rho);
+}
+
 __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
                                                 int flat, float* __restrict__ S_out) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
@@ -1544,7 +1648,11 @@ __global__ void __launch_bounds__(256) k_ps_multi(const JobDesc* __restrict__ jo
     const int npx = J.W * J.Hh;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (!participates(J, !from_A) || J.C != C || p >= npx) return;
-    ps_px<C>(p, npx, J.K, &J.M[0][0], from_A ? J.A : J.I0, J.n, J.rho);
+    // after a correction, the shadow-aware solve uses this iteration's S
+    if (from_A && (J.flags & kFlagShadowPs))
+        ps_px_masked<C>(p, npx, J.K, &J.M[0][0], &J.L[0][0], J.s, J.A, J.S + (size_t)p * J.K, J.n, J.rho);
+    else
+        ps_px<C>(p, npx, J.K, &J.M[0][0], from_A ? J.A : J.I0, J.n, J.rho);
 }
 
 __global__ void __launch_bounds__(256) k_direct_multi(const JobDesc* __restrict__ jobs) {
@@ -1755,6 +1863,30 @@ __global__ void k_stop_multi(JobDesc* jobs, int njobs) {
 
 // ===========================================================================
 // Probes.
+// Issue-rate probe: each lane runs `iters` rounds of eight independent 32-bit
+// integer chains (a shift and a xor-add each: 16 VALU instructions per round, no
+// memory access in the loop).  Lanes at or above `active` of their wave skip the
+// work (the wave still issues it with those lanes masked off).  A counted, timed
+// launch gives the wave64 VALU instructions the chip retires per second, and how
+// that rate depends on the active lanes.
+__global__ void __launch_bounds__(256) k_probe_valu(int iters, int active, uint32_t* out) {
+    uint32_t x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = threadIdx.x * 0x9E3779B9u + blockIdx.x * 0x85EBCA6Bu + (uint32_t)r;
+    const bool on = (int)(threadIdx.x & 63) < active;
+    for (int i = 0; i < iters; ++i) {
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = (x[r] ^ (x[r] >> 7)) + 0x7F4A7C15u;
+        }
+        __asm__ volatile("" ::: "memory");  // keeps the masked body inside the loop
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc ^= x[r];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 __global__ void k_probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1,
                                uint32_t* out) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1812,6 +1944,14 @@ hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, fl
     const unsigned g = blocks_for(npx, 256);
     if (C == 1) hipLaunchKernelGGL(k_ps_solve<1>, dim3(g), dim3(256), 0, st, npx, K, M, A, n, rho);
     else hipLaunchKernelGGL(k_ps_solve<3>, dim3(g), dim3(256), 0, st, npx, K, M, A, n, rho);
+    return hipGetLastError();
+}
+
+hipError_t ps_solve_masked(int npx, int C, int K, const PsMatrix& M, const LightSet& L, const float* A,
+                           const float* S, float* n, float* rho, hipStream_t st) {
+    const unsigned g = blocks_for(npx, 256);
+    if (C == 1) hipLaunchKernelGGL(k_ps_solve_masked<1>, dim3(g), dim3(256), 0, st, npx, K, M, L, A, S, n, rho);
+    else hipLaunchKernelGGL(k_ps_solve_masked<3>, dim3(g), dim3(256), 0, st, npx, K, M, L, A, S, n, rho);
     return hipGetLastError();
 }
 
@@ -2082,6 +2222,11 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     hipLaunchKernelGGL(k_anchor_multi, gpx, dim3(256), 0, st, jobs, cold);
     if (!cold)
         hipLaunchKernelGGL(k_stop_multi, dim3(blocks_for(nj, 64)), dim3(64), 0, st, const_cast<JobDesc*>(jobs), nj);
+    return hipGetLastError();
+}
+
+hipError_t probe_valu(int blocks, int iters, int active, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_probe_valu, dim3(blocks), dim3(256), 0, st, iters, active, out);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ __host__ __device__ inline int max_trace_tiles(int W, int H) {
 constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
+constexpr int kFlagShadowPs = 8;  // IRTPS_FLAG_SHADOW_AWARE_PS
 
 // Eq.4 solve matrix, rows x, y, z over the K lights (passed by value).
 struct PsMatrix {
@@ -169,6 +170,9 @@ struct BatchShape {
 
 hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, float* n, float* rho,
                     hipStream_t st);
+// Eq.4 per pixel over the lights with S[p][k] > 0 (at least three), else all.
+hipError_t ps_solve_masked(int npx, int C, int K, const PsMatrix& M, const LightSet& L, const float* A,
+                           const float* S, float* n, float* rho, hipStream_t st);
 hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
                   hipStream_t st);
 hipError_t trace(TraceArgs a, hipStream_t st);
@@ -209,6 +213,8 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
 hipError_t batch_advance(JobDesc* jobs, int njobs, hipStream_t st);
 
 // ---- probes ----
+// out: blocks x 256 uint32.
+hipError_t probe_valu(int blocks, int iters, int active, uint32_t* out, hipStream_t st);
 hipError_t probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                         hipStream_t st);
 hipError_t probe_sample(long long count, const float* n, const float* u, float* d, hipStream_t st);

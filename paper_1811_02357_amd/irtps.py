@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libirtps.so")
 
 OK = 0
 RHO_FIT, RHO_PREV = 0, 1
-FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL = 1, 2, 4
+FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL, FLAG_SHADOW_AWARE_PS = 1, 2, 4, 8
+FLAG_GRAPH = 16  # irtps_solve: capture once in a hipGraph, replay on identical calls
 TAG_SOLVE, TAG_RENDER = 0, 1
 NUM_COUNTERS = 5  # segments, hits, escapes, continuations, IRT iterations run
 
@@ -104,6 +105,8 @@ def lib():
             "irtps_workspace_bytes": [P(Problem), P(Params), P(_sz)],
             "irtps_solve": [P(Problem), P(Params), P(Outputs), _vp, _sz, _vp],
             "irtps_ps_solve": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
+            "irtps_ps_solve_masked": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+            "irtps_probe_valu": [_i32, _i32, _i32, _vp, _vp],
             "irtps_integrate_workspace_bytes": [_i32, _i32, P(_sz)],
             "irtps_integrate": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp],
             "irtps_pyramid_bytes": [_i32, _i32, P(_sz)],
@@ -269,6 +272,21 @@ def ps_solve(A, light_dirs, light_intensity=None, stream=None):
     rho = torch.empty((C, H, W), device=A.device)
     _check("irtps_ps_solve", lib().irtps_ps_solve(W, H, C, K, lp, sp, _dev(A, name="A"),
                                                   _dev(n), _dev(rho), _stream(stream)))
+    return n, rho
+
+
+@_on_stream
+def ps_solve_masked(A, S, light_dirs, light_intensity=None, stream=None):
+    """Eq.4 per pixel over the lights with S[p][k] > 0 (at least three), else
+    all lights.  A [K][C][H][W], S [H][W][K] (irtps_direct)."""
+    K, C, H, W = A.shape
+    l, lp = _host_f32(light_dirs, (K, 3), "light_dirs")
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    n = torch.empty((H, W, 3), device=A.device)
+    rho = torch.empty((C, H, W), device=A.device)
+    _check("irtps_ps_solve_masked", lib().irtps_ps_solve_masked(
+        W, H, C, K, lp, sp, _dev(A, name="A"), _dev(S, shape=(H, W, K), name="S"), _dev(n), _dev(rho),
+        _stream(stream)))
     return n, rho
 
 
@@ -570,6 +588,14 @@ def profile_end():
 
 
 # ---- probes ----------------------------------------------------------------
+def probe_valu(blocks, iters, active_lanes=64, stream=None):
+    """Launch the VALU issue-rate probe once; returns its output buffer."""
+    out = torch.empty(blocks * 256, dtype=torch.int32, device=torch.device("cuda"))
+    _check("irtps_probe_valu", lib().irtps_probe_valu(blocks, iters, active_lanes, _dev(out, dtype=torch.int32),
+                                                      _stream(stream)))
+    return out
+
+
 def probe_philox(ctr, seed):
     out = torch.empty_like(ctr)
     _check("irtps_probe_philox", lib().irtps_probe_philox(ctr.shape[0], _dev(ctr, dtype=torch.int32),

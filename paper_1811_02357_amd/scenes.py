@@ -184,6 +184,30 @@ def fbm_terrain(seed: int = 0, size: int = 2048, channels: int = 3, num_lights: 
                   render_spp=render_spp, render_bounces=render_bounces)
 
 
+def step_hill(seed: int = 4, w: int = 48, hgt: int = 40, channels: int = 3, num_lights: int = 12,
+              env_shape=(2, 4), env_level: float = 0.0, spp: int = 16, bounces: int = 2,
+              iterations: int = 3, render_spp: int = 0, render_bounces: int = 0) -> Scene:
+    """A shadow-heavy surface: a floor with a step (a plateau of height 10 from
+    column 30 w/48) cut by a narrow trench, and a paraboloid hill of height 4;
+    albedo i.i.d. U[0.3, 0.9]; K Fibonacci lights (the lowest 2.4 deg above the
+    horizon for K = 12) with intensities spread over [0.8, 1.3]; uniform
+    environment `env_level`.  Without indirect light (render_bounces = 0,
+    env_level = 0) the images hold attached and cast shadows only."""
+    rng = np.random.default_rng(seed)
+    f = w / 48.0
+    yy, xx = np.mgrid[0:hgt, 0:w].astype(np.float64)
+    h = np.where(xx >= 30 * f, 10.0, 0.0)
+    r2 = (xx - 14.0 * f) ** 2 + (yy - hgt / 2.0) ** 2
+    h = h + np.where(r2 < 64.0 * f * f, 4.0 * (1 - r2 / (64.0 * f * f)), 0.0)
+    h = np.where((xx >= 39 * f) & (xx <= 41 * f) & (yy >= 0.15 * hgt) & (yy <= 0.85 * hgt), -12.0, h)
+    albedo = rng.uniform(0.3, 0.9, size=(channels, hgt, w))
+    intens = np.linspace(0.8, 1.3, num_lights)
+    env = np.full((env_shape[0], env_shape[1], channels), env_level)
+    return _scene("step_hill", h, albedo, fibonacci_lights(num_lights), intens, env, spp=spp,
+                  bounces=bounces, iterations=iterations, seed=0, render_spp=max(render_spp, 1),
+                  render_bounces=render_bounces)
+
+
 def _loguniform_side(rng, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 

@@ -200,6 +200,39 @@ def test_ps_solve_stage(dev, C, K, shape):
     assert np.array_equal(H(n), rn) and np.array_equal(H(rho), rr)
 
 
+@pytest.mark.parametrize("C,K,shape", [(1, 8, (64, 64)), (3, 16, (33, 47)), (1, 64, (20, 19)), (3, 5, (5, 300))])
+def test_ps_solve_masked_stage(dev, C, K, shape):
+    """Shadow-aware PS: per pixel, the lights with S > 0.  Random masks give
+    pixels with 0..K kept lights; rows of coplanar kept lights (all in the
+    x-z plane) fall back to the all-light matrix; K = 64 uses every mask bit."""
+    say(f"case: ps_solve_masked C={C} K={K} {shape}")
+    rng = np.random.default_rng(C * 1000 + K)
+    Hh, W = shape
+    A = rng.uniform(-0.2, 1.5, (K, C, Hh, W)).astype(F32)
+    l = scenes.fibonacci_lights(K)
+    half = K // 2 + 1
+    l[:half] = scenes.ring_lights(rng.uniform(10, 80, half), ([0.0, 180.0] * K)[:half])
+    s = rng.uniform(0.5, 1.5, K).astype(F32)
+    S = rng.uniform(0, 1, (Hh, W, K)).astype(F32)
+    S[S < rng.uniform(0, 1, (Hh, W, 1))] = 0                   # 0..K kept lights per pixel
+    S[0, :, K // 2 + 1:] = 0                                    # first row: the coplanar lights only
+    n, rho = irtps.ps_solve_masked(T(A, dev), T(S, dev), l, s)
+    rn, rr = O.ps_solve_masked(l, s, A, S)
+    assert np.array_equal(H(n), rn) and np.array_equal(H(rho), rr)
+    kept = (S > 0).sum(-1)
+    assert (kept < 3).any() and (kept >= 3).any()
+
+
+def test_ps_solve_masked_shadowed_scene(dev):
+    say("case: ps_solve_masked on the step-and-hill scene (shadows only)")
+    sc = scenes.step_hill()
+    I0, _ = O.render_scene(sc)
+    S = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity)
+    n, rho = irtps.ps_solve_masked(T(I0, dev), T(S, dev), sc.light_dirs, sc.light_intensity)
+    rn, rr = O.ps_solve_masked(sc.light_dirs, sc.light_intensity, I0, S)
+    assert np.array_equal(H(n), rn) and np.array_equal(H(rho), rr)
+
+
 @pytest.mark.parametrize("shape", [(64, 64), (37, 61), (3, 200), (2, 2), (257, 129), (2, 5000), (2, 16384)])
 def test_integrate_stage(dev, shape):
     say(f"case: integrate {shape}")
@@ -301,7 +334,8 @@ def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None, stop
     Tn = sc.iterations if T_ is None else T_
     ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, Tn,
                   seed=sc.seed, rho_mode=rho_mode,
-                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE), stop_tol=stop_tol)
+                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE | irtps.FLAG_SHADOW_AWARE_PS),
+                  stop_tol=stop_tol)
     out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
                       sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
     return ref, {k: H(v) for k, v in out.items()}
@@ -377,6 +411,67 @@ def test_solve_fused_correction_modes(dev, rho_mode, flags, stop_tol):
     ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
     _compare_solve(ref, got, "fbm160x120")
     assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
+
+
+# shadow-aware PS inside the loop: the per-path tracer (48 x 40), the per-pixel
+# tracer with its fused correction (160 x 120 RGB), and the cumulative reading
+@pytest.mark.parametrize("case", ["step_hill", "step_hill_env", "fbm160x120", "bowl64_cumulative"])
+def test_solve_shadow_aware(dev, case):
+    say(f"case: solve with shadow-aware PS, {case}")
+    flags = irtps.FLAG_SHADOW_AWARE_PS
+    rho_mode = irtps.RHO_FIT
+    if case == "step_hill":
+        sc = scenes.step_hill(render_spp=16, render_bounces=2)
+    elif case == "step_hill_env":
+        sc = scenes.step_hill(w=96, hgt=80, env_level=0.3, render_spp=16, render_bounces=2, spp=8, bounces=3)
+    elif case == "fbm160x120":
+        sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=16, env_shape=(16, 32),
+                                ptp=24.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+        sc.heights = np.ascontiguousarray(sc.heights[:120])
+        sc.normals = np.ascontiguousarray(sc.normals[:120])
+        sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    else:
+        sc = scenes.bowl_64()
+        flags |= irtps.FLAG_LITERAL_CUMULATIVE
+        rho_mode = irtps.RHO_PREV
+    ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags)
+    _compare_solve(ref, got, case)
+    assert np.array_equal(got["normals"], ref["normals"]) and np.array_equal(got["depth"], ref["depth"])
+
+
+@pytest.mark.parametrize("case", ["bowl64", "fbm160x120"])
+def test_solve_graph_replays_equal_eager(dev, case):
+    """IRTPS_FLAG_GRAPH: the first call captures the solve into a hipGraph, later
+    identical calls replay it.  Every replay, with eager solves and host
+    synchronisations in between, must equal the eager solve bit for bit (the
+    per-path tracer at 64^2; the per-pixel tracer with heaviest-first tile order
+    and fused correction at 160 x 120)."""
+    say(f"case: solve replayed from a hipGraph, {case}")
+    if case == "bowl64":
+        sc = scenes.bowl_64()
+    else:
+        sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=8, env_shape=(16, 32),
+                                ptp=16.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+        sc.heights = np.ascontiguousarray(sc.heights[:120])
+        sc.normals = np.ascontiguousarray(sc.normals[:120])
+        sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 1, seed=1)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        args = (T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp, sc.bounces, sc.iterations)
+        ref = {k: H(v) for k, v in irtps.solve(*args, seed=3).items()}
+        ws = torch.empty(irtps.workspace_bytes(*args, seed=3), dtype=torch.uint8, device=dev)
+        out = irtps._outputs_for(args[0], dev)
+        for rep in range(4):
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH, out=out, workspace=ws)
+            got = {k: H(v) for k, v in out.items()}
+            for key in ("normals", "albedo", "depth", "indirect", "counters"):
+                assert np.array_equal(got[key], ref[key]), (rep, key)
+            irtps.solve(*args, seed=3)  # eager work between the replays
+            torch.cuda.synchronize()
+    with pytest.raises(irtps.IrtpsError):  # the stop rule's read-back cannot be captured
+        with torch.cuda.stream(stream):
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH, stop_tol=0.5)
 
 
 def test_solve_T0_is_plain_ps(dev):
