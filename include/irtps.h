@@ -150,6 +150,22 @@ int irtps_solve(const irtps_problem* problem, const irtps_params* params,
                 const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
                 void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): irtps_solve
+ * with the workspace taken from a scratch area the library owns, a device
+ * array of IRTPS_STATIC_SCRATCH_BYTES on every GPU the library runs on (held
+ * until the process ends).  The call allocates nothing and frees nothing; the
+ * caller still passes inputs and outputs.  Problems whose irtps_workspace_bytes
+ * exceed IRTPS_STATIC_SCRATCH_BYTES are refused with IRTPS_ERR_WORKSPACE (a
+ * 512 x 512 grey solve with 12 lights needs about 48 MiB).  All calls on one
+ * GPU share its scratch: calls that overlap on one GPU (another stream,
+ * another thread) race and must be serialised by the caller.  With stop_tol >
+ * 0 the call synchronises the stream after each iteration, as irtps_solve
+ * does.  Results are bit-identical to irtps_solve. */
+#define IRTPS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int irtps_solve_static(const irtps_problem* problem, const irtps_params* params,
+                       const irtps_outputs* outputs, void* stream);
+
 /* ---- stages (teacher-forced parity and custom loops) -------------------- */
 /* Eq.4 per pixel: g_c = M A_c, albedo_c = |g_c|, normal = sum_c g_c / |sum_c g_c|
  * ((0,0,1) where that sum is 0).  A_dev is [K][C][H][W]. */

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libirtps.so")
-SOURCES = ["kernels.hip", "capi.cpp", "batch.cpp", "server.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "capi.cpp", "batch.cpp", "server.cpp", "tune.cpp", "noalloc.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -104,6 +104,7 @@ def lib():
             "irtps_ps_matrix": [_i32, _vp, _vp, _vp],
             "irtps_workspace_bytes": [P(Problem), P(Params), P(_sz)],
             "irtps_solve": [P(Problem), P(Params), P(Outputs), _vp, _sz, _vp],
+            "irtps_solve_static": [P(Problem), P(Params), P(Outputs), _vp],
             "irtps_ps_solve": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
             "irtps_ps_solve_masked": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
             "irtps_probe_valu": [_i32, _i32, _i32, _vp, _vp],
@@ -251,6 +252,35 @@ def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, se
     _check("irtps_solve", lib().irtps_solve(ct.byref(pr), ct.byref(pa), ct.byref(o),
                                             ct.c_void_p(workspace.data_ptr()),
                                             workspace.numel(), _stream(stream)))
+    return out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # IRTPS_STATIC_SCRATCH_BYTES
+
+
+@_on_stream
+def solve_static(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
+                 rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None, stream=None,
+                 stop_tol=0.0):
+    """solve() with the workspace in the library's own device scratch (no
+    allocation by the library; the outputs are allocated here unless `out` is
+    given).  Problems needing more than STATIC_SCRATCH_BYTES are refused."""
+    K, C, H, W = images.shape
+    dev = images.device
+    pr, keep = _problem(images, light_dirs, light_intensity, env)
+    pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, float(stop_tol), seed)
+    if out is None:
+        out = {"normals": torch.empty((H, W, 3), device=dev),
+               "albedo": torch.empty((C, H, W), device=dev),
+               "depth": torch.empty((H, W), device=dev),
+               "indirect": torch.empty((K, C, H, W), device=dev),
+               "counters": torch.empty(NUM_COUNTERS, dtype=torch.int64, device=dev)}
+    o = Outputs(_dev(out["normals"], shape=(H, W, 3), name="normals"),
+                _dev(out["albedo"], shape=(C, H, W), name="albedo"),
+                _dev(out["depth"], shape=(H, W), name="depth"),
+                _dev(out.get("indirect"), shape=(K, C, H, W), name="indirect"),
+                _dev(out.get("counters"), dtype=torch.int64, shape=(NUM_COUNTERS,), name="counters"))
+    _check("irtps_solve_static", lib().irtps_solve_static(ct.byref(pr), ct.byref(pa), ct.byref(o), _stream(stream)))
     return out
 
 

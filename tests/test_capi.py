@@ -126,3 +126,26 @@ def test_workspace_holds_small_problem_records():
     assert ws(128, 128, 3, 32, 3) - ws(128, 128, 3, 32, 0) == align(128 * 128 * 32 * 3 * 4 * 4)
     assert ws(129, 128, 1, 16, 1) == ws(129, 128, 1, 16, 0)       # more than 16384 pixels
     assert ws(128, 128, 3, 128, 3) == ws(128, 128, 3, 128, 0)     # records above 64 MiB
+
+
+def test_static_solve_refuses_oversized_problem_on_host():
+    """irtps_solve_static checks the problem against its scratch size before any
+    device call: a 1024^2 RGB problem with 16 lights needs far more than
+    IRTPS_STATIC_SCRATCH_BYTES and is refused with IRTPS_ERR_WORKSPACE; an
+    invalid problem is refused as by irtps_solve."""
+    L = irtps.lib()
+    K, side = 16, 1024
+    l = scenes.fibonacci_lights(K)
+    pr = irtps.Problem(side, side, 3, K, ct.c_void_p(256), l.ctypes.data_as(ct.c_void_p), None,
+                       ct.c_void_p(256), 4, 8)
+    pa = irtps.Params(4, 1, 1, 0, 0, 0, 0, 0, 0)
+    o = irtps.Outputs(ct.c_void_p(256), ct.c_void_p(256), ct.c_void_p(256), None, None)
+    n = ct.c_size_t()
+    assert L.irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n)) == 0
+    assert n.value > irtps.STATIC_SCRATCH_BYTES
+    assert L.irtps_solve_static(ct.byref(pr), ct.byref(pa), ct.byref(o), None) == 3
+    bad = irtps.Params(0, 1, 1, 0, 0, 0, 0, 0, 0)  # spp 0
+    assert L.irtps_solve_static(ct.byref(pr), ct.byref(bad), ct.byref(o), None) == 1
+    src = open(os.path.join(ROOT, "include", "irtps.h")).read()
+    m = re.search(r"#define IRTPS_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == irtps.STATIC_SCRATCH_BYTES
