@@ -12,12 +12,20 @@ environment; solve with 256 spp, 3 bounces, 5 iterations (FP32).  The input
 images are rendered on the GPU (64 spp, 3 bounces) before timing.
 
 Prints one JSON line.  `value` is traced gather segments (rays) per second of
-the whole job; the roofline object is for the tracer kernel, timed with HIP
-events around its launches inside the timed steps; `cpu_baseline` is the CPU
-oracle on a bounded sample of the same workload.
+the whole job.  The `roofline` object is for the tracer kernel, timed with HIP
+events around its launches inside the timed steps: it is bound by VALU issue,
+so it is given in lane-operations (counted wave64 VALU instructions times
+their active lanes, from the committed counter profile of the same machine
+code) against the full-lane peak measured with the issue-rate probe;
+`hbm_yardstick` gives the tracer's algorithmic bytes against 8 TB/s, with the
+fabric bytes (copy-calibrated FETCH_SIZE + WRITE_SIZE, MALL hits included) of
+the counter profile.  `cpu_baseline` is the CPU oracle on bounded samples of
+the same workload (all host threads, and one thread).
 
-Two more legs compare the multi-job modes with the plain per-job path on the
-same GPU (objects `batched` and `served`):
+`small` times the 64^2 bowl launch by launch and replayed from a HIP graph;
+`groove512` times the 512^2 V-groove and checks its normals against the
+oracle's whole solve.  Two more legs compare the multi-job modes with the
+plain per-job path on the same GPU (objects `batched` and `served`):
 - batched: 64 independent jobs (side log-uniform 128..1024, bowl / V-groove /
   fBm, grey, K 6..20; 64 spp, 2 bounces, 4 iterations) run one at a time
   through the plain solve and then as one batch replayed from a HIP graph;
@@ -54,6 +62,7 @@ def log(msg):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_fbm2048_rgb_counters.md")
+VALU_PROBE_PROFILE = os.path.join(ROOT, "profiles", "k_probe_valu_calibration.md")
 TRACER_SYMBOL = "_ZN5irtps4kern7k_traceILi3EEEvNS0_9TraceArgsE"  # k_trace<3>
 
 
@@ -122,14 +131,27 @@ def profiled_values(workload):
         return None
 
 
+def probe_peak():
+    """The measured VALU issue peak (wave64 instructions per second with every
+    lane active) from the committed calibration profile, or None."""
+    try:
+        with open(VALU_PROBE_PROFILE) as f:
+            kv = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
+        return float(kv["valu_peak_wave_instructions_per_s"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def profiled_traffic(workload):
     v = profiled_values(workload)
     return None if v is None else v["traffic"]
 
 
-# VALU issue rate: 256 CUs x 4 SIMDs, one wave64 VALU instruction per 4 cycles
-# each at 2.4 GHz (non-packed FP32: the kernels are built without packed ops)
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# Nominal VALU issue rate: 256 CUs x 4 SIMDs, one wave64 instruction per 4
+# cycles each at 2.4 GHz (non-packed: the kernels are built without packed FP32),
+# i.e. 39.3 T lane-operations/s; the measured peak comes from the issue-rate
+# probe (irtps_probe_valu), whose calibration profile bench.py reads.
+VALU_ISSUE_NOMINAL = 256 * 4 * 2.4e9 / 4
 
 
 def algorithmic_bytes(cnt, npx, K, C, iterations):
@@ -148,13 +170,13 @@ def algorithmic_bytes(cnt, npx, K, C, iterations):
     return gather + correction
 
 
-def cpu_baseline(sc, args):
-    """The CPU oracle, as it stands, on a tile of the same terrain: the whole
-    solve (all stages, same K, C, spp, bounces, iterations)."""
+def _oracle_tile_solve(sc, t):
+    """The CPU oracle, as it stands, on the t x t centre tile of the terrain: the
+    whole solve (all stages, same K, C, spp, bounces, iterations).  Returns
+    (segments, seconds, threads)."""
     import numpy as np
     from oracle import oracle as O
     from paper_1811_02357_amd import scenes
-    t = args.cpu_tile
     y0 = x0 = (sc.width - t) // 2
     h = np.ascontiguousarray(sc.heights[y0:y0 + t, x0:x0 + t])
     tile = scenes._scene("tile", h, sc.albedo[:, y0:y0 + t, x0:x0 + t], sc.light_dirs,
@@ -164,12 +186,42 @@ def cpu_baseline(sc, args):
     t0 = time.perf_counter()
     r = O.solve(I0, tile.light_dirs, tile.light_intensity, tile.env, sc.spp, sc.bounces,
                 sc.iterations, seed=sc.seed)
-    dt = time.perf_counter() - t0
-    seg = r["counters"]["segments"]
-    return {"value": seg / dt, "unit": "rays/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": (f"{t}x{t} centre tile of the {sc.width}^2 terrain, whole solve "
-                       f"(T={sc.iterations}, spp {sc.spp}, B {sc.bounces}, K {sc.num_lights}, "
-                       f"C {sc.channels}): {seg} segments in {dt:.1f} s")}
+    return r["counters"]["segments"], time.perf_counter() - t0, O.num_threads()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(sc, args):
+    """The oracle on the host's cores (all threads, a 512^2 tile) and on one
+    thread (a 128^2 tile, in a child process with OMP_NUM_THREADS=1)."""
+    import subprocess
+    seg, dt, threads = _oracle_tile_solve(sc, args.cpu_tile)
+    one = None
+    if args.cpu_tile_1t > 0:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-tile", str(args.cpu_tile_1t),
+               "--workload", args.workload]
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+    out = {"value": seg / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+           "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": (f"{args.cpu_tile}x{args.cpu_tile} centre tile of the {sc.width}^2 terrain, whole solve "
+                      f"(T={sc.iterations}, spp {sc.spp}, B {sc.bounces}, K {sc.num_lights}, "
+                      f"C {sc.channels}) on {threads} threads: {seg} segments in {dt:.1f} s")}
+    if one is not None:
+        out["one_thread"] = {"value": one["segments"] / one["s"], "unit": "rays/s", "cores": one["threads"],
+                             "sample": (f"{args.cpu_tile_1t}x{args.cpu_tile_1t} centre tile, whole solve, "
+                                        f"one thread: {one['segments']} segments in {one['s']:.1f} s")}
+    return out
 
 
 def _job(sc, dev, irtps, torch, np):
@@ -231,6 +283,49 @@ def batched_leg(args, dev):
                         "p99_s": float(np.quantile(batch_t, 0.99)), "graph": True,
                         "tuned_classes": irtps.tuning_entries()},
             "speedup": tp / tb, "repeats": args.mode_reps}
+
+
+def groove_leg(args, dev):
+    """The 512 x 512 V-groove (12 lights, grey, 32 x 64 environment; spp 64,
+    B 2, T 5): input images rendered by the CPU oracle, solves timed one by one
+    through the plain solve, and the GPU normals compared with the oracle's
+    whole solve on every pixel (the metric's 0.05 degree gate)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1811_02357_amd import irtps, scenes
+    sc = scenes.vgroove_512()
+    log("bench: C2 leg, 512^2 V-groove, oracle render and solve")
+    I0, _ = O.render_scene(sc)
+    ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, sc.iterations, seed=sc.seed)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    job = dict(images=T(I0), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity, env=T(sc.env),
+               spp=sc.spp, bounces=sc.bounces, iterations=sc.iterations, seed=sc.seed)
+    ws = torch.empty(irtps.workspace_bytes(**job), dtype=torch.uint8, device=dev)
+    out = irtps.solve(**job, workspace=ws)  # warm-up
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(args.groove_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        irtps.solve(**job, out=out, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    n = out["normals"].cpu().numpy().astype(np.float64)
+    rn = ref["normals"].astype(np.float64)
+    cosang = (n * rn).sum(-1) / (np.linalg.norm(n, axis=-1) * np.linalg.norm(rn, axis=-1))
+    ang = np.degrees(np.arccos(np.clip(cosang, -1, 1)))
+    seg = int(out["counters"][0])
+    med = float(np.median(ts))
+    log(f"bench: C2 solve {med:.2f} ms, max normal angle vs oracle {ang.max():.2e} deg")
+    return {"workload": "vgroove512: 512x512 V-groove (60 deg, depth 64) + 8 px egg-crate, K 12, grey, "
+                        "env 32x64 U[0,0.5]; spp 64, bounces 2, iterations 5",
+            "repeats": args.groove_reps, "median_ms": med, "p99_ms": float(np.quantile(ts, 0.99)),
+            "rays_per_s": seg / (med / 1e3), "reconstructions_per_s": 1e3 / med, "segments": seg,
+            "max_normal_err_deg_vs_oracle": float(ang.max()),
+            "counters_equal_oracle": out["counters"].cpu().numpy().tolist()[:4] == [
+                ref["counters"][k] for k in ("segments", "hits", "escapes", "continuations")]}
 
 
 def small_leg(args, dev):
@@ -313,36 +408,46 @@ def served_leg(args, dev):
     plain_outs, plain_lat, plain_span = replay_plain()
     seg = int(sum(int(o["counters"][0]) for o in plain_outs))
 
-    log("bench: served leg, continuous-batching server")
     budget = int(args.served_budget_gib * (1 << 30))
-    srv = irtps.Server(budget, device=dev)
-    try:
-        ids = []
-        t0 = time.perf_counter()
-        for a, job in zip(arr, jobs):
-            now = time.perf_counter() - t0
-            if now < a:
-                time.sleep(a - now)
-            ids.append(srv.submit(job))
-        sts = [srv.wait(i, 600.0) for i in ids]
-        torch.cuda.synchronize()
-        ok = all(st.state == irtps.JOB_DONE for st in sts)
-        lat = np.asarray([st.end_s - st.submit_s for st in sts])
-        span = max(st.end_s for st in sts) - min(st.submit_s for st in sts)
-        same = ok and all(_same(a, srv.outputs(i), torch) for a, i in zip(plain_outs, ids))
-        stats = srv.stats()
-    finally:
-        srv.close()
-    log(f"bench: served {span:.2f} s vs FIFO plain {plain_span:.2f} s for {n} jobs")
+
+    def replay_server(fill):
+        srv = irtps.Server(budget, device=dev, fill_pixels=fill)
+        try:
+            ids = []
+            t0 = time.perf_counter()
+            for a, job in zip(arr, jobs):
+                now = time.perf_counter() - t0
+                if now < a:
+                    time.sleep(a - now)
+                ids.append(srv.submit(job))
+            sts = [srv.wait(i, 600.0) for i in ids]
+            torch.cuda.synchronize()
+            ok = all(st.state == irtps.JOB_DONE for st in sts)
+            lat = np.asarray([st.end_s - st.submit_s for st in sts])
+            span = max(st.end_s for st in sts) - min(st.submit_s for st in sts)
+            same = ok and all(_same(a, srv.outputs(i), torch) for a, i in zip(plain_outs, ids))
+            stats = srv.stats()
+        finally:
+            srv.close()
+        return lat, span, same, stats
 
     def summary(l, sp):
         return {"jobs_per_s": n / sp, "rays_per_s": seg / sp, "p50_latency_s": float(np.quantile(l, 0.5)),
                 "p99_latency_s": float(np.quantile(l, 0.99)), "span_s": sp}
-    return {"jobs": n, "arrival_rate_per_s": 20.0, "offered_s": float(arr[-1]), "segments": seg,
-            "equal_to_plain": bool(same), "plain_fifo": summary(plain_lat, plain_span),
-            "served": dict(summary(lat, span), budget_gib=args.served_budget_gib,
-                           scheduler_iterations=int(stats["iterations"])),
-            "speedup": plain_span / span}
+
+    res = {"jobs": n, "arrival_rate_per_s": 20.0, "offered_s": float(arr[-1]), "segments": seg,
+           "plain_fifo": summary(plain_lat, plain_span)}
+    same_all = True
+    for name, fill in (("served", args.served_fill), ("served_every_job", 0)):
+        log(f"bench: served leg, continuous-batching server (fill_pixels {fill})")
+        lat, span, same, stats = replay_server(fill)
+        same_all = same_all and same
+        res[name] = dict(summary(lat, span), budget_gib=args.served_budget_gib, fill_pixels=fill,
+                         scheduler_iterations=int(stats["iterations"]))
+        log(f"bench: served (fill {fill}) {span:.2f} s vs FIFO plain {plain_span:.2f} s for {n} jobs")
+    res["equal_to_plain"] = bool(same_all)
+    res["speedup"] = plain_span / res["served"]["span_s"]
+    return res
 
 
 def main():
@@ -353,13 +458,18 @@ def main():
     ap.add_argument("--workload", default="fbm2048_rgb", choices=sorted(WORKLOADS))
     ap.add_argument("--flat", action="store_true", help="walk every crossing (no pyramid skips)")
     ap.add_argument("--cpu-tile", type=int, default=512)
+    ap.add_argument("--cpu-tile-1t", type=int, default=128, help="tile of the one-thread oracle timing (0: off)")
+    ap.add_argument("--oracle-tile", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--groove-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="all", choices=["all", "plain", "small", "batched", "served"],
-                    help="plain: the main workload only; small/batched/served: the main workload and that leg")
+    ap.add_argument("--mode", default="all", choices=["all", "plain", "small", "groove", "batched", "served"],
+                    help="plain: the main workload only; small/groove/batched/served: the main workload and that leg")
     ap.add_argument("--small-reps", type=int, default=200)
     ap.add_argument("--batched-jobs", type=int, default=64)
     ap.add_argument("--served-jobs", type=int, default=24)
     ap.add_argument("--served-budget-gib", type=float, default=96.0)
+    ap.add_argument("--served-fill", type=int, default=1 << 20,
+                    help="server fill_pixels: least-remaining-work jobs first, this many pixels per round")
     ap.add_argument("--mode-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device to device three times (calibrates byte counters) and exit")
@@ -368,6 +478,14 @@ def main():
                          "per lane, 8 waves per SIMD) three times each with 64, 32, 16 and 1 active lanes "
                          "per wave, print the fastest launch times and exit")
     args = ap.parse_args()
+
+    if args.oracle_tile:
+        # child of cpu_baseline: the oracle alone (no GPU touched)
+        from paper_1811_02357_amd import scenes
+        sc = scenes.fbm_terrain(seed=0, **WORKLOADS[args.workload])
+        seg, dt, threads = _oracle_tile_solve(sc, args.oracle_tile)
+        print(json.dumps({"segments": seg, "s": dt, "threads": threads}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -476,23 +594,39 @@ def main():
         "counters_per_step": {"segments": cnt[0], "hits": cnt[1], "escapes": cnt[2], "continuations": cnt[3]},
         "trace_kernel": {"launches": launches, "avg_ms": per_launch_ms,
                          "share_of_step": trace_ms / sum(step_ms)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if args.flat else profiled_traffic(args.workload)},
+        # the tracer's bytes by the algorithmic yardstick against HBM; the
+        # fabric traffic (copy-calibrated FETCH_SIZE + WRITE_SIZE, MALL hits
+        # included) from the counter profile of the same kernel
+        "hbm_yardstick": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch,
+                          "fabric_bytes_per_launch": None if args.flat else profiled_traffic(args.workload)},
     }
     prof = None if args.flat else profiled_values(args.workload)
-    if prof is not None:
-        # the binding limit: VALU issue (counted instructions of the profiled
-        # kernel over this run's launch time)
-        line["valu_issue"] = {"wave_instructions_per_launch": prof["valu"],
-                              "per_s": prof["valu"] / (per_launch_ms / 1e3), "peak_per_s": VALU_ISSUE_PEAK,
-                              "frac": prof["valu"] / (per_launch_ms / 1e3) / VALU_ISSUE_PEAK,
-                              "lane_utilisation": prof["lanes"],
-                              "source": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
+    peak = probe_peak()
+    if prof is not None and peak is not None:
+        # The binding limit is VALU issue: the counted wave64 VALU instructions of
+        # the profiled kernel over this run's launch time, each carrying the
+        # profile's mean active lanes.  The roofline is in lane-operations
+        # (instructions x active lanes) against the measured full-lane peak.
+        issue = prof["valu"] / (per_launch_ms / 1e3)
+        lane_ops = issue * 64 * prof["lanes"] / 1e12
+        line["roofline"] = {"bound": "alu", "achieved": lane_ops, "peak": peak * 64 / 1e12,
+                            "unit": "Tlane-op/s", "frac": lane_ops / (peak * 64 / 1e12),
+                            "traffic": prof["traffic"]}
+        line["valu"] = {"wave_instructions_per_launch": prof["valu"], "issue_per_s": issue,
+                        "probe_peak_issue_per_s": peak, "nominal_issue_per_s": VALU_ISSUE_NOMINAL,
+                        "issue_ratio_to_probe": issue / peak, "lane_utilisation": prof["lanes"],
+                        "sources": [os.path.relpath(TRAFFIC_PROFILE, ROOT), os.path.relpath(VALU_PROBE_PROFILE, ROOT)]}
+    else:
+        line["roofline"] = dict(line["hbm_yardstick"], bound="hbm",
+                                traffic=line["hbm_yardstick"]["fabric_bytes_per_launch"])
     del ws, out, I0
     torch.cuda.empty_cache()
     if args.mode in ("all", "small"):
         line["small"] = small_leg(args, dev)
+    if args.mode in ("all", "groove"):
+        line["groove512"] = groove_leg(args, dev)
+        torch.cuda.empty_cache()
     if args.mode in ("all", "batched"):
         line["batched"] = batched_leg(args, dev)
         torch.cuda.empty_cache()

@@ -290,10 +290,11 @@ int irtps_batch_solve(int32_t n, const irtps_problem* problems, const irtps_para
 /* A server runs reconstructions as they arrive (continuous batching): a
  * scheduler thread admits queued jobs in FIFO order when their workspace
  * footprint fits in the device memory the caller handed over, gives new jobs
- * their t = 0 steps, and advances every resident job by one IRT iteration in
- * the same set of launches (irtps_batch_solve's engine), so jobs join and leave
- * at iteration boundaries.  Each job's outputs are bit-identical to
- * irtps_solve of that job.  The server reads the job's device inputs and writes
+ * their t = 0 steps, and advances resident jobs by one IRT iteration per round
+ * in one set of launches (irtps_batch_solve's engine): every resident job, or,
+ * with fill_pixels, those with the least remaining work, enough of them to fill
+ * the GPU.  Jobs join and leave at iteration boundaries.  Each job's outputs
+ * are bit-identical to irtps_solve of that job.  The server reads the job's device inputs and writes
  * its outputs until the job is DONE, FAILED or CANCELLED; host arrays are
  * copied at submission.  All calls are thread-safe. */
 typedef struct irtps_server irtps_server;
@@ -305,7 +306,11 @@ typedef struct irtps_server_cfg {
     uint64_t table_bytes;      /* head of the workspace kept for job and tile tables
                                   (0: workspace/64, at least 1 MiB) */
     int32_t reserved;          /* must be 0 */
-    int32_t reserved2;
+    int32_t fill_pixels;       /* 0: every resident job advances one iteration per round;
+                                  > 0: the jobs with the least remaining work (iterations left
+                                  x pixels x spp x bounces) advance first, and a round takes jobs
+                                  in that order until their pixels reach fill_pixels (at least
+                                  one job); admission stays FIFO by footprint */
 } irtps_server_cfg;
 
 enum { IRTPS_JOB_QUEUED = 0, IRTPS_JOB_RUNNING = 1, IRTPS_JOB_DONE = 2, IRTPS_JOB_FAILED = 3,

@@ -189,7 +189,22 @@ bool irtps_server::step() {
             resident.push_back(J.id);
             queue.pop_front();
         }
-        for (uint64_t id : resident) {
+        // Which resident jobs advance this round: all of them, or (fill policy)
+        // those with the least remaining work, in that order, until their
+        // pixels reach cfg.fill_pixels, so that a round is no longer than it
+        // must be to fill the GPU and short jobs are not held behind the
+        // iterations of long ones.
+        std::vector<uint64_t> order(resident.begin(), resident.end());
+        if (cfg.fill_pixels > 0) {
+            auto remaining = [&](uint64_t id) {
+                const Job& J = jobs[id];
+                return (double)(J.t_last - J.t) * J.pr.width * J.pr.height * J.pa.spp * std::max(J.pa.bounces, 1);
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](uint64_t a, uint64_t b) { return remaining(a) < remaining(b); });
+        }
+        long long picked_px = 0;
+        for (uint64_t id : order) {
             Job& J = jobs[id];
             kern::JobDesc D;
             const int rc = eng::fill_job(D, J.pr, J.pa, J.out, base + table_bytes + J.offset);
@@ -201,10 +216,12 @@ bool irtps_server::step() {
                 fresh.push_back(D);
                 fresh_ids.push_back(id);
             }
-            if (J.t < J.t_last) {
+            const bool room = cfg.fill_pixels <= 0 || running.empty() || picked_px < cfg.fill_pixels;
+            if (J.t < J.t_last && room) {
                 D.t = J.t;
                 running.push_back(D);
                 running_ids.push_back(id);
+                picked_px += (long long)J.pr.width * J.pr.height;
             }
         }
         if (fresh.empty() && running.empty()) {
@@ -306,7 +323,8 @@ void irtps_server::run() {
 extern "C" {
 
 int irtps_server_create(const irtps_server_cfg* cfg, void* ws_dev, size_t ws_bytes, irtps_server** out) {
-    if (!cfg || !out || cfg->max_resident_jobs < 0 || cfg->reserved != 0 || (cfg->dry_run != 0 && cfg->dry_run != 1))
+    if (!cfg || !out || cfg->max_resident_jobs < 0 || cfg->reserved != 0 || cfg->fill_pixels < 0 ||
+        (cfg->dry_run != 0 && cfg->dry_run != 1))
         return IRTPS_ERR_INVALID_ARG;
     if (cfg->dry_run == 0 && (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign))) return IRTPS_ERR_WORKSPACE;
     const size_t tables = cfg->table_bytes ? align_up(cfg->table_bytes) : align_up(std::max<size_t>(ws_bytes / 64, 1 << 20));

@@ -68,7 +68,7 @@ TUNE_CANDIDATES = 16
 
 class ServerCfg(ct.Structure):
     _fields_ = [("max_resident_jobs", _i32), ("dry_run", _i32), ("table_bytes", _u64),
-                ("reserved", _i32), ("reserved2", _i32)]
+                ("reserved", _i32), ("fill_pixels", _i32)]
 
 
 class JobStatus(ct.Structure):
@@ -477,14 +477,15 @@ class Server:
     job's output tensors are returned by outputs(id) and are valid once wait(id)
     reports JOB_DONE.  dry_run=True schedules without launching kernels."""
 
-    def __init__(self, budget_bytes, device=None, max_resident_jobs=0, dry_run=False, table_bytes=0):
+    def __init__(self, budget_bytes, device=None, max_resident_jobs=0, dry_run=False, table_bytes=0,
+                 fill_pixels=0):
         self.device = device
         self.ws = None
         ptr = None
         if not dry_run:
             self.ws = torch.empty(int(budget_bytes), dtype=torch.uint8, device=device)
             ptr = ct.c_void_p(self.ws.data_ptr())
-        cfg = ServerCfg(max_resident_jobs, 1 if dry_run else 0, table_bytes, 0, 0)
+        cfg = ServerCfg(max_resident_jobs, 1 if dry_run else 0, table_bytes, 0, int(fill_pixels))
         h = ct.c_void_p()
         _check("irtps_server_create", lib().irtps_server_create(ct.byref(cfg), ptr, int(budget_bytes), ct.byref(h)))
         self.h = h

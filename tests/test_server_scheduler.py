@@ -169,3 +169,30 @@ def test_cancel_of_only_job_wakes_its_waiter():
         assert srv.stats()["cancelled"] == 40
     finally:
         srv.close()
+
+
+def test_fill_policy_runs_short_jobs_first():
+    """With fill_pixels, a round advances the resident jobs with the least
+    remaining work until their pixels reach the target: a short job submitted
+    behind a long one (both resident) finishes first, and every job still
+    completes with all its iterations."""
+    srv = irtps.Server(256 << 20, dry_run=True, fill_pixels=64 * 64)
+    try:
+        rc, big = _submit_dry(srv, 64, T=200)
+        assert rc == 0
+        time.sleep(0.01)
+        rc, small = _submit_dry(srv, 64, T=3)
+        assert rc == 0
+        sb, ss = srv.wait(big, 60.0), srv.wait(small, 60.0)
+        assert sb.state == ss.state == irtps.JOB_DONE
+        assert sb.iteration == 200 and ss.iteration == 3
+        assert ss.end_s < sb.end_s
+        # with fill_pixels = 64^2 a round takes one 64^2 job: the big job made no
+        # progress while the small one ran, so it ends well after it
+        assert sb.end_s - ss.end_s > 0.02
+    finally:
+        srv.close()
+    L = irtps.lib()
+    h = ct.c_void_p()
+    cfg = irtps.ServerCfg(0, 1, 0, 0, -1)
+    assert L.irtps_server_create(ct.byref(cfg), None, 1 << 20, ct.byref(h)) == 1  # negative fill refused
