@@ -800,7 +800,30 @@ static void mg_vcycle(const mg_level* lv, int nlev, int l, int W0, int H0,
     mg_smooth(L, W0, H0, X[l], b[l], 2);
 }
 
-void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles, float* Hout) {
+/* Right-hand side of the normal equations for explicit edge targets: tx at
+ * [j][i] for the edge (i,j)-(i+1,j), ty at [j][i] for (i,j)-(i,j+1). */
+static void rhs_from_targets(int W, int Hh, const float* tx, const float* ty, float* b) {
+    for (int j = 0; j < Hh; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t v = (size_t)j * W + i;
+            float acc = 0.0f;
+            if (i > 0) acc = acc + tx[v - 1];
+            if (i < W - 1) acc = acc - tx[v];
+            if (j > 0) acc = acc + ty[v - W];
+            if (j < Hh - 1) acc = acc - ty[v];
+            b[v] = acc;
+        }
+}
+
+/* Huber shrinkage of an edge residual: the part of r beyond +-delta. */
+static float shrink(float r, float delta) {
+    if (r > delta) return r - delta;
+    if (r < -delta) return r + delta;
+    return 0.0f;
+}
+
+static void integrate_impl(int W, int Hh, const float* n, const float* Hinit, int cycles, float delta,
+                           int rounds, int rcycles, float* Hout) {
     const size_t npx = (size_t)W * Hh;
     float* pg = (float*)malloc(sizeof(float) * npx);
     float* qg = (float*)malloc(sizeof(float) * npx);
@@ -839,6 +862,34 @@ void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles,
         }
     if (Hinit) memcpy(X[0], Hinit, sizeof(float) * npx);
     for (int c = 0; c < cycles; ++c) mg_vcycle(lv, nlev, 0, W, Hh, X, b, r);
+    if (rounds > 0) {
+        /* Huber M-estimator by half-quadratic splitting: the Huber cost of an edge
+         * residual is the least, over an offset z, of (r - z)^2 / 2 + delta |z|.
+         * Alternately z = shrink(r) on every edge for the current surface, and
+         * more V-cycles on the least-squares problem whose edge targets are
+         * moved by z.  Both steps lower the joint (convex) cost. */
+        float* tx = (float*)calloc(npx, sizeof(float));
+        float* ty = (float*)calloc(npx, sizeof(float));
+        for (int rd = 0; rd < rounds; ++rd) {
+            const float* H = X[0];
+            for (int j = 0; j < Hh; ++j)
+                for (int i = 0; i < W; ++i) {
+                    const size_t v = (size_t)j * W + i;
+                    if (i < W - 1) {
+                        const float g = (pg[v] + pg[v + 1]) * 0.5f;
+                        tx[v] = g + shrink((H[v + 1] - H[v]) - g, delta);
+                    }
+                    if (j < Hh - 1) {
+                        const float g = (qg[v] + qg[v + W]) * 0.5f;
+                        ty[v] = g + shrink((H[v + W] - H[v]) - g, delta);
+                    }
+                }
+            rhs_from_targets(W, Hh, tx, ty, b[0]);
+            for (int c = 0; c < rcycles; ++c) mg_vcycle(lv, nlev, 0, W, Hh, X, b, r);
+        }
+        free(tx);
+        free(ty);
+    }
     /* the minimum is taken over X + 0, so that a -0 and a +0 count as one zero */
     float mn = X[0][0] + 0.0f;
     for (size_t v = 1; v < npx; ++v) {
@@ -853,6 +904,20 @@ void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles,
     free(r);
     free(pg);
     free(qg);
+}
+
+void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles, float* Hout) {
+    integrate_impl(W, Hh, n, Hinit, cycles, 0.0f, 0, 0, Hout);
+}
+
+/* Robust integration (the M-estimator of Sec. IV, stage 1): or_integrate's
+ * `cycles` V-cycles, then `rounds` rounds of the Huber M-estimator (threshold
+ * delta on the edge residual H_b - H_a - g, pixel units) by half-quadratic
+ * splitting, each new edge targets g + shrink(residual) and `rcycles` more
+ * V-cycles; then min(H) = 0. */
+void or_integrate_robust(int W, int Hh, const float* n, const float* Hinit, int cycles, float delta,
+                         int rounds, int rcycles, float* Hout) {
+    integrate_impl(W, Hh, n, Hinit, cycles, delta, rounds, rcycles, Hout);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -896,7 +961,10 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
     float* Hn = (float*)malloc(sizeof(float) * npx);
     memcpy(A, I0, sizeof(float) * npx * K * C);
     or_ps_solve(W, Hh, C, K, M, A, n, rho);
-    or_integrate(W, Hh, n, NULL, cycles_cold, H);
+    if (flags & OR_FLAG_ROBUST_INTEGRATION)
+        or_integrate_robust(W, Hh, n, NULL, cycles_cold, OR_ROBUST_DELTA, OR_ROBUST_ROUNDS, OR_ROBUST_CYCLES, H);
+    else
+        or_integrate(W, Hh, n, NULL, cycles_cold, H);
     if (E) memset(E, 0, sizeof(float) * npx * K * C);
     for (int t = 0; t < T; ++t) {
         or_direct(W, Hh, K, H, n, l, s, S);
@@ -908,7 +976,10 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
             or_ps_solve_masked(W, Hh, C, K, l, s, A, S, n, rho);
         else
             or_ps_solve(W, Hh, C, K, M, A, n, rho);
-        or_integrate(W, Hh, n, H, cycles_warm, Hn);
+        if (flags & OR_FLAG_ROBUST_INTEGRATION)
+            or_integrate_robust(W, Hh, n, H, cycles_warm, OR_ROBUST_DELTA, OR_ROBUST_ROUNDS, OR_ROBUST_CYCLES, Hn);
+        else
+            or_integrate(W, Hh, n, H, cycles_warm, Hn);
         /* D_H: the largest change of the surface in this iteration */
         float dh = 0.0f;
         for (size_t p = 0; p < npx; ++p) {

@@ -33,7 +33,13 @@ extern "C" {
 
 enum { OR_TAG_SOLVE = 0, OR_TAG_RENDER = 1 };
 enum { OR_RHO_FIT = 0, OR_RHO_PREV = 1 };
-enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2, OR_FLAG_SHADOW_AWARE_PS = 8 };
+enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2, OR_FLAG_SHADOW_AWARE_PS = 8,
+       OR_FLAG_ROBUST_INTEGRATION = 32 };
+/* The loop's robust integration: Huber threshold (pixel units of the edge
+ * residual), rounds, and V-cycles per round. */
+#define OR_ROBUST_DELTA 0.1f
+#define OR_ROBUST_ROUNDS 6
+#define OR_ROBUST_CYCLES 2
 enum { OR_MISS = 0, OR_HIT = 1 };
 
 /* counters of one trace: [0] segments, [1] hits, [2] escapes, [3] continuations */
@@ -102,6 +108,13 @@ void or_correct(int W, int Hh, int C, int K, int rho_mode, int flags,
 /* Least-squares integration of the normal field into heights, min(H) = 0. */
 void or_integrate(int W, int Hh, const float* n, const float* Hinit, int cycles, float* H);
 
+/* Robust integration (Huber M-estimator): or_integrate's V-cycles, then
+ * `rounds` rounds of half-quadratic splitting, each moving every edge target g
+ * by shrink(H_b - H_a - g, delta) (the part of the residual beyond +-delta)
+ * for the current surface and running `rcycles` more V-cycles; min(H) = 0. */
+void or_integrate_robust(int W, int Hh, const float* n, const float* Hinit, int cycles, float delta,
+                         int rounds, int rcycles, float* H);
+
 /* Forward render I0 = rho (S + G) of a ground-truth surface (tag RENDER). */
 int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
               const float* rho, const float* l, const float* s, const float* env,
@@ -112,8 +125,9 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
  * max_p |H_{t+1}(p) - H_t(p)| < stop_tol (last paragraph of Sec. IV).  With
  * OR_FLAG_SHADOW_AWARE_PS the PS after each correction keeps, per pixel, only
  * the lights that reach it (or_ps_solve_masked with that iteration's S); the
- * first PS of the input images uses every light.  Returns 0 or -1 (singular
- * lights). */
+ * first PS of the input images uses every light.  With OR_FLAG_ROBUST_INTEGRATION
+ * every integration is or_integrate_robust (OR_ROBUST_DELTA, _ROUNDS, _CYCLES).
+ * Returns 0 or -1 (singular lights). */
 int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
              const float* s, const float* env, int He, int We, int spp, int B,
              int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,

@@ -16,7 +16,8 @@ _LIB = None
 
 TAG_SOLVE, TAG_RENDER = 0, 1
 RHO_FIT, RHO_PREV = 0, 1
-FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_SHADOW_AWARE_PS = 1, 2, 8
+FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_SHADOW_AWARE_PS, FLAG_ROBUST_INTEGRATION = 1, 2, 8, 32
+ROBUST_DELTA, ROBUST_ROUNDS, ROBUST_CYCLES = 0.1, 6, 2
 
 _f = ct.POINTER(ct.c_float)
 _u32 = ct.POINTER(ct.c_uint32)
@@ -63,6 +64,7 @@ def lib():
         L.or_trace_at.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
                                   + [ct.c_int] * 3 + [ct.c_longlong, _pll, _f, ct.POINTER(Counters)])
         L.or_integrate.argtypes = [ct.c_int, ct.c_int, _f, _f, ct.c_int, _f]
+        L.or_integrate_robust.argtypes = [ct.c_int, ct.c_int, _f, _f, ct.c_int, ct.c_float, ct.c_int, ct.c_int, _f]
         L.or_render.argtypes = ([ct.c_int] * 4 + [_f] * 6 + [ct.c_int] * 4 + [ct.c_uint64]
                                 + [_f, ct.POINTER(Counters)])
         L.or_render.restype = ct.c_int
@@ -297,6 +299,14 @@ def integrate(n, Hinit=None, cycles=8):
     Hh, W = n.shape[:2]
     H = np.zeros((Hh, W), np.float32)
     lib().or_integrate(W, Hh, _p(n), _p(_f32(Hinit)), cycles, _p(H))
+    return H
+
+
+def integrate_robust(n, Hinit=None, cycles=8, delta=ROBUST_DELTA, rounds=ROBUST_ROUNDS, rcycles=ROBUST_CYCLES):
+    n = _f32(n)
+    Hh, W = n.shape[:2]
+    H = np.zeros((Hh, W), np.float32)
+    lib().or_integrate_robust(W, Hh, _p(n), _p(_f32(Hinit)), cycles, float(delta), rounds, rcycles, _p(H))
     return H
 
 

@@ -1002,3 +1002,79 @@ def test_shadow_aware_ps_recovers_normals_where_three_lights_remain():
     # rounding of the per-pixel matrix
     full = kept.all(-1)
     assert angle_deg(n[full], n0[full]).max() < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Robust integration (Sec. IV stage 1, "M-estimator"): the Huber M-estimator by
+# half-quadratic splitting on top of the least-squares multigrid.
+def _edge_targets(n):
+    n = n.astype(np.float64)
+    nz = np.maximum(n[..., 2], 0.05)
+    p, q = -n[..., 0] / nz, -n[..., 1] / nz
+    return 0.5 * (p[:, :-1] + p[:, 1:]), 0.5 * (q[:-1] + q[1:])
+
+
+def _huber_energy(H, gx, gy, delta):
+    H = H.astype(np.float64)
+    r = np.concatenate([((H[:, 1:] - H[:, :-1]) - gx).ravel(), ((H[1:] - H[:-1]) - gy).ravel()])
+    a = np.abs(r)
+    return float(np.where(a <= delta, 0.5 * r * r, delta * a - 0.5 * delta * delta).sum())
+
+
+def _plane_with_outliers(W=40, Hh=36):
+    """Normals of the plane H = 0.3 x - 0.2 y with a 2 x 2 block of wrong ones
+    (a specular spike: a 60 deg tilt towards +x)."""
+    gx = np.full((Hh, W), 0.3)
+    gy = np.full((Hh, W), -0.2)
+    n = _normals_of_gradient(gx, gy).astype(np.float64)
+    n[17:19, 19:21] = [math.sin(math.radians(60)), 0.0, math.cos(math.radians(60))]
+    yy, xx = np.mgrid[0:Hh, 0:W].astype(np.float64)
+    ref = 0.3 * xx - 0.2 * yy
+    return n.astype(F32), ref - ref.min()
+
+
+def test_robust_integration_huber_energy_never_rises():
+    """The Huber cost of a residual r is min over z of (r - z)^2 / 2 + delta |z|,
+    attained at z = shrink(r).  A round sets z for the current surface (the
+    joint cost then equals the Huber energy) and V-cycles lower the joint cost in
+    H for that z; so the Huber energy of the surface never rises from round to
+    round, and it falls while outliers remain."""
+    n, _ = _plane_with_outliers()
+    gx, gy = _edge_targets(n)
+    e = [_huber_energy(O.integrate_robust(n, None, 8, delta=0.5, rounds=r, rcycles=2), gx, gy, 0.5)
+         for r in range(0, 7)]
+    for a, b in zip(e, e[1:]):
+        assert b <= a * (1 + 1e-6) + 1e-6, e
+    assert e[-1] < 0.9 * e[0], e
+
+
+def test_robust_integration_without_outliers_is_least_squares():
+    """With a threshold no residual reaches, every shrinkage is 0, the edge
+    targets are the least-squares ones and the extra V-cycles stay at the exact
+    least-squares surface (binary64 sparse solve) within 1e-3 px; with no round
+    the result is or_integrate's, bit for bit."""
+    rng = np.random.default_rng(12)
+    for shape in [(24, 31), (9, 40)]:
+        nn = rng.standard_normal((*shape, 3))
+        nn[..., 2] = np.abs(nn[..., 2]) + 1.0
+        nn = (nn / np.linalg.norm(nn, axis=-1, keepdims=True)).astype(F32)
+        H = O.integrate_robust(nn, None, 8, delta=1e30, rounds=3, rcycles=2)
+        assert np.abs(H - _exact_lsq(nn)).max() < 1e-3
+        assert np.array_equal(O.integrate_robust(nn, None, 8, 0.5, 0, 2), O.integrate(nn, None, 8))
+
+
+def test_robust_integration_suppresses_an_outlier_block():
+    """A plane whose normals are wrong in one 2 x 2 block: least squares spreads
+    the wrong gradients over a wide neighbourhood, the Huber solution keeps the
+    plane away from the block.  A Huber edge pulls with at most delta instead of
+    its residual (here about 0.7), so with delta = 0.1 the error more than 4
+    samples from the block is at most a quarter of the L2 error there."""
+    n, ref = _plane_with_outliers()
+    l2 = O.integrate(n, None, 8)
+    rb = O.integrate_robust(n, None, 8, delta=0.1, rounds=8, rcycles=2)
+    Hh, W = n.shape[:2]
+    yy, xx = np.mgrid[0:Hh, 0:W]
+    far = (np.abs(yy - 17.5) > 4) | (np.abs(xx - 19.5) > 4)
+    e_l2 = np.abs((l2 - l2[0, 0]) - (ref - ref[0, 0]))[far].max()
+    e_rb = np.abs((rb - rb[0, 0]) - (ref - ref[0, 0]))[far].max()
+    assert e_l2 > 0.2 and e_rb < 0.25 * e_l2, (e_l2, e_rb)
