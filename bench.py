@@ -438,7 +438,9 @@ def served_leg(args, dev):
     res = {"jobs": n, "arrival_rate_per_s": 20.0, "offered_s": float(arr[-1]), "segments": seg,
            "plain_fifo": summary(plain_lat, plain_span)}
     same_all = True
-    for name, fill in (("served", args.served_fill), ("served_every_job", 0)):
+    runs = [("served", args.served_fill), ("served_every_job", 0)]
+    runs += [(f"served_fill_{f}", f) for f in args.served_extra_fills]
+    for name, fill in runs:
         log(f"bench: served leg, continuous-batching server (fill_pixels {fill})")
         lat, span, same, stats = replay_server(fill)
         same_all = same_all and same
@@ -448,6 +450,63 @@ def served_leg(args, dev):
     res["equal_to_plain"] = bool(same_all)
     res["speedup"] = plain_span / res["served"]["span_s"]
     return res
+
+
+def served_sweep(args, dev):
+    """Sustainable arrival rate of the server on the served workload law: for
+    rising Poisson rates, jobs arrive for `sweep_window` seconds (cycling
+    through a pool of `sweep_pool` jobs of the law, inputs rendered on the GPU
+    beforehand) and the sweep stops at the first rate the GPU cannot keep up
+    with: fewer than 95% of the arrival rate completed per second over the
+    trial, or latencies of the last third of the jobs more than twice those of
+    the first third (a growing backlog)."""
+    import numpy as np
+    import torch
+    from paper_1811_02357_amd import irtps, scenes
+    log(f"bench: served sweep, generating a pool of {args.sweep_pool} jobs")
+    pool = [_job(scenes.served_job(j), dev, irtps, torch, np) for j in range(args.sweep_pool)]
+    torch.cuda.synchronize()
+    budget = int(args.served_budget_gib * (1 << 30))
+    trials = []
+    for rate in args.sweep_rates:
+        arr = scenes.served_arrivals(rate, args.sweep_window, seed=1)
+        srv = irtps.Server(budget, device=dev, fill_pixels=args.served_fill)
+        try:
+            ids = []
+            t0 = time.perf_counter()
+            for k, a in enumerate(arr):
+                now = time.perf_counter() - t0
+                if now < a:
+                    time.sleep(a - now)
+                job = pool[k % len(pool)]
+                K, C, Hh, W = job["images"].shape
+                out = {"normals": torch.empty((Hh, W, 3), device=dev), "albedo": torch.empty((C, Hh, W), device=dev),
+                       "depth": torch.empty((Hh, W), device=dev), "indirect": None, "counters": None}
+                ids.append(srv.submit(job, outs=out))
+            sts = [srv.wait(i, 600.0) for i in ids]
+        finally:
+            srv.close()
+        del srv  # its workspace and the trial's outputs go before the next trial's
+        torch.cuda.empty_cache()
+        ok = all(st.state == irtps.JOB_DONE for st in sts)
+        lat = np.asarray([st.end_s - st.submit_s for st in sts])
+        span = max(st.end_s for st in sts) - min(st.submit_s for st in sts)
+        third = max(len(lat) // 3, 1)
+        growth = float(np.median(lat[-third:]) / max(np.median(lat[:third]), 1e-9))
+        done_rate = len(lat) / span
+        sustained = ok and done_rate >= 0.95 * len(arr) / args.sweep_window and growth <= 2.0
+        trials.append({"rate_per_s": rate, "jobs": len(arr), "completed_per_s": done_rate,
+                       "p50_latency_s": float(np.quantile(lat, 0.5)), "p99_latency_s": float(np.quantile(lat, 0.99)),
+                       "latency_growth_last_vs_first_third": growth, "sustained": bool(sustained)})
+        log(f"bench: served sweep rate {rate}/s: {len(arr)} jobs, {done_rate:.2f} done/s, "
+            f"p50 {np.quantile(lat, 0.5):.3f} s, p99 {np.quantile(lat, 0.99):.3f} s, growth {growth:.2f}")
+        torch.cuda.empty_cache()
+        if not sustained:
+            break
+    ok_rates = [t["rate_per_s"] for t in trials if t["sustained"]]
+    return {"window_s": args.sweep_window, "pool": len(pool), "fill_pixels": args.served_fill,
+            "trials": trials, "sustainable_rate_per_s": max(ok_rates) if ok_rates else None,
+            "first_unsustained_rate_per_s": next((t["rate_per_s"] for t in trials if not t["sustained"]), None)}
 
 
 def main():
@@ -462,14 +521,22 @@ def main():
     ap.add_argument("--oracle-tile", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--groove-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="all", choices=["all", "plain", "small", "groove", "batched", "served"],
-                    help="plain: the main workload only; small/groove/batched/served: the main workload and that leg")
+    ap.add_argument("--mode", default="all",
+                    choices=["all", "plain", "small", "groove", "batched", "served", "served-sweep"],
+                    help="plain: the main workload only; small/groove/batched/served/served-sweep: the main "
+                         "workload and that leg (served-sweep is not part of all)")
+    ap.add_argument("--sweep-rates", type=lambda v: [float(x) for x in v.split(",") if x],
+                    default=[6.0, 9.0, 12.0, 15.0, 18.0, 21.0, 24.0, 27.0])
+    ap.add_argument("--sweep-window", type=float, default=5.0)
+    ap.add_argument("--sweep-pool", type=int, default=12)
     ap.add_argument("--small-reps", type=int, default=200)
     ap.add_argument("--batched-jobs", type=int, default=64)
     ap.add_argument("--served-jobs", type=int, default=24)
     ap.add_argument("--served-budget-gib", type=float, default=96.0)
-    ap.add_argument("--served-fill", type=int, default=1 << 20,
-                    help="server fill_pixels: least-remaining-work jobs first, this many pixels per round")
+    ap.add_argument("--served-fill", type=int, default=1 << 21,
+                    help="server fill_pixels: the oldest job, then least-remaining-work jobs, this many pixels per round")
+    ap.add_argument("--served-extra-fills", type=lambda v: [int(x) for x in v.split(",") if x], default=[],
+                    help="more fill_pixels values to replay the served trace with (comma-separated)")
     ap.add_argument("--mode-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device to device three times (calibrates byte counters) and exit")
@@ -632,6 +699,9 @@ def main():
         torch.cuda.empty_cache()
     if args.mode in ("all", "served"):
         line["served"] = served_leg(args, dev)
+        torch.cuda.empty_cache()
+    if args.mode == "served-sweep":
+        line["served_sweep"] = served_sweep(args, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on a tile")

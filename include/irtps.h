@@ -74,11 +74,15 @@ enum {
     IRTPS_FLAG_SHADOW_AWARE_PS = 8,    /* the PS after each correction keeps, per pixel, only the
                                           lights that reach it (irtps_ps_solve_masked with that
                                           iteration's direct irradiance); the first PS uses all */
-    IRTPS_FLAG_GRAPH = 16              /* irtps_solve only: capture the solve's launches in a
+    IRTPS_FLAG_GRAPH = 16,             /* irtps_solve only: capture the solve's launches in a
                                           hipGraph the first time, replay it on later calls with
                                           identical arguments (same pointers, lights, schedule);
                                           needs stop_tol = 0 and a stream other than the legacy
                                           default one; changes no result */
+    IRTPS_FLAG_ROBUST_INTEGRATION = 32 /* irtps_solve and irtps_solve_static only (the batched and
+                                          served engines refuse it): every integration is
+                                          irtps_integrate_robust with delta 0.1, 6 rounds of 2
+                                          V-cycles after the least-squares cycles */
 };
 
 /* Sample-stream tags (word 3 of the Philox counter). */
@@ -198,6 +202,19 @@ int irtps_integrate(int32_t W, int32_t H, const float* normals_dev,
                     const float* depth_init_dev, int32_t cycles, float* depth_dev,
                     void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Robust integration, the M-estimator of Sec. IV, stage 1: irtps_integrate's
+ * `cycles` least-squares V-cycles, then `rounds` rounds of the Huber
+ * M-estimator (threshold delta >= 0 on the edge residual H_b - H_a - g, g the
+ * least-squares edge target, pixel units) by half-quadratic splitting: each
+ * round moves every edge target to g + shrink(residual), shrink(r) being the
+ * part of r beyond +-delta for the current surface, and runs `rcycles` more
+ * V-cycles.  Result shifted to min 0.  rounds = 0 gives irtps_integrate.
+ * Workspace as irtps_integrate_workspace_bytes. */
+int irtps_integrate_robust(int32_t W, int32_t H, const float* normals_dev,
+                           const float* depth_init_dev, int32_t cycles, float delta,
+                           int32_t rounds, int32_t rcycles, float* depth_dev,
+                           void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Bytes of the min-max pyramid of a W x H surface. */
 int irtps_pyramid_bytes(int32_t W, int32_t H, size_t* bytes);
 /* Per level l, cell (cx, cy) spans samples [cx 2^l, (cx+1) 2^l] x [cy 2^l, (cy+1) 2^l]
@@ -292,8 +309,8 @@ int irtps_batch_solve(int32_t n, const irtps_problem* problems, const irtps_para
  * footprint fits in the device memory the caller handed over, gives new jobs
  * their t = 0 steps, and advances resident jobs by one IRT iteration per round
  * in one set of launches (irtps_batch_solve's engine): every resident job, or,
- * with fill_pixels, those with the least remaining work, enough of them to fill
- * the GPU.  Jobs join and leave at iteration boundaries.  Each job's outputs
+ * with fill_pixels, the oldest and those with the least remaining work, enough
+ * of them to fill the GPU.  Jobs join and leave at iteration boundaries.  Each job's outputs
  * are bit-identical to irtps_solve of that job.  The server reads the job's device inputs and writes
  * its outputs until the job is DONE, FAILED or CANCELLED; host arrays are
  * copied at submission.  All calls are thread-safe. */
@@ -307,10 +324,10 @@ typedef struct irtps_server_cfg {
                                   (0: workspace/64, at least 1 MiB) */
     int32_t reserved;          /* must be 0 */
     int32_t fill_pixels;       /* 0: every resident job advances one iteration per round;
-                                  > 0: the jobs with the least remaining work (iterations left
-                                  x pixels x spp x bounces) advance first, and a round takes jobs
-                                  in that order until their pixels reach fill_pixels (at least
-                                  one job); admission stays FIFO by footprint */
+                                  > 0: a round advances the oldest resident job, then the jobs
+                                  with the least remaining work (iterations left x pixels x spp
+                                  x bounces) in that order until their pixels reach fill_pixels;
+                                  admission stays FIFO by footprint */
 } irtps_server_cfg;
 
 enum { IRTPS_JOB_QUEUED = 0, IRTPS_JOB_RUNNING = 1, IRTPS_JOB_DONE = 2, IRTPS_JOB_FAILED = 3,

@@ -78,10 +78,17 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
     const bool cumulative = (pa->flags & IRTPS_FLAG_LITERAL_CUMULATIVE) != 0;
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(out->counters_dev);
 
+    kern::Robust robust;  // the M-estimator of stage 1: least squares, or Huber
+    if (pa->flags & IRTPS_FLAG_ROBUST_INTEGRATION) {
+        robust.delta = kern::kRobustDelta;
+        robust.rounds = kern::kRobustRounds;
+        robust.cycles = kern::kRobustCycles;
+    }
+
     if (cnt) HIP_TRY(kern::fill_u64_zero(cnt, IRTPS_NUM_COUNTERS, st));
     // t = 0: plain photometric stereo and integration (stage 1)
     HIP_TRY(kern::ps_solve(npx, C, K, M, pr->images_dev, out->normals_dev, out->albedo_dev, st));
-    HIP_TRY(kern::integrate(lay.plan, out->normals_dev, nullptr, cold, out->depth_dev, mg, st));
+    HIP_TRY(kern::integrate(lay.plan, out->normals_dev, nullptr, cold, out->depth_dev, mg, st, false, robust));
     if (out->indirect_dev) HIP_TRY(kern::fill_f32(out->indirect_dev, 0.0f, (long long)npx * K * C, st));
 
     const kern::SurfaceArgs sa = surface(W, H, out->depth_dev, pyr);
@@ -144,7 +151,8 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
             HIP_TRY(kern::ps_solve_masked(npx, C, K, M, Ls, A, S, out->normals_dev, out->albedo_dev, st));
         else
             HIP_TRY(kern::ps_solve(npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
-        HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st, stop));
+        HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, warm, out->depth_dev, mg, st, stop,
+                                robust));
         ++run;
         if (stop) {
             // the paper's stop rule: D_H = max |H_{t+1} - H_t| below the tolerance
@@ -297,6 +305,24 @@ int irtps_integrate(int32_t W, int32_t H, const float* normals_dev, const float*
         return IRTPS_ERR_WORKSPACE;
     HIP_TRY(kern::integrate(plan, normals_dev, depth_init_dev, cycles, depth_dev, static_cast<float*>(ws_dev),
                             reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_integrate_robust(int32_t W, int32_t H, const float* normals_dev, const float* depth_init_dev,
+                           int32_t cycles, float delta, int32_t rounds, int32_t rcycles, float* depth_dev,
+                           void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!dims_ok(W, H) || !normals_dev || !depth_dev || cycles < 0 || rounds < 0 || rcycles < 0 ||
+        !(delta >= 0.0f) || !(delta <= 3.0e38f))
+        return IRTPS_ERR_INVALID_ARG;
+    const kern::MgPlan plan = mg_plan(W, H);
+    if (!ws_dev || ws_bytes < sizeof(float) * (size_t)plan.total || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign))
+        return IRTPS_ERR_WORKSPACE;
+    kern::Robust robust;
+    robust.delta = delta;
+    robust.rounds = rounds;
+    robust.cycles = rcycles;
+    HIP_TRY(kern::integrate(plan, normals_dev, depth_init_dev, cycles, depth_dev, static_cast<float*>(ws_dev),
+                            reinterpret_cast<hipStream_t>(stream), false, robust));
     return IRTPS_OK;
 }
 

@@ -262,7 +262,7 @@ inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
         pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || !(pa->stop_tol >= 0.0f) ||
         !(pa->stop_tol <= 3.0e38f) ||
         (pa->flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_LITERAL_CUMULATIVE | IRTPS_FLAG_FLAT_TRAVERSAL |
-                       IRTPS_FLAG_SHADOW_AWARE_PS | IRTPS_FLAG_GRAPH)))
+                       IRTPS_FLAG_SHADOW_AWARE_PS | IRTPS_FLAG_GRAPH | IRTPS_FLAG_ROBUST_INTEGRATION)))
         return IRTPS_ERR_INVALID_ARG;
     return IRTPS_OK;
 }

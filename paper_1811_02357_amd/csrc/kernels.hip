@@ -733,6 +733,34 @@ __device__ __forceinline__ void mg_rhs_node(int v, int W, int Hh, const float* _
     b[v] = acc;
 }
 
+// Robust integration (Huber M-estimator by half-quadratic splitting): the
+// right-hand side for edge targets g + shrink(residual) against the current
+// level-0 surface X, shrink(r) being the part of r beyond +-delta.  An edge's
+// target depends on its two ends only, so both of its nodes compute the same
+// value.
+__device__ __forceinline__ float huber_shrink(float r, float delta) {
+    return r > delta ? r - delta : (r < -delta ? r + delta : 0.0f);
+}
+__device__ __forceinline__ float robust_target(const float* __restrict__ n, const float* __restrict__ X,
+                                               size_t a, size_t b, bool xedge, float delta) {
+    float pa, qa, pb, qb;
+    grad_at(n, a, pa, qa);
+    grad_at(n, b, pb, qb);
+    const float g = xedge ? (pa + pb) * 0.5f : (qa + qb) * 0.5f;
+    return g + huber_shrink((X[b] - X[a]) - g, delta);
+}
+__device__ __forceinline__ void mg_rhs_robust_node(int v, int W, int Hh, const float* __restrict__ n,
+                                                   const float* __restrict__ X, float delta,
+                                                   float* __restrict__ b) {
+    const int i = v % W, j = v / W;
+    float acc = 0.0f;
+    if (i > 0) acc = acc + robust_target(n, X, v - 1, v, true, delta);
+    if (i < W - 1) acc = acc - robust_target(n, X, v, v + 1, true, delta);
+    if (j > 0) acc = acc + robust_target(n, X, v - W, v, false, delta);
+    if (j < Hh - 1) acc = acc - robust_target(n, X, v, v + W, false, delta);
+    b[v] = acc;
+}
+
 // Edge weights of level `shift`: horizontal edges of row J carry the number of
 // finest rows in that aggregate, vertical edges of column I its column count.
 __device__ __forceinline__ float w_row(int H0, int shift, int J) {
@@ -1451,6 +1479,12 @@ __global__ void __launch_bounds__(256) k_mg_rhs(int W, int Hh, const float* __re
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < W * Hh) mg_rhs_node(v, W, Hh, n, b);
 }
+__global__ void __launch_bounds__(256) k_mg_rhs_robust(int W, int Hh, const float* __restrict__ n,
+                                                       const float* __restrict__ X, float delta,
+                                                       float* __restrict__ b) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < W * Hh) mg_rhs_robust_node(v, W, Hh, n, X, delta, b);
+}
 
 __global__ void __launch_bounds__(256) k_mg_smooth(int Wl, int Hl, int shift, int W0, int H0,
                                                    float* __restrict__ X, const float* __restrict__ b,
@@ -2039,7 +2073,7 @@ hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, f
 constexpr unsigned kMinKeyBlocks = 512;
 
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
-                     float* ws, hipStream_t st, bool measure_change) {
+                     float* ws, hipStream_t st, bool measure_change, const Robust& robust) {
     if (measure_change && Hinit != Hout) return hipErrorInvalidValue;
     const int W0 = plan.W[0], H0 = plan.H[0];
     const int npx = W0 * H0;
@@ -2066,7 +2100,7 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
     };
     // the plan chose the tail so that its levels fit the default 64 KiB of LDS
     if ((long long)sizeof(float) * mg_tail_floats(plan) > kMgTailLdsBytes) return hipErrorInvalidValue;
-    for (int c = 0; c < cycles; ++c) {
+    auto vcycle = [&]() {
         for (int l = 0; l < plan.tail; ++l) {
             smooth(l, 2);
             const int nc = plan.W[l + 1] * plan.H[l + 1];
@@ -2081,6 +2115,12 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
                                st, plan.W[l], plan.H[l], X[l], plan.W[l + 1], X[l + 1]);
             smooth(l, 2);
         }
+    };
+    for (int c = 0; c < cycles; ++c) vcycle();
+    for (int r = 0; r < robust.rounds; ++r) {
+        hipLaunchKernelGGL(k_mg_rhs_robust, dim3(blocks_for(npx, 256)), dim3(256), 0, st, W0, H0, n, X[0],
+                           robust.delta, b[0]);
+        for (int c = 0; c < robust.cycles; ++c) vcycle();
     }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, key, 0xffffffffu, 1);
     unsigned* change = measure_change ? change_key_of(plan, ws) : nullptr;

@@ -30,6 +30,7 @@ constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
 constexpr int kFlagShadowPs = 8;  // IRTPS_FLAG_SHADOW_AWARE_PS
+constexpr int kFlagRobust = 32;   // IRTPS_FLAG_ROBUST_INTEGRATION
 
 // Eq.4 solve matrix, rows x, y, z over the K lights (passed by value).
 struct PsMatrix {
@@ -186,11 +187,23 @@ hipError_t compose(int npx, int C, int K, const float* rho, const float* S, cons
 // Apron-max levels of P at pyr, then the block tables at pyr + quad_off.
 hipError_t build_pyramid(int W, int Hh, const float* H, const trv::Pyramid& P, float* pyr,
                          long long quad_off, hipStream_t st);
+// Robust integration: after the least-squares V-cycles, `rounds` rounds of the
+// Huber M-estimator (threshold delta), each a right-hand side from the shrunk
+// edge residuals and `cycles` more V-cycles.  rounds = 0: least squares.
+struct Robust {
+    float delta = 0.0f;
+    int rounds = 0;
+    int cycles = 0;
+};
+// The loop's robust integration (IRTPS_FLAG_ROBUST_INTEGRATION).
+constexpr float kRobustDelta = 0.1f;
+constexpr int kRobustRounds = 6;
+constexpr int kRobustCycles = 2;
 // With measure_change (Hinit == Hout), the largest |H_new - H_old| over the
 // nodes is left, as float bits, in uint32 [1] of the key area of ws
 // (change_key_of(plan, ws)).
 hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int cycles, float* Hout,
-                     float* ws, hipStream_t st, bool measure_change = false);
+                     float* ws, hipStream_t st, bool measure_change = false, const Robust& robust = Robust{});
 inline unsigned* change_key_of(const MgPlan& plan, float* ws) {
     return reinterpret_cast<unsigned*>(ws + plan.keyoff) + 1;
 }

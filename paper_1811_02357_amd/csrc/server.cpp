@@ -190,17 +190,21 @@ bool irtps_server::step() {
             queue.pop_front();
         }
         // Which resident jobs advance this round: all of them, or (fill policy)
-        // those with the least remaining work, in that order, until their
-        // pixels reach cfg.fill_pixels, so that a round is no longer than it
-        // must be to fill the GPU and short jobs are not held behind the
-        // iterations of long ones.
+        // the oldest one and then those with the least remaining work, in that
+        // order, until their pixels reach cfg.fill_pixels, so that a round is no
+        // longer than it must be to fill the GPU, short jobs are not held behind
+        // the iterations of long ones, and no job waits for ever.
         std::vector<uint64_t> order(resident.begin(), resident.end());
-        if (cfg.fill_pixels > 0) {
+        if (cfg.fill_pixels > 0 && !order.empty()) {
             auto remaining = [&](uint64_t id) {
                 const Job& J = jobs[id];
                 return (double)(J.t_last - J.t) * J.pr.width * J.pr.height * J.pa.spp * std::max(J.pa.bounces, 1);
             };
-            std::stable_sort(order.begin(), order.end(),
+            auto oldest = std::min_element(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+                return jobs[a].t_submit < jobs[b].t_submit;
+            });
+            std::iter_swap(order.begin(), oldest);
+            std::stable_sort(order.begin() + 1, order.end(),
                              [&](uint64_t a, uint64_t b) { return remaining(a) < remaining(b); });
         }
         long long picked_px = 0;

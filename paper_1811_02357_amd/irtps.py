@@ -23,6 +23,8 @@ OK = 0
 RHO_FIT, RHO_PREV = 0, 1
 FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL, FLAG_SHADOW_AWARE_PS = 1, 2, 4, 8
 FLAG_GRAPH = 16  # irtps_solve: capture once in a hipGraph, replay on identical calls
+FLAG_ROBUST_INTEGRATION = 32  # Huber M-estimator integration (plain solves only)
+ROBUST_DELTA, ROBUST_ROUNDS, ROBUST_CYCLES = 0.1, 6, 2  # the loop's robust integration
 TAG_SOLVE, TAG_RENDER = 0, 1
 NUM_COUNTERS = 5  # segments, hits, escapes, continuations, IRT iterations run
 
@@ -110,6 +112,7 @@ def lib():
             "irtps_probe_valu": [_i32, _i32, _i32, _vp, _vp],
             "irtps_integrate_workspace_bytes": [_i32, _i32, P(_sz)],
             "irtps_integrate": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp],
+            "irtps_integrate_robust": [_i32, _i32, _vp, _vp, _i32, ct.c_float, _i32, _i32, _vp, _vp, _sz, _vp],
             "irtps_pyramid_bytes": [_i32, _i32, P(_sz)],
             "irtps_build_pyramid": [_i32, _i32, _vp, _vp, _vp],
             "irtps_direct": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -330,6 +333,21 @@ def integrate(normals, depth_init=None, cycles=8, stream=None):
     _check("irtps_integrate", lib().irtps_integrate(
         W, H, _dev(normals, shape=(H, W, 3), name="normals"),
         _dev(depth_init, shape=(H, W), name="depth_init"), cycles, _dev(depth),
+        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return depth
+
+
+@_on_stream
+def integrate_robust(normals, depth_init=None, cycles=8, delta=ROBUST_DELTA, rounds=ROBUST_ROUNDS,
+                     rcycles=ROBUST_CYCLES, stream=None):
+    H, W = normals.shape[:2]
+    nb = _sz()
+    _check("irtps_integrate_workspace_bytes", lib().irtps_integrate_workspace_bytes(W, H, ct.byref(nb)))
+    ws = _alloc_ws(nb.value, normals.device)
+    depth = torch.empty((H, W), device=normals.device)
+    _check("irtps_integrate_robust", lib().irtps_integrate_robust(
+        W, H, _dev(normals, shape=(H, W, 3), name="normals"),
+        _dev(depth_init, shape=(H, W), name="depth_init"), cycles, float(delta), rounds, rcycles, _dev(depth),
         ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
     return depth
 

@@ -248,6 +248,22 @@ def test_integrate_stage(dev, shape):
     assert np.array_equal(H(warm), O.integrate(n, ref, 3))
 
 
+@pytest.mark.parametrize("shape,delta,rounds,rcycles", [((64, 64), 0.1, 6, 2), ((37, 61), 0.5, 3, 1),
+                                                        ((257, 129), 0.05, 4, 2), ((2, 300), 0.1, 2, 3)])
+def test_integrate_robust_stage(dev, shape, delta, rounds, rcycles):
+    say(f"case: integrate_robust {shape} delta={delta} rounds={rounds} rcycles={rcycles}")
+    rng = np.random.default_rng(shape[0] * 13 + shape[1])
+    n = rng.standard_normal((*shape, 3))
+    n[..., 2] = np.abs(n[..., 2]) + 0.3
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    n = n.astype(F32)
+    depth = irtps.integrate_robust(T(n, dev), None, 8, delta, rounds, rcycles)
+    ref = O.integrate_robust(n, None, 8, delta, rounds, rcycles)
+    assert np.array_equal(H(depth), ref)
+    warm = irtps.integrate_robust(T(n, dev), depth, 4, delta, rounds, rcycles)
+    assert np.array_equal(H(warm), O.integrate_robust(n, ref, 4, delta, rounds, rcycles))
+
+
 # ragged against the 8 x 32 tiles of the direct kernel: 61 x 37, 277 x 300, 53 x 97
 @pytest.mark.parametrize("name,make", SURFACES[1:], ids=[s[0] for s in SURFACES[1:]])
 def test_direct_stage(dev, name, make):
@@ -334,7 +350,8 @@ def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None, stop
     Tn = sc.iterations if T_ is None else T_
     ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, Tn,
                   seed=sc.seed, rho_mode=rho_mode,
-                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE | irtps.FLAG_SHADOW_AWARE_PS),
+                  flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE | irtps.FLAG_SHADOW_AWARE_PS
+                                 | irtps.FLAG_ROBUST_INTEGRATION),
                   stop_tol=stop_tol)
     out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
                       sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
@@ -437,6 +454,32 @@ def test_solve_shadow_aware(dev, case):
     ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags)
     _compare_solve(ref, got, case)
     assert np.array_equal(got["normals"], ref["normals"]) and np.array_equal(got["depth"], ref["depth"])
+
+
+# robust (Huber) integration in every integration of the loop, alone and with
+# shadow-aware PS; the batched engine refuses the flag
+@pytest.mark.parametrize("case", ["bowl64", "fbm160x120_shadow_aware"])
+def test_solve_robust_integration(dev, case):
+    say(f"case: solve with robust integration, {case}")
+    flags = irtps.FLAG_ROBUST_INTEGRATION
+    if case == "bowl64":
+        sc = scenes.bowl_64()
+    else:
+        flags |= irtps.FLAG_SHADOW_AWARE_PS
+        sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=16, env_shape=(16, 32),
+                                ptp=24.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+        sc.heights = np.ascontiguousarray(sc.heights[:120])
+        sc.normals = np.ascontiguousarray(sc.normals[:120])
+        sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    ref, got = _solve_both(sc, dev, flags=flags)
+    _compare_solve(ref, got, case)
+    assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["normals"], ref["normals"])
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 4, 1, seed=2)
+    job = dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+               env=T(sc.env, dev), spp=4, bounces=1, iterations=1, flags=flags)
+    with pytest.raises(irtps.IrtpsError) as e:
+        irtps.batch_solve([job])
+    assert e.value.status == 1
 
 
 @pytest.mark.parametrize("case", ["bowl64", "fbm160x120"])

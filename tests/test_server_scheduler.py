@@ -172,24 +172,28 @@ def test_cancel_of_only_job_wakes_its_waiter():
 
 
 def test_fill_policy_runs_short_jobs_first():
-    """With fill_pixels, a round advances the resident jobs with the least
-    remaining work until their pixels reach the target: a short job submitted
-    behind a long one (both resident) finishes first, and every job still
-    completes with all its iterations."""
-    srv = irtps.Server(256 << 20, dry_run=True, fill_pixels=64 * 64)
+    """With fill_pixels, a round advances the oldest resident job, then those
+    with the least remaining work until their pixels reach the target: short
+    jobs submitted behind a long one finish long before it, in order of their
+    work, and the long (oldest) job still advances every round."""
+    srv = irtps.Server(256 << 20, dry_run=True, fill_pixels=2 * 64 * 64)
     try:
-        rc, big = _submit_dry(srv, 64, T=200)
+        rc, big = _submit_dry(srv, 64, T=400)
         assert rc == 0
-        time.sleep(0.01)
-        rc, small = _submit_dry(srv, 64, T=3)
-        assert rc == 0
-        sb, ss = srv.wait(big, 60.0), srv.wait(small, 60.0)
-        assert sb.state == ss.state == irtps.JOB_DONE
-        assert sb.iteration == 200 and ss.iteration == 3
-        assert ss.end_s < sb.end_s
-        # with fill_pixels = 64^2 a round takes one 64^2 job: the big job made no
-        # progress while the small one ran, so it ends well after it
-        assert sb.end_s - ss.end_s > 0.02
+        time.sleep(0.005)
+        ids = []
+        for T_ in (40, 20, 3):
+            rc, j = _submit_dry(srv, 64, T=T_)
+            assert rc == 0
+            ids.append(j)
+        sts = [srv.wait(j, 60.0) for j in ids]
+        sb = srv.wait(big, 60.0)
+        assert sb.state == irtps.JOB_DONE and sb.iteration == 400
+        assert all(st.state == irtps.JOB_DONE for st in sts)
+        assert [st.iteration for st in sts] == [40, 20, 3]
+        # a round holds the big (oldest) job and one more: 3 finishes before 20
+        # before 40, all before the big one
+        assert sts[2].end_s < sts[1].end_s < sts[0].end_s < sb.end_s
     finally:
         srv.close()
     L = irtps.lib()
