@@ -678,6 +678,126 @@ void or_trace_at(int W, int Hh, int C, int K, const float* H, const float* n,
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's own variant of the tracer (Sec. IV, the tracing paragraph and
+ * Fig. 5): a single path per pixel (sample 0) that reflects exactly r - 1
+ * times and leaves for the environment on its r-th ray.  Such a pixel gets the
+ * environment colour through r reflections: the albedo products of the hits
+ * (c1, c1 c2, ... of Fig. 5) times pi L of the texel the r-th ray reaches.  A
+ * path that escapes earlier, or whose r-th ray hits the surface, leaves its
+ * pixel without a value.  The rays are the gather's sample 0, segments 1..r
+ * (same Philox counters), so where the r-th ray escapes the value equals the
+ * gather's with spp 1, B = r and no direct light. */
+void or_trace_exact_r(int W, int Hh, int C, const float* H, const float* n, const float* rho,
+                      const float* env, int He, int We, int r, uint64_t seed, int t, int tag,
+                      float* Er, unsigned char* valid) {
+    const size_t npx = (size_t)W * Hh;
+    const float hmax = max_height(H, npx);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long long pp = 0; pp < (long long)npx; ++pp) {
+        const size_t p = (size_t)pp;
+        float beta[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        int ci = (int)(p % W), cj = (int)(p / W);
+        const float* N = n + 3 * p;
+        int ok = 0;
+        for (int b = 1; b <= r; ++b) {
+            const uint32_t ctr[4] = {(uint32_t)p, 0u, (uint32_t)t * 256u + (uint32_t)b, (uint32_t)tag};
+            uint32_t rr[4];
+            or_philox4x32_10(ctr, key, rr);
+            float d[3];
+            or_sample_cosine(N, u24(rr[0]), u24(rr[1]), d);
+            int qi, qj;
+            if (!or_traverse(H, W, Hh, hmax, ci, cj, d, &qi, &qj)) {
+                if (b == r) {
+                    int er, ec;
+                    or_env_texel(d, He, We, &er, &ec);
+                    const float* L = env + ((size_t)er * We + ec) * C;
+                    for (int c = 0; c < C; ++c) Er[(size_t)c * npx + p] = beta[c] * (OR_PI * L[c]);
+                    ok = 1;
+                }
+                break;
+            }
+            if (b == r) break; /* the r-th ray met the surface */
+            const size_t q = (size_t)qj * W + qi;
+            for (int c = 0; c < C; ++c) beta[c] = beta[c] * rho[(size_t)c * npx + q];
+            ci = qi;
+            cj = qj;
+            N = n + 3 * q;
+        }
+        valid[p] = (unsigned char)ok;
+        if (!ok)
+            for (int c = 0; c < C; ++c) Er[(size_t)c * npx + p] = 0.0f;
+    }
+}
+
+/* Non-uniform interpolation of the missing pixels (the paper interpolates the
+ * pixels the r-ray images leave empty; it names no method): pull-push over a
+ * pyramid of 2 x 2 aggregates.  Pull: a coarse cell holds the weighted mean of
+ * its children that carry a value (weights = counts of valid pixels below them,
+ * children in the order (0,0), (1,0), (0,1), (1,1), ragged edges with the
+ * children that exist), and their summed weight.  Push: from the coarsest level
+ * down, a cell without a value takes its parent's.  Pixels with a value keep it;
+ * with no valid pixel at all every pixel gets 0.  E is [C][Hh][W]. */
+void or_fill_missing(int W, int Hh, int C, float* E, const unsigned char* valid) {
+    int lw[40], lh[40];
+    int nl = 1;
+    lw[0] = W;
+    lh[0] = Hh;
+    while ((lw[nl - 1] > 1 || lh[nl - 1] > 1) && nl < 40) {
+        lw[nl] = (lw[nl - 1] + 1) / 2;
+        lh[nl] = (lh[nl - 1] + 1) / 2;
+        ++nl;
+    }
+    float* v[40];
+    float* w[40];
+    for (int l = 0; l < nl; ++l) {
+        v[l] = (float*)calloc((size_t)lw[l] * lh[l] * C, sizeof(float));
+        w[l] = (float*)calloc((size_t)lw[l] * lh[l], sizeof(float));
+    }
+    const size_t npx = (size_t)W * Hh;
+    for (size_t p = 0; p < npx; ++p) {
+        w[0][p] = valid[p] ? 1.0f : 0.0f;
+        for (int c = 0; c < C; ++c) v[0][(size_t)c * npx + p] = valid[p] ? E[(size_t)c * npx + p] : 0.0f;
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        const size_t nf = (size_t)lw[l] * lh[l], ncs = (size_t)lw[l + 1] * lh[l + 1];
+        for (int J = 0; J < lh[l + 1]; ++J)
+            for (int I = 0; I < lw[l + 1]; ++I) {
+                const size_t u = (size_t)J * lw[l + 1] + I;
+                float den = 0.0f, num[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) {
+                        const int fi = 2 * I + di, fj = 2 * J + dj;
+                        if (fi >= lw[l] || fj >= lh[l]) continue;
+                        const size_t f = (size_t)fj * lw[l] + fi;
+                        const float wf = w[l][f];
+                        if (!(wf > 0.0f)) continue;
+                        for (int c = 0; c < C; ++c) num[c] = fmaf(wf, v[l][(size_t)c * nf + f], num[c]);
+                        den = den + wf;
+                    }
+                w[l + 1][u] = den;
+                for (int c = 0; c < C; ++c) v[l + 1][(size_t)c * ncs + u] = den > 0.0f ? num[c] / den : 0.0f;
+            }
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const size_t nf = (size_t)lw[l] * lh[l], ncs = (size_t)lw[l + 1] * lh[l + 1];
+        for (int j = 0; j < lh[l]; ++j)
+            for (int i = 0; i < lw[l]; ++i) {
+                const size_t f = (size_t)j * lw[l] + i;
+                if (w[l][f] > 0.0f) continue;
+                const size_t u = (size_t)(j / 2) * lw[l + 1] + i / 2;
+                for (int c = 0; c < C; ++c) v[l][(size_t)c * nf + f] = v[l + 1][(size_t)c * ncs + u];
+            }
+    }
+    for (size_t p = 0; p < npx; ++p)
+        for (int c = 0; c < C; ++c) E[(size_t)c * npx + p] = v[0][(size_t)c * npx + p];
+    for (int l = 0; l < nl; ++l) {
+        free(v[l]);
+        free(w[l]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Stage 5: the indirect estimate E = rho~ G is removed from the input images.
  * rho~ is either the albedo fitted to the model I0 = rho (S + G) over the K
  * images (default), or the previous PS albedo (literal reading). */
@@ -968,8 +1088,23 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
     if (E) memset(E, 0, sizeof(float) * npx * K * C);
     for (int t = 0; t < T; ++t) {
         or_direct(W, Hh, K, H, n, l, s, S);
-        or_trace(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, OR_TAG_SOLVE,
-                 flags & OR_FLAG_QUADRATURE, G, cnt);
+        const int r_exact = OR_EXACT_R_OF(flags);
+        if (r_exact > 0) {
+            /* the paper's r-ray variant: one environment image, the same for
+             * every light, in place of the gather */
+            float* Er = (float*)malloc(sizeof(float) * npx * C);
+            unsigned char* ok = (unsigned char*)malloc(npx);
+            or_trace_exact_r(W, Hh, C, H, n, rho, env, He, We, r_exact, seed, t, OR_TAG_SOLVE, Er, ok);
+            or_fill_missing(W, Hh, C, Er, ok);
+            for (int k = 0; k < K; ++k)
+                for (int c = 0; c < C; ++c)
+                    memcpy(G + ((size_t)k * C + c) * npx, Er + (size_t)c * npx, sizeof(float) * npx);
+            free(Er);
+            free(ok);
+        } else {
+            or_trace(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, OR_TAG_SOLVE,
+                     flags & OR_FLAG_QUADRATURE, G, cnt);
+        }
         or_correct(W, Hh, C, K, rho_mode, flags, I0, A, G, S, rho, E, A2);
         float* tmp = A; A = A2; A2 = tmp;
         if (flags & OR_FLAG_SHADOW_AWARE_PS)

@@ -35,6 +35,9 @@ enum { OR_TAG_SOLVE = 0, OR_TAG_RENDER = 1 };
 enum { OR_RHO_FIT = 0, OR_RHO_PREV = 1 };
 enum { OR_FLAG_QUADRATURE = 1, OR_FLAG_LITERAL_CUMULATIVE = 2, OR_FLAG_SHADOW_AWARE_PS = 8,
        OR_FLAG_ROBUST_INTEGRATION = 32 };
+/* The paper's r-ray variant (flags bits 8-10 hold r = 1..7; 0: the gather). */
+#define OR_FLAG_EXACT_R(r) ((r) << 8)
+#define OR_EXACT_R_OF(flags) (((flags) >> 8) & 7)
 /* The loop's robust integration: Huber threshold (pixel units of the edge
  * residual), rounds, and V-cycles per round. */
 #define OR_ROBUST_DELTA 0.1f
@@ -100,6 +103,16 @@ void or_trace_at(int W, int Hh, int C, int K, const float* H, const float* n,
                  int spp, int B, uint64_t seed, int t, int tag, int flags,
                  long long count, const long long* pix, float* G_sel, or_counters* cnt);
 
+/* The paper's r-ray variant of the tracer: per pixel one path (sample 0, the
+ * gather's Philox counters) that must reflect r - 1 times and leave on its r-th
+ * ray; Er[c][p] = albedo product of the hits times pi L(texel) there, valid[p]
+ * = 1; otherwise valid[p] = 0 and Er = 0. */
+void or_trace_exact_r(int W, int Hh, int C, const float* H, const float* n, const float* rho,
+                      const float* env, int He, int We, int r, uint64_t seed, int t, int tag,
+                      float* Er, unsigned char* valid);
+/* Pull-push fill of the pixels without a value (valid[p] = 0) of E [C][Hh][W]. */
+void or_fill_missing(int W, int Hh, int C, float* E, const unsigned char* valid);
+
 /* Stage-5 subtraction: E = rho~ G, A_next = I0 - E (or A_prev - E). */
 void or_correct(int W, int Hh, int C, int K, int rho_mode, int flags,
                 const float* I0, const float* Aprev, const float* G, const float* S,
@@ -127,7 +140,9 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
  * the lights that reach it (or_ps_solve_masked with that iteration's S); the
  * first PS of the input images uses every light.  With OR_FLAG_ROBUST_INTEGRATION
  * every integration is or_integrate_robust (OR_ROBUST_DELTA, _ROUNDS, _CYCLES).
- * Returns 0 or -1 (singular lights). */
+ * With OR_FLAG_EXACT_R(r) the gather is replaced by the r-ray environment image
+ * (or_trace_exact_r, then or_fill_missing), the same for every light; spp and
+ * B are then unused.  Returns 0 or -1 (singular lights). */
 int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
              const float* s, const float* env, int He, int We, int spp, int B,
              int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,

@@ -64,6 +64,10 @@ def lib():
         L.or_trace_at.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
                                   + [ct.c_int] * 3 + [ct.c_longlong, _pll, _f, ct.POINTER(Counters)])
         L.or_integrate.argtypes = [ct.c_int, ct.c_int, _f, _f, ct.c_int, _f]
+        _u8 = ct.POINTER(ct.c_uint8)
+        L.or_trace_exact_r.argtypes = ([ct.c_int] * 3 + [_f] * 4 + [ct.c_int] * 3 + [ct.c_uint64]
+                                       + [ct.c_int] * 2 + [_f, _u8])
+        L.or_fill_missing.argtypes = [ct.c_int] * 3 + [_f, _u8]
         L.or_integrate_robust.argtypes = [ct.c_int, ct.c_int, _f, _f, ct.c_int, ct.c_float, ct.c_int, ct.c_int, _f]
         L.or_render.argtypes = ([ct.c_int] * 4 + [_f] * 6 + [ct.c_int] * 4 + [ct.c_uint64]
                                 + [_f, ct.POINTER(Counters)])
@@ -300,6 +304,32 @@ def integrate(n, Hinit=None, cycles=8):
     H = np.zeros((Hh, W), np.float32)
     lib().or_integrate(W, Hh, _p(n), _p(_f32(Hinit)), cycles, _p(H))
     return H
+
+
+def flag_exact_r(r):
+    return int(r) << 8
+
+
+def trace_exact_r(H, n, rho, env, r, seed, t=0, tag=TAG_SOLVE):
+    """The r-ray environment image [C][H][W] and its valid mask [H][W] (uint8)."""
+    H, n, rho, env = map(_f32, (H, n, rho, env))
+    Hh, W = H.shape
+    C = rho.shape[0]
+    assert env.shape[2] == C
+    E = np.zeros((C, Hh, W), np.float32)
+    ok = np.zeros((Hh, W), np.uint8)
+    lib().or_trace_exact_r(W, Hh, C, _p(H), _p(n), _p(rho), _p(env), env.shape[0], env.shape[1], int(r),
+                           int(seed), t, tag, _p(E), ok.ctypes.data_as(ct.POINTER(ct.c_uint8)))
+    return E, ok
+
+
+def fill_missing(E, valid):
+    """Pull-push fill of E [C][H][W] where valid [H][W] is 0 (returns a copy)."""
+    E = np.array(E, dtype=np.float32, order="C", copy=True)
+    ok = np.ascontiguousarray(valid, dtype=np.uint8)
+    C, Hh, W = E.shape
+    lib().or_fill_missing(W, Hh, C, _p(E), ok.ctypes.data_as(ct.POINTER(ct.c_uint8)))
+    return E
 
 
 def integrate_robust(n, Hinit=None, cycles=8, delta=ROBUST_DELTA, rounds=ROBUST_ROUNDS, rcycles=ROBUST_CYCLES):

@@ -1078,3 +1078,50 @@ def test_robust_integration_suppresses_an_outlier_block():
     e_l2 = np.abs((l2 - l2[0, 0]) - (ref - ref[0, 0]))[far].max()
     e_rb = np.abs((rb - rb[0, 0]) - (ref - ref[0, 0]))[far].max()
     assert e_l2 > 0.2 and e_rb < 0.25 * e_l2, (e_l2, e_rb)
+
+
+# ---------------------------------------------------------------------------
+# The paper's r-ray variant (Sec. IV, tracing paragraph, Fig. 5) and the fill of
+# the pixels it leaves empty.
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_exact_r_trace_is_the_gather_sample_that_escapes_on_its_r_th_ray(r):
+    """The r-ray image uses the gather's sample 0 (same counters).  With no
+    direct light (S = 0), spp 1 and B = r the gather adds only the environment
+    term of an escape, so a pixel whose path escapes on ray r has exactly the
+    gather's value; a path that escapes earlier gives the same gather value
+    with B = r - 1 and r, one whose r-th ray hits gives 0 in both.  So the
+    pixel is valid exactly where the gathers with B = r and B = r - 1 differ
+    (every texel is positive), and its value is the B = r gather's."""
+    sc = scenes.tiny_scene(23, 19, seed=7, channels=3, num_lights=4, amp=4.0)
+    S0 = np.zeros(sc.heights.shape + (4,), F32)
+    env = sc.env + F32(0.05)
+    E, ok = O.trace_exact_r(sc.heights, sc.normals, sc.albedo, env, r, seed=99, t=2)
+    Gr, _ = O.trace(sc.heights, sc.normals, sc.albedo, S0, env, 1, r, 99, t=2)
+    Gp, _ = O.trace(sc.heights, sc.normals, sc.albedo, S0, env, 1, r - 1, 99, t=2)
+    differ = (Gr[0] != Gp[0]).any(0)
+    assert np.array_equal(ok.astype(bool), differ)
+    assert np.array_equal(E[:, ok.astype(bool)], Gr[0][:, ok.astype(bool)])
+    assert (E[:, ~ok.astype(bool)] == 0).all()
+    assert 0 < ok.mean() < 1  # the scene leaves pixels empty at every depth
+
+
+def test_fill_missing_pull_push():
+    """Pull-push fill: pixels with a value keep it bit for bit; a constant field
+    with holes is filled with that constant (3/4: weighted sums of it are
+    exact); a pixel alone in its 2 x 2 block without a value takes the mean of
+    its three siblings; with no valid pixel everything is 0."""
+    rng = np.random.default_rng(3)
+    E = rng.uniform(0, 1, (3, 37, 53)).astype(F32)
+    ok = (rng.uniform(0, 1, (37, 53)) < 0.3).astype(np.uint8)
+    F = O.fill_missing(E, ok)
+    m = ok.astype(bool)
+    assert np.array_equal(F[:, m], E[:, m]) and np.isfinite(F).all()
+    assert np.array_equal(O.fill_missing(E, np.ones_like(ok)), E)
+    c = np.full((1, 37, 53), 0.75, F32)
+    assert (O.fill_missing(c, ok) == F32(0.75)).all()
+    one = np.ones((8, 8), np.uint8)
+    one[2, 5] = 0
+    G = O.fill_missing(E[:1, :8, :8], one)
+    sib = [E[0, 2, 4], E[0, 3, 4], E[0, 3, 5]]  # block rows 2-3, columns 4-5, in (0,0),(1,0),(0,1),(1,1) order
+    assert G[0, 2, 5] == np.float32(np.float32(np.float32(sib[0] + sib[1]) + sib[2]) / np.float32(3))
+    assert (O.fill_missing(E, np.zeros_like(ok)) == 0).all()
