@@ -79,11 +79,21 @@ enum {
                                           identical arguments (same pointers, lights, schedule);
                                           needs stop_tol = 0 and a stream other than the legacy
                                           default one; changes no result */
-    IRTPS_FLAG_ROBUST_INTEGRATION = 32 /* irtps_solve and irtps_solve_static only (the batched and
-                                          served engines refuse it): every integration is
-                                          irtps_integrate_robust with delta 0.1, 6 rounds of 2
-                                          V-cycles after the least-squares cycles */
+    IRTPS_FLAG_ROBUST_INTEGRATION = 32, /* irtps_solve and irtps_solve_static only (the batched and
+                                           served engines refuse it): every integration is
+                                           irtps_integrate_robust with delta 0.1, 6 rounds of 2
+                                           V-cycles after the least-squares cycles */
+    IRTPS_FLAG_EXACT_R_MASK = 0x700     /* bits of IRTPS_FLAG_EXACT_R(r) */
 };
+/* The paper's r-ray variant of the tracer (Sec. IV, the tracing paragraph, and
+ * Fig. 5), r in 1..7, for irtps_solve and irtps_solve_static only (the batched
+ * and served engines refuse it): each iteration's gather is replaced by one
+ * environment image, the same for every light: irtps_trace_exact_r (one path
+ * per pixel that leaves on its r-th ray), the pixels it leaves empty filled by
+ * irtps_fill_missing, then stage 5 (irtps_correct) with G[p][k] = that image.
+ * spp, bounces and IRTPS_FLAG_QUADRATURE are then unused; the trace counters
+ * [0..3] stay 0. */
+#define IRTPS_FLAG_EXACT_R(r) ((int32_t)(r) << 8)
 
 /* Sample-stream tags (word 3 of the Philox counter). */
 enum { IRTPS_TAG_SOLVE = 0, IRTPS_TAG_RENDER = 1 };
@@ -261,6 +271,35 @@ int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_d
                 const float* pyramid_dev, int32_t spp, int32_t B, uint64_t seed,
                 int32_t t, int32_t tag, int32_t flags, float* G_dev,
                 uint64_t* counters_dev, void* stream);
+
+/* The r-ray variant's trace (Sec. IV, the tracing paragraph; Fig. 5): per
+ * pixel p = j W + i, the single path of sample 0 (the counters irtps_trace
+ * gives sample 0, segments b = 1..r) that reflects r - 1 times and leaves for
+ * the environment on its r-th ray.  Such a pixel gets, per channel, the product
+ * of the albedos of its r - 1 hits times pi L_env,c of the texel that ray
+ * reaches, and valid_dev[p] = 1; a path that escapes earlier, or whose r-th ray
+ * meets the surface, leaves E_dev[p] = 0 and valid_dev[p] = 0.  E_dev is
+ * [H][W][C], valid_dev [H][W] uint8 (may be NULL); flags: 0 or
+ * IRTPS_FLAG_FLAT_TRAVERSAL; r in 1..7.  pyramid_dev as for irtps_trace. */
+int irtps_trace_exact_r(int32_t W, int32_t H, int32_t C, const float* depth_dev,
+                        const float* normals_dev, const float* albedo_dev, const float* env_dev,
+                        int32_t env_h, int32_t env_w, const float* pyramid_dev, int32_t r,
+                        uint64_t seed, int32_t t, int32_t tag, int32_t flags, float* E_dev,
+                        unsigned char* valid_dev, void* stream);
+
+/* Bytes of workspace for irtps_fill_missing. */
+int irtps_fill_workspace_bytes(int32_t W, int32_t H, int32_t C, size_t* bytes);
+/* Fill of the pixels the r-ray image leaves empty (the paper interpolates them
+ * and names no method): pull-push over levels of 2 x 2 aggregates down to
+ * 1 x 1 (level sizes ceil(w/2) x ceil(h/2)).  Pull: a coarse cell holds the
+ * weighted mean of its children that carry weight (weights: counts of valid
+ * pixels below; children taken (0,0), (1,0), (0,1), (1,1), each channel summed
+ * with fused multiply-adds, then divided by the summed weight) and that weight.
+ * Push: from the coarsest level down, a cell of weight 0 takes its parent's
+ * value.  Pixels with valid_dev[p] != 0 keep their value; with no valid pixel
+ * every pixel becomes 0.  E_dev [H][W][C] is filled in place. */
+int irtps_fill_missing(int32_t W, int32_t H, int32_t C, float* E_dev, const unsigned char* valid_dev,
+                       void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Stage 5: E = rho~ G and A_next = I0 - E (or A_prev - E with
  * IRTPS_FLAG_LITERAL_CUMULATIVE).  rho~ per IRTPS_RHO_*: the fit is

@@ -49,8 +49,7 @@ int irtps_ps_matrix(int32_t K, const float* light_dirs_host, const float* light_
 int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* params, size_t* bytes) {
     STATUS_TRY(check_problem(problem, params));
     if (!bytes) return IRTPS_ERR_INVALID_ARG;
-    *bytes = solve_workspace_bytes(problem->width, problem->height, problem->channels, problem->num_lights,
-                                   params->spp, params->bounces);
+    *bytes = solve_workspace_bytes(problem->width, problem->height, problem->channels, problem->num_lights, params);
     return IRTPS_OK;
 }
 
@@ -63,7 +62,8 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
                    const kern::PsMatrix& M, const kern::LightSet& Ls, hipStream_t st) {
     const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
     const SolveLayout lay = solve_layout(W, H, C, K);
-    const size_t rec_bytes = split_bytes(W, H, C, pa->spp, pa->bounces);
+    const int r_exact = kern::exact_r_of(pa->flags);
+    const size_t rec_bytes = r_exact ? 0 : split_bytes(W, H, C, pa->spp, pa->bounces);
     char* base = static_cast<char*>(ws);
     float* A = reinterpret_cast<float*>(base + lay.A);
     float* S = reinterpret_cast<float*>(base + lay.S);
@@ -97,56 +97,71 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
     for (int t = 0; t < pa->iterations; ++t) {
         HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
         HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
-        kern::TraceArgs ta{};
-        ta.sa = sa;
-        ta.n = out->normals_dev;
-        ta.rho = out->albedo_dev;
-        ta.S = S;
-        ta.env = pr->env_dev;
-        ta.G = G;
-        ta.counters = cnt;
-        ta.env_h = pr->env_h;
-        ta.env_w = pr->env_w;
-        ta.C = C;
-        ta.K = K;
-        ta.spp = pa->spp;
-        ta.B = pa->bounces;
-        ta.t = t;
-        ta.tag = IRTPS_TAG_SOLVE;
-        ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
-        ta.key0 = (uint32_t)pa->seed;
-        ta.key1 = (uint32_t)(pa->seed >> 32);
-        const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
-        ta.ready_batch = sched.ready_batch;
-        ta.tile_shift = sched.tile_shift;
-        // Each launch records its blocks' times per tile; from the second
-        // iteration on, the tiles go out heaviest first by the previous
-        // iteration's times, so that the launch ends on short blocks (the
-        // surface changes little between iterations).
-        ta.tile_cost = tile_cost;
-        // a small problem traces one path per (pixel, sample) lane instead
-        ta.records = rec_bytes ? reinterpret_cast<float*>(base + lay.total) : nullptr;
-        if (t > 0 && !ta.records) {
-            HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
-            ta.order = tile_order;
-        }
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
         // the last iteration writes E; with a stop rule any iteration may be the last
         float* E = (t == pa->iterations - 1 || stop) ? out->indirect_dev : nullptr;
-        if (!ta.records) {
-            // the per-pixel tracer corrects each pixel as soon as its G is final
-            ta.I0 = pr->images_dev;
-            ta.Aprev = Aprev;
-            ta.Anext = A;
-            ta.E = E;
-            ta.rho_mode = pa->rho_mode;
-            ta.cumulative = cumulative ? 1 : 0;
-        }
-        HIP_TRY(traced(ta, st));
-        if (ta.records)
+        if (r_exact) {
+            // the r-ray variant: one environment image, its holes filled, as G of every light
+            const kern::FillPlan fp = kern::fill_plan(W, H, C);
+            float* fill = reinterpret_cast<float*>(base + lay.total);
+            float* v0 = fill + fp.v0off;
+            HIP_TRY(kern::trace_exact_r(sa, C, out->normals_dev, out->albedo_dev, pr->env_dev, pr->env_h, pr->env_w,
+                                        r_exact, t, IRTPS_TAG_SOLVE, (uint32_t)pa->seed, (uint32_t)(pa->seed >> 32),
+                                        (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, v0, fill + fp.woff[0],
+                                        nullptr, st));
+            HIP_TRY(kern::fill_pull_push(fp, C, v0, fill, st));
+            HIP_TRY(kern::fill_push0_broadcast(fp, C, K, v0, fill, G, st));
             HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
                                   out->albedo_dev, E, A, st));
+        } else {
+            kern::TraceArgs ta{};
+            ta.sa = sa;
+            ta.n = out->normals_dev;
+            ta.rho = out->albedo_dev;
+            ta.S = S;
+            ta.env = pr->env_dev;
+            ta.G = G;
+            ta.counters = cnt;
+            ta.env_h = pr->env_h;
+            ta.env_w = pr->env_w;
+            ta.C = C;
+            ta.K = K;
+            ta.spp = pa->spp;
+            ta.B = pa->bounces;
+            ta.t = t;
+            ta.tag = IRTPS_TAG_SOLVE;
+            ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
+            ta.key0 = (uint32_t)pa->seed;
+            ta.key1 = (uint32_t)(pa->seed >> 32);
+            const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
+            ta.ready_batch = sched.ready_batch;
+            ta.tile_shift = sched.tile_shift;
+            // Each launch records its blocks' times per tile; from the second
+            // iteration on, the tiles go out heaviest first by the previous
+            // iteration's times, so that the launch ends on short blocks (the
+            // surface changes little between iterations).
+            ta.tile_cost = tile_cost;
+            // a small problem traces one path per (pixel, sample) lane instead
+            ta.records = rec_bytes ? reinterpret_cast<float*>(base + lay.total) : nullptr;
+            if (t > 0 && !ta.records) {
+                HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
+                ta.order = tile_order;
+            }
+            if (!ta.records) {
+                // the per-pixel tracer corrects each pixel as soon as its G is final
+                ta.I0 = pr->images_dev;
+                ta.Aprev = Aprev;
+                ta.Anext = A;
+                ta.E = E;
+                ta.rho_mode = pa->rho_mode;
+                ta.cumulative = cumulative ? 1 : 0;
+            }
+            HIP_TRY(traced(ta, st));
+            if (ta.records)
+                HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
+                                      out->albedo_dev, E, A, st));
+        }
         if (pa->flags & IRTPS_FLAG_SHADOW_AWARE_PS)  // per pixel, the lights that reach it (S of H_t, n_t)
             HIP_TRY(kern::ps_solve_masked(npx, C, K, M, Ls, A, S, out->normals_dev, out->albedo_dev, st));
         else
@@ -252,9 +267,7 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
     STATUS_TRY(check_problem(pr, pa));
     if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
     const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
-    const SolveLayout lay = solve_layout(W, H, C, K);
-    const size_t rec_bytes = split_bytes(W, H, C, pa->spp, pa->bounces);
-    if (!ws || ws_bytes < lay.total + rec_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign))
+    if (!ws || ws_bytes < solve_workspace_bytes(W, H, C, K, pa) || (reinterpret_cast<uintptr_t>(ws) % kAlign))
         return IRTPS_ERR_WORKSPACE;
     const bool graph = (pa->flags & IRTPS_FLAG_GRAPH) != 0;
     // a graph cannot hold the stop rule's read-back, nor run on the legacy stream
@@ -383,6 +396,41 @@ int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_d
     ta.ready_batch = sched.ready_batch;
     ta.tile_shift = sched.tile_shift;
     HIP_TRY(traced(ta, reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_trace_exact_r(int32_t W, int32_t H, int32_t C, const float* depth_dev, const float* normals_dev,
+                        const float* albedo_dev, const float* env_dev, int32_t env_h, int32_t env_w,
+                        const float* pyramid_dev, int32_t r, uint64_t seed, int32_t t, int32_t tag, int32_t flags,
+                        float* E_dev, unsigned char* valid_dev, void* stream) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !depth_dev || !normals_dev || !albedo_dev || !env_dev || env_h < 1 ||
+        env_w < 1 || !pyramid_dev || r < 1 || r > 7 || t < 0 || t >= (1 << 23) || tag < 0 || !E_dev ||
+        (flags & ~IRTPS_FLAG_FLAT_TRAVERSAL))
+        return IRTPS_ERR_INVALID_ARG;
+    HIP_TRY(kern::trace_exact_r(surface(W, H, depth_dev, pyramid_dev), C, normals_dev, albedo_dev, env_dev, env_h,
+                                env_w, r, t, tag, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                (flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, E_dev, nullptr, valid_dev,
+                                reinterpret_cast<hipStream_t>(stream)));
+    return IRTPS_OK;
+}
+
+int irtps_fill_workspace_bytes(int32_t W, int32_t H, int32_t C, size_t* bytes) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !bytes) return IRTPS_ERR_INVALID_ARG;
+    *bytes = align_up(sizeof(float) * (size_t)kern::fill_plan(W, H, C).total);
+    return IRTPS_OK;
+}
+
+int irtps_fill_missing(int32_t W, int32_t H, int32_t C, float* E_dev, const unsigned char* valid_dev, void* ws_dev,
+                       size_t ws_bytes, void* stream) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !E_dev || !valid_dev) return IRTPS_ERR_INVALID_ARG;
+    const kern::FillPlan fp = kern::fill_plan(W, H, C);
+    if (!ws_dev || ws_bytes < sizeof(float) * (size_t)fp.total || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign))
+        return IRTPS_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float* ws = static_cast<float*>(ws_dev);
+    HIP_TRY(kern::fill_weights((long long)W * H, valid_dev, ws + fp.woff[0], st));
+    HIP_TRY(kern::fill_pull_push(fp, C, E_dev, ws, st));
+    HIP_TRY(kern::fill_push0(fp, C, E_dev, ws, st));
     return IRTPS_OK;
 }
 

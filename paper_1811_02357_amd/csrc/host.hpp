@@ -242,13 +242,20 @@ inline SolveLayout solve_layout(int W, int H, int C, int K) {
     return L;
 }
 
-// The solve's workspace: the layout above, then (small problems) the per-path
-// tracer's segment records.
+// The solve's workspace: the layout above, then a tail: with the r-ray variant
+// its pull-push levels, else (small problems) the per-path tracer's segment
+// records.
 inline size_t split_bytes(int W, int H, int C, int spp, int B) {
     return align_up((size_t)kern::split_record_bytes((long long)W * H, C, spp, B));
 }
-inline size_t solve_workspace_bytes(int W, int H, int C, int K, int spp, int B) {
-    return solve_layout(W, H, C, K).total + split_bytes(W, H, C, spp, B);
+inline size_t fill_bytes(int W, int H, int C) {
+    return align_up(sizeof(float) * (size_t)kern::fill_plan(W, H, C).total_v0);
+}
+inline size_t tail_bytes(int W, int H, int C, const irtps_params* pa) {
+    return kern::exact_r_of(pa->flags) ? fill_bytes(W, H, C) : split_bytes(W, H, C, pa->spp, pa->bounces);
+}
+inline size_t solve_workspace_bytes(int W, int H, int C, int K, const irtps_params* pa) {
+    return solve_layout(W, H, C, K).total + tail_bytes(W, H, C, pa);
 }
 
 inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
@@ -262,7 +269,8 @@ inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
         pa->mg_cycles_cold < 0 || pa->mg_cycles_warm < 0 || !(pa->stop_tol >= 0.0f) ||
         !(pa->stop_tol <= 3.0e38f) ||
         (pa->flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_LITERAL_CUMULATIVE | IRTPS_FLAG_FLAT_TRAVERSAL |
-                       IRTPS_FLAG_SHADOW_AWARE_PS | IRTPS_FLAG_GRAPH | IRTPS_FLAG_ROBUST_INTEGRATION)))
+                       IRTPS_FLAG_SHADOW_AWARE_PS | IRTPS_FLAG_GRAPH | IRTPS_FLAG_ROBUST_INTEGRATION |
+                       IRTPS_FLAG_EXACT_R_MASK)))
         return IRTPS_ERR_INVALID_ARG;
     return IRTPS_OK;
 }

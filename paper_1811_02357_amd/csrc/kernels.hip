@@ -1297,6 +1297,139 @@ __global__ void __launch_bounds__(256) k_gather_paths(TraceArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// The r-ray variant: one lane per pixel follows sample 0's path (the gather's
+// counters for s = 0) through at most r segments.  Only a path whose r-th ray
+// escapes gives its pixel a value: the albedo products of its r - 1 hits times
+// pi times the environment texel that ray reaches.
+template <int C>
+__global__ void __launch_bounds__(256) k_trace_exact_r(SurfaceArgs sa, const float* __restrict__ n,
+                                                       const float* __restrict__ rho,
+                                                       const float* __restrict__ env, int He, int We, int r,
+                                                       int t, int tag, uint32_t key0, uint32_t key1, int flat,
+                                                       float* __restrict__ E, float* __restrict__ w0,
+                                                       unsigned char* __restrict__ valid) {
+    __shared__ int2 s_lvl[trv::kMaxLevels];
+    load_level_table(sa.off, sa.wc, s_lvl);
+    const int W = sa.W, npx = W * sa.Hh;
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= npx) return;
+    const Surface S = make_surface(sa, s_lvl);
+    float beta[C], out[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        beta[c] = 1.0f;
+        out[c] = 0.0f;
+    }
+    bool ok = false;
+    int ci = p % W, cj = p / W;
+    for (int b = 1; b <= r; ++b) {
+        const dm::U4 u = dm::philox((uint32_t)p, 0u, (uint32_t)t * 256u + (uint32_t)b, (uint32_t)tag, key0, key1);
+        const float* nq = n + 3 * (cj * W + ci);
+        const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], dm::unit24(u.x), dm::unit24(u.y));
+        trv::Walker w;
+        trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat != 0);
+        int res = trv::kMiss, qi = 0, qj = 0;
+        if (!trv::leaves_at_once(w, S)) {
+            do {
+                res = trv::walker_step<false>(w, S, qi, qj);
+            } while (res == trv::kGoOn);
+        }
+        if (res == trv::kMiss) {
+            if (b == r) {
+                int er, ec;
+                dm::env_texel(w.r.dx, w.r.dy, w.r.dz, He, We, er, ec);
+                const float* L = env + ((size_t)er * We + ec) * C;
+#pragma unroll
+                for (int c = 0; c < C; ++c) out[c] = beta[c] * (dm::kPi * L[c]);
+                ok = true;
+            }
+            break;
+        }
+        if (b == r) break;  // the r-th ray met the surface
+        const int q = qj * W + qi;
+#pragma unroll
+        for (int c = 0; c < C; ++c) beta[c] = beta[c] * rho[(size_t)c * npx + q];
+        ci = qi;
+        cj = qj;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) E[(size_t)p * C + c] = out[c];
+    if (w0) w0[p] = ok ? 1.0f : 0.0f;
+    if (valid) valid[p] = ok ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_fill_weights(long long npx, const unsigned char* __restrict__ valid,
+                                                      float* __restrict__ w0) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npx) w0[p] = valid[p] ? 1.0f : 0.0f;
+}
+
+// Pull one level: coarse cell u averages its children (fine cells 2I + di,
+// 2J + dj, taken in the order dj, then di) that carry weight, weighted by it.
+template <int C>
+__global__ void __launch_bounds__(256) k_fill_pull(const float* __restrict__ wf, const float* __restrict__ vf,
+                                                   int fw, int fh, float* __restrict__ wc,
+                                                   float* __restrict__ vc, int cw, int ch) {
+    const int u = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (u >= cw * ch) return;
+    const int I = u % cw, J = u / cw;
+    float den = 0.0f, num[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) num[c] = 0.0f;
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const int fi = 2 * I + di, fj = 2 * J + dj;
+            if (fi >= fw || fj >= fh) continue;
+            const size_t f = (size_t)fj * fw + fi;
+            const float wgt = wf[f];
+            if (!(wgt > 0.0f)) continue;
+#pragma unroll
+            for (int c = 0; c < C; ++c) num[c] = fmaf(wgt, vf[f * C + c], num[c]);
+            den = den + wgt;
+        }
+    wc[u] = den;
+#pragma unroll
+    for (int c = 0; c < C; ++c) vc[(size_t)u * C + c] = den > 0.0f ? num[c] / den : 0.0f;
+}
+
+// Push one level, in place: a fine cell of weight 0 takes its parent's value
+// (vc null: no parent, the value is 0).
+template <int C>
+__global__ void __launch_bounds__(256) k_fill_push(const float* __restrict__ wf, float* __restrict__ vf, int fw,
+                                                   int fh, const float* __restrict__ vc, int cw) {
+    const int f = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (f >= fw * fh || wf[f] > 0.0f) return;
+    const int i = f % fw, j = f / fw;
+    const size_t u = (size_t)(j / 2) * cw + i / 2;
+#pragma unroll
+    for (int c = 0; c < C; ++c) vf[(size_t)f * C + c] = vc ? vc[u * C + c] : 0.0f;
+}
+
+// Level 0's push into G [p][k][c]: one lane per element of G, so the stores
+// are contiguous across the wave.
+template <int C>
+__global__ void __launch_bounds__(256) k_fill_push0_broadcast(const float* __restrict__ w0,
+                                                              const float* __restrict__ v0, int W, int Hh,
+                                                              const float* __restrict__ v1, int cw, int K,
+                                                              float* __restrict__ G) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long KC = (long long)K * C;
+    if (x >= KC * W * Hh) return;
+    const int p = (int)(x / KC);
+    const int c = (int)(x % KC) % C;
+    float v;
+    if (w0[p] > 0.0f) {
+        v = v0[(size_t)p * C + c];
+    } else {
+        const int i = p % W, j = p / W;
+        v = v1 ? v1[((size_t)(j / 2) * cw + i / 2) * C + c] : 0.0f;
+    }
+    G[x] = v;
+}
+
 // Blocks take their tiles in XCD order, or in the given order (a permutation of
 // the tiles: block b < tiles takes order[b]).  With tile_cost, each block
 // records its time (wall clock, its slowest wave's) under its tile.
@@ -2128,6 +2261,77 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
     const unsigned gm = blocks_for(npx, 256) < kMinKeyBlocks ? blocks_for(npx, 256) : kMinKeyBlocks;
     hipLaunchKernelGGL(k_min_key, dim3(gm), dim3(256), 0, st, X[0], npx, key);
     hipLaunchKernelGGL(k_anchor, dim3(blocks_for(npx, 256)), dim3(256), 0, st, X[0], npx, key, Hout, change);
+    return hipGetLastError();
+}
+
+hipError_t trace_exact_r(const SurfaceArgs& sa, int C, const float* n, const float* rho, const float* env,
+                         int He, int We, int r, int t, int tag, uint32_t key0, uint32_t key1, int flat, float* E,
+                         float* w0, unsigned char* valid, hipStream_t st) {
+    const long long npx = (long long)sa.W * sa.Hh;
+    const dim3 g(blocks_for(npx, 256)), b(256);
+    if (C == 1)
+        hipLaunchKernelGGL(k_trace_exact_r<1>, g, b, 0, st, sa, n, rho, env, He, We, r, t, tag, key0, key1, flat, E,
+                           w0, valid);
+    else
+        hipLaunchKernelGGL(k_trace_exact_r<3>, g, b, 0, st, sa, n, rho, env, He, We, r, t, tag, key0, key1, flat, E,
+                           w0, valid);
+    return hipGetLastError();
+}
+
+hipError_t fill_weights(long long npx, const unsigned char* valid, float* ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_weights, dim3(blocks_for(npx, 256)), dim3(256), 0, st, npx, valid, ws);
+    return hipGetLastError();
+}
+
+hipError_t fill_pull_push(const FillPlan& fp, int C, const float* v0, float* ws, hipStream_t st) {
+    for (int l = 0; l + 1 < fp.levels; ++l) {
+        const float* vf = l ? ws + fp.voff[l] : v0;
+        const long long cells = (long long)fp.w[l + 1] * fp.h[l + 1];
+        const dim3 g(blocks_for(cells, 256)), b(256);
+        if (C == 1)
+            hipLaunchKernelGGL(k_fill_pull<1>, g, b, 0, st, ws + fp.woff[l], vf, fp.w[l], fp.h[l], ws + fp.woff[l + 1],
+                               ws + fp.voff[l + 1], fp.w[l + 1], fp.h[l + 1]);
+        else
+            hipLaunchKernelGGL(k_fill_pull<3>, g, b, 0, st, ws + fp.woff[l], vf, fp.w[l], fp.h[l], ws + fp.woff[l + 1],
+                               ws + fp.voff[l + 1], fp.w[l + 1], fp.h[l + 1]);
+    }
+    for (int l = fp.levels - 2; l >= 1; --l) {
+        const long long cells = (long long)fp.w[l] * fp.h[l];
+        const dim3 g(blocks_for(cells, 256)), b(256);
+        if (C == 1)
+            hipLaunchKernelGGL(k_fill_push<1>, g, b, 0, st, ws + fp.woff[l], ws + fp.voff[l], fp.w[l], fp.h[l],
+                               ws + fp.voff[l + 1], fp.w[l + 1]);
+        else
+            hipLaunchKernelGGL(k_fill_push<3>, g, b, 0, st, ws + fp.woff[l], ws + fp.voff[l], fp.w[l], fp.h[l],
+                               ws + fp.voff[l + 1], fp.w[l + 1]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t fill_push0(const FillPlan& fp, int C, float* v0, const float* ws, hipStream_t st) {
+    const long long cells = (long long)fp.w[0] * fp.h[0];
+    const float* v1 = fp.levels > 1 ? ws + fp.voff[1] : nullptr;
+    const int cw = fp.levels > 1 ? fp.w[1] : 1;
+    const dim3 g(blocks_for(cells, 256)), b(256);
+    if (C == 1)
+        hipLaunchKernelGGL(k_fill_push<1>, g, b, 0, st, ws + fp.woff[0], v0, fp.w[0], fp.h[0], v1, cw);
+    else
+        hipLaunchKernelGGL(k_fill_push<3>, g, b, 0, st, ws + fp.woff[0], v0, fp.w[0], fp.h[0], v1, cw);
+    return hipGetLastError();
+}
+
+hipError_t fill_push0_broadcast(const FillPlan& fp, int C, int K, const float* v0, const float* ws, float* G,
+                                hipStream_t st) {
+    const long long n = (long long)fp.w[0] * fp.h[0] * K * C;
+    const float* v1 = fp.levels > 1 ? ws + fp.voff[1] : nullptr;
+    const int cw = fp.levels > 1 ? fp.w[1] : 1;
+    const dim3 g(blocks_for(n, 256)), b(256);
+    if (C == 1)
+        hipLaunchKernelGGL(k_fill_push0_broadcast<1>, g, b, 0, st, ws + fp.woff[0], v0, fp.w[0], fp.h[0], v1, cw, K,
+                           G);
+    else
+        hipLaunchKernelGGL(k_fill_push0_broadcast<3>, g, b, 0, st, ws + fp.woff[0], v0, fp.w[0], fp.h[0], v1, cw, K,
+                           G);
     return hipGetLastError();
 }
 

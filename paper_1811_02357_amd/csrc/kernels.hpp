@@ -207,6 +207,69 @@ hipError_t integrate(const MgPlan& plan, const float* n, const float* Hinit, int
 inline unsigned* change_key_of(const MgPlan& plan, float* ws) {
     return reinterpret_cast<unsigned*>(ws + plan.keyoff) + 1;
 }
+// ---- the r-ray variant (Sec. IV, the tracing paragraph; Fig. 5) ----
+// One path per pixel, on sample 0's counters of the gather, that leaves for the
+// environment on its r-th ray: E[p][c] = (albedo product of its r - 1 hits)
+// pi L_env,c, valid; any other path leaves E[p] = 0, not valid.  w0 (float
+// 1 / 0) and valid (uint8 1 / 0) may each be null.
+constexpr int kExactRShift = 8;  // IRTPS_FLAG_EXACT_R(r) = r << 8, r in 1..7
+inline int exact_r_of(int flags) { return (flags >> kExactRShift) & 7; }
+hipError_t trace_exact_r(const SurfaceArgs& sa, int C, const float* n, const float* rho, const float* env,
+                         int He, int We, int r, int t, int tag, uint32_t key0, uint32_t key1, int flat, float* E,
+                         float* w0, unsigned char* valid, hipStream_t st);
+
+// Pull-push fill of the pixels without a value: levels of 2 x 2 aggregates
+// (ragged edges keep the children that exist) down to 1 x 1, each a weight
+// plane [h][w] at woff and (levels >= 1) a value plane [h][w][C] at voff, in
+// floats from the region's start; `total` floats in all.  Level 0's values are
+// the image being filled; the solve keeps them in the region too, at v0off
+// (total_v0 floats then).
+constexpr int kMaxFillLevels = 32;
+struct FillPlan {
+    int levels;
+    int w[kMaxFillLevels], h[kMaxFillLevels];
+    long long woff[kMaxFillLevels], voff[kMaxFillLevels];
+    long long total, v0off, total_v0;
+};
+inline FillPlan fill_plan(int W, int H, int C) {
+    FillPlan f{};
+    auto up64 = [](long long x) { return (x + 63) & ~63LL; };
+    f.w[0] = W;
+    f.h[0] = H;
+    f.levels = 1;
+    while ((f.w[f.levels - 1] > 1 || f.h[f.levels - 1] > 1) && f.levels < kMaxFillLevels) {
+        f.w[f.levels] = (f.w[f.levels - 1] + 1) / 2;
+        f.h[f.levels] = (f.h[f.levels - 1] + 1) / 2;
+        ++f.levels;
+    }
+    long long off = 0;
+    for (int l = 0; l < f.levels; ++l) {
+        const long long cells = (long long)f.w[l] * f.h[l];
+        f.woff[l] = off;
+        off = up64(off + cells);
+        f.voff[l] = l ? off : -1;
+        if (l) off = up64(off + cells * C);
+    }
+    f.total = off;
+    f.v0off = off;
+    f.total_v0 = up64(off + (long long)W * H * C);
+    return f;
+}
+// w0[p] = valid[p] ? 1 : 0 (the region's level-0 weights).
+hipError_t fill_weights(long long npx, const unsigned char* valid, float* ws, hipStream_t st);
+// Pull from level 0 (weights in ws, values v0 [npx][C]) up to 1 x 1, then push
+// back down to level 1: a coarse cell holds the weighted mean of its children
+// with a value and their summed weight; going down, a cell of weight 0 takes
+// its parent's value.
+hipError_t fill_pull_push(const FillPlan& fp, int C, const float* v0, float* ws, hipStream_t st);
+// Level 0's push, in place: pixels of weight 0 take their parent's value (0 for
+// a 1 x 1 image).
+hipError_t fill_push0(const FillPlan& fp, int C, float* v0, const float* ws, hipStream_t st);
+// Level 0's push written into G [p][k][c] for every light k (the r-ray image is
+// the same for all lights).
+hipError_t fill_push0_broadcast(const FillPlan& fp, int C, int K, const float* v0, const float* ws, float* G,
+                                hipStream_t st);
+
 hipError_t fill_f32(float* p, float v, long long n, hipStream_t st);
 hipError_t fill_u64_zero(unsigned long long* p, int n, hipStream_t st);
 hipError_t add_u64(unsigned long long* p, unsigned long long v, hipStream_t st);

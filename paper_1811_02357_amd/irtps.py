@@ -25,6 +25,14 @@ FLAG_QUADRATURE, FLAG_LITERAL_CUMULATIVE, FLAG_FLAT_TRAVERSAL, FLAG_SHADOW_AWARE
 FLAG_GRAPH = 16  # irtps_solve: capture once in a hipGraph, replay on identical calls
 FLAG_ROBUST_INTEGRATION = 32  # Huber M-estimator integration (plain solves only)
 ROBUST_DELTA, ROBUST_ROUNDS, ROBUST_CYCLES = 0.1, 6, 2  # the loop's robust integration
+FLAG_EXACT_R_MASK = 0x700  # the r-ray variant's bits (plain solves only)
+
+
+def flag_exact_r(r):
+    """IRTPS_FLAG_EXACT_R(r): the r-ray environment image (r in 1..7) in place of the gather."""
+    return int(r) << 8
+
+
 TAG_SOLVE, TAG_RENDER = 0, 1
 NUM_COUNTERS = 5  # segments, hits, escapes, continuations, IRT iterations run
 
@@ -120,6 +128,10 @@ def lib():
                             _i32, _i32, _u64, _i32, _i32, _i32, _vp, _vp, _vp],
             "irtps_correct": [_i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp],
+            "irtps_trace_exact_r": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _i32, _u64,
+                                    _i32, _i32, _i32, _vp, _vp, _vp],
+            "irtps_fill_workspace_bytes": [_i32, _i32, _i32, P(_sz)],
+            "irtps_fill_missing": [_i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp],
             "irtps_render_workspace_bytes": [_i32, _i32, _i32, _i32, P(_sz)],
             "irtps_render": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                              _i32, _i32, _u64, _vp, _vp, _sz, _vp],
@@ -393,6 +405,37 @@ def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOL
         spp, bounces, seed, t, tag, flags, _dev(G),
         _dev(counters, dtype=torch.int64, shape=(NUM_COUNTERS,)), _stream(stream)))
     return G
+
+
+@_on_stream
+def trace_exact_r(depth, normals, albedo, env, r, seed=0, t=0, tag=TAG_SOLVE, flags=0, pyramid=None,
+                  stream=None):
+    """The r-ray environment image E [H][W][C] and its valid mask [H][W] (uint8)."""
+    H, W = depth.shape
+    C = albedo.shape[0]
+    if pyramid is None:
+        pyramid = build_pyramid(depth, stream)
+    E = torch.empty((H, W, C), device=depth.device)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=depth.device)
+    _check("irtps_trace_exact_r", lib().irtps_trace_exact_r(
+        W, H, C, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)), _dev(env),
+        env.shape[0], env.shape[1], _dev(pyramid), int(r), seed, t, tag, flags, _dev(E),
+        _dev(valid, dtype=torch.uint8), _stream(stream)))
+    return E, valid
+
+
+@_on_stream
+def fill_missing(E, valid, stream=None):
+    """Pull-push fill of E [H][W][C] where valid [H][W] (uint8) is 0 (returns a new tensor)."""
+    H, W, C = E.shape
+    out = E.clone()
+    nb = _sz()
+    _check("irtps_fill_workspace_bytes", lib().irtps_fill_workspace_bytes(W, H, C, ct.byref(nb)))
+    ws = _alloc_ws(nb.value, E.device)
+    _check("irtps_fill_missing", lib().irtps_fill_missing(
+        W, H, C, _dev(out), _dev(valid, dtype=torch.uint8, shape=(H, W), name="valid"),
+        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return out
 
 
 @_on_stream

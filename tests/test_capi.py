@@ -149,3 +149,56 @@ def test_static_solve_refuses_oversized_problem_on_host():
     src = open(os.path.join(ROOT, "include", "irtps.h")).read()
     m = re.search(r"#define IRTPS_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
     assert m and int(m.group(1)) << int(m.group(2)) == irtps.STATIC_SCRATCH_BYTES
+
+
+def _fill_floats(W, H, C, with_v0):
+    """The pull-push region written out: per level a weight plane and (levels
+    >= 1) a value plane of C floats per cell, each from a multiple of 64 floats;
+    the solve adds level 0's values."""
+    up = lambda x: (x + 63) // 64 * 64
+    sizes = [(W, H)]
+    while sizes[-1] != (1, 1):
+        w, h = sizes[-1]
+        sizes.append(((w + 1) // 2, (h + 1) // 2))
+    off = 0
+    for l, (w, h) in enumerate(sizes):
+        off = up(off + w * h)
+        if l:
+            off = up(off + w * h * C)
+    return up(off + W * H * C) if with_v0 else off
+
+
+def test_exact_r_flag_and_fill_workspace_on_host():
+    """IRTPS_FLAG_EXACT_R(r) takes r in 1..7 (bits 8..10); with it the solve's
+    workspace carries the pull-push levels in place of the segment records.  The
+    r-ray stage entries refuse bad arguments before any device work."""
+    L = irtps.lib()
+    n = ct.c_size_t()
+    l = np.zeros((8, 3), np.float32)
+    lp = l.ctypes.data_as(ct.c_void_p)
+
+    def ws(W, H, C, flags, spp=16, B=1):
+        pr = irtps.Problem(W, H, C, 8, ct.c_void_p(256), lp, None, ct.c_void_p(256), 2, 4)
+        pa = irtps.Params(spp, B, 3, 0, flags, 0, 0, 0, 0)
+        st = L.irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n))
+        return n.value if st == 0 else -st
+
+    def align(x):
+        return (x + 255) // 256 * 256
+
+    for W, H, C in ((64, 64, 1), (37, 61, 3), (2, 300, 1), (1000, 3, 3)):
+        base = ws(W, H, C, 0, B=0)  # no records at B = 0
+        for r in range(1, 8):
+            assert ws(W, H, C, irtps.flag_exact_r(r)) - base == align(4 * _fill_floats(W, H, C, True))
+        b = ct.c_size_t()
+        assert L.irtps_fill_workspace_bytes(W, H, C, ct.byref(b)) == 0
+        assert b.value == align(4 * _fill_floats(W, H, C, False))
+    assert irtps.flag_exact_r(7) == irtps.FLAG_EXACT_R_MASK
+    assert ws(64, 64, 1, 1 << 11) == -1  # the bit above r's
+    assert L.irtps_fill_workspace_bytes(1, 64, 1, ct.byref(n)) == 1
+    assert L.irtps_fill_workspace_bytes(64, 64, 2, ct.byref(n)) == 1
+    p = ct.c_void_p(256)
+    for r, flags in ((0, 0), (8, 0), (2, irtps.FLAG_QUADRATURE)):
+        assert L.irtps_trace_exact_r(64, 64, 1, p, p, p, p, 2, 4, p, r, 0, 0, 0, flags, p, None, None) == 1
+    assert L.irtps_fill_missing(64, 64, 1, p, p, p, 16, None) == 3  # workspace too small
+    assert L.irtps_fill_missing(64, 64, 1, p, None, p, 1 << 20, None) == 1

@@ -2,8 +2,9 @@
 configuration bench.py times, checked where the oracle can afford it: on the
 2048^2 RGB frame, teacher-forced with seeded inputs, the pyramid (against its
 definition), direct shading, correction, PS (plain and shadow-aware) and
-integration on every pixel, and the gather on sampled pixels (the oracle's
-per-pixel entry point), all bitwise; served jobs of the batched and served
+integration on every pixel, the r-ray image and its pull-push fill on every
+pixel, and the gather on sampled pixels (the oracle's per-pixel entry point),
+all bitwise; served jobs of the batched and served
 workload laws (side <= 512) against the oracle's whole solve; and the batched
 and served modes at their full job laws against the plain path (bitwise, any
 size)."""
@@ -59,6 +60,25 @@ def test_direct_2048_full_frame(dev, terrain):
     ref = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity)
     say(f"  shadowed or facing away: {np.mean(ref == 0):.3f}; equal {np.mean(S == ref) * 100:.4f}%")
     assert np.array_equal(S, ref)
+
+
+def test_exact_r_trace_and_fill_2048_full_frame(dev, terrain):
+    """The r-ray variant on the 2048^2 RGB frame, every pixel: the r-ray image
+    and its valid mask (r = 1, 2, 3), then the pull-push fill of its holes,
+    teacher-forced on the true surface, against the oracle bit for bit."""
+    sc = terrain
+    Hh, W = sc.height, sc.width
+    dH, dn, drho, denv = T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), T(sc.env, dev)
+    pyr = irtps.build_pyramid(dH)
+    for r in (1, 2, 3):
+        say(f"case: r-ray image r={r} and its fill at {W}x{Hh} C=3, every pixel")
+        E, valid = irtps.trace_exact_r(dH, dn, drho, denv, r, 0x5EED_0003, t=1, pyramid=pyr)
+        F = irtps.fill_missing(E, valid)
+        ref, ok = O.trace_exact_r(sc.heights, sc.normals, sc.albedo, sc.env, r, 0x5EED_0003, t=1)
+        say(f"  valid {ok.mean():.4f}")
+        assert np.array_equal(H(valid), ok)
+        assert np.array_equal(H(E), np.transpose(ref, (1, 2, 0)))
+        assert np.array_equal(H(F), np.transpose(O.fill_missing(ref, ok), (1, 2, 0)))
 
 
 def _window_max(a, lo, width, axis):

@@ -351,7 +351,7 @@ def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None, stop
     ref = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, Tn,
                   seed=sc.seed, rho_mode=rho_mode,
                   flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE | irtps.FLAG_SHADOW_AWARE_PS
-                                 | irtps.FLAG_ROBUST_INTEGRATION),
+                                 | irtps.FLAG_ROBUST_INTEGRATION | irtps.FLAG_EXACT_R_MASK),
                   stop_tol=stop_tol)
     out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
                       sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
@@ -482,7 +482,98 @@ def test_solve_robust_integration(dev, case):
     assert e.value.status == 1
 
 
-@pytest.mark.parametrize("case", ["bowl64", "fbm160x120"])
+# ---------------------------------------------------------------------------
+# The r-ray variant: its trace, the pull-push fill, and the loop with both.
+EXACT_R_CASES = [
+    # name, scene maker, r, flags, t, tag
+    ("bowl_r1", lambda: scenes.bowl_64(), 1, 0, 0, 0),
+    ("bowl_r2", lambda: scenes.bowl_64(), 2, 0, 1, 0),
+    ("bowl_r3_flat", lambda: scenes.bowl_64(), 3, irtps.FLAG_FLAT_TRAVERSAL, 2, 1),
+    ("tiny_rgb_r4", lambda: scenes.tiny_scene(13, 11, seed=4, channels=3, num_lights=20), 4, 0, 1, 0),
+    ("groove_rgb_r2", lambda: scenes._scene("g", scenes.vgroove_heights(96, 80, 24, 3, 24),
+                                            np.random.default_rng(0).uniform(0.3, 0.9, (3, 80, 96)),
+                                            scenes.fibonacci_lights(16), np.ones(16),
+                                            np.random.default_rng(1).uniform(0, 1, (16, 32, 3))), 2, 0, 4, 0),
+    ("step_hill_r7", lambda: _lit(scenes.step_hill()), 7, 0, 0, 0),
+]
+
+
+def _lit(sc):
+    """The scene under a random environment (the step hill's is black)."""
+    sc.env = np.random.default_rng(9).uniform(0.2, 1.0, (8, 16, sc.albedo.shape[0])).astype(F32)
+    return sc
+
+
+@pytest.mark.parametrize("case", EXACT_R_CASES, ids=[c[0] for c in EXACT_R_CASES])
+def test_trace_exact_r_stage(dev, case):
+    name, make, r, flags, t, tag = case
+    say(f"case: r-ray trace {name} r={r} flags={flags}")
+    sc = make()
+    seed = 0x0BAD_CAFE_F00D
+    ref, ok = O.trace_exact_r(sc.heights, sc.normals, sc.albedo, sc.env, r, seed, t=t, tag=tag)
+    E, valid = irtps.trace_exact_r(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), T(sc.env, dev), r,
+                                   seed, t=t, tag=tag, flags=flags)
+    assert np.array_equal(H(valid), ok)
+    assert 0 < ok.sum() < ok.size and ref.max() > 0  # both kinds of path occur
+    assert np.array_equal(H(E), np.transpose(ref, (1, 2, 0)))
+
+
+@pytest.mark.parametrize("C", [1, 3])
+@pytest.mark.parametrize("shape", [(2, 2), (3, 1000), (61, 37), (129, 257), (512, 512)])
+def test_fill_missing_stage(dev, C, shape):
+    Hh, W = shape
+    say(f"case: pull-push fill {Hh}x{W} C={C}")
+    rng = np.random.default_rng(Hh * 1000 + W + C)
+    E = rng.uniform(0.0, 4.0, (C, Hh, W)).astype(F32)
+    for density in (0.0, 1.0 / (Hh * W), 0.03, 0.5, 1.0):
+        ok = (rng.uniform(0, 1, (Hh, W)) < density).astype(np.uint8)
+        if density == 1.0 / (Hh * W):  # exactly one valid pixel, away from the corner
+            ok[:] = 0
+            ok[Hh // 2, W // 2] = 1
+        ref = O.fill_missing(E, ok)
+        garbage = E.copy()
+        garbage[:, ok == 0] = np.nan  # values at invalid pixels are never read
+        got = irtps.fill_missing(T(np.transpose(garbage, (1, 2, 0)), dev), T(ok, dev))
+        assert np.array_equal(H(got), np.transpose(ref, (1, 2, 0))), density
+
+
+@pytest.mark.parametrize("case", ["bowl64_r2", "fbm160x120_rgb_r3_shadow_aware", "step_hill_r1_stop"])
+def test_solve_exact_r(dev, case):
+    """The loop with the r-ray image in place of the gather: trace, fill,
+    broadcast to every light, stage 5, PS and integration, against the oracle's
+    loop with the same flag.  The trace counters stay 0."""
+    say(f"case: solve with the r-ray variant, {case}")
+    rho_mode, stop_tol = irtps.RHO_FIT, 0.0
+    if case == "bowl64_r2":
+        sc = scenes.bowl_64()
+        flags = irtps.flag_exact_r(2)
+    elif case.startswith("fbm"):
+        sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=16, env_shape=(16, 32),
+                                ptp=24.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+        sc.heights = np.ascontiguousarray(sc.heights[:120])
+        sc.normals = np.ascontiguousarray(sc.normals[:120])
+        sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+        flags = irtps.flag_exact_r(3) | irtps.FLAG_SHADOW_AWARE_PS
+    else:  # the stop rule ends it after 2 of 5 iterations
+        sc = scenes.step_hill(iterations=5)
+        sc.env = np.random.default_rng(9).uniform(0.05, 0.2, (8, 16, 3)).astype(F32)
+        flags = irtps.flag_exact_r(1)
+        stop_tol = 4.0
+    ref, got = _solve_both(sc, dev, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
+    assert ref["counters"]["iterations"] == (2 if stop_tol else sc.iterations)
+    _compare_solve(ref, got, case)
+    assert got["counters"].tolist()[:4] == [0, 0, 0, 0]
+    for key in ("normals", "albedo", "depth", "indirect"):
+        assert np.array_equal(got[key], ref[key]), key
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 4, 1, seed=2)
+    job = dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+               env=T(sc.env, dev), spp=4, bounces=1, iterations=1, flags=flags)
+    with pytest.raises(irtps.IrtpsError) as e:  # the batched engine runs the gather only
+        irtps.batch_solve([job])
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("case", ["bowl64", "fbm160x120", "bowl64_exact_r2"])
 def test_solve_graph_replays_equal_eager(dev, case):
     """IRTPS_FLAG_GRAPH: the first call captures the solve into a hipGraph, later
     identical calls replay it.  Every replay, with eager solves and host
@@ -490,7 +581,8 @@ def test_solve_graph_replays_equal_eager(dev, case):
     per-path tracer at 64^2; the per-pixel tracer with heaviest-first tile order
     and fused correction at 160 x 120)."""
     say(f"case: solve replayed from a hipGraph, {case}")
-    if case == "bowl64":
+    extra = irtps.flag_exact_r(2) if case.endswith("exact_r2") else 0
+    if case.startswith("bowl64"):
         sc = scenes.bowl_64()
     else:
         sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=8, env_shape=(16, 32),
@@ -502,19 +594,19 @@ def test_solve_graph_replays_equal_eager(dev, case):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         args = (T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp, sc.bounces, sc.iterations)
-        ref = {k: H(v) for k, v in irtps.solve(*args, seed=3).items()}
-        ws = torch.empty(irtps.workspace_bytes(*args, seed=3), dtype=torch.uint8, device=dev)
+        ref = {k: H(v) for k, v in irtps.solve(*args, seed=3, flags=extra).items()}
+        ws = torch.empty(irtps.workspace_bytes(*args, seed=3, flags=extra), dtype=torch.uint8, device=dev)
         out = irtps._outputs_for(args[0], dev)
         for rep in range(4):
-            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH, out=out, workspace=ws)
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, out=out, workspace=ws)
             got = {k: H(v) for k, v in out.items()}
             for key in ("normals", "albedo", "depth", "indirect", "counters"):
                 assert np.array_equal(got[key], ref[key]), (rep, key)
-            irtps.solve(*args, seed=3)  # eager work between the replays
+            irtps.solve(*args, seed=3, flags=extra)  # eager work between the replays
             torch.cuda.synchronize()
     with pytest.raises(irtps.IrtpsError):  # the stop rule's read-back cannot be captured
         with torch.cuda.stream(stream):
-            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH, stop_tol=0.5)
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, stop_tol=0.5)
 
 
 def test_solve_T0_is_plain_ps(dev):
