@@ -473,11 +473,82 @@ int or_ps_solve_masked(int W, int Hh, int C, int K, const float* l, const float*
 }
 
 /* ------------------------------------------------------------------------- */
+/* The known environment as geometry (Sec. IV, stages 0, 3 and 4: the surface
+ * sits in a Cornell box).  Four vertical walls stand on the borders of the
+ * sample grid, x = 0, x = W - 1, y = 0 and y = Hh - 1, from below the surface
+ * up to height Z; above them the box is open to the environment map. */
+
+/* Does a ray from (x0, y0, z0) along d (d[2] > 0) leave through the open top,
+ * i.e. is it still inside the walls' footprint when it reaches height Z?
+ * Starting at or above Z it is out already. */
+static int box_top_exit(int W, int Hh, float Z, float x0, float y0, float z0, const float d[3]) {
+    if (z0 >= Z) return 1;
+    const float t = (Z - z0) / d[2];
+    const float x = fmaf(t, d[0], x0), y = fmaf(t, d[1], y0);
+    return x >= 0.0f && x <= (float)(W - 1) && y >= 0.0f && y <= (float)(Hh - 1);
+}
+
+/* A wall coordinate scaled to texels: floor, clamped to [0, n - 1]. */
+static int texel_index(float f, int n) {
+    if (!(f >= 0.0f)) return 0;
+    if (f >= (float)(n - 1)) return n - 1;
+    return (int)f;
+}
+
+int or_box_wall(int W, int Hh, const or_box* b, int i0, int j0, float z0, const float d[3], int* texel) {
+    const float xmax = (float)(W - 1), ymax = (float)(Hh - 1);
+    const float x0 = (float)i0, y0 = (float)j0;
+    /* travel to the wall plane ahead in x and in y */
+    float tx = INFINITY, ty = INFINITY;
+    if (d[0] > 0.0f) tx = (xmax - x0) / d[0];
+    else if (d[0] < 0.0f) tx = -x0 / d[0];
+    if (d[1] > 0.0f) ty = (ymax - y0) / d[1];
+    else if (d[1] < 0.0f) ty = -y0 / d[1];
+    const int xwall = tx <= ty; /* a corner counts as the x wall */
+    const float t = xwall ? tx : ty;
+    if (t == INFINITY) return -1; /* straight up */
+    const float zw = fmaf(t, d[2], z0);
+    if (!(zw < b->Z)) return -1; /* over the walls */
+    const int wall = xwall ? (d[0] > 0.0f ? 1 : 0) : (d[1] > 0.0f ? 3 : 2);
+    const float u = xwall ? fmaf(t, d[1], y0) : fmaf(t, d[0], x0); /* position along the wall */
+    const float len = xwall ? ymax : xmax;
+    const int col = texel_index((u / len) * (float)b->tw, b->tw);
+    const int row = texel_index((zw / b->Z) * (float)b->th, b->th);
+    *texel = (wall * b->th + row) * b->tw + col;
+    return wall;
+}
+
+/* Eq.2 on the walls' inner faces at texel centres, without the albedo: a wall
+ * faces into the box (normals +x, -x, +y, -y for walls 0..3), so its cosine
+ * with light k is a coordinate of l_k; the light reaches the point when its
+ * ray leaves through the open top (the walls shade each other; the surface
+ * casts no shadow on them). */
+void or_box_shade(int W, int Hh, int K, const or_box* b, const float* l, const float* s, float* Sw) {
+    const float xmax = (float)(W - 1), ymax = (float)(Hh - 1);
+    for (int wall = 0; wall < 4; ++wall)
+        for (int row = 0; row < b->th; ++row)
+            for (int col = 0; col < b->tw; ++col) {
+                const float len = wall < 2 ? ymax : xmax;
+                const float u = (((float)col + 0.5f) / (float)b->tw) * len;
+                const float z = (((float)row + 0.5f) / (float)b->th) * b->Z;
+                const float px = wall == 0 ? 0.0f : (wall == 1 ? xmax : u);
+                const float py = wall == 2 ? 0.0f : (wall == 3 ? ymax : u);
+                float* out = Sw + ((size_t)(wall * b->th + row) * b->tw + col) * K;
+                for (int k = 0; k < K; ++k) {
+                    const float* lk = l + 3 * k;
+                    const float c = wall == 0 ? lk[0] : (wall == 1 ? -lk[0] : (wall == 2 ? lk[1] : -lk[1]));
+                    float v = 0.0f;
+                    if (c > 0.0f && box_top_exit(W, Hh, b->Z, px, py, z, lk)) v = (s ? s[k] : 1.0f) * c;
+                    out[k] = v;
+                }
+            }
+}
+
 /* Eq.2 at every sample without the albedo: the irradiance from light k, zero
  * where the sample faces away or a shadow ray towards the light hits the
- * surface. */
+ * surface (or, with walls of height Z > 0, meets a wall). */
 static void direct_pixel(int W, int Hh, int K, const float* H, float hmax, const float* n,
-                         const float* l, const float* s, size_t p, float* out) {
+                         const float* l, const float* s, float Z, size_t p, float* out) {
     const int i = (int)(p % W), j = (int)(p / W);
     for (int k = 0; k < K; ++k) {
         const float* lk = l + 3 * k;
@@ -485,20 +556,26 @@ static void direct_pixel(int W, int Hh, int K, const float* H, float hmax, const
         float v = 0.0f;
         if (c > 0.0f) {
             int qi, qj;
-            const int blocked = or_traverse(H, W, Hh, hmax, i, j, lk, &qi, &qj);
+            int blocked = or_traverse(H, W, Hh, hmax, i, j, lk, &qi, &qj);
+            if (Z > 0.0f && !box_top_exit(W, Hh, Z, (float)i, (float)j, H[p], lk)) blocked = 1;
             if (!blocked) v = (s ? s[k] : 1.0f) * c;
         }
         out[k] = v;
     }
 }
 
-void or_direct(int W, int Hh, int K, const float* H, const float* n,
-               const float* l, const float* s, float* S) {
+void or_direct_box(int W, int Hh, int K, const float* H, const float* n, const float* l, const float* s,
+                   float Z, float* S) {
     const size_t npx = (size_t)W * Hh;
     const float hmax = max_height(H, npx);
 #pragma omp parallel for schedule(dynamic, 16)
     for (long long pp = 0; pp < (long long)npx; ++pp)
-        direct_pixel(W, Hh, K, H, hmax, n, l, s, (size_t)pp, S + (size_t)pp * K);
+        direct_pixel(W, Hh, K, H, hmax, n, l, s, Z, (size_t)pp, S + (size_t)pp * K);
+}
+
+void or_direct(int W, int Hh, int K, const float* H, const float* n,
+               const float* l, const float* s, float* S) {
+    or_direct_box(W, Hh, K, H, n, l, s, 0.0f, S);
 }
 
 /* The same at the listed samples only: S_sel[m][k] for pixel index pix[m]. */
@@ -507,7 +584,7 @@ void or_direct_at(int W, int Hh, int K, const float* H, const float* n,
     const float hmax = max_height(H, (size_t)W * Hh);
 #pragma omp parallel for schedule(dynamic, 4)
     for (long long m = 0; m < count; ++m)
-        direct_pixel(W, Hh, K, H, hmax, n, l, s, (size_t)pix[m], S_sel + (size_t)m * K);
+        direct_pixel(W, Hh, K, H, hmax, n, l, s, 0.0f, (size_t)pix[m], S_sel + (size_t)m * K);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -524,6 +601,7 @@ typedef struct {
     int He, We, spp, B, t, tag, M;
     float hmax;
     uint32_t key[2];
+    const or_box* box; /* walls, or NULL */
 } trace_ctx;
 
 /* One pixel's gather: out[k][c] = mean over the spp paths; events added to ev. */
@@ -564,10 +642,24 @@ static void trace_pixel(const trace_ctx* x, size_t p, float* out, uint64_t ev[4]
             int qi, qj;
             ++ev[0];
             if (!or_traverse(x->H, W, x->Hh, x->hmax, ci, cj, d, &qi, &qj)) {
-                int er, ec;
-                or_env_texel(d, x->He, x->We, &er, &ec);
-                const float* L = x->env + ((size_t)er * x->We + ec) * C;
-                for (int c = 0; c < C; ++c) envacc[c] = fmaf(beta[c], OR_PI * L[c], envacc[c]);
+                int tex = 0;
+                const int wall = x->box ? or_box_wall(W, x->Hh, x->box, ci, cj, x->H[(size_t)cj * W + ci], d, &tex)
+                                        : -1;
+                if (wall >= 0) {
+                    /* a wall: its Lambertian reflection of its own direct light,
+                     * weighted like a surface hit; the path ends there */
+                    float w[4];
+                    for (int c = 0; c < C; ++c) w[c] = beta[c] * x->box->albedo[(size_t)tex * C + c];
+                    for (int k = 0; k < K; ++k) {
+                        const float sq = x->box->S[(size_t)tex * K + k];
+                        for (int c = 0; c < C; ++c) acc[k * C + c] = fmaf(w[c], sq, acc[k * C + c]);
+                    }
+                } else {
+                    int er, ec;
+                    or_env_texel(d, x->He, x->We, &er, &ec);
+                    const float* L = x->env + ((size_t)er * x->We + ec) * C;
+                    for (int c = 0; c < C; ++c) envacc[c] = fmaf(beta[c], OR_PI * L[c], envacc[c]);
+                }
                 ++ev[2];
                 break;
             }
@@ -604,6 +696,7 @@ static trace_ctx make_trace_ctx(int W, int Hh, int C, int K, const float* H, con
     x.key[0] = (uint32_t)seed;
     x.key[1] = (uint32_t)(seed >> 32);
     x.M = 0;
+    x.box = NULL;
     if (flags & OR_FLAG_QUADRATURE) {
         x.M = 1;
         while (x.M * x.M < spp) ++x.M;
@@ -618,12 +711,13 @@ static trace_ctx make_trace_ctx(int W, int Hh, int C, int K, const float* H, con
  * of the albedos met before (the colour products of Fig. 5), and at an escape the
  * environment radiance times pi.  Up to B segments per path; G is the mean over
  * spp paths of the summed contributions. */
-void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
-              const float* rho, const float* S, const float* env, int He, int We,
-              int spp, int B, uint64_t seed, int t, int tag, int flags,
-              float* G, or_counters* cnt) {
+void or_trace_box(int W, int Hh, int C, int K, const float* H, const float* n,
+                  const float* rho, const float* S, const float* env, int He, int We,
+                  int spp, int B, uint64_t seed, int t, int tag, int flags,
+                  const or_box* box, float* G, or_counters* cnt) {
     const size_t npx = (size_t)W * Hh;
-    const trace_ctx x = make_trace_ctx(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, tag, flags);
+    trace_ctx x = make_trace_ctx(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, tag, flags);
+    x.box = box;
     uint64_t tot_seg = 0, tot_hit = 0, tot_esc = 0, tot_cont = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : tot_seg, tot_hit, tot_esc, tot_cont)
     for (long long pp = 0; pp < (long long)npx; ++pp) {
@@ -650,6 +744,13 @@ void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
         cnt->v[2] += tot_esc;
         cnt->v[3] += tot_cont;
     }
+}
+
+void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
+              const float* rho, const float* S, const float* env, int He, int We,
+              int spp, int B, uint64_t seed, int t, int tag, int flags,
+              float* G, or_counters* cnt) {
+    or_trace_box(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, tag, flags, NULL, G, cnt);
 }
 
 /* The same gather at the listed pixels only: G_sel[m][k][c] for pixel pix[m];
@@ -1041,14 +1142,30 @@ void or_integrate_robust(int W, int Hh, const float* n, const float* Hinit, int 
 }
 
 /* ------------------------------------------------------------------------- */
-int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
-              const float* rho, const float* l, const float* s, const float* env,
-              int He, int We, int spp, int B, uint64_t seed, float* I0, or_counters* cnt) {
+/* The walls' direct light for lights (l, s): a copy of *box with S set
+ * (caller frees *Sw). */
+static or_box shaded_box(int W, int Hh, int K, const or_box* box, const float* l, const float* s, float** Sw) {
+    or_box b = *box;
+    *Sw = (float*)malloc(sizeof(float) * 4 * (size_t)box->th * box->tw * K);
+    or_box_shade(W, Hh, K, box, l, s, *Sw);
+    b.S = *Sw;
+    return b;
+}
+
+int or_render_box(int W, int Hh, int C, int K, const float* H, const float* n,
+                  const float* rho, const float* l, const float* s, const float* env,
+                  int He, int We, int spp, int B, uint64_t seed, const or_box* box, float* I0,
+                  or_counters* cnt) {
     const size_t npx = (size_t)W * Hh;
     float* S = (float*)malloc(sizeof(float) * npx * K);
     float* G = (float*)malloc(sizeof(float) * npx * K * C);
-    or_direct(W, Hh, K, H, n, l, s, S);
-    or_trace(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, 0, OR_TAG_RENDER, 0, G, cnt);
+    float* Sw = NULL;
+    or_box b;
+    if (box) b = shaded_box(W, Hh, K, box, l, s, &Sw);
+    or_direct_box(W, Hh, K, H, n, l, s, box ? box->Z : 0.0f, S);
+    or_trace_box(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, 0, OR_TAG_RENDER, 0, box ? &b : NULL, G,
+                 cnt);
+    free(Sw);
     for (int k = 0; k < K; ++k)
         for (int c = 0; c < C; ++c)
             for (size_t p = 0; p < npx; ++p) {
@@ -1060,20 +1177,31 @@ int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
     return 0;
 }
 
+int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
+              const float* rho, const float* l, const float* s, const float* env,
+              int He, int We, int spp, int B, uint64_t seed, float* I0, or_counters* cnt) {
+    return or_render_box(W, Hh, C, K, H, n, rho, l, s, env, He, We, spp, B, seed, NULL, I0, cnt);
+}
+
 /* The IRT-PS loop (Sec. IV): plain PS and integration of the input images, then
  * T passes of trace -> subtract -> PS -> integrate, each warm-started from the
  * previous surface. */
-int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
-             const float* s, const float* env, int He, int We, int spp, int B,
-             int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
-             int cycles_warm, float stop_tol, float* n, float* rho, float* H, float* E,
-             or_counters* cnt) {
+int or_solve_box(int W, int Hh, int C, int K, const float* I0, const float* l,
+                 const float* s, const float* env, int He, int We, int spp, int B,
+                 int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
+                 int cycles_warm, float stop_tol, const or_box* box, float* n, float* rho, float* H,
+                 float* E, or_counters* cnt) {
     const size_t npx = (size_t)W * Hh;
+    if (box && OR_EXACT_R_OF(flags) > 0) return -2; /* the r-ray image has no per-light wall term */
     float* M = (float*)malloc(sizeof(float) * 3 * K);
     if (or_ps_matrix(K, l, s, M) != 0) {
         free(M);
         return -1;
     }
+    float* Sw = NULL;
+    or_box bx;
+    if (box) bx = shaded_box(W, Hh, K, box, l, s, &Sw); /* the lights do not move: once per solve */
+    const float Z = box ? box->Z : 0.0f;
     float* A = (float*)malloc(sizeof(float) * npx * K * C);
     float* A2 = (float*)malloc(sizeof(float) * npx * K * C);
     float* S = (float*)malloc(sizeof(float) * npx * K);
@@ -1087,7 +1215,7 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
         or_integrate(W, Hh, n, NULL, cycles_cold, H);
     if (E) memset(E, 0, sizeof(float) * npx * K * C);
     for (int t = 0; t < T; ++t) {
-        or_direct(W, Hh, K, H, n, l, s, S);
+        or_direct_box(W, Hh, K, H, n, l, s, Z, S);
         const int r_exact = OR_EXACT_R_OF(flags);
         if (r_exact > 0) {
             /* the paper's r-ray variant: one environment image, the same for
@@ -1102,8 +1230,8 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
             free(Er);
             free(ok);
         } else {
-            or_trace(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, OR_TAG_SOLVE,
-                     flags & OR_FLAG_QUADRATURE, G, cnt);
+            or_trace_box(W, Hh, C, K, H, n, rho, S, env, He, We, spp, B, seed, t, OR_TAG_SOLVE,
+                         flags & OR_FLAG_QUADRATURE, box ? &bx : NULL, G, cnt);
         }
         or_correct(W, Hh, C, K, rho_mode, flags, I0, A, G, S, rho, E, A2);
         float* tmp = A; A = A2; A2 = tmp;
@@ -1131,5 +1259,25 @@ int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
     free(S);
     free(G);
     free(Hn);
+    free(Sw);
     return 0;
+}
+
+int or_solve(int W, int Hh, int C, int K, const float* I0, const float* l,
+             const float* s, const float* env, int He, int We, int spp, int B,
+             int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
+             int cycles_warm, float stop_tol, float* n, float* rho, float* H, float* E,
+             or_counters* cnt) {
+    return or_solve_box(W, Hh, C, K, I0, l, s, env, He, We, spp, B, T, seed, rho_mode, flags, cycles_cold,
+                        cycles_warm, stop_tol, NULL, n, rho, H, E, cnt);
+}
+
+void or_box_wall_n(int W, int Hh, const or_box* b, long long count, const int* ij, const float* z0,
+                   const float* d, int* wall_texel) {
+    for (long long r = 0; r < count; ++r) {
+        int tex = -1;
+        const int w = or_box_wall(W, Hh, b, ij[2 * r], ij[2 * r + 1], z0[r], d + 3 * r, &tex);
+        wall_texel[2 * r] = w;
+        wall_texel[2 * r + 1] = w >= 0 ? tex : -1;
+    }
 }

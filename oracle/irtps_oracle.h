@@ -89,11 +89,40 @@ int or_ps_solve_masked(int W, int Hh, int C, int K, const float* l, const float*
 void or_direct(int W, int Hh, int K, const float* H, const float* n,
                const float* l, const float* s, float* S);
 
+/* The known environment as geometry (Sec. IV stages 0, 3, 4: a Cornell box):
+ * four vertical Lambertian walls on the borders of the sample grid (wall 0 at
+ * x = 0, 1 at x = W - 1, 2 at y = 0, 3 at y = Hh - 1, facing into the box) up
+ * to height Z > 0, open above to the environment map.  Each wall is a texture
+ * of th rows (height 0..Z) by tw columns (along the wall, 0..length). */
+typedef struct {
+    float Z;
+    int th, tw;
+    const float* albedo; /* [4][th][tw][C] */
+    const float* S;      /* [4][th][tw][K] the walls' direct irradiance (or_box_shade) */
+} or_box;
+/* The wall a ray from sample (i0, j0) at height z0 along d meets below Z, and
+ * its texel (wall th + row) tw + col; -1 when it leaves through the top. */
+int or_box_wall(int W, int Hh, const or_box* b, int i0, int j0, float z0, const float d[3], int* texel);
+/* Eq.2 on the walls at texel centres: Sw[wall][row][col][k] = s_k max(0, n_wall.l_k)
+ * V_k, V_k = 1 when the light's ray leaves through the open top. */
+void or_box_shade(int W, int Hh, int K, const or_box* b, const float* l, const float* s, float* Sw);
+/* or_direct with the walls (Z > 0) as occluders too. */
+void or_direct_box(int W, int Hh, int K, const float* H, const float* n, const float* l, const float* s,
+                   float Z, float* S);
+
 /* Monte Carlo gather of indirect light (Eq.5-7): G[k][c][p]. */
 void or_trace(int W, int Hh, int C, int K, const float* H, const float* n,
               const float* rho, const float* S, const float* env, int He, int We,
               int spp, int B, uint64_t seed, int t, int tag, int flags,
               float* G, or_counters* cnt);
+/* or_trace with the walls: a ray that leaves the surface and meets a wall
+ * below Z adds the wall texel's albedo (times the path's albedo product) times
+ * its direct irradiance for every light, like a surface hit, and ends; over the
+ * walls it takes the environment map.  box->S must be set. */
+void or_trace_box(int W, int Hh, int C, int K, const float* H, const float* n,
+                  const float* rho, const float* S, const float* env, int He, int We,
+                  int spp, int B, uint64_t seed, int t, int tag, int flags,
+                  const or_box* box, float* G, or_counters* cnt);
 /* Pixel-subset forms (same per-pixel arithmetic) for checks at full image
  * sizes: rows for the pixel indices pix[0..count). */
 void or_direct_at(int W, int Hh, int K, const float* H, const float* n,
@@ -132,6 +161,21 @@ void or_integrate_robust(int W, int Hh, const float* n, const float* Hinit, int 
 int or_render(int W, int Hh, int C, int K, const float* H, const float* n,
               const float* rho, const float* l, const float* s, const float* env,
               int He, int We, int spp, int B, uint64_t seed, float* I0, or_counters* cnt);
+
+/* or_render and or_solve with the walls (box->S is computed inside from the
+ * lights; box may be NULL).  or_solve_box returns -2 for walls with the r-ray
+ * variant. */
+int or_render_box(int W, int Hh, int C, int K, const float* H, const float* n,
+                  const float* rho, const float* l, const float* s, const float* env,
+                  int He, int We, int spp, int B, uint64_t seed, const or_box* box, float* I0,
+                  or_counters* cnt);
+int or_solve_box(int W, int Hh, int C, int K, const float* I0, const float* l,
+                 const float* s, const float* env, int He, int We, int spp, int B,
+                 int T, uint64_t seed, int rho_mode, int flags, int cycles_cold,
+                 int cycles_warm, float stop_tol, const or_box* box, float* n, float* rho, float* H,
+                 float* E, or_counters* cnt);
+void or_box_wall_n(int W, int Hh, const or_box* b, long long count, const int* ij, const float* z0,
+                   const float* d, int* wall_texel);
 
 /* The whole IRT-PS loop (Sec. IV): T iterations, or fewer when stop_tol > 0
  * and an iteration changes the surface by less than stop_tol, D_H =

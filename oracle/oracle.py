@@ -32,6 +32,25 @@ class Counters(ct.Structure):
                 "continuations": self.v[3], "iterations": self.v[4]}
 
 
+class OrBox(ct.Structure):
+    _fields_ = [("Z", ct.c_float), ("th", ct.c_int), ("tw", ct.c_int), ("albedo", ct.c_void_p),
+                ("S", ct.c_void_p)]
+
+
+def _box(box, keep):
+    """A box dict {"Z", "albedo" [4][th][tw][C], optional "S" [4][th][tw][K]} as an
+    or_box (arrays kept alive in `keep`), or None."""
+    if box is None:
+        return None
+    alb = _f32(box["albedo"])
+    assert alb.ndim == 4 and alb.shape[0] == 4
+    Sw = _f32(box.get("S"))
+    keep += [alb, Sw]
+    b = OrBox(float(box["Z"]), alb.shape[1], alb.shape[2], alb.ctypes.data,
+              None if Sw is None else Sw.ctypes.data)
+    return ct.byref(b), b
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -75,6 +94,18 @@ def lib():
         L.or_solve.argtypes = ([ct.c_int] * 4 + [_f] * 4 + [ct.c_int] * 5 + [ct.c_uint64]
                                + [ct.c_int] * 4 + [ct.c_float] + [_f] * 4 + [ct.POINTER(Counters)])
         L.or_solve.restype = ct.c_int
+        _bp = ct.POINTER(OrBox)
+        L.or_direct_box.argtypes = [ct.c_int] * 3 + [_f] * 4 + [ct.c_float, _f]
+        L.or_box_shade.argtypes = [ct.c_int] * 3 + [_bp, _f, _f, _f]
+        L.or_box_wall_n.argtypes = [ct.c_int, ct.c_int, _bp, ct.c_longlong, _i, _f, _f, _i]
+        L.or_trace_box.argtypes = ([ct.c_int] * 4 + [_f] * 5 + [ct.c_int] * 4 + [ct.c_uint64]
+                                   + [ct.c_int] * 3 + [_bp, _f, ct.POINTER(Counters)])
+        L.or_render_box.argtypes = ([ct.c_int] * 4 + [_f] * 6 + [ct.c_int] * 4 + [ct.c_uint64]
+                                    + [_bp, _f, ct.POINTER(Counters)])
+        L.or_render_box.restype = ct.c_int
+        L.or_solve_box.argtypes = ([ct.c_int] * 4 + [_f] * 4 + [ct.c_int] * 5 + [ct.c_uint64]
+                                   + [ct.c_int] * 4 + [ct.c_float, _bp] + [_f] * 4 + [ct.POINTER(Counters)])
+        L.or_solve_box.restype = ct.c_int
         L.or_num_threads.restype = ct.c_int
         _ll = ct.c_longlong
         L.or_sincos_quarter_n.argtypes = [_ll, _f, _f, _f]
@@ -230,26 +261,54 @@ def ps_solve_masked(l, s, A, S):
     return n, rho
 
 
-def direct(H, n, l, s=None):
+def direct(H, n, l, s=None, box_z=0.0):
+    """S [H][W][K]; with box_z > 0 the walls of that height occlude too."""
     H, n, l = _f32(H), _f32(n), _f32(l)
     Hh, W = H.shape
     K = l.shape[0]
     S = np.zeros((Hh, W, K), np.float32)
-    lib().or_direct(W, Hh, K, _p(H), _p(n), _p(l), _p(_f32(s)), _p(S))
+    lib().or_direct_box(W, Hh, K, _p(H), _p(n), _p(l), _p(_f32(s)), float(box_z), _p(S))
     return S
 
 
-def trace(H, n, rho, S, env, spp, B, seed, t=0, tag=TAG_SOLVE, flags=0):
+def box_shade(W, Hh, box, l, s=None):
+    """The walls' direct irradiance [4][th][tw][K] at texel centres."""
+    l = _f32(l)
+    keep = []
+    bp, b = _box(box, keep)
+    Sw = np.zeros((4, b.th, b.tw, l.shape[0]), np.float32)
+    lib().or_box_shade(W, Hh, l.shape[0], bp, _p(l), _p(_f32(s)), _p(Sw))
+    return Sw
+
+
+def box_wall_n(W, Hh, box, ij, z0, d):
+    """Per ray (origin sample ij [R][2], height z0 [R], direction d [R][3]): the
+    wall met below Z (-1: through the top) and its texel index."""
+    keep = []
+    bp, _ = _box(box, keep)
+    ij = np.ascontiguousarray(ij, dtype=np.int32)
+    z0, d = _f32(z0), _f32(d)
+    out = np.zeros((len(ij), 2), np.int32)
+    lib().or_box_wall_n(W, Hh, bp, len(ij), ij.ctypes.data_as(_i), _p(z0), _p(d), out.ctypes.data_as(_i))
+    return out[:, 0], out[:, 1]
+
+
+def trace(H, n, rho, S, env, spp, B, seed, t=0, tag=TAG_SOLVE, flags=0, box=None):
+    """G [K][C][H][W] and the event counts; box needs "S" (box_shade)."""
     H, n, rho, S, env = map(_f32, (H, n, rho, S, env))
     Hh, W = H.shape
     C = rho.shape[0]
     K = S.shape[2]
     He, We = env.shape[0], env.shape[1]
     assert env.shape[2] == C and C <= 4
+    keep = []
+    bx = _box(box, keep)
+    if bx is not None:
+        assert box["S"] is not None and np.shape(box["S"])[3] == K and np.shape(box["albedo"])[3] == C
     G = np.zeros((K, C, Hh, W), np.float32)
     cnt = Counters()
-    lib().or_trace(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(S), _p(env), He, We, spp, B,
-                   int(seed), t, tag, flags, _p(G), ct.byref(cnt))
+    lib().or_trace_box(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(S), _p(env), He, We, spp, B,
+                       int(seed), t, tag, flags, None if bx is None else bx[0], _p(G), ct.byref(cnt))
     return G, cnt.as_dict()
 
 
@@ -340,25 +399,28 @@ def integrate_robust(n, Hinit=None, cycles=8, delta=ROBUST_DELTA, rounds=ROBUST_
     return H
 
 
-def render(H, n, rho, l, s, env, spp, B, seed=0):
+def render(H, n, rho, l, s, env, spp, B, seed=0, box=None):
     H, n, rho, l, s, env = map(_f32, (H, n, rho, l, s, env))
     Hh, W = H.shape
     C = rho.shape[0]
     K = l.shape[0]
+    keep = []
+    bx = _box(box, keep)
     I0 = np.zeros((K, C, Hh, W), np.float32)
     cnt = Counters()
-    lib().or_render(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(l), _p(s), _p(env),
-                    env.shape[0], env.shape[1], spp, B, int(seed), _p(I0), ct.byref(cnt))
+    lib().or_render_box(W, Hh, C, K, _p(H), _p(n), _p(rho), _p(l), _p(s), _p(env),
+                        env.shape[0], env.shape[1], spp, B, int(seed), None if bx is None else bx[0], _p(I0),
+                        ct.byref(cnt))
     return I0, cnt.as_dict()
 
 
 def render_scene(sc):
     return render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity,
-                  sc.env, sc.render_spp, sc.render_bounces, 0)
+                  sc.env, sc.render_spp, sc.render_bounces, 0, box=getattr(sc, "box", None))
 
 
 def solve(I0, l, s, env, spp, B, T, seed=0, rho_mode=RHO_FIT, flags=0,
-          cycles_cold=8, cycles_warm=4, stop_tol=0.0):
+          cycles_cold=8, cycles_warm=4, stop_tol=0.0, box=None):
     I0, l, s, env = map(_f32, (I0, l, s, env))
     K, C, Hh, W = I0.shape
     n = np.zeros((Hh, W, 3), np.float32)
@@ -366,9 +428,14 @@ def solve(I0, l, s, env, spp, B, T, seed=0, rho_mode=RHO_FIT, flags=0,
     H = np.zeros((Hh, W), np.float32)
     E = np.zeros_like(I0)
     cnt = Counters()
-    rc = lib().or_solve(W, Hh, C, K, _p(I0), _p(l), _p(s), _p(env), env.shape[0], env.shape[1],
-                        spp, B, T, int(seed), rho_mode, flags, cycles_cold, cycles_warm,
-                        float(stop_tol), _p(n), _p(rho), _p(H), _p(E), ct.byref(cnt))
+    keep = []
+    bx = _box(box, keep)
+    rc = lib().or_solve_box(W, Hh, C, K, _p(I0), _p(l), _p(s), _p(env), env.shape[0], env.shape[1],
+                            spp, B, T, int(seed), rho_mode, flags, cycles_cold, cycles_warm,
+                            float(stop_tol), None if bx is None else bx[0], _p(n), _p(rho), _p(H), _p(E),
+                            ct.byref(cnt))
+    if rc == -2:
+        raise ValueError("walls with the r-ray variant")
     if rc != 0:
         raise ValueError("singular light configuration")
     return {"normals": n, "albedo": rho, "depth": H, "indirect": E, "counters": cnt.as_dict()}

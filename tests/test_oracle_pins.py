@@ -1125,3 +1125,150 @@ def test_fill_missing_pull_push():
     sib = [E[0, 2, 4], E[0, 3, 4], E[0, 3, 5]]  # block rows 2-3, columns 4-5, in (0,0),(1,0),(0,1),(1,1) order
     assert G[0, 2, 5] == np.float32(np.float32(np.float32(sib[0] + sib[1]) + sib[2]) / np.float32(3))
     assert (O.fill_missing(E, np.zeros_like(ok)) == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# The known environment as geometry (Sec. IV stages 0, 3 and 4): walls on the
+# borders of the sample grid, up to height Z, open above.
+def _wall_box(Z, th, tw, C, K, rng=None, S_val=None):
+    rng = rng or np.random.default_rng(0)
+    alb = rng.uniform(0.2, 0.9, (4, th, tw, C)).astype(F32)
+    box = dict(Z=Z, albedo=alb)
+    if S_val is not None:
+        box["S"] = np.full((4, th, tw, K), S_val, F32)
+    return box
+
+
+def test_box_below_the_surface_changes_nothing():
+    """Walls lower than every sample can never be met: a ray that leaves the
+    surface crosses the border above it, so above the walls.  Gather, direct
+    light, render and the loop then equal the environment-only oracle bit for bit."""
+    sc = scenes.tiny_scene(17, 13, seed=3, channels=3, num_lights=6, amp=3.0)
+    Hf = (sc.heights - sc.heights.min() + 1.0).astype(F32)
+    box = _wall_box(0.5, 3, 5, 3, 6)
+    box["S"] = O.box_shade(17, 13, box, sc.light_dirs, sc.light_intensity)
+    S = O.direct(Hf, sc.normals, sc.light_dirs, sc.light_intensity)
+    assert np.array_equal(O.direct(Hf, sc.normals, sc.light_dirs, sc.light_intensity, box_z=0.5), S)
+    G0, c0 = O.trace(Hf, sc.normals, sc.albedo, S, sc.env, 16, 3, 5)
+    G1, c1 = O.trace(Hf, sc.normals, sc.albedo, S, sc.env, 16, 3, 5, box=box)
+    assert np.array_equal(G0, G1) and c0 == c1
+    I0, _ = O.render(Hf, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 2, 1)
+    I1, _ = O.render(Hf, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 2, 1, box=box)
+    assert np.array_equal(I0, I1)
+
+
+def _corner_factor(a, b, c):
+    """View factor from a differential area to a parallel a x b rectangle at
+    distance c with one corner above the area (the standard closed form)."""
+    X, Y = a / c, b / c
+    return (X / math.sqrt(1 + X * X) * math.atan(Y / math.sqrt(1 + X * X))
+            + Y / math.sqrt(1 + Y * Y) * math.atan(X / math.sqrt(1 + Y * Y))) / (2 * math.pi)
+
+
+def test_box_walls_take_their_view_factor():
+    """Eq.5-7 on a flat floor in the box, one bounce, uniform wall albedo and
+    wall irradiance, uniform environment: a sample sees the open top through the
+    view factor F of the rectangle of the walls' rims (four corner rectangles
+    from the sample's foot), so G = rho_w S_w (1 - F) + pi L F.  Cosine-weighted
+    quadrature over 128^2 strata, at the centre and at off-centre samples."""
+    W, Hh, Z, K = 9, 9, 4.0, 2
+    Hf = np.zeros((Hh, W), F32)
+    n = np.zeros((Hh, W, 3), F32)
+    n[..., 2] = 1
+    rho = np.full((3, Hh, W), 0.5, F32)
+    env = np.empty((2, 4, 3), F32)
+    env[:] = np.array([0.1, 0.2, 0.3], F32)
+    box = dict(Z=Z, albedo=np.empty((4, 4, 6, 3), F32), S=np.empty((4, 4, 6, K), F32))
+    box["albedo"][:] = np.array([0.6, 0.3, 0.9], F32)
+    box["S"][..., 0], box["S"][..., 1] = 1.5, 0.25
+    M = 128
+    G, cnt = O.trace(Hf, n, rho, np.zeros((Hh, W, K), F32), env, M * M, 1, 0, flags=O.FLAG_QUADRATURE, box=box)
+    assert cnt["hits"] == 0
+    for i, j in ((4, 4), (2, 5), (1, 7), (6, 1)):
+        F = sum(_corner_factor(a, b, Z) for a in (i, W - 1 - i) for b in (j, Hh - 1 - j))
+        ref = np.array([[box["albedo"][0, 0, 0, c] * box["S"][0, 0, 0, k] * (1 - F) + math.pi * env[0, 0, c] * F
+                         for c in range(3)] for k in range(K)])
+        assert np.abs(G[:, :, j, i] - ref).max() <= 2e-3 * np.abs(ref).max(), (i, j)
+
+
+def test_box_wall_and_texel_against_binary64_geometry():
+    """The wall a ray meets and its texel, against an independent binary64
+    intersection with the four planes (nearest plane ahead, height below Z),
+    for rays from every kind of sample, away from texel edges, corners and the
+    rim."""
+    rng = np.random.default_rng(5)
+    W, Hh, Z, th, tw = 23, 17, 6.0, 5, 7
+    box = _wall_box(Z, th, tw, 1, 1)
+    R = 20000
+    ij = np.stack([rng.integers(0, W, R), rng.integers(0, Hh, R)], 1).astype(np.int32)
+    ij[:50, 0] = 0
+    ij[50:100, 1] = Hh - 1
+    z0 = rng.uniform(-2.0, 8.0, R).astype(F32)
+    d = rng.standard_normal((R, 3))
+    d[:, 2] = np.abs(d[:, 2]) * rng.choice([-1, 1], R, p=[0.2, 0.8])
+    d[:300, 1] = 0.0  # rays along x
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(F32)
+    wall, tex = O.box_wall_n(W, Hh, box, ij, z0, d)
+    x0, y0 = ij[:, 0].astype(np.float64), ij[:, 1].astype(np.float64)
+    dd = d.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = np.where(dd[:, 0] > 0, (W - 1 - x0) / dd[:, 0], np.where(dd[:, 0] < 0, -x0 / dd[:, 0], np.inf))
+        ty = np.where(dd[:, 1] > 0, (Hh - 1 - y0) / dd[:, 1], np.where(dd[:, 1] < 0, -y0 / dd[:, 1], np.inf))
+    xw = tx <= ty
+    t = np.where(xw, tx, ty)
+    zw = z0 + t * dd[:, 2]
+    ref_wall = np.where(zw < Z, np.where(xw, np.where(dd[:, 0] > 0, 1, 0), np.where(dd[:, 1] > 0, 3, 2)), -1)
+    u = np.where(xw, y0 + t * dd[:, 1], x0 + t * dd[:, 0]) / np.where(xw, Hh - 1, W - 1)
+    col = np.clip(np.floor(u * tw), 0, tw - 1)
+    row = np.clip(np.floor(zw / Z * th), 0, th - 1)
+    ref_tex = np.where(ref_wall >= 0, (ref_wall * th + row) * tw + col, -1)
+    edge = lambda f: np.abs(f - np.round(f)) < 1e-4
+    clear = (np.abs(tx - ty) > 1e-4 * np.maximum(t, 1)) & (np.abs(zw - Z) > 1e-4) & ~edge(u * tw) & \
+        ~edge(zw / Z * th)
+    assert clear.mean() > 0.95 and (ref_wall[clear] >= 0).mean() > 0.2 and (ref_wall[clear] < 0).mean() > 0.2
+    assert np.array_equal(wall[clear], ref_wall[clear])
+    assert np.array_equal(tex[clear], ref_tex[clear].astype(np.int32))
+
+
+def test_box_shade_against_the_opposite_rim():
+    """Eq.2 on the walls for lights in the x-z plane at elevation e: the inner
+    face of wall 0 (x = 0, facing +x) gets s cos e where the light clears the
+    rim of wall 1, i.e. at texel-centre heights z >= Z - (W - 1) tan e, and 0
+    below; wall 1 faces away and walls 2, 3 are edge-on (cosine 0)."""
+    W, Hh, Z, th, tw = 21, 15, 12.0, 24, 3
+    box = _wall_box(Z, th, tw, 1, 1)
+    es = np.radians([10.0, 25.0, 40.0, 70.0])
+    l = np.stack([np.cos(es), np.zeros(4), np.sin(es)], 1).astype(F32)
+    s = np.array([1.0, 0.7, 1.3, 0.9], F32)
+    Sw = O.box_shade(W, Hh, box, l, s)
+    zc = (np.arange(th) + 0.5) / th * Z
+    for k, e in enumerate(es):
+        lit = zc >= Z - (W - 1) * math.tan(e)
+        away = np.abs(zc - (Z - (W - 1) * math.tan(e))) > 1e-3
+        ref = np.where(lit, F32(s[k] * l[k, 0]), 0.0).astype(F32)
+        for col in range(tw):
+            assert np.array_equal(Sw[0, away, col, k], ref[away]), k
+        assert lit.any() or e < 0.6
+        assert (Sw[1:, ..., k] == 0).all()
+
+
+def test_direct_with_walls_against_the_rim():
+    """Direct light on a flat floor inside walls of height Z, lights in the x-z
+    plane at elevation e towards +x: a sample at column i is lit (S = s sin e)
+    when its shadow ray clears the rim of wall 1 before x = W - 1, i.e.
+    i + Z / tan e <= W - 1, and dark otherwise (the floor casts no shadow)."""
+    W, Hh, Z = 40, 6, 5.0
+    Hf = np.zeros((Hh, W), F32)
+    n = np.zeros((Hh, W, 3), F32)
+    n[..., 2] = 1
+    es = np.radians([15.0, 30.0, 55.0])
+    l = np.stack([np.cos(es), np.zeros(3), np.sin(es)], 1).astype(F32)
+    S = O.direct(Hf, n, l, None, box_z=Z)
+    i = np.arange(W)
+    for k, e in enumerate(es):
+        edge = i + Z / math.tan(e)
+        away = np.abs(edge - (W - 1)) > 1e-3
+        ref = np.where(edge <= W - 1, F32(l[k, 2]), 0.0).astype(F32)
+        for j in range(Hh):
+            assert np.array_equal(S[j, away, k], ref[away]), (k, j)
+    assert (O.direct(Hf, n, l) > 0).all()  # without walls every sample is lit
