@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define IRTPS_ABI_VERSION 2
+#define IRTPS_ABI_VERSION 3
 
 typedef enum irtps_status {
     IRTPS_OK = 0,
@@ -104,6 +104,35 @@ enum { IRTPS_TAG_SOLVE = 0, IRTPS_TAG_RENDER = 1 };
  * solves: T, or fewer with stop_tol). */
 #define IRTPS_NUM_COUNTERS 5
 
+/* The known environment as geometry (Sec. IV, stages 0, 3 and 4: the surface
+ * sits in a Cornell box whose walls may carry textures).  Four vertical
+ * Lambertian walls stand on the borders of the sample grid -- wall 0 at x = 0,
+ * 1 at x = W - 1, 2 at y = 0, 3 at y = H - 1, each facing into the box -- from
+ * below the surface up to height Z; above them the box is open to the
+ * environment map.  Each wall is a texture of tex_h rows (heights 0..Z) by
+ * tex_w columns (along the wall: y from 0 to H - 1 on walls 0 and 1, x from 0
+ * to W - 1 on walls 2 and 3), nearest texel.
+ *
+ * With a box, (1) a shadow ray (direct light, Eq.2) is blocked too when it
+ * meets a wall, i.e. when it is outside the footprint [0, W-1] x [0, H-1] on
+ * reaching height Z from below; (2) each wall texel's direct irradiance
+ * S_w[k] = s_k max(0, n_wall . l_k) V_k is taken at its centre, V_k = 1 when
+ * the light's ray leaves through the open top (walls shade walls; the surface
+ * casts no shadow on them); (3) a gathered ray that leaves the surface and
+ * meets a wall below Z (the first wall plane ahead, a corner counting as the x
+ * wall) adds, for every light k, the path's albedo product times the texel's
+ * albedo times S_w[k] -- the wall's Lambertian reflection of its own direct
+ * light, weighted like a surface hit -- and ends the path; a ray over the
+ * walls takes the environment map.  Texel of a wall point at height z and
+ * position u along a wall of length len: row = floor(z / Z tex_h), col =
+ * floor(u / len tex_w), each clamped to the texture.  Counter [2] counts wall
+ * hits with the escapes. */
+typedef struct irtps_box {
+    float height;             /* Z > 0, pixel units of the depth */
+    int32_t tex_h, tex_w;     /* 1..4096 each */
+    const float* albedo_dev;  /* [4][tex_h][tex_w][C] wall albedo */
+} irtps_box;
+
 typedef struct irtps_problem {
     int32_t width, height, channels, num_lights; /* W, H, C in {1,3}, K in 3..64 */
     const float* images_dev;          /* [K][C][H][W] input images I0 (stage 0) */
@@ -111,6 +140,10 @@ typedef struct irtps_problem {
     const float* light_intensity_host;/* [K] or NULL (all 1) */
     const float* env_dev;             /* [He][We][C] radiance of the known surroundings */
     int32_t env_h, env_w;             /* He, We >= 1 */
+    const irtps_box* box;             /* host pointer, or NULL: the environment map alone.
+                                         irtps_solve and irtps_solve_static only (the batched
+                                         and served engines refuse it); not with
+                                         IRTPS_FLAG_EXACT_R */
 } irtps_problem;
 
 typedef struct irtps_params {
@@ -251,12 +284,20 @@ int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyr
                         void* stream);
 
 /* Direct irradiance without albedo (Eq.2): S[q][k] = s_k max(0, n(q).l_k) V_k(q),
- * V_k = 1 when the shadow ray from sample q towards light k escapes the surface.
- * pyramid_dev from irtps_build_pyramid of the same depth.  S_dev is [H][W][K]. */
+ * V_k = 1 when the shadow ray from sample q towards light k escapes the surface
+ * (and, with box non-NULL, leaves through the box's open top; only
+ * box->height is read).  pyramid_dev from irtps_build_pyramid of the same
+ * depth.  S_dev is [H][W][K]. */
 int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev,
                  const float* normals_dev, const float* light_dirs_host,
                  const float* light_intensity_host, const float* pyramid_dev,
-                 float* S_dev, void* stream);
+                 float* S_dev, const irtps_box* box, void* stream);
+
+/* The box walls' direct irradiance (Eq.2 on the walls, at texel centres; see
+ * irtps_box): wall_S_dev [4][tex_h][tex_w][K]. */
+int irtps_box_shade(int32_t W, int32_t H, int32_t K, const irtps_box* box,
+                    const float* light_dirs_host, const float* light_intensity_host,
+                    float* wall_S_dev, void* stream);
 
 /* Monte Carlo gather of indirect light (Sec. IV, Eq.5-7): per pixel, spp
  * cosine-weighted paths of up to B segments on the current surface.  A hit at
@@ -264,13 +305,16 @@ int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev,
  * beta_c pi L_env,c(d) and ends the path; beta is the product of the albedos
  * met so far.  G_dev[p][k][c] = (sum over paths) / spp.  Sample s, segment b of
  * pixel p = j W + i draw Philox4x32-10(key = seed, counter = (p, s, t 256 + b,
- * tag)).  counters_dev (IRTPS_NUM_COUNTERS uint64, accumulated) may be NULL. */
+ * tag)).  counters_dev (IRTPS_NUM_COUNTERS uint64, accumulated) may be NULL.
+ * With box non-NULL, an escaping ray that meets a wall below its rim adds the
+ * wall term instead (see irtps_box), wall_S_dev from irtps_box_shade. */
 int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev,
                 const float* normals_dev, const float* albedo_dev, const float* S_dev,
                 const float* env_dev, int32_t env_h, int32_t env_w,
                 const float* pyramid_dev, int32_t spp, int32_t B, uint64_t seed,
                 int32_t t, int32_t tag, int32_t flags, float* G_dev,
-                uint64_t* counters_dev, void* stream);
+                uint64_t* counters_dev, const irtps_box* box, const float* wall_S_dev,
+                void* stream);
 
 /* The r-ray variant's trace (Sec. IV, the tracing paragraph; Fig. 5): per
  * pixel p = j W + i, the single path of sample 0 (the counters irtps_trace
@@ -310,17 +354,18 @@ int irtps_correct(int32_t W, int32_t H, int32_t C, int32_t K, int32_t rho_mode,
                   const float* G_dev, const float* S_dev, const float* albedo_dev,
                   float* E_dev, float* A_next_dev, void* stream);
 
-/* Bytes of workspace for irtps_render. */
-int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, size_t* bytes);
+/* Bytes of workspace for irtps_render (box may be NULL). */
+int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, const irtps_box* box,
+                                 size_t* bytes);
 /* Forward render of a known surface (Sec. III, n-bounce sum truncated at B + 1):
  * images = albedo (S + G) with G traced under tag RENDER, t = 0.  B = 0 renders
- * direct light only. */
+ * direct light only.  box (may be NULL) as in irtps_problem. */
 int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev,
                  const float* normals_dev, const float* albedo_dev,
                  const float* light_dirs_host, const float* light_intensity_host,
                  const float* env_dev, int32_t env_h, int32_t env_w, int32_t spp,
                  int32_t B, uint64_t seed, float* images_dev, void* ws_dev,
-                 size_t ws_bytes, void* stream);
+                 size_t ws_bytes, const irtps_box* box, void* stream);
 
 /* ---- batched mode --------------------------------------------------------- */
 /* Options of irtps_batch_solve. */

@@ -42,8 +42,8 @@ int fill_job(kern::JobDesc& J, const irtps_problem& pr, const irtps_params& pa, 
              char* region) {
     STATUS_TRY(check_problem(&pr, &pa));
     if (!out.normals_dev || !out.albedo_dev || !out.depth_dev) return IRTPS_ERR_INVALID_ARG;
-    // the multi-job engine runs the gather and least-squares integration only
-    if (pa.flags & (IRTPS_FLAG_ROBUST_INTEGRATION | IRTPS_FLAG_EXACT_R_MASK)) return IRTPS_ERR_INVALID_ARG;
+    // the multi-job engine runs the gather (environment map only) and least-squares integration only
+    if ((pa.flags & (IRTPS_FLAG_ROBUST_INTEGRATION | IRTPS_FLAG_EXACT_R_MASK)) || pr.box) return IRTPS_ERR_INVALID_ARG;
     std::memset(&J, 0, sizeof(J));
     const int W = pr.width, H = pr.height, C = pr.channels, K = pr.num_lights;
     kern::PsMatrix M;

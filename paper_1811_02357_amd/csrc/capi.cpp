@@ -49,7 +49,7 @@ int irtps_ps_matrix(int32_t K, const float* light_dirs_host, const float* light_
 int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* params, size_t* bytes) {
     STATUS_TRY(check_problem(problem, params));
     if (!bytes) return IRTPS_ERR_INVALID_ARG;
-    *bytes = solve_workspace_bytes(problem->width, problem->height, problem->channels, problem->num_lights, params);
+    *bytes = solve_workspace_bytes(problem, params);
     return IRTPS_OK;
 }
 
@@ -85,6 +85,12 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
         robust.cycles = kern::kRobustCycles;
     }
 
+    // the walls' direct light: the lights do not move, so once per solve
+    const irtps_box* box = pr->box;
+    float* wall_S = box ? reinterpret_cast<float*>(base + lay.total + tail_bytes(W, H, C, pa)) : nullptr;
+    if (box) HIP_TRY(kern::box_shade(W, H, box_args(box), Ls, wall_S, st));
+    const float box_z = box ? box->height : 0.0f;
+
     if (cnt) HIP_TRY(kern::fill_u64_zero(cnt, IRTPS_NUM_COUNTERS, st));
     // t = 0: plain photometric stereo and integration (stage 1)
     HIP_TRY(kern::ps_solve(npx, C, K, M, pr->images_dev, out->normals_dev, out->albedo_dev, st));
@@ -96,7 +102,8 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
     int run = 0;  // IRT iterations run
     for (int t = 0; t < pa->iterations; ++t) {
         HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
-        HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
+        HIP_TRY(kern::direct(sa, out->normals_dev, Ls, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st,
+                             box_z));
         // stage 5: subtract; the cumulative reading starts from A_0 = I0
         const float* Aprev = (cumulative && t > 0) ? A : pr->images_dev;
         // the last iteration writes E; with a stop rule any iteration may be the last
@@ -134,6 +141,13 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
             ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
             ta.key0 = (uint32_t)pa->seed;
             ta.key1 = (uint32_t)(pa->seed >> 32);
+            if (box) {
+                ta.box_z = box->height;
+                ta.box_th = box->tex_h;
+                ta.box_tw = box->tex_w;
+                ta.box_albedo = box->albedo_dev;
+                ta.box_S = wall_S;
+            }
             const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
             ta.ready_batch = sched.ready_batch;
             ta.tile_shift = sched.tile_shift;
@@ -211,6 +225,7 @@ std::vector<char> solve_key(const irtps_problem* pr, const irtps_params* pa, con
     put(k, ws);
     put(k, M);
     put(k, Ls);
+    if (pr->box) put(k, *pr->box);  // the problem holds only its host address
     const Schedule sc = schedule_for(pr->width, pr->height, pr->channels, pr->num_lights, pa->bounces);
     put(k, sc.tile_shift);
     put(k, sc.ready_batch);
@@ -266,8 +281,8 @@ int irtps_solve(const irtps_problem* pr, const irtps_params* pa, const irtps_out
                 size_t ws_bytes, void* stream) {
     STATUS_TRY(check_problem(pr, pa));
     if (!out || !out->normals_dev || !out->albedo_dev || !out->depth_dev) return IRTPS_ERR_INVALID_ARG;
-    const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
-    if (!ws || ws_bytes < solve_workspace_bytes(W, H, C, K, pa) || (reinterpret_cast<uintptr_t>(ws) % kAlign))
+    const int K = pr->num_lights;
+    if (!ws || ws_bytes < solve_workspace_bytes(pr, pa) || (reinterpret_cast<uintptr_t>(ws) % kAlign))
         return IRTPS_ERR_WORKSPACE;
     const bool graph = (pa->flags & IRTPS_FLAG_GRAPH) != 0;
     // a graph cannot hold the stop rule's read-back, nor run on the legacy stream
@@ -355,23 +370,34 @@ int irtps_build_pyramid(int32_t W, int32_t H, const float* depth_dev, float* pyr
 
 int irtps_direct(int32_t W, int32_t H, int32_t K, const float* depth_dev, const float* normals_dev,
                  const float* light_dirs_host, const float* light_intensity_host, const float* pyramid_dev,
-                 float* S_dev, void* stream) {
+                 float* S_dev, const irtps_box* box, void* stream) {
     if (!dims_ok(W, H) || !depth_dev || !normals_dev || !pyramid_dev || !S_dev) return IRTPS_ERR_INVALID_ARG;
+    if (box && !(box->height > 0.0f && box->height <= 3.0e38f)) return IRTPS_ERR_INVALID_ARG;
     kern::LightSet Ls;
     STATUS_TRY(make_lights(K, light_dirs_host, light_intensity_host, Ls));
     HIP_TRY(kern::direct(surface(W, H, depth_dev, pyramid_dev), normals_dev, Ls, 0, S_dev,
-                         reinterpret_cast<hipStream_t>(stream)));
+                         reinterpret_cast<hipStream_t>(stream), box ? box->height : 0.0f));
+    return IRTPS_OK;
+}
+
+int irtps_box_shade(int32_t W, int32_t H, int32_t K, const irtps_box* box, const float* light_dirs_host,
+                    const float* light_intensity_host, float* wall_S_dev, void* stream) {
+    if (!dims_ok(W, H) || !box_ok(box) || !wall_S_dev) return IRTPS_ERR_INVALID_ARG;
+    kern::LightSet Ls;
+    STATUS_TRY(make_lights(K, light_dirs_host, light_intensity_host, Ls));
+    HIP_TRY(kern::box_shade(W, H, box_args(box), Ls, wall_S_dev, reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
 
 int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev, const float* normals_dev,
                 const float* albedo_dev, const float* S_dev, const float* env_dev, int32_t env_h,
                 int32_t env_w, const float* pyramid_dev, int32_t spp, int32_t B, uint64_t seed, int32_t t,
-                int32_t tag, int32_t flags, float* G_dev, uint64_t* counters_dev, void* stream) {
+                int32_t tag, int32_t flags, float* G_dev, uint64_t* counters_dev, const irtps_box* box,
+                const float* wall_S_dev, void* stream) {
     if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !depth_dev || !normals_dev || !albedo_dev ||
         !S_dev || !env_dev || env_h < 1 || env_w < 1 || !pyramid_dev || spp < 1 || B < 0 || B > 8 || t < 0 ||
         t >= (1 << 23) || tag < 0 || !G_dev ||
-        (flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL)))
+        (flags & ~(IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL)) || (box && (!box_ok(box) || !wall_S_dev)))
         return IRTPS_ERR_INVALID_ARG;
     kern::TraceArgs ta{};
     ta.sa = surface(W, H, depth_dev, pyramid_dev);
@@ -392,6 +418,13 @@ int irtps_trace(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_d
     ta.flags = flags;
     ta.key0 = (uint32_t)seed;
     ta.key1 = (uint32_t)(seed >> 32);
+    if (box) {
+        ta.box_z = box->height;
+        ta.box_th = box->tex_h;
+        ta.box_tw = box->tex_w;
+        ta.box_albedo = box->albedo_dev;
+        ta.box_S = wall_S_dev;
+    }
     const Schedule sched = schedule_for(W, H, C, K, B);
     ta.ready_batch = sched.ready_batch;
     ta.tile_shift = sched.tile_shift;
@@ -446,20 +479,22 @@ int irtps_correct(int32_t W, int32_t H, int32_t C, int32_t K, int32_t rho_mode, 
     return IRTPS_OK;
 }
 
-int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, size_t* bytes) {
-    if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !bytes) return IRTPS_ERR_INVALID_ARG;
+int irtps_render_workspace_bytes(int32_t W, int32_t H, int32_t C, int32_t K, const irtps_box* box,
+                                 size_t* bytes) {
+    if (!dims_ok(W, H) || !channels_ok(C) || !lights_ok(K) || !bytes || (box && !box_ok(box)))
+        return IRTPS_ERR_INVALID_ARG;
     const size_t npx = (size_t)W * H;
     *bytes = align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C) +
-             align_up(sizeof(float) * (size_t)pyramid_floats(W, H));
+             align_up(sizeof(float) * (size_t)pyramid_floats(W, H)) + box_shade_bytes(box, K);
     return IRTPS_OK;
 }
 
 int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_dev, const float* normals_dev,
                  const float* albedo_dev, const float* light_dirs_host, const float* light_intensity_host,
                  const float* env_dev, int32_t env_h, int32_t env_w, int32_t spp, int32_t B, uint64_t seed,
-                 float* images_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+                 float* images_dev, void* ws_dev, size_t ws_bytes, const irtps_box* box, void* stream) {
     size_t need = 0;
-    STATUS_TRY(irtps_render_workspace_bytes(W, H, C, K, &need));
+    STATUS_TRY(irtps_render_workspace_bytes(W, H, C, K, box, &need));
     if (!depth_dev || !normals_dev || !albedo_dev || !env_dev || env_h < 1 || env_w < 1 || !images_dev ||
         spp < 1 || B < 0 || B > 8)
         return IRTPS_ERR_INVALID_ARG;
@@ -472,10 +507,20 @@ int irtps_render(int32_t W, int32_t H, int32_t C, int32_t K, const float* depth_
     float* S = reinterpret_cast<float*>(base);
     float* G = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K));
     float* pyr = reinterpret_cast<float*>(base + align_up(sizeof(float) * npx * K) + align_up(sizeof(float) * npx * K * C));
+    float* wall_S = reinterpret_cast<float*>(reinterpret_cast<char*>(pyr) +
+                                             align_up(sizeof(float) * (size_t)pyramid_floats(W, H)));
     const kern::SurfaceArgs sa = surface(W, H, depth_dev, pyr);
     HIP_TRY(kern::build_pyramid(W, H, depth_dev, pyramid_plan(W, H), pyr, sa.quad_off, st));
-    HIP_TRY(kern::direct(sa, normals_dev, Ls, 0, S, st));
+    HIP_TRY(kern::direct(sa, normals_dev, Ls, 0, S, st, box ? box->height : 0.0f));
     kern::TraceArgs ta{};
+    if (box) {
+        HIP_TRY(kern::box_shade(W, H, box_args(box), Ls, wall_S, st));
+        ta.box_z = box->height;
+        ta.box_th = box->tex_h;
+        ta.box_tw = box->tex_w;
+        ta.box_albedo = box->albedo_dev;
+        ta.box_S = wall_S;
+    }
     ta.sa = sa;
     ta.n = normals_dev;
     ta.rho = albedo_dev;

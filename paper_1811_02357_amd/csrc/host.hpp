@@ -78,6 +78,22 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline bool dims_ok(int W, int H) { return W >= 2 && H >= 2 && W <= 16384 && H <= 16384 && (long long)W * H <= (1LL << 28); }
 inline bool channels_ok(int C) { return C == 1 || C == 3; }
 inline bool lights_ok(int K) { return K >= 3 && K <= kern::kMaxLights; }
+// A box: a positive finite height, textures of 1..4096 texels a side, albedo given.
+inline bool box_ok(const irtps_box* b) {
+    return b && b->height > 0.0f && b->height <= 3.0e38f && b->tex_h >= 1 && b->tex_w >= 1 && b->tex_h <= 4096 &&
+           b->tex_w <= 4096 && b->albedo_dev;
+}
+inline kern::BoxArgs box_args(const irtps_box* b) {
+    kern::BoxArgs a{};
+    a.z = b->height;
+    a.th = b->tex_h;
+    a.tw = b->tex_w;
+    return a;
+}
+// Bytes of the walls' direct irradiance [4][tex_h][tex_w][K] (0 without a box).
+inline size_t box_shade_bytes(const irtps_box* b, int K) {
+    return b ? align_up(sizeof(float) * 4 * (size_t)b->tex_h * (size_t)b->tex_w * (size_t)K) : 0;
+}
 
 inline trv::Pyramid pyramid_plan(int W, int H) {
     trv::Pyramid P{};
@@ -254,8 +270,10 @@ inline size_t fill_bytes(int W, int H, int C) {
 inline size_t tail_bytes(int W, int H, int C, const irtps_params* pa) {
     return kern::exact_r_of(pa->flags) ? fill_bytes(W, H, C) : split_bytes(W, H, C, pa->spp, pa->bounces);
 }
-inline size_t solve_workspace_bytes(int W, int H, int C, int K, const irtps_params* pa) {
-    return solve_layout(W, H, C, K).total + tail_bytes(W, H, C, pa);
+// ... and, with a box, the walls' direct irradiance after the tail.
+inline size_t solve_workspace_bytes(const irtps_problem* pr, const irtps_params* pa) {
+    const int W = pr->width, H = pr->height, C = pr->channels, K = pr->num_lights;
+    return solve_layout(W, H, C, K).total + tail_bytes(W, H, C, pa) + box_shade_bytes(pr->box, K);
 }
 
 inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
@@ -272,6 +290,8 @@ inline int check_problem(const irtps_problem* pr, const irtps_params* pa) {
                        IRTPS_FLAG_SHADOW_AWARE_PS | IRTPS_FLAG_GRAPH | IRTPS_FLAG_ROBUST_INTEGRATION |
                        IRTPS_FLAG_EXACT_R_MASK)))
         return IRTPS_ERR_INVALID_ARG;
+    // the r-ray image is one per solve, the walls' light one per light
+    if (pr->box && (!box_ok(pr->box) || kern::exact_r_of(pa->flags))) return IRTPS_ERR_INVALID_ARG;
     return IRTPS_OK;
 }
 

@@ -193,6 +193,70 @@ __device__ __forceinline__ void ps_px_masked(int p, int npx, int K, const float*
     n[3 * (size_t)p + 2] = nz;
 }
 
+// ---------------------------------------------------------------------------
+// The box: four walls on the borders of the sample grid (x = 0, x = W - 1,
+// y = 0, y = H - 1) up to height z, open above.
+
+// A ray from (x0, y0, z0) along l (l.z > 0) that reaches height z inside the
+// walls' footprint leaves through the open top (one starting at or above z
+// is out already).
+__device__ __forceinline__ bool over_rim(float z, float xmax, float ymax, float x0, float y0, float z0, float lx,
+                                         float ly, float lz) {
+    if (z0 >= z) return true;
+    const float t = (z - z0) / lz;
+    const float x = fmaf(t, lx, x0), y = fmaf(t, ly, y0);
+    return x >= 0.0f && x <= xmax && y >= 0.0f && y <= ymax;
+}
+
+// floor(f) clamped to [0, n - 1].
+__device__ __forceinline__ int clamp_texel(float f, int n) {
+    return !(f >= 0.0f) ? 0 : (f >= (float)(n - 1) ? n - 1 : (int)f);
+}
+
+// The texel ((wall th + row) tw + col) of the wall that a ray leaving the
+// surface from sample (i0, j0) at height z0 meets below the rim: the first
+// wall plane ahead (a corner counts as the x wall); -1 when the ray passes
+// over the walls.
+__device__ __forceinline__ int wall_texel(float z, int th, int tw, int W, int Hh, int i0, int j0, float z0,
+                                          float dx, float dy, float dz) {
+    const float xmax = (float)(W - 1), ymax = (float)(Hh - 1);
+    const float x0 = (float)i0, y0 = (float)j0;
+    const float inf = __builtin_inff();
+    const float tx = dx > 0.0f ? (xmax - x0) / dx : (dx < 0.0f ? -x0 / dx : inf);
+    const float ty = dy > 0.0f ? (ymax - y0) / dy : (dy < 0.0f ? -y0 / dy : inf);
+    const bool xwall = tx <= ty;
+    const float t = xwall ? tx : ty;
+    if (t == inf) return -1;
+    const float zw = fmaf(t, dz, z0);
+    if (!(zw < z)) return -1;
+    const int wall = xwall ? (dx > 0.0f ? 1 : 0) : (dy > 0.0f ? 3 : 2);
+    const float u = xwall ? fmaf(t, dy, y0) : fmaf(t, dx, x0);
+    const float len = xwall ? ymax : xmax;
+    const int col = clamp_texel((u / len) * (float)tw, tw);
+    const int row = clamp_texel((zw / z) * (float)th, th);
+    return (wall * th + row) * tw + col;
+}
+
+// The walls' own direct light at texel centres: a wall faces into the box, so
+// its cosine with light k is a coordinate of l_k; the light reaches the
+// point when its ray leaves through the open top.  One lane per texel.
+__global__ void __launch_bounds__(256) k_box_shade(int W, int Hh, BoxArgs b, LightSet L, float* __restrict__ Sw) {
+    const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (x >= 4 * b.th * b.tw) return;
+    const int wall = x / (b.th * b.tw), row = (x / b.tw) % b.th, col = x % b.tw;
+    const float xmax = (float)(W - 1), ymax = (float)(Hh - 1);
+    const float len = wall < 2 ? ymax : xmax;
+    const float u = (((float)col + 0.5f) / (float)b.tw) * len;
+    const float zc = (((float)row + 0.5f) / (float)b.th) * b.z;
+    const float px = wall == 0 ? 0.0f : (wall == 1 ? xmax : u);
+    const float py = wall == 2 ? 0.0f : (wall == 3 ? ymax : u);
+    for (int k = 0; k < L.K; ++k) {
+        const float lx = L.l[k][0], ly = L.l[k][1], lz = L.l[k][2];
+        const float c = wall == 0 ? lx : (wall == 1 ? -lx : (wall == 2 ? ly : -ly));
+        Sw[(size_t)x * L.K + k] = (c > 0.0f && over_rim(b.z, xmax, ymax, px, py, zc, lx, ly, lz)) ? L.s[k] * c : 0.0f;
+    }
+}
+
 // Walker steps per pass of the shadow-ray loop.
 constexpr int kDirectSteps = 8;
 
@@ -204,7 +268,7 @@ constexpr int kDirectSteps = 8;
 // light only.
 __device__ __forceinline__ void direct_wave(const Surface& S, int p_self, const float* __restrict__ n, int K,
                                             const float* __restrict__ L, const float* __restrict__ s, bool flat,
-                                            float* __restrict__ S_out) {
+                                            float* __restrict__ S_out, float box_z = 0.0f) {
     const int lane = (int)(threadIdx.x & 63);
     const unsigned long long below = (1ull << lane) - 1ull;
     const int total = 64 * K;
@@ -233,7 +297,9 @@ __device__ __forceinline__ void direct_wave(const Surface& S, int p_self, const 
                     const float nx = n[3 * (size_t)p], ny = n[3 * (size_t)p + 1], nz = n[3 * (size_t)p + 2];
                     const float lx = L[3 * k], ly = L[3 * k + 1], lz = L[3 * k + 2];
                     c = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
-                    if (c > 0.0f) {
+                    // with walls, a light that the rim hides needs no walk
+                    if (c > 0.0f && (box_z <= 0.0f || over_rim(box_z, (float)(S.W - 1), (float)(S.Hh - 1), (float)i,
+                                                               (float)j, S.H[p], lx, ly, lz))) {
                         trv::walker_init(w, S, i, j, lx, ly, lz, flat);
                         have = true;
                     } else {
@@ -1003,9 +1069,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     const int KC = K * C;
     const int batch = a.ready_batch;
     float* __restrict__ gp = a.G + (size_t)p * KC;  // this pixel's sums
-    // whole float4 rows of S and G when K is a multiple of 4 and G is 16-byte aligned
+    // whole float4 rows of S (and of the walls' S) and G when K is a multiple of
+    // 4 and the rows are 16-byte aligned
     const bool vec4 = (K & 3) == 0 && (reinterpret_cast<uintptr_t>(a.G) & 15) == 0 &&
-                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0;
+                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.box_S) & 15) == 0;
+    const bool box = a.box_z > 0.0f;
 
     if (live)
         for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
@@ -1087,7 +1156,13 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
         }
         if (!finished && ready) {
             bool next_sample = true;
-            if (res == trv::kMiss) {
+            // an escape that meets a wall is shaded like a surface hit, from
+            // the wall texel's albedo and direct light, and ends the path
+            const int wt = (box && res == trv::kMiss)
+                               ? wall_texel(a.box_z, a.box_th, a.box_tw, a.sa.W, a.sa.Hh, ci, cj, w.r.oz, w.r.dx,
+                                            w.r.dy, w.r.dz)
+                               : -1;
+            if (res == trv::kMiss && wt < 0) {
                 int er, ec;
                 dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
                 const float* L = a.env + (er * a.env_w + ec) * C;
@@ -1095,11 +1170,13 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
                 for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
             } else {
                 const int q = qj * a.sa.W + qi;
+                const bool on_wall = wt >= 0;
                 float wgt[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) wgt[c] = beta[c] * a.rho[c * npx + q];
-                accumulate_hit<C>(gp, a.S + (size_t)q * K, wgt, K, vec4);
-                if (b < a.B) {
+                for (int c = 0; c < C; ++c)
+                    wgt[c] = beta[c] * (on_wall ? a.box_albedo[(size_t)wt * C + c] : a.rho[c * npx + q]);
+                accumulate_hit<C>(gp, on_wall ? a.box_S + (size_t)wt * K : a.S + (size_t)q * K, wgt, K, vec4);
+                if (!on_wall && b < a.B) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) beta[c] = wgt[c];
                     ci = qi;
@@ -1161,12 +1238,12 @@ __global__ void __launch_bounds__(256) k_ps_solve_masked(int npx, int K, PsMatri
 }
 
 __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __restrict__ n, LightSet L,
-                                                int flat, float* __restrict__ S_out) {
+                                                int flat, float* __restrict__ S_out, float box_z) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(sa.off, sa.wc, s_lvl);
     const int p = direct_pixel(sa.W, sa.Hh, blockIdx.x, gridDim.x);
     const Surface S = make_surface(sa, s_lvl);
-    direct_wave(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out);
+    direct_wave(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out, box_z);
 }
 
 // The tracer is issue- and latency-bound: ask for seven waves per SIMD (at most
@@ -1225,6 +1302,16 @@ __global__ void IRTPS_TRACER_OCCUPANCY k_trace_paths(TraceArgs a) {
             const size_t r = ((size_t)(b - 1) * a.spp + s) * npx + p;
             if (res == trv::kMiss) {
                 ++cnt[2];
+                const int wt = a.box_z > 0.0f ? wall_texel(a.box_z, a.box_th, a.box_tw, W, a.sa.Hh, ci, cj, w.r.oz,
+                                                           w.r.dx, w.r.dy, w.r.dz)
+                                              : -1;
+                if (wt >= 0) {  // a wall: code npx + texel, weight beta times its albedo
+                    a.records[r] = __int_as_float(npx + wt);
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        a.records[(1 + c) * plane + r] = beta[c] * a.box_albedo[(size_t)wt * C + c];
+                    break;
+                }
                 int er, ec;
                 dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
                 a.records[r] = __int_as_float(-(er * a.env_w + ec) - 1);
@@ -1269,7 +1356,8 @@ __global__ void __launch_bounds__(256) k_gather_paths(TraceArgs a) {
     const int K = a.K, KC = K * C;
     float* __restrict__ gp = a.G + (size_t)p * KC;
     const bool vec4 = (K & 3) == 0 && (reinterpret_cast<uintptr_t>(a.G) & 15) == 0 &&
-                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0;
+                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.box_S) & 15) == 0;
     for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
     float eacc[C];
 #pragma unroll
@@ -1286,6 +1374,10 @@ __global__ void __launch_bounds__(256) k_gather_paths(TraceArgs a) {
                 const float* L = a.env + (size_t)(-code - 1) * C;
 #pragma unroll
                 for (int c = 0; c < C; ++c) eacc[c] = fmaf(w[c], dm::kPi * L[c], eacc[c]);
+                break;
+            }
+            if (code >= npx) {  // a wall texel ends the path
+                accumulate_hit<C>(gp, a.box_S + (size_t)(code - npx) * K, w, K, vec4);
                 break;
             }
             accumulate_hit<C>(gp, a.S + (size_t)code * K, w, K, vec4);
@@ -2123,9 +2215,15 @@ hipError_t ps_solve_masked(int npx, int C, int K, const PsMatrix& M, const Light
 }
 
 hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
-                  hipStream_t st) {
+                  hipStream_t st, float box_z) {
     const int tiles = tiles_for(sa.W, sa.Hh, kDirectTileW);
-    hipLaunchKernelGGL(k_direct, dim3((tiles + 7) / 8 * 8), dim3(256), 0, st, sa, n, L, flat, S);
+    hipLaunchKernelGGL(k_direct, dim3((tiles + 7) / 8 * 8), dim3(256), 0, st, sa, n, L, flat, S, box_z);
+    return hipGetLastError();
+}
+
+hipError_t box_shade(int W, int H, const BoxArgs& b, const LightSet& L, float* S, hipStream_t st) {
+    const long long n = 4LL * b.th * b.tw;
+    hipLaunchKernelGGL(k_box_shade, dim3(blocks_for(n, 256)), dim3(256), 0, st, W, H, b, L, S);
     return hipGetLastError();
 }
 

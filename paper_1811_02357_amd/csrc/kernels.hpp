@@ -80,6 +80,20 @@ struct TraceArgs {
     float* Anext;         // [K][C][H][W], or null: no fused correction
     float* E;             // [K][C][H][W] or null
     int rho_mode, cumulative;
+    // Walls (the known environment as geometry), or box_z <= 0: none.  A ray
+    // that leaves the surface and meets a wall below box_z adds the wall
+    // texel's term like a surface hit (row box_S, weight beta times its albedo).
+    float box_z;
+    int box_th, box_tw;
+    const float* box_albedo;  // [4][th][tw][C]
+    const float* box_S;       // [4][th][tw][K]
+};
+
+// The walls of the box: height and texture size (the walls' own direct light,
+// box_shade, goes to S [4][th][tw][K]).
+struct BoxArgs {
+    float z;
+    int th, tw;
 };
 
 // Small problems can trace one path per (pixel, sample) lane: each lane records
@@ -174,8 +188,11 @@ hipError_t ps_solve(int npx, int C, int K, const PsMatrix& M, const float* A, fl
 // Eq.4 per pixel over the lights with S[p][k] > 0 (at least three), else all.
 hipError_t ps_solve_masked(int npx, int C, int K, const PsMatrix& M, const LightSet& L, const float* A,
                            const float* S, float* n, float* rho, hipStream_t st);
+// box_z > 0: the walls of that height block shadow rays too.
 hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int flat, float* S,
-                  hipStream_t st);
+                  hipStream_t st, float box_z = 0.0f);
+// The walls' direct irradiance at texel centres, S [4][th][tw][K].
+hipError_t box_shade(int W, int H, const BoxArgs& b, const LightSet& L, float* S, hipStream_t st);
 hipError_t trace(TraceArgs a, hipStream_t st);
 // order[0..tiles) = the tiles by descending cost (ties in any order).
 hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t st);

@@ -356,6 +356,9 @@ int irtps_server_submit(irtps_server* s, const irtps_problem* problem, const irt
     if (!s || !problem || !params || !outputs || !job_id) return IRTPS_ERR_INVALID_ARG;
     STATUS_TRY(check_problem(problem, params));
     if (!outputs->normals_dev || !outputs->albedo_dev || !outputs->depth_dev) return IRTPS_ERR_INVALID_ARG;
+    // what the batched kernels do not run is refused here, not when the job starts
+    if (problem->box || (params->flags & (IRTPS_FLAG_ROBUST_INTEGRATION | IRTPS_FLAG_EXACT_R_MASK)))
+        return IRTPS_ERR_INVALID_ARG;
     Job J;
     J.pr = *problem;
     J.pa = *params;

@@ -52,10 +52,40 @@ class IrtpsError(RuntimeError):
         self.status = status
 
 
+class BoxC(ct.Structure):
+    """irtps_box."""
+    _fields_ = [("height", ct.c_float), ("tex_h", _i32), ("tex_w", _i32), ("albedo_dev", _vp)]
+
+
+class Box:
+    """Walls of height `height` on the borders of the sample grid, open above;
+    `albedo` a device tensor [4][tex_h][tex_w][C] (walls x = 0, x = W - 1,
+    y = 0, y = H - 1; rows from height 0 to `height`, columns along the wall)."""
+
+    def __init__(self, height, albedo):
+        if not (isinstance(albedo, torch.Tensor) and albedo.dim() == 4 and albedo.shape[0] == 4):
+            raise ValueError("box albedo must be a [4][tex_h][tex_w][C] tensor")
+        self.height = float(height)
+        self.albedo = albedo
+
+    def c(self, C=None):
+        if C is not None and self.albedo.shape[3] != C:
+            raise ValueError(f"box albedo has {self.albedo.shape[3]} channels, expected {C}")
+        return BoxC(self.height, self.albedo.shape[1], self.albedo.shape[2], _dev(self.albedo, name="box albedo"))
+
+
+def _boxp(box, C=None):
+    """(pointer or None, the struct to keep alive) for an optional Box."""
+    if box is None:
+        return None, None
+    b = box.c(C)
+    return ct.byref(b), b
+
+
 class Problem(ct.Structure):
     _fields_ = [("width", _i32), ("height", _i32), ("channels", _i32), ("num_lights", _i32),
                 ("images_dev", _vp), ("light_dirs_host", _vp), ("light_intensity_host", _vp),
-                ("env_dev", _vp), ("env_h", _i32), ("env_w", _i32)]
+                ("env_dev", _vp), ("env_h", _i32), ("env_w", _i32), ("box", ct.POINTER(BoxC))]
 
 
 class Params(ct.Structure):
@@ -123,18 +153,19 @@ def lib():
             "irtps_integrate_robust": [_i32, _i32, _vp, _vp, _i32, ct.c_float, _i32, _i32, _vp, _vp, _sz, _vp],
             "irtps_pyramid_bytes": [_i32, _i32, P(_sz)],
             "irtps_build_pyramid": [_i32, _i32, _vp, _vp, _vp],
-            "irtps_direct": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+            "irtps_direct": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, P(BoxC), _vp],
+            "irtps_box_shade": [_i32, _i32, _i32, P(BoxC), _vp, _vp, _vp, _vp],
             "irtps_trace": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
-                            _i32, _i32, _u64, _i32, _i32, _i32, _vp, _vp, _vp],
+                            _i32, _i32, _u64, _i32, _i32, _i32, _vp, _vp, P(BoxC), _vp, _vp],
             "irtps_correct": [_i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp],
             "irtps_trace_exact_r": [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _i32, _u64,
                                     _i32, _i32, _i32, _vp, _vp, _vp],
             "irtps_fill_workspace_bytes": [_i32, _i32, _i32, P(_sz)],
             "irtps_fill_missing": [_i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp],
-            "irtps_render_workspace_bytes": [_i32, _i32, _i32, _i32, P(_sz)],
+            "irtps_render_workspace_bytes": [_i32, _i32, _i32, _i32, P(BoxC), P(_sz)],
             "irtps_render": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
-                             _i32, _i32, _u64, _vp, _vp, _sz, _vp],
+                             _i32, _i32, _u64, _vp, _vp, _sz, P(BoxC), _vp],
             "irtps_batch_workspace_bytes": [_i32, _vp, _vp, P(_sz)],
             "irtps_batch_solve": [_i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp],
             "irtps_set_ready_batch": [_i32],
@@ -226,28 +257,30 @@ def ps_matrix(light_dirs, light_intensity=None):
     return M
 
 
-def _problem(images, light_dirs, light_intensity, env):
+def _problem(images, light_dirs, light_intensity, env, box=None):
     K, C, H, W = images.shape
     l, lp = _host_f32(light_dirs, (K, 3), "light_dirs")
     s, sp = _host_f32(light_intensity, (K,), "light_intensity")
     if env.dim() != 3 or env.shape[2] != C:
         raise ValueError("env must be [He][We][C]")
+    bc = box.c(C) if box is not None else None
     pr = Problem(W, H, C, K, _dev(images, name="images"), lp, sp, _dev(env, name="env"),
-                 env.shape[0], env.shape[1])
-    return pr, (l, s)
+                 env.shape[0], env.shape[1], ct.pointer(bc) if bc is not None else None)
+    return pr, (l, s, bc)
 
 
 @_on_stream
 def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
           rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None,
-          workspace=None, stream=None, stop_tol=0.0):
+          workspace=None, stream=None, stop_tol=0.0, box=None):
     """The whole IRT-PS loop.  images [K][C][H][W], env [He][We][C] on the device.
     stop_tol > 0 ends the loop after the first iteration that moves the surface
     by less than stop_tol (pixel units) everywhere.
+    box: a Box (walls around the surface) or None.
     Returns a dict of device tensors: normals, albedo, depth, indirect, counters."""
     K, C, H, W = images.shape
     dev = images.device
-    pr, keep = _problem(images, light_dirs, light_intensity, env)
+    pr, keep = _problem(images, light_dirs, light_intensity, env, box)
     pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, float(stop_tol), seed)
     if out is None:
         out = {"normals": torch.empty((H, W, 3), device=dev),
@@ -261,7 +294,7 @@ def solve(images, light_dirs, light_intensity, env, spp, bounces, iterations, se
                 _dev(out.get("indirect"), shape=(K, C, H, W), name="indirect"),
                 _dev(out.get("counters"), dtype=torch.int64, shape=(NUM_COUNTERS,), name="counters"))
     need = workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iterations,
-                           seed, rho_mode, flags)
+                           seed, rho_mode, flags, box=box)
     if workspace is None:
         workspace = _alloc_ws(need, dev)
     _check("irtps_solve", lib().irtps_solve(ct.byref(pr), ct.byref(pa), ct.byref(o),
@@ -276,13 +309,13 @@ STATIC_SCRATCH_BYTES = 64 << 20  # IRTPS_STATIC_SCRATCH_BYTES
 @_on_stream
 def solve_static(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
                  rho_mode=RHO_FIT, flags=0, mg_cycles_cold=0, mg_cycles_warm=0, out=None, stream=None,
-                 stop_tol=0.0):
+                 stop_tol=0.0, box=None):
     """solve() with the workspace in the library's own device scratch (no
     allocation by the library; the outputs are allocated here unless `out` is
     given).  Problems needing more than STATIC_SCRATCH_BYTES are refused."""
     K, C, H, W = images.shape
     dev = images.device
-    pr, keep = _problem(images, light_dirs, light_intensity, env)
+    pr, keep = _problem(images, light_dirs, light_intensity, env, box)
     pa = Params(spp, bounces, iterations, rho_mode, flags, mg_cycles_cold, mg_cycles_warm, float(stop_tol), seed)
     if out is None:
         out = {"normals": torch.empty((H, W, 3), device=dev),
@@ -300,8 +333,8 @@ def solve_static(images, light_dirs, light_intensity, env, spp, bounces, iterati
 
 
 def workspace_bytes(images, light_dirs, light_intensity, env, spp, bounces, iterations, seed=0,
-                    rho_mode=RHO_FIT, flags=0, stop_tol=0.0):
-    pr, keep = _problem(images, light_dirs, light_intensity, env)
+                    rho_mode=RHO_FIT, flags=0, stop_tol=0.0, box=None):
+    pr, keep = _problem(images, light_dirs, light_intensity, env, box)
     pa = Params(spp, bounces, iterations, rho_mode, flags, 0, 0, float(stop_tol), seed)
     n = _sz()
     _check("irtps_workspace_bytes", lib().irtps_workspace_bytes(ct.byref(pr), ct.byref(pa), ct.byref(n)))
@@ -376,7 +409,8 @@ def build_pyramid(depth, stream=None):
 
 
 @_on_stream
-def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, stream=None):
+def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, stream=None, box=None):
+    """S [H][W][K]; with a Box its walls block shadow rays too."""
     H, W = depth.shape
     l, lp = _host_f32(light_dirs, name="light_dirs")
     K = l.shape[0]
@@ -384,26 +418,43 @@ def direct(depth, normals, light_dirs, light_intensity=None, pyramid=None, strea
     if pyramid is None:
         pyramid = build_pyramid(depth, stream)
     S = torch.empty((H, W, K), device=depth.device)
+    bp, bkeep = _boxp(box)
     _check("irtps_direct", lib().irtps_direct(W, H, K, _dev(depth), _dev(normals, shape=(H, W, 3)),
-                                              lp, sp, _dev(pyramid), _dev(S), _stream(stream)))
+                                              lp, sp, _dev(pyramid), _dev(S), bp, _stream(stream)))
     return S
 
 
 @_on_stream
+def box_shade(W, H, box, light_dirs, light_intensity=None, stream=None):
+    """The walls' direct irradiance [4][tex_h][tex_w][K] at texel centres."""
+    l, lp = _host_f32(light_dirs, name="light_dirs")
+    K = l.shape[0]
+    s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    Sw = torch.empty((4, box.albedo.shape[1], box.albedo.shape[2], K), device=box.albedo.device)
+    bp, bkeep = _boxp(box)
+    _check("irtps_box_shade", lib().irtps_box_shade(W, H, K, bp, lp, sp, _dev(Sw), _stream(stream)))
+    return Sw
+
+
+@_on_stream
 def trace(depth, normals, albedo, S, env, spp, bounces, seed=0, t=0, tag=TAG_SOLVE, flags=0,
-          pyramid=None, counters=None, stream=None):
-    """Gathered radiance G, pixel-major [H][W][K][C]."""
+          pyramid=None, counters=None, stream=None, box=None, wall_S=None):
+    """Gathered radiance G, pixel-major [H][W][K][C]; with a Box, wall_S from box_shade."""
     H, W = depth.shape
     C = albedo.shape[0]
     K = S.shape[2]
     if pyramid is None:
         pyramid = build_pyramid(depth, stream)
     G = torch.empty((H, W, K, C), device=depth.device)
+    bp, bkeep = _boxp(box, C)
+    if box is not None and wall_S is None:
+        raise ValueError("a box needs wall_S (box_shade)")
     _check("irtps_trace", lib().irtps_trace(
         W, H, C, K, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)),
         _dev(S, shape=(H, W, K)), _dev(env), env.shape[0], env.shape[1], _dev(pyramid),
         spp, bounces, seed, t, tag, flags, _dev(G),
-        _dev(counters, dtype=torch.int64, shape=(NUM_COUNTERS,)), _stream(stream)))
+        _dev(counters, dtype=torch.int64, shape=(NUM_COUNTERS,)), bp, _dev(wall_S, name="wall_S"),
+        _stream(stream)))
     return G
 
 
@@ -452,20 +503,21 @@ def correct(I0, G, S, albedo, rho_mode=RHO_FIT, flags=0, A_prev=None, want_E=Tru
 
 @_on_stream
 def render(depth, normals, albedo, light_dirs, light_intensity, env, spp, bounces, seed=0,
-           stream=None):
+           stream=None, box=None):
     H, W = depth.shape
     C = albedo.shape[0]
     l, lp = _host_f32(light_dirs, name="light_dirs")
     K = l.shape[0]
     s, sp = _host_f32(light_intensity, (K,), "light_intensity")
+    bp, bkeep = _boxp(box, C)
     nb = _sz()
-    _check("irtps_render_workspace_bytes", lib().irtps_render_workspace_bytes(W, H, C, K, ct.byref(nb)))
+    _check("irtps_render_workspace_bytes", lib().irtps_render_workspace_bytes(W, H, C, K, bp, ct.byref(nb)))
     ws = _alloc_ws(nb.value, depth.device)
     I = torch.empty((K, C, H, W), device=depth.device)
     _check("irtps_render", lib().irtps_render(
         W, H, C, K, _dev(depth), _dev(normals, shape=(H, W, 3)), _dev(albedo, shape=(C, H, W)),
         lp, sp, _dev(env), env.shape[0], env.shape[1], spp, bounces, seed, _dev(I),
-        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+        ct.c_void_p(ws.data_ptr()), ws.numel(), bp, _stream(stream)))
     return I
 
 
@@ -490,7 +542,7 @@ def _batch_structs(jobs, outs):
     o = (Outputs * n)()
     keep = []
     for j, job in enumerate(jobs):
-        pr, k = _problem(job["images"], job["light_dirs"], job.get("light_intensity"), job["env"])
+        pr, k = _problem(job["images"], job["light_dirs"], job.get("light_intensity"), job["env"], job.get("box"))
         keep.append(k)
         probs[j] = pr
         pars[j] = Params(job["spp"], job["bounces"], job["iterations"], job.get("rho_mode", RHO_FIT),

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Scene", "normals_from_heights", "ring_lights", "fibonacci_lights",
     "bowl_64", "vgroove_512", "fbm_terrain", "fbm_heights", "batched_job",
-    "served_job", "served_arrivals", "tiny_scene",
+    "served_job", "served_arrivals", "tiny_scene", "cornell_walls", "in_box",
 ]
 
 
@@ -46,6 +46,8 @@ class Scene:
     render_spp: int = 1024
     render_bounces: int = 1
     extra: dict = field(default_factory=dict)
+    # walls around the surface: {"Z": height, "albedo": [4][th][tw][C]}, or None
+    box: dict | None = None
 
     @property
     def width(self) -> int:
@@ -271,3 +273,23 @@ def tiny_scene(w: int = 8, hgt: int = 8, seed: int = 0, channels: int = 1,
     lights = fibonacci_lights(num_lights)
     env = rng.uniform(0.0, 1.0, size=(env_shape[0], env_shape[1], channels))
     return _scene(f"tiny{w}x{hgt}", h, albedo, lights, np.ones(num_lights), env)
+
+
+def cornell_walls(channels: int = 3, tex=(16, 32), seed: int = 0) -> np.ndarray:
+    """Albedo [4][th][tw][C] of a Cornell-like box (Sec. IV stages 0 and 3): wall
+    0 (x = 0) red, wall 1 (x = W - 1) green, walls 2 and 3 white, each times a
+    seeded texture in [0.85, 1.15] (the paper allows textured walls); grey
+    images take the channel mean."""
+    base = np.array([[0.63, 0.07, 0.05], [0.12, 0.45, 0.09], [0.73, 0.73, 0.73], [0.73, 0.73, 0.73]])
+    th, tw = tex
+    rng = np.random.default_rng(seed)
+    alb = base[:, None, None, :] * rng.uniform(0.85, 1.15, (4, th, tw, 1))
+    if channels == 1:
+        alb = alb.mean(axis=-1, keepdims=True)
+    return np.ascontiguousarray(alb, dtype=np.float32)
+
+
+def in_box(sc: Scene, height: float, tex=(16, 32), seed: int = 0) -> Scene:
+    """The scene with Cornell-like walls of the given height around it."""
+    sc.box = {"Z": float(height), "albedo": cornell_walls(sc.channels, tex, seed)}
+    return sc

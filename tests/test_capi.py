@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 20
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    assert L.irtps_abi_version() == 2
+    assert L.irtps_abi_version() == 3
     assert L.irtps_status_string(0) == b"ok"
     assert L.irtps_status_string(2) == b"singular light configuration"
 
@@ -73,7 +73,7 @@ def test_invalid_arguments_rejected_on_host():
     o = irtps.Outputs(ct.c_void_p(256), ct.c_void_p(256), ct.c_void_p(256), None, None)
     assert L.irtps_solve(ct.byref(pr), ct.byref(pa), ct.byref(o), ct.c_void_p(256), 16, None) == 3
     assert L.irtps_trace(64, 64, 2, 8, *([ct.c_void_p(256)] * 5), 2, 4, ct.c_void_p(256), 16, 1, 0,
-                         0, 0, 0, ct.c_void_p(256), None, None) == 1  # C = 2
+                         0, 0, 0, ct.c_void_p(256), None, None, None, None) == 1  # C = 2
     assert L.irtps_probe_philox(-1, None, 0, None, None) == 1
 
 
@@ -202,3 +202,52 @@ def test_exact_r_flag_and_fill_workspace_on_host():
         assert L.irtps_trace_exact_r(64, 64, 1, p, p, p, p, 2, 4, p, r, 0, 0, 0, flags, p, None, None) == 1
     assert L.irtps_fill_missing(64, 64, 1, p, p, p, 16, None) == 3  # workspace too small
     assert L.irtps_fill_missing(64, 64, 1, p, None, p, 1 << 20, None) == 1
+
+
+def test_box_validation_and_workspace_on_host():
+    """A box (walls around the surface) must have a positive height, textures
+    of 1..4096 texels a side and an albedo; it adds the walls' direct light
+    [4][tex_h][tex_w][K] to the solve's and the render's workspace, and is
+    refused with the r-ray variant, by the batched engine and by the server."""
+    L = irtps.lib()
+    n = ct.c_size_t()
+    l = np.zeros((8, 3), np.float32)
+    lp = l.ctypes.data_as(ct.c_void_p)
+    pa = irtps.Params(16, 1, 3, 0, 0, 0, 0, 0, 0)
+
+    def ws(box, params=pa):
+        pr = irtps.Problem(300, 200, 3, 8, ct.c_void_p(256), lp, None, ct.c_void_p(256), 2, 4,
+                           ct.pointer(box) if box is not None else None)
+        st = L.irtps_workspace_bytes(ct.byref(pr), ct.byref(params), ct.byref(n))
+        return n.value if st == 0 else -st
+
+    base = ws(None)
+    good = irtps.BoxC(40.0, 16, 24, ct.c_void_p(256))
+    assert ws(good) - base == (4 * 16 * 24 * 8 * 4 + 255) // 256 * 256
+    for bad in (irtps.BoxC(0.0, 16, 24, ct.c_void_p(256)), irtps.BoxC(float("nan"), 16, 24, ct.c_void_p(256)),
+                irtps.BoxC(40.0, 0, 24, ct.c_void_p(256)), irtps.BoxC(40.0, 16, 4097, ct.c_void_p(256)),
+                irtps.BoxC(40.0, 16, 24, None)):
+        assert ws(bad) == -1
+    assert ws(good, irtps.Params(16, 1, 3, 0, irtps.flag_exact_r(2), 0, 0, 0, 0)) == -1
+    b = ct.c_size_t()
+    b0 = ct.c_size_t()
+    assert L.irtps_render_workspace_bytes(300, 200, 3, 8, None, ct.byref(b0)) == 0
+    assert L.irtps_render_workspace_bytes(300, 200, 3, 8, ct.byref(good), ct.byref(b)) == 0
+    assert b.value - b0.value == (4 * 16 * 24 * 8 * 4 + 255) // 256 * 256
+    p = ct.c_void_p(256)
+    assert L.irtps_box_shade(300, 200, 8, ct.byref(irtps.BoxC(-1.0, 16, 24, p)), lp, None, p, None) == 1
+    assert L.irtps_box_shade(300, 200, 8, None, lp, None, p, None) == 1
+    # the server refuses what the batched kernels do not run, at submit
+    srv = ct.c_void_p()
+    cfg = irtps.ServerCfg(0, 1, 0, 0, 0)  # dry run: no device work
+    assert L.irtps_server_create(ct.byref(cfg), None, 1 << 30, ct.byref(srv)) == 0
+    try:
+        pr = irtps.Problem(300, 200, 3, 8, p, lp, None, p, 2, 4, ct.pointer(good))
+        o = irtps.Outputs(p, p, p, None, None)
+        job = ct.c_uint64()
+        assert L.irtps_server_submit(srv, ct.byref(pr), ct.byref(pa), ct.byref(o), ct.byref(job)) == 1
+        pr.box = None
+        robust = irtps.Params(16, 1, 3, 0, irtps.FLAG_ROBUST_INTEGRATION, 0, 0, 0, 0)
+        assert L.irtps_server_submit(srv, ct.byref(pr), ct.byref(robust), ct.byref(o), ct.byref(job)) == 1
+    finally:
+        L.irtps_server_destroy(srv)

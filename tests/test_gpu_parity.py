@@ -46,6 +46,11 @@ def H(t):
     return t.cpu().numpy()
 
 
+def gbox(sc, dev):
+    """The scene's walls for the library (None without walls)."""
+    return None if sc.box is None else irtps.Box(sc.box["Z"], T(sc.box["albedo"], dev))
+
+
 def angle_deg(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -352,9 +357,10 @@ def _solve_both(sc, dev, I0=None, rho_mode=irtps.RHO_FIT, flags=0, T_=None, stop
                   seed=sc.seed, rho_mode=rho_mode,
                   flags=flags & (irtps.FLAG_QUADRATURE | irtps.FLAG_LITERAL_CUMULATIVE | irtps.FLAG_SHADOW_AWARE_PS
                                  | irtps.FLAG_ROBUST_INTEGRATION | irtps.FLAG_EXACT_R_MASK),
-                  stop_tol=stop_tol)
+                  stop_tol=stop_tol, box=sc.box)
     out = irtps.solve(T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp,
-                      sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol)
+                      sc.bounces, Tn, seed=sc.seed, rho_mode=rho_mode, flags=flags, stop_tol=stop_tol,
+                      box=gbox(sc, dev))
     return ref, {k: H(v) for k, v in out.items()}
 
 
@@ -573,7 +579,109 @@ def test_solve_exact_r(dev, case):
     assert e.value.status == 1
 
 
-@pytest.mark.parametrize("case", ["bowl64", "fbm160x120", "bowl64_exact_r2"])
+# ---------------------------------------------------------------------------
+# The known environment as geometry: walls around the surface.
+def _fbm160x120(ptp=24.0, K=16):
+    sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=K, env_shape=(16, 32),
+                            ptp=ptp, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+    sc.heights = np.ascontiguousarray(sc.heights[:120])
+    sc.normals = np.ascontiguousarray(sc.normals[:120])
+    sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    return sc
+
+
+BOX_SCENES = {
+    "bowl64_Z12": lambda: scenes.in_box(scenes.bowl_64(), 12.0, tex=(8, 16), seed=1),
+    "fbm160x120_rgb_Z30": lambda: scenes.in_box(_fbm160x120(), 30.0, tex=(16, 32), seed=2),
+    "step_hill_Z6": lambda: scenes.in_box(scenes.step_hill(), 6.0, tex=(5, 7), seed=3),
+    "tiny_rgb_Z2": lambda: scenes.in_box(scenes.tiny_scene(13, 11, seed=4, channels=3, num_lights=20), 2.0,
+                                         tex=(3, 4), seed=4),
+}
+
+
+@pytest.mark.parametrize("name", list(BOX_SCENES))
+def test_box_shade_and_direct_stages(dev, name):
+    say(f"case: wall shading and direct light with walls, {name}")
+    sc = BOX_SCENES[name]()
+    Z = sc.box["Z"]
+    Sw = irtps.box_shade(sc.width, sc.height, gbox(sc, dev), sc.light_dirs, sc.light_intensity)
+    ref = O.box_shade(sc.width, sc.height, sc.box, sc.light_dirs, sc.light_intensity)
+    assert np.array_equal(H(Sw), ref) and (ref > 0).any() and (ref == 0).any()
+    S = irtps.direct(T(sc.heights, dev), T(sc.normals, dev), sc.light_dirs, sc.light_intensity, box=gbox(sc, dev))
+    Sref = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity, box_z=Z)
+    assert np.array_equal(H(S), Sref)
+    say(f"  lit without walls {np.mean(O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity) > 0):.3f},"
+        f" with {np.mean(Sref > 0):.3f}")
+
+
+BOX_TRACE_CASES = [
+    # scene, spp, B, flags, t, tag
+    ("bowl64_Z12", 16, 2, 0, 0, 0),
+    ("bowl64_Z12", 9, 3, irtps.FLAG_FLAT_TRAVERSAL | irtps.FLAG_QUADRATURE, 1, 1),
+    ("fbm160x120_rgb_Z30", 8, 3, 0, 2, 0),
+    ("step_hill_Z6", 12, 2, 0, 0, 0),
+    ("tiny_rgb_Z2", 9, 4, 0, 1, 1),
+]
+
+
+@pytest.mark.parametrize("case", BOX_TRACE_CASES, ids=[f"{c[0]}_B{c[2]}_f{c[3]}" for c in BOX_TRACE_CASES])
+def test_trace_with_box_stage(dev, case):
+    name, spp, B, flags, t, tag = case
+    say(f"case: gather with walls {name} spp={spp} B={B} flags={flags}")
+    sc = BOX_SCENES[name]()
+    S = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity, box_z=sc.box["Z"])
+    box = dict(sc.box, S=O.box_shade(sc.width, sc.height, sc.box, sc.light_dirs, sc.light_intensity))
+    seed = 0x1234_5678_9ABC
+    ref, rc = O.trace(sc.heights, sc.normals, sc.albedo, S, sc.env, spp, B, seed, t=t, tag=tag,
+                      flags=flags & irtps.FLAG_QUADRATURE, box=box)
+    walls_only = O.trace(sc.heights, sc.normals, sc.albedo, S, sc.env, spp, B, seed, t=t, tag=tag,
+                         flags=flags & irtps.FLAG_QUADRATURE)[0]
+    assert not np.array_equal(ref, walls_only)  # the walls are met
+    cnt = torch.zeros(irtps.NUM_COUNTERS, dtype=torch.int64, device=dev)
+    G = irtps.trace(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), T(S, dev), T(sc.env, dev), spp, B,
+                    seed, t=t, tag=tag, flags=flags, counters=cnt, box=gbox(sc, dev), wall_S=T(box["S"], dev))
+    ref = np.transpose(ref, (2, 3, 0, 1))
+    assert_radiance(H(G), ref, name)
+    assert H(cnt).tolist() == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"], 0]
+    assert np.array_equal(H(G), ref)
+
+
+def test_render_with_box(dev):
+    say("case: render bowl64 in walls spp 64 B 2")
+    sc = BOX_SCENES["bowl64_Z12"]()
+    ref, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 64, 2, 3,
+                      box=sc.box)
+    I = irtps.render(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), sc.light_dirs,
+                     sc.light_intensity, T(sc.env, dev), 64, 2, 3, box=gbox(sc, dev))
+    assert np.array_equal(H(I), ref)
+
+
+@pytest.mark.parametrize("case", ["bowl64_Z12", "fbm160x120_rgb_Z30", "fbm160x120_rgb_Z30_shadow_aware",
+                                  "step_hill_Z6_stop"])
+def test_solve_in_box(dev, case):
+    """The loop inside walls: inputs rendered in the walls (oracle), then the
+    GPU solve against the oracle's (the walls' light computed once per solve,
+    direct light with wall shadows, wall hits in the gather: the per-path
+    tracer at 64^2, the per-pixel tracer with fused correction at 160 x 120).
+    The batched engine refuses walls."""
+    say(f"case: solve in walls, {case}")
+    name = case.replace("_shadow_aware", "").replace("_stop", "")
+    sc = BOX_SCENES[name]()
+    flags = irtps.FLAG_SHADOW_AWARE_PS if case.endswith("shadow_aware") else 0
+    stop_tol = 0.5 if case.endswith("_stop") else 0.0
+    ref, got = _solve_both(sc, dev, flags=flags, stop_tol=stop_tol)
+    _compare_solve(ref, got, case)
+    for key in ("normals", "albedo", "depth", "indirect"):
+        assert np.array_equal(got[key], ref[key]), key
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 4, 1, seed=2)
+    job = dict(images=T(I0, dev), light_dirs=sc.light_dirs, light_intensity=sc.light_intensity,
+               env=T(sc.env, dev), spp=4, bounces=1, iterations=1, box=gbox(sc, dev))
+    with pytest.raises(irtps.IrtpsError) as e:
+        irtps.batch_solve([job], workspace=torch.empty(1 << 24, dtype=torch.uint8, device=dev))
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("case", ["bowl64", "fbm160x120", "bowl64_exact_r2", "bowl64_in_box"])
 def test_solve_graph_replays_equal_eager(dev, case):
     """IRTPS_FLAG_GRAPH: the first call captures the solve into a hipGraph, later
     identical calls replay it.  Every replay, with eager solves and host
@@ -584,29 +692,33 @@ def test_solve_graph_replays_equal_eager(dev, case):
     extra = irtps.flag_exact_r(2) if case.endswith("exact_r2") else 0
     if case.startswith("bowl64"):
         sc = scenes.bowl_64()
+        if case.endswith("in_box"):
+            sc = scenes.in_box(sc, 12.0, tex=(8, 16), seed=1)
     else:
         sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=8, env_shape=(16, 32),
                                 ptp=16.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
         sc.heights = np.ascontiguousarray(sc.heights[:120])
         sc.normals = np.ascontiguousarray(sc.normals[:120])
         sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
-    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 1, seed=1)
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 1, seed=1,
+                     box=sc.box)
+    bx = gbox(sc, dev)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         args = (T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp, sc.bounces, sc.iterations)
-        ref = {k: H(v) for k, v in irtps.solve(*args, seed=3, flags=extra).items()}
-        ws = torch.empty(irtps.workspace_bytes(*args, seed=3, flags=extra), dtype=torch.uint8, device=dev)
+        ref = {k: H(v) for k, v in irtps.solve(*args, seed=3, flags=extra, box=bx).items()}
+        ws = torch.empty(irtps.workspace_bytes(*args, seed=3, flags=extra, box=bx), dtype=torch.uint8, device=dev)
         out = irtps._outputs_for(args[0], dev)
         for rep in range(4):
-            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, out=out, workspace=ws)
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, out=out, workspace=ws, box=bx)
             got = {k: H(v) for k, v in out.items()}
             for key in ("normals", "albedo", "depth", "indirect", "counters"):
                 assert np.array_equal(got[key], ref[key]), (rep, key)
-            irtps.solve(*args, seed=3, flags=extra)  # eager work between the replays
+            irtps.solve(*args, seed=3, flags=extra, box=bx)  # eager work between the replays
             torch.cuda.synchronize()
     with pytest.raises(irtps.IrtpsError):  # the stop rule's read-back cannot be captured
         with torch.cuda.stream(stream):
-            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, stop_tol=0.5)
+            irtps.solve(*args, seed=3, flags=irtps.FLAG_GRAPH | extra, stop_tol=0.5, box=bx)
 
 
 def test_solve_T0_is_plain_ps(dev):

@@ -166,6 +166,11 @@ def test_cancel_of_only_job_wakes_its_waiter():
         assert not th.is_alive()
         assert got["st"].state == irtps.JOB_CANCELLED
         assert got["s"] < 10.0  # woken by the cancellation, not by the time-out
+        # the other jobs retire at the scheduler's next rounds, after cancel() returned
+        t2 = time.monotonic()
+        while srv.stats()["cancelled"] < 40:
+            assert time.monotonic() - t2 < 20.0
+            time.sleep(0.001)
         assert srv.stats()["cancelled"] == 40
     finally:
         srv.close()
