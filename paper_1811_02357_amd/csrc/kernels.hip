@@ -1010,7 +1010,7 @@ __device__ __forceinline__ void min_key_strided(const float* __restrict__ X, lon
 // until at least ready_batch lanes (or all that still have work) have finished
 // theirs, with a phase that shades the finished segments and starts the next
 // ones.  A lane's segments are summed in (sample, bounce) order.
-constexpr int kStepsPerVote = 3;
+constexpr int kStepsPerVote = 4;
 // Shading rounds in a row for segments the horizon bounds let go at once.
 constexpr int kEscapeRounds = 3;
 

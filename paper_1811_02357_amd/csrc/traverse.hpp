@@ -263,11 +263,17 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
     const bool rising = r.dz >= 0.0f;
     // at or above every sample and not descending: no crossing ahead can hit
     if (z_now >= S.hmax && rising) return kMiss;
-    if (w.level >= kMinSkipLevel) {
+    // The walker's next state is computed as values and stored once at the
+    // end: with one store per field, divergent lanes need no register copies
+    // where the branches join (the step is the tracer's inner loop).
+    int mx = w.mx, my = w.my, level = w.level;
+    float tX = w.tX, tY = w.tY;
+    bool cross = true;  // evaluate the crossing at t_now in this step
+    if (level >= kMinSkipLevel) {
         const float px = fmaf(t_now, r.dx, r.nx0);
         const float py = fmaf(t_now, r.dy, r.ny0);
         if (px >= 2.0f && px <= (float)(S.W - 3) && py >= 2.0f && py <= (float)(S.Hh - 3)) {
-            const int l = w.level;
+            const int l = level;
             const unsigned ix = (unsigned)px, iy = (unsigned)py;  // px, py > 0: truncation is floor
             // Escape windows of the block holding the (nudged) position: every
             // sample a later crossing can read within escape_scale(k) of travel
@@ -297,65 +303,72 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
             // every crossing with t in [t_now, t_exit) lies in the grown cell and
             // the ray is at or above its maximum over that range (t_exit is finite:
             // a ray with no travel along either axis never gets here)
-            if (((int)(z_now >= cmax) & (int)(z_exit >= cmax) & (int)(t_exit > t_now)) != 0) {
+            const bool skip = ((int)(z_now >= cmax) & (int)(z_exit >= cmax) & (int)(t_exit > t_now)) != 0;
+            if (skip) {
                 // Resume at the first crossing of each family at or after t_exit:
                 // the exit line itself for the family the ray leaves through (t is
                 // strictly increasing in the index), a search for the other.
                 float t_o;
                 const int m_o = first_index_at_or_after(x_exit ? r.ainv_y : r.ainv_x,
                                                         fabsf(x_exit ? r.dy : r.dx), t_exit, t_o);
-                w.mx = x_exit ? mxa : m_o;
-                w.tX = x_exit ? t_exit : t_o;
-                w.my = x_exit ? m_o : mya;
-                w.tY = x_exit ? t_o : t_exit;
-                if (l < S.top) w.level = l + 1;
-                return kGoOn;
+                mx = x_exit ? mxa : m_o;
+                tX = x_exit ? t_exit : t_o;
+                my = x_exit ? m_o : mya;
+                tY = x_exit ? t_o : t_exit;
             }
-            if (l > kMinSkipLevel) {
-                w.level = l - 1;
-                return kGoOn;
+            // a skip climbs a level; a failed test descends one, or, at the
+            // finest skip level, falls through to the crossing
+            level = skip ? (l < S.top ? l + 1 : l) : (l > kMinSkipLevel ? l - 1 : l);
+            cross = !skip && l <= kMinSkipLevel;
+        }
+    }
+    int res = kGoOn;
+    if (cross) {
+        // Evaluate the nearer crossing at t = t_now and height z_now.  It hits
+        // when the ray is strictly below the surface there; the shading sample
+        // is the nearer end of that grid segment.
+        const int m = xline ? mx : my;
+        const int o_major = xline ? r.i0 : r.j0;
+        const int major = __mul24(xline ? r.sx : r.sy, m) + o_major;  // sx, sy are +-1
+        const int n_major = xline ? S.W : S.Hh;
+        const int n_minor = xline ? S.Hh : S.W;
+        const float minor = fmaf(t_now, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
+        if ((unsigned)major > (unsigned)(n_major - 1) || !(minor >= 0.0f && minor <= (float)(n_minor - 1))) {
+            res = kMiss;  // the ray has left the domain
+        } else {
+            const float fm = floorf(minor);
+            const int m0 = (int)fm;
+            const float f = minor - fm;
+            const unsigned idx0 = xline ? __umul24((unsigned)m0, (unsigned)S.W) + (unsigned)major
+                                        : __umul24((unsigned)major, (unsigned)S.W) + (unsigned)m0;
+            // the segment's second sample (the first again when the crossing is on a
+            // sample: then the lerp below returns h0 without reading past the border)
+            const unsigned step1 = f != 0.0f ? (xline ? (unsigned)S.W : 1u) : 0u;
+            const float h0 = ld32(S.H, idx0);
+            const float h1 = ld32(S.H, idx0 + step1);
+            // h0 + f (h1 - h0), clamped to the segment's range (the median of the three)
+            const float h = __builtin_amdgcn_fmed3f(fmaf(f, h1 - h0, h0), h0, h1);
+            if (z_now < h) {
+                const int qm = f < 0.5f ? m0 : m0 + 1;
+                qi = xline ? major : qm;
+                qj = xline ? qm : major;
+                res = kHit;
+            } else {
+                const int m1 = m + 1;
+                const float t1 = (float)m1 * (xline ? r.ainv_x : r.ainv_y);
+                mx = xline ? m1 : mx;
+                tX = xline ? t1 : tX;
+                my = xline ? my : m1;
+                tY = xline ? tY : t1;
             }
         }
     }
-    // Evaluate the nearer crossing at t = t_now and height z_now.  It hits when
-    // the ray is strictly below the surface there; the shading sample is the
-    // nearer end of that grid segment.
-    const int m = xline ? w.mx : w.my;
-    const int o_major = xline ? r.i0 : r.j0;
-    const int major = (xline ? r.sx > 0 : r.sy > 0) ? o_major + m : o_major - m;
-    const int n_major = xline ? S.W : S.Hh;
-    if ((unsigned)major > (unsigned)(n_major - 1)) return kMiss;
-    const int n_minor = xline ? S.Hh : S.W;
-    const float minor = fmaf(t_now, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
-    if (!(minor >= 0.0f && minor <= (float)(n_minor - 1))) return kMiss;
-    const float fm = floorf(minor);
-    const int m0 = (int)fm;
-    const float f = minor - fm;
-    const unsigned idx0 = xline ? __umul24((unsigned)m0, (unsigned)S.W) + (unsigned)major
-                                : __umul24((unsigned)major, (unsigned)S.W) + (unsigned)m0;
-    // the segment's second sample (the first again when the crossing is on a
-    // sample: then the lerp below returns h0 without reading past the border)
-    const unsigned step1 = f != 0.0f ? (xline ? (unsigned)S.W : 1u) : 0u;
-    const float h0 = ld32(S.H, idx0);
-    const float h1 = ld32(S.H, idx0 + step1);
-    // h0 + f (h1 - h0), clamped to the segment's range (the median of the three)
-    const float h = __builtin_amdgcn_fmed3f(fmaf(f, h1 - h0, h0), h0, h1);
-    if (z_now < h) {
-        const int qm = f < 0.5f ? m0 : m0 + 1;
-        qi = xline ? major : qm;
-        qj = xline ? qm : major;
-        return kHit;
-    }
-    const int m1 = m + 1;
-    const float t1 = (float)m1 * (xline ? r.ainv_x : r.ainv_y);
-    if (xline) {
-        w.mx = m1;
-        w.tX = t1;
-    } else {
-        w.my = m1;
-        w.tY = t1;
-    }
-    return kGoOn;
+    w.mx = mx;
+    w.my = my;
+    w.tX = tX;
+    w.tY = tY;
+    w.level = level;
+    return res;
 }
 
 // Whole walk in one call (shadow rays, probes).
