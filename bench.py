@@ -131,13 +131,17 @@ def profiled_values(workload):
         return None
 
 
-def probe_peak():
-    """The measured VALU issue peak (wave64 instructions per second with every
-    lane active) from the committed calibration profile, or None."""
+def probe_rates():
+    """The measured VALU issue rates (wave64 instructions per second, every lane
+    active) from the committed calibration profile: the peak (the fastest
+    instruction kind) and the rate of each kind, or None."""
     try:
         with open(VALU_PROBE_PROFILE) as f:
             kv = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
-        return float(kv["valu_peak_wave_instructions_per_s"])
+        return {"peak": float(kv["valu_peak_wave_instructions_per_s"]),
+                "integer_shift_xor_add": float(kv["valu_integer_wave_instructions_per_s"]),
+                "register_move": float(kv["valu_move_wave_instructions_per_s"]),
+                "fma_f32": float(kv["valu_fma_wave_instructions_per_s"])}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -531,7 +535,7 @@ def main():
     ap.add_argument("--sweep-pool", type=int, default=12)
     ap.add_argument("--small-reps", type=int, default=200)
     ap.add_argument("--batched-jobs", type=int, default=64)
-    ap.add_argument("--served-jobs", type=int, default=24)
+    ap.add_argument("--served-jobs", type=int, default=60)
     ap.add_argument("--served-budget-gib", type=float, default=96.0)
     ap.add_argument("--served-fill", type=int, default=1 << 21,
                     help="server fill_pixels: the oldest job, then least-remaining-work jobs, this many pixels per round")
@@ -580,22 +584,28 @@ def main():
         blocks = cus * 8  # 256-thread blocks: 8 waves per SIMD
         stream = torch.cuda.current_stream()
         irtps.probe_valu(blocks, 16)  # warm-up
-        res = {}
-        for active in (64, 32, 16, 1):
+
+        def best_ms(active, kind):
             ms = []
             for _ in range(3):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                irtps.probe_valu(blocks, args.valu_probe, active)
+                irtps.probe_valu(blocks, args.valu_probe, active, kind)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ms.append(e0.elapsed_time(e1))
-            res[str(active)] = min(ms)
-        waves = blocks * 4
-        loop = waves * 16 * args.valu_probe
+            return min(ms)
+
+        # launch order: integer kind at 64, 32, 16, 1 active lanes, then the
+        # register-move and fma kinds at 64 (three launches each)
+        res = {str(active): best_ms(active, 0) for active in (64, 32, 16, 1)}
+        kinds = {"integer_shift_xor_add": res["64"], "register_move": best_ms(64, 1), "fma_f32": best_ms(64, 2)}
+        loop = blocks * 4 * 16 * args.valu_probe
         print(json.dumps({"valu_probe": {"cus": cus, "blocks": blocks, "iters": args.valu_probe,
-                                         "min_ms_by_active_lanes": res, "loop_wave_instructions": loop,
-                                         "loop_rate_per_s": loop / (res["64"] / 1e3)}}), flush=True)
+                                         "min_ms_by_active_lanes": res, "min_ms_by_kind": kinds,
+                                         "loop_wave_instructions": loop,
+                                         "rate_per_s_by_kind": {k: loop / (v / 1e3) for k, v in kinds.items()}}}),
+              flush=True)
         return
     wl = WORKLOADS[args.workload]
     log(f"bench: building scene {args.workload}")
@@ -669,20 +679,25 @@ def main():
                           "fabric_bytes_per_launch": None if args.flat else profiled_traffic(args.workload)},
     }
     prof = None if args.flat else profiled_values(args.workload)
-    peak = probe_peak()
-    if prof is not None and peak is not None:
+    rates = probe_rates()
+    if prof is not None and rates is not None:
         # The binding limit is VALU issue: the counted wave64 VALU instructions of
         # the profiled kernel over this run's launch time, each carrying the
         # profile's mean active lanes.  The roofline is in lane-operations
-        # (instructions x active lanes) against the measured full-lane peak.
+        # (instructions x active lanes) against the measured full-lane peak, the
+        # issue rate of the fastest instruction kind (register moves); the
+        # issue rate itself lies between the probe's kinds.
+        peak = rates["peak"]
         issue = prof["valu"] / (per_launch_ms / 1e3)
         lane_ops = issue * 64 * prof["lanes"] / 1e12
         line["roofline"] = {"bound": "alu", "achieved": lane_ops, "peak": peak * 64 / 1e12,
                             "unit": "Tlane-op/s", "frac": lane_ops / (peak * 64 / 1e12),
                             "traffic": prof["traffic"]}
         line["valu"] = {"wave_instructions_per_launch": prof["valu"], "issue_per_s": issue,
-                        "probe_peak_issue_per_s": peak, "nominal_issue_per_s": VALU_ISSUE_NOMINAL,
-                        "issue_ratio_to_probe": issue / peak, "lane_utilisation": prof["lanes"],
+                        "issue_frac_of_peak": issue / peak, "lane_utilisation": prof["lanes"],
+                        "useful_lane_frac_of_peak": issue * prof["lanes"] / peak,
+                        "probe_issue_per_s": {k: v for k, v in rates.items() if k != "peak"},
+                        "nominal_issue_per_s": VALU_ISSUE_NOMINAL,
                         "sources": [os.path.relpath(TRAFFIC_PROFILE, ROOT), os.path.relpath(VALU_PROBE_PROFILE, ROOT)]}
     else:
         line["roofline"] = dict(line["hbm_yardstick"], bound="hbm",

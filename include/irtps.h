@@ -507,12 +507,15 @@ int irtps_profile_end(double* trace_ms, int64_t* launches);
 
 /* ---- probes of the device arithmetic (parity checks) -------------------- */
 /* Issue-rate calibration (not part of the method): `blocks` blocks of 256
- * threads, each lane running `iters` rounds of 16 independent 32-bit integer
- * VALU instructions; only lanes below active_lanes (1..64) of each wave do the
- * work, the others are masked off.  out_dev receives blocks x 256 uint32 (the
- * chains' values, so that the work is kept).  A counted and timed launch
- * measures the VALU instruction rate the tracer's is compared with. */
-int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, uint32_t* out_dev, void* stream);
+ * threads, each lane running `iters` rounds of 16 independent VALU
+ * instructions of one kind -- 0: 32-bit integer shift and xor-add pairs, 1:
+ * register moves, 2: fp32 fused multiply-adds; only lanes below active_lanes
+ * (1..64) of each wave do the work, the others are masked off.  out_dev
+ * receives blocks x 256 uint32 (the chains' values, so that the work is
+ * kept).  Counted and timed launches measure the VALU instruction rates the
+ * tracer's is compared with (the rate depends on the kind). */
+int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, int32_t kind, uint32_t* out_dev,
+                     void* stream);
 /* Philox4x32-10 of count counters [count][4] under key (seed lo, hi) -> out [count][4]. */
 int irtps_probe_philox(int64_t count, const uint32_t* ctr_dev, uint64_t seed,
                        uint32_t* out_dev, void* stream);

@@ -582,10 +582,12 @@ int irtps_profile_end(double* trace_ms, int64_t* launches) {
     return IRTPS_OK;
 }
 
-int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, uint32_t* out_dev, void* stream) {
-    if (blocks < 1 || blocks > (1 << 24) || iters < 0 || active_lanes < 1 || active_lanes > 64 || !out_dev)
+int irtps_probe_valu(int32_t blocks, int32_t iters, int32_t active_lanes, int32_t kind, uint32_t* out_dev,
+                     void* stream) {
+    if (blocks < 1 || blocks > (1 << 24) || iters < 0 || active_lanes < 1 || active_lanes > 64 || kind < 0 ||
+        kind > 2 || !out_dev)
         return IRTPS_ERR_INVALID_ARG;
-    HIP_TRY(kern::probe_valu(blocks, iters, active_lanes, out_dev, reinterpret_cast<hipStream_t>(stream)));
+    HIP_TRY(kern::probe_valu(blocks, iters, active_lanes, kind, out_dev, reinterpret_cast<hipStream_t>(stream)));
     return IRTPS_OK;
 }
 

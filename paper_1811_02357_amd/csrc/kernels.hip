@@ -2128,21 +2128,48 @@ __global__ void k_stop_multi(JobDesc* jobs, int njobs) {
 // work (the wave still issues it with those lanes masked off).  A counted, timed
 // launch gives the wave64 VALU instructions the chip retires per second, and how
 // that rate depends on the active lanes.
+// VALU issue-rate probe: each round 16 independent wave64 instructions of one
+// kind -- 0: integer shift and xor-add pairs (compiler-chosen encodings), 1:
+// register moves, 2: fp32 fma -- on the lanes below `active`; no memory access
+// in the loop.  One kernel per kind, so that a round holds nothing else; kinds
+// 1 and 2 are written out so that each round is exactly those 16 instructions.
+template <int KIND>
 __global__ void __launch_bounds__(256) k_probe_valu(int iters, int active, uint32_t* out) {
     uint32_t x[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) x[r] = threadIdx.x * 0x9E3779B9u + blockIdx.x * 0x85EBCA6Bu + (uint32_t)r;
+    float f[4] = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
     const bool on = (int)(threadIdx.x & 63) < active;
     for (int i = 0; i < iters; ++i) {
         if (on) {
+            if (KIND == 0) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) x[r] = (x[r] ^ (x[r] >> 7)) + 0x7F4A7C15u;
+                for (int r = 0; r < 8; ++r) x[r] = (x[r] ^ (x[r] >> 7)) + 0x7F4A7C15u;
+            } else if (KIND == 1) {
+                __asm__ volatile(
+                    "v_mov_b32 %0, %4\n v_mov_b32 %1, %4\n v_mov_b32 %2, %4\n v_mov_b32 %3, %4\n"
+                    "v_mov_b32 %0, %5\n v_mov_b32 %1, %5\n v_mov_b32 %2, %5\n v_mov_b32 %3, %5\n"
+                    "v_mov_b32 %0, %4\n v_mov_b32 %1, %4\n v_mov_b32 %2, %4\n v_mov_b32 %3, %4\n"
+                    "v_mov_b32 %0, %5\n v_mov_b32 %1, %5\n v_mov_b32 %2, %5\n v_mov_b32 %3, %5\n"
+                    : "=v"(x[0]), "=v"(x[1]), "=v"(x[2]), "=v"(x[3])
+                    : "v"(x[4]), "v"(x[5]));
+            } else {
+                __asm__ volatile(
+                    "v_fma_f32 %0, %4, %6, %5\n v_fma_f32 %1, %5, %6, %4\n v_fma_f32 %2, %4, %6, %4\n v_fma_f32 %3, %5, %6, %5\n"
+                    "v_fma_f32 %0, %5, %6, %4\n v_fma_f32 %1, %4, %6, %5\n v_fma_f32 %2, %5, %6, %5\n v_fma_f32 %3, %4, %6, %4\n"
+                    "v_fma_f32 %0, %4, %6, %5\n v_fma_f32 %1, %5, %6, %4\n v_fma_f32 %2, %4, %6, %4\n v_fma_f32 %3, %5, %6, %5\n"
+                    "v_fma_f32 %0, %5, %6, %4\n v_fma_f32 %1, %4, %6, %5\n v_fma_f32 %2, %5, %6, %5\n v_fma_f32 %3, %4, %6, %4\n"
+                    : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3])
+                    : "v"(__uint_as_float(x[4])), "v"(__uint_as_float(x[5])), "v"(0.5f));
+            }
         }
         __asm__ volatile("" ::: "memory");  // keeps the masked body inside the loop
     }
     uint32_t acc = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc ^= x[r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc ^= __float_as_uint(f[r]);
     out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
@@ -2567,8 +2594,10 @@ hipError_t batch_integrate(const JobDesc* jobs, const BatchShape& bs, int cold, 
     return hipGetLastError();
 }
 
-hipError_t probe_valu(int blocks, int iters, int active, uint32_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_probe_valu, dim3(blocks), dim3(256), 0, st, iters, active, out);
+hipError_t probe_valu(int blocks, int iters, int active, int kind, uint32_t* out, hipStream_t st) {
+    if (kind == 0) hipLaunchKernelGGL(k_probe_valu<0>, dim3(blocks), dim3(256), 0, st, iters, active, out);
+    else if (kind == 1) hipLaunchKernelGGL(k_probe_valu<1>, dim3(blocks), dim3(256), 0, st, iters, active, out);
+    else hipLaunchKernelGGL(k_probe_valu<2>, dim3(blocks), dim3(256), 0, st, iters, active, out);
     return hipGetLastError();
 }
 

@@ -307,7 +307,7 @@ hipError_t batch_advance(JobDesc* jobs, int njobs, hipStream_t st);
 
 // ---- probes ----
 // out: blocks x 256 uint32.
-hipError_t probe_valu(int blocks, int iters, int active, uint32_t* out, hipStream_t st);
+hipError_t probe_valu(int blocks, int iters, int active, int kind, uint32_t* out, hipStream_t st);
 hipError_t probe_philox(long long count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                         hipStream_t st);
 hipError_t probe_sample(long long count, const float* n, const float* u, float* d, hipStream_t st);

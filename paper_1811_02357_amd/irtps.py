@@ -147,7 +147,7 @@ def lib():
             "irtps_solve_static": [P(Problem), P(Params), P(Outputs), _vp],
             "irtps_ps_solve": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
             "irtps_ps_solve_masked": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-            "irtps_probe_valu": [_i32, _i32, _i32, _vp, _vp],
+            "irtps_probe_valu": [_i32, _i32, _i32, _i32, _vp, _vp],
             "irtps_integrate_workspace_bytes": [_i32, _i32, P(_sz)],
             "irtps_integrate": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp],
             "irtps_integrate_robust": [_i32, _i32, _vp, _vp, _i32, ct.c_float, _i32, _i32, _vp, _vp, _sz, _vp],
@@ -732,11 +732,12 @@ def profile_end():
 
 
 # ---- probes ----------------------------------------------------------------
-def probe_valu(blocks, iters, active_lanes=64, stream=None):
-    """Launch the VALU issue-rate probe once; returns its output buffer."""
+def probe_valu(blocks, iters, active_lanes=64, kind=0, stream=None):
+    """Launch the VALU issue-rate probe once (kind 0: integer shift/xor-add, 1:
+    register moves, 2: fp32 fma); returns its output buffer."""
     out = torch.empty(blocks * 256, dtype=torch.int32, device=torch.device("cuda"))
-    _check("irtps_probe_valu", lib().irtps_probe_valu(blocks, iters, active_lanes, _dev(out, dtype=torch.int32),
-                                                      _stream(stream)))
+    _check("irtps_probe_valu", lib().irtps_probe_valu(blocks, iters, active_lanes, kind,
+                                                      _dev(out, dtype=torch.int32), _stream(stream)))
     return out
 
 
