@@ -251,3 +251,12 @@ def test_box_validation_and_workspace_on_host():
         assert L.irtps_server_submit(srv, ct.byref(pr), ct.byref(robust), ct.byref(o), ct.byref(job)) == 1
     finally:
         L.irtps_server_destroy(srv)
+
+
+def test_valu_probe_arguments_on_host():
+    """The issue-rate probe takes kinds 0..2 and 1..64 active lanes."""
+    L = irtps.lib()
+    p = ct.c_void_p(256)
+    for blocks, iters, active, kind in ((1, 1, 0, 0), (1, 1, 65, 0), (1, 1, 64, 3), (1, 1, 64, -1), (0, 1, 64, 0)):
+        assert L.irtps_probe_valu(blocks, iters, active, kind, p, None) == 1
+    assert L.irtps_probe_valu(1, 1, 64, 0, None, None) == 1

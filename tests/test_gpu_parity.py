@@ -99,6 +99,61 @@ def test_philox_probe(dev):
         assert np.array_equal(got, ref)
 
 
+def _probe_valu_model(blocks, iters, active, kind):
+    """The issue-rate probe's outputs by its definition: per lane eight integer
+    chains (and four float values), the kind's 16 instructions per round on the
+    lanes below `active` of each wave, then everything xor-ed together."""
+    tid = np.arange(256, dtype=np.uint64)
+    outs = []
+    for b in range(blocks):
+        x = [((tid * 0x9E3779B9 + b * 0x85EBCA6B + r) & 0xFFFFFFFF).astype(np.uint32) for r in range(8)]
+        f = [x[r].astype(np.float32) for r in range(4)]
+        on = (tid & 63) < active
+        if iters > 0:
+            if kind == 0:
+                for _ in range(iters):
+                    for r in range(8):
+                        x[r] = np.where(on, (x[r] ^ (x[r] >> np.uint32(7))) + np.uint32(0x7F4A7C15), x[r])
+            elif kind == 1:  # the last four moves copy x[5]
+                for r in range(4):
+                    x[r] = np.where(on, x[5], x[r])
+            else:  # the last four fma of a round
+                x4, x5, h = x[4].view(np.float32), x[5].view(np.float32), np.float32(0.5)
+                with np.errstate(all="ignore"):  # non-finite operands are not compared
+                    last = [fmaf(x5, h, x4), fmaf(x4, h, x5), fmaf(x5, h, x5), fmaf(x4, h, x4)]
+                for r in range(4):
+                    f[r] = np.where(on, last[r], f[r])
+        acc = np.zeros(256, np.uint32)
+        for r in range(8):
+            acc ^= x[r]
+        for r in range(4):
+            acc ^= np.asarray(f[r], np.float32).view(np.uint32)
+        outs.append(acc)
+    return np.concatenate(outs)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_valu_probe_kinds(dev, kind):
+    """The issue-rate probe computes what it states for each instruction kind,
+    with the lanes at or above `active` masked off (its outputs are kept so that
+    no work is dropped).  The fma kind is compared where the operands are
+    finite."""
+    say(f"case: VALU probe kind {kind}")
+    for iters, active in ((0, 64), (3, 64), (5, 40), (2, 1)):
+        got = H(irtps.probe_valu(3, iters, active, kind)).view(np.uint32)
+        ref = _probe_valu_model(3, iters, active, kind)
+        if kind == 2:
+            tid = np.tile(np.arange(256), 3)
+            b = np.repeat(np.arange(3), 256)
+            x4 = ((tid * 0x9E3779B9 + b * 0x85EBCA6B + 4) & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+            x5 = ((tid * 0x9E3779B9 + b * 0x85EBCA6B + 5) & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+            keep = np.isfinite(x4) & np.isfinite(x5) & (np.abs(x4) < 1e30) & (np.abs(x5) < 1e30)
+            assert keep.mean() > 0.5
+            assert np.array_equal(got[keep], ref[keep]), (iters, active)
+        else:
+            assert np.array_equal(got, ref), (iters, active)
+
+
 def test_sample_probe(dev):
     say("case: cosine sampling probe, 300k normals")
     rng = np.random.default_rng(1)
