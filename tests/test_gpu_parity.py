@@ -701,6 +701,71 @@ def test_trace_with_box_stage(dev, case):
     assert np.array_equal(H(G), ref)
 
 
+def _edge_scene(name):
+    rng = np.random.default_rng(77)
+    if name == "2x2_rgb_K5":
+        Hf = np.array([[0.0, 1.5], [0.7, -0.4]], F32)
+        sc = scenes._scene(name, Hf, rng.uniform(0.3, 0.9, (3, 2, 2)), scenes.fibonacci_lights(5),
+                           rng.uniform(0.6, 1.4, 5), rng.uniform(0.1, 1.0, (4, 8, 3)))
+    elif name == "3x257_grey_K7":
+        Hf = (np.sin(np.arange(257) / 9.0)[None, :] * 3.0 + np.arange(3)[:, None]).astype(F32)
+        sc = scenes._scene(name, Hf, rng.uniform(0.3, 0.9, (1, 3, 257)), scenes.fibonacci_lights(7),
+                           np.ones(7), rng.uniform(0.1, 1.0, (8, 16, 1)))
+    else:  # walls below every sample: no ray can meet them
+        sc = scenes.tiny_scene(17, 13, seed=3, channels=3, num_lights=6, amp=3.0)
+        sc.heights = (sc.heights - sc.heights.min() + 1.0).astype(F32)
+        sc.box = {"Z": 0.5, "albedo": scenes.cornell_walls(3, (3, 5), 9)}
+        return sc
+    return scenes.in_box(sc, 2.5, tex=(3, 2), seed=5)
+
+
+@pytest.mark.parametrize("name", ["2x2_rgb_K5", "3x257_grey_K7", "walls_below_surface"])
+def test_box_edge_cases(dev, name):
+    """Walls around a 2 x 2 RGB surface with 5 lights (no float4 rows), a
+    3 x 257 grey strip with 7 lights, and walls lower than every sample (which
+    must change nothing): wall light, direct light, gather (B = 3) and render
+    against the oracle."""
+    say(f"case: walls, edge case {name}")
+    sc = _edge_scene(name)
+    W, Hh, Z = sc.width, sc.height, sc.box["Z"]
+    Sw = O.box_shade(W, Hh, sc.box, sc.light_dirs, sc.light_intensity)
+    assert np.array_equal(H(irtps.box_shade(W, Hh, gbox(sc, dev), sc.light_dirs, sc.light_intensity)), Sw)
+    S = O.direct(sc.heights, sc.normals, sc.light_dirs, sc.light_intensity, box_z=Z)
+    assert np.array_equal(H(irtps.direct(T(sc.heights, dev), T(sc.normals, dev), sc.light_dirs, sc.light_intensity,
+                                         box=gbox(sc, dev))), S)
+    box = dict(sc.box, S=Sw)
+    ref, rc = O.trace(sc.heights, sc.normals, sc.albedo, S, sc.env, 12, 3, 5, box=box)
+    cnt = torch.zeros(irtps.NUM_COUNTERS, dtype=torch.int64, device=dev)
+    G = irtps.trace(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), T(S, dev), T(sc.env, dev), 12, 3, 5,
+                    counters=cnt, box=gbox(sc, dev), wall_S=T(Sw, dev))
+    assert np.array_equal(H(G), np.transpose(ref, (2, 3, 0, 1)))
+    assert H(cnt).tolist()[:4] == [rc["segments"], rc["hits"], rc["escapes"], rc["continuations"]]
+    if name == "walls_below_surface":
+        assert np.array_equal(ref, O.trace(sc.heights, sc.normals, sc.albedo, S, sc.env, 12, 3, 5)[0])
+    I = irtps.render(T(sc.heights, dev), T(sc.normals, dev), T(sc.albedo, dev), sc.light_dirs, sc.light_intensity,
+                     T(sc.env, dev), 8, 2, 1, box=gbox(sc, dev))
+    Iref, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 8, 2, 1,
+                       box=sc.box)
+    assert np.array_equal(H(I), Iref)
+
+
+@pytest.mark.parametrize("shape,C,K,r", [((2, 2), 3, 5, 1), ((2, 2), 1, 3, 3), ((3, 257), 1, 7, 2),
+                                          ((129, 3), 3, 6, 4)])
+def test_exact_r_edge_cases(dev, shape, C, K, r):
+    """The r-ray loop on a 2 x 2 image (one coarse level), one-row-like strips
+    and light counts that are not a multiple of 4, against the oracle."""
+    Hh, W = shape
+    say(f"case: r-ray loop {Hh}x{W} C={C} K={K} r={r}")
+    rng = np.random.default_rng(Hh * 31 + W + r)
+    Hf = rng.uniform(0.0, 2.0, (Hh, W)).astype(F32)
+    sc = scenes._scene("edge", Hf, rng.uniform(0.3, 0.9, (C, Hh, W)), scenes.fibonacci_lights(K),
+                       rng.uniform(0.6, 1.4, K), rng.uniform(0.1, 1.0, (4, 8, C)), spp=4, bounces=2, iterations=2)
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 16, 2, 4)
+    ref, got = _solve_both(sc, dev, I0=I0, flags=irtps.flag_exact_r(r))
+    for key in ("normals", "albedo", "depth", "indirect"):
+        assert np.array_equal(got[key], ref[key]), key
+
+
 def test_render_with_box(dev):
     say("case: render bowl64 in walls spp 64 B 2")
     sc = BOX_SCENES["bowl64_Z12"]()
