@@ -466,7 +466,7 @@ typedef struct {
     int32_t ready_batch;
 } irtps_schedule;
 
-#define IRTPS_TUNE_CANDIDATES 16
+#define IRTPS_TUNE_CANDIDATES 20
 
 /* Force tile_w and/or ready_batch for every later trace in the process; 0
  * returns that field to the table / default.  Process-wide, thread-safe. */
@@ -478,14 +478,17 @@ int irtps_get_schedule(int32_t W, int32_t H, int32_t C, int32_t K, int32_t B, ir
 int irtps_set_ready_batch(int32_t lanes);
 int irtps_get_ready_batch(void);
 
-/* Autotuner: brings the problem to the state of its first traced iteration (PS
- * of the images, integration, pyramid, direct light, written to outputs and the
- * workspace) and times trace launches (the faster of two) for each of the IRTPS_TUNE_CANDIDATES
- * schedules (tile_w in 8, 16, 32, 64 times ready_batch in 16, 24, 32, 48, in that
- * order; ms_out, if not NULL, receives the times in milliseconds).  The fastest
- * goes into the process's tuning table for the problem's class and to *best.
- * Workspace as for irtps_solve (irtps_workspace_bytes); the call synchronises
- * the stream. */
+/* Autotuner: brings the problem to the state its second traced iteration
+ * sees (PS of the images, integration, one IRT iteration with the default
+ * schedule, then pyramid and direct light; written to outputs and the
+ * workspace) and, for each of the IRTPS_TUNE_CANDIDATES schedules (tile_w in
+ * 8, 16, 32, 64 times ready_batch in 24, 32, 40, 48, 56, in that order), runs
+ * one trace launch that records the tiles' times and then times launches that
+ * deal the tiles heaviest first, as the solve's later iterations do (the
+ * faster of two; ms_out, if not NULL, receives the times in milliseconds).
+ * The fastest goes into the process's tuning table for the problem's class and
+ * to *best.  Workspace as for irtps_solve (irtps_workspace_bytes); the call
+ * synchronises the stream. */
 int irtps_autotune(const irtps_problem* problem, const irtps_params* params, const irtps_outputs* outputs,
                    void* ws_dev, size_t ws_bytes, void* stream, irtps_schedule* best, float* ms_out);
 /* The tuning table as JSON: {"arch": "<gcnArchName>", "entries": [{"side",

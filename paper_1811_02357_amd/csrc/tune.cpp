@@ -30,7 +30,7 @@ namespace {
 constexpr int kDefaultShift = 4;   // 16 x 16 tiles
 constexpr int kDefaultBatch = 32;  // half a wave
 constexpr int kShifts[] = {3, 4, 5, 6};
-constexpr int kBatches[] = {16, 24, 32, 48};
+constexpr int kBatches[] = {24, 32, 40, 48, 56};
 constexpr int kRepeats = 2;
 
 struct Key {
@@ -241,13 +241,17 @@ int irtps_autotune(const irtps_problem* pr, const irtps_params* pa, const irtps_
     if (pa->bounces < 1) return IRTPS_ERR_INVALID_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws_dev);
+    float* A = reinterpret_cast<float*>(base + lay.A);
     float* S = reinterpret_cast<float*>(base + lay.S);
     float* G = reinterpret_cast<float*>(base + lay.G);
     float* pyr = reinterpret_cast<float*>(base + lay.pyr);
     float* mg = reinterpret_cast<float*>(base + lay.mg);
+    unsigned* tile_cost = reinterpret_cast<unsigned*>(base + lay.tile_cost);
+    int* tile_order = reinterpret_cast<int*>(base + lay.tile_order);
     const long long npx = (long long)W * H;
+    const int flat = (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0;
 
-    // the state the first traced iteration sees: PS of the inputs, integrated
+    // t = 0: PS of the inputs, integrated
     kern::PsMatrix M;
     kern::LightSet L;
     STATUS_TRY(make_psmatrix(K, pr->light_dirs_host, pr->light_intensity_host, M));
@@ -255,10 +259,10 @@ int irtps_autotune(const irtps_problem* pr, const irtps_params* pa, const irtps_
     HIP_TRY(kern::ps_solve((int)npx, C, K, M, pr->images_dev, out->normals_dev, out->albedo_dev, st));
     HIP_TRY(kern::integrate(lay.plan, out->normals_dev, nullptr, pa->mg_cycles_cold ? pa->mg_cycles_cold : 8,
                             out->depth_dev, mg, st));
-    HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr,
-                                pyramid_level_floats(pyramid_plan(W, H)), st));
+    const long long quad = pyramid_level_floats(pyramid_plan(W, H));
+    HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, quad, st));
     const kern::SurfaceArgs sa = surface(W, H, out->depth_dev, pyr);
-    HIP_TRY(kern::direct(sa, out->normals_dev, L, (pa->flags & IRTPS_FLAG_FLAT_TRAVERSAL) ? 1 : 0, S, st));
+    HIP_TRY(kern::direct(sa, out->normals_dev, L, flat, S, st));
 
     kern::TraceArgs ta;
     std::memset(&ta, 0, sizeof(ta));
@@ -275,11 +279,31 @@ int irtps_autotune(const irtps_problem* pr, const irtps_params* pa, const irtps_
     ta.K = K;
     ta.spp = pa->spp;
     ta.B = pa->bounces;
-    ta.t = 1;
+    ta.t = 0;
     ta.tag = IRTPS_TAG_SOLVE;
     ta.flags = pa->flags & (IRTPS_FLAG_QUADRATURE | IRTPS_FLAG_FLAT_TRAVERSAL);
     ta.key0 = (uint32_t)pa->seed;
     ta.key1 = (uint32_t)(pa->seed >> 32);
+    ta.tile_shift = kDefaultShift;
+    ta.ready_batch = kDefaultBatch;
+
+    // One IRT iteration with the default schedule, so that the candidates are
+    // timed on the state the solve's later iterations trace (H_1, n_1, rho_1):
+    // its surface is much closer to the final one than H_0, and those
+    // iterations are most of a solve's tracing.
+    HIP_TRY(kern::trace(ta, st));
+    HIP_TRY(kern::correct((int)npx, C, K, pa->rho_mode, (pa->flags & IRTPS_FLAG_LITERAL_CUMULATIVE) ? 1 : 0,
+                          pr->images_dev, pr->images_dev, G, S, out->albedo_dev, nullptr, A, st));
+    if (pa->flags & IRTPS_FLAG_SHADOW_AWARE_PS)
+        HIP_TRY(kern::ps_solve_masked((int)npx, C, K, M, L, A, S, out->normals_dev, out->albedo_dev, st));
+    else
+        HIP_TRY(kern::ps_solve((int)npx, C, K, M, A, out->normals_dev, out->albedo_dev, st));
+    HIP_TRY(kern::integrate(lay.plan, out->normals_dev, out->depth_dev, pa->mg_cycles_warm ? pa->mg_cycles_warm : 4,
+                            out->depth_dev, mg, st));
+    HIP_TRY(kern::build_pyramid(W, H, out->depth_dev, pyramid_plan(W, H), pyr, quad, st));
+    HIP_TRY(kern::direct(sa, out->normals_dev, L, flat, S, st));
+    ta.t = 1;
+    ta.tile_cost = tile_cost;
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -291,15 +315,17 @@ int irtps_autotune(const irtps_problem* pr, const irtps_params* pa, const irtps_
     Schedule pick{kDefaultShift, kDefaultBatch};
     float pick_ms = 0.0f;
     int cand = 0;
-    // one untimed launch first (code objects, caches)
-    ta.tile_shift = kDefaultShift;
-    ta.ready_batch = kDefaultBatch;
-    err = kern::trace(ta, st);
     for (int shift : kShifts) {
         for (int rb : kBatches) {
             if (err != hipSuccess) break;
             ta.tile_shift = shift;
             ta.ready_batch = rb;
+            // as in the solve: a launch in XCD order records the tiles' times,
+            // the timed launches deal the tiles heaviest first
+            ta.order = nullptr;
+            err = kern::trace(ta, st);
+            if (err == hipSuccess) err = kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << shift), tile_order, st);
+            ta.order = tile_order;
             float t_ms = 0.0f;
             for (int rep = 0; rep < kRepeats && err == hipSuccess; ++rep) {  // the faster of two
                 err = hipEventRecord(e0, st);

@@ -103,7 +103,7 @@ class Schedule(ct.Structure):
     _fields_ = [("tile_w", _i32), ("ready_batch", _i32)]
 
 
-TUNE_CANDIDATES = 16
+TUNE_CANDIDATES = 20
 
 
 class ServerCfg(ct.Structure):
@@ -687,7 +687,7 @@ def autotune(job, outs=None, workspace=None, stream=None):
     _check("irtps_autotune", lib().irtps_autotune(ct.byref(probs[0]), ct.byref(pars[0]), ct.byref(o[0]),
                                                   ct.c_void_p(workspace.data_ptr()), workspace.numel(),
                                                   _stream(stream), ct.byref(best), ms))
-    cands = [(tw, rb) for tw in (8, 16, 32, 64) for rb in (16, 24, 32, 48)]
+    cands = [(tw, rb) for tw in (8, 16, 32, 64) for rb in (24, 32, 40, 48, 56)]
     return {"tile_w": best.tile_w, "ready_batch": best.ready_batch}, dict(zip(cands, list(ms)))
 
 
