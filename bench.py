@@ -34,6 +34,9 @@ plain per-job path on the same GPU (objects `batched` and `served`):
   replayed through a FIFO loop over the plain solve and through the
   continuous-batching server; latency is arrival to completion.
 Both legs require every job's outputs to be bit-identical to the plain path.
+`variants` times the paper's variants (shadow-aware PS, robust integration,
+the r-ray images) and the scene inside Cornell-like walls on the main
+workload, each with its normal and depth error against the ground truth.
 """
 import argparse
 import json
@@ -332,6 +335,68 @@ def groove_leg(args, dev):
                 ref["counters"][k] for k in ("segments", "hits", "escapes", "continuations")]}
 
 
+def variants_leg(args, dev):
+    """The paper's variants and the environment as geometry on the main
+    workload (2048^2 RGB fBm, K 16, spp 256, B 3, T 5): whole solves timed (one
+    warm-up, median of two) and their normals and depth compared with the
+    ground truth.  plain: the default loop; shadow_aware: per-pixel light
+    masks in PS; robust: Huber integration; exact_r1..3: the r-ray image in
+    place of the gather; box: the scene inside Cornell-like walls of height
+    300 px (inputs rendered in the walls), solved with the walls, and
+    box_not_modelled: the same images solved with the environment map alone."""
+    import numpy as np
+    import torch
+    from paper_1811_02357_amd import irtps, scenes
+    wl = WORKLOADS[args.workload]
+    sc = scenes.fbm_terrain(seed=0, **wl)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    gt_n = T(sc.normals).double()
+    gt_h = T(sc.heights).double()
+    env = T(sc.env)
+
+    def render(box):
+        return irtps.render(T(sc.heights), T(sc.normals), T(sc.albedo), sc.light_dirs, sc.light_intensity, env,
+                            sc.render_spp, sc.render_bounces, seed=0, box=box)
+
+    walls = scenes.cornell_walls(sc.channels, (64, 128), seed=1)
+    box = irtps.Box(300.0, T(walls))
+    inputs = {"env": render(None), "box": render(box)}
+    runs = [("plain", "env", 0, None), ("shadow_aware", "env", irtps.FLAG_SHADOW_AWARE_PS, None),
+            ("robust", "env", irtps.FLAG_ROBUST_INTEGRATION, None),
+            ("exact_r1", "env", irtps.flag_exact_r(1), None), ("exact_r2", "env", irtps.flag_exact_r(2), None),
+            ("exact_r3", "env", irtps.flag_exact_r(3), None),
+            ("box", "box", 0, box), ("box_not_modelled", "box", 0, None)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, src, flags, bx in runs:
+        I0 = inputs[src]
+        job = dict(images=I0, light_dirs=sc.light_dirs, light_intensity=sc.light_intensity, env=env, spp=sc.spp,
+                   bounces=sc.bounces, iterations=sc.iterations, seed=sc.seed, flags=flags, box=bx)
+        ws = torch.empty(irtps.workspace_bytes(**{k: v for k, v in job.items()}), dtype=torch.uint8, device=dev)
+        out = irtps.solve(**job, workspace=ws)  # warm-up
+        ts = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            irtps.solve(**job, out=out, workspace=ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        n = out["normals"].double()
+        cosang = (n * gt_n).sum(-1) / (n.norm(dim=-1) * gt_n.norm(dim=-1))
+        ang = torch.rad2deg(torch.arccos(cosang.clamp(-1, 1)))
+        d = out["depth"].double()
+        rms = float(((d - d.mean()) - (gt_h - gt_h.mean())).pow(2).mean().sqrt())
+        res[name] = {"ms": float(np.median(ts)), "segments": int(out["counters"][0]),
+                     "median_normal_err_deg": float(ang.median()), "p90_normal_err_deg": float(ang.quantile(0.9)),
+                     "depth_rms_px": rms}
+        log(f"bench: variant {name}: {res[name]['ms']:.1f} ms, median normal error "
+            f"{res[name]['median_normal_err_deg']:.3f} deg, depth rms {rms:.2f} px")
+        del ws, out
+        torch.cuda.empty_cache()
+    return {"workload": args.workload, "box": {"height_px": 300.0, "texture": [64, 128]}, "runs": res}
+
+
 def small_leg(args, dev):
     """The 64 x 64 bowl (8 lights, grey, spp 16, B 1, T 3), a solve short enough
     that launches matter: timed call by call through the plain solve (kernels
@@ -526,9 +591,9 @@ def main():
     ap.add_argument("--groove-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="all",
-                    choices=["all", "plain", "small", "groove", "batched", "served", "served-sweep"],
-                    help="plain: the main workload only; small/groove/batched/served/served-sweep: the main "
-                         "workload and that leg (served-sweep is not part of all)")
+                    choices=["all", "plain", "small", "groove", "batched", "served", "served-sweep", "variants"],
+                    help="plain: the main workload only; small/groove/batched/served/served-sweep/variants: the "
+                         "main workload and that leg (served-sweep is not part of all)")
     ap.add_argument("--sweep-rates", type=lambda v: [float(x) for x in v.split(",") if x],
                     default=[6.0, 9.0, 12.0, 15.0, 18.0, 21.0, 24.0, 27.0])
     ap.add_argument("--sweep-window", type=float, default=5.0)
@@ -714,6 +779,9 @@ def main():
         torch.cuda.empty_cache()
     if args.mode in ("all", "served"):
         line["served"] = served_leg(args, dev)
+        torch.cuda.empty_cache()
+    if args.mode in ("all", "variants"):
+        line["variants"] = variants_leg(args, dev)
         torch.cuda.empty_cache()
     if args.mode == "served-sweep":
         line["served_sweep"] = served_sweep(args, dev)
