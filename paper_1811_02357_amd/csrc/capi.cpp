@@ -151,30 +151,20 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
             const Schedule sched = schedule_for(W, H, C, K, pa->bounces);
             ta.ready_batch = sched.ready_batch;
             ta.tile_shift = sched.tile_shift;
-            // Each launch records its blocks' times per tile; from the second
-            // iteration on, the tiles go out heaviest first by the previous
-            // iteration's times, so that the launch ends on short blocks (the
+            // Each launch records its pixels' times per chunk; from the second
+            // iteration on, the chunks go out heaviest first by the previous
+            // iteration's times, so that the launch ends on short ones (the
             // surface changes little between iterations).
             ta.tile_cost = tile_cost;
             // a small problem traces one path per (pixel, sample) lane instead
             ta.records = rec_bytes ? reinterpret_cast<float*>(base + lay.total) : nullptr;
             if (t > 0 && !ta.records) {
-                HIP_TRY(kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << sched.tile_shift), tile_order, st));
+                HIP_TRY(kern::order_tiles(tile_cost, kern::chunks_for(W, H, 1 << sched.tile_shift), tile_order, st));
                 ta.order = tile_order;
             }
-            if (!ta.records) {
-                // the per-pixel tracer corrects each pixel as soon as its G is final
-                ta.I0 = pr->images_dev;
-                ta.Aprev = Aprev;
-                ta.Anext = A;
-                ta.E = E;
-                ta.rho_mode = pa->rho_mode;
-                ta.cumulative = cumulative ? 1 : 0;
-            }
             HIP_TRY(traced(ta, st));
-            if (ta.records)
-                HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
-                                      out->albedo_dev, E, A, st));
+            HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
+                                  out->albedo_dev, E, A, st));
         }
         if (pa->flags & IRTPS_FLAG_SHADOW_AWARE_PS)  // per pixel, the lights that reach it (S of H_t, n_t)
             HIP_TRY(kern::ps_solve_masked(npx, C, K, M, Ls, A, S, out->normals_dev, out->albedo_dev, st));

@@ -250,10 +250,10 @@ inline SolveLayout solve_layout(int W, int H, int C, int K) {
     L.plan = mg_plan(W, H);
     L.mg = off;
     off = align_up(off + sizeof(float) * (size_t)L.plan.total);
-    L.tile_cost = off;
-    off = align_up(off + sizeof(unsigned) * (size_t)kern::max_trace_tiles(W, H));
+    L.tile_cost = off;  // the tracer's chunk costs, then its queue slot
+    off = align_up(off + sizeof(unsigned) * ((size_t)kern::max_trace_chunks(W, H) + 1));
     L.tile_order = off;
-    off = align_up(off + sizeof(int) * (size_t)kern::max_trace_tiles(W, H));
+    off = align_up(off + sizeof(int) * (size_t)kern::max_trace_chunks(W, H));
     L.total = off;
     return L;
 }

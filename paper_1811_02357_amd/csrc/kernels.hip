@@ -9,6 +9,8 @@
 // batch of reconstructions of different sizes runs as one launch per step.
 #include "kernels.hpp"
 
+#include <atomic>
+
 #include "device_math.hpp"
 #include "traverse.hpp"
 
@@ -1045,16 +1047,6 @@ __device__ __forceinline__ void accumulate_hit(float* __restrict__ g, const floa
     }
 }
 
-// Kept out of line: inlined, its unrolled loops would raise the register budget
-// of the whole tracer.
-template <int C>
-__device__ __attribute__((noinline)) void fused_correct(int p, int npx, int K, int rho_mode, int cumulative,
-                                                        const float* I0, const float* Aprev, const float* gp,
-                                                        const float* Srow, const float* rho, float* E,
-                                                        float* Anext) {
-    correct_px<C>(p, npx, K, rho_mode, cumulative, I0, Aprev, gp, Srow, rho, E, Anext);
-}
-
 template <int C>
 __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S, int tile) {
     const int tw = 1 << a.tile_shift;
@@ -1203,11 +1195,266 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
 #pragma unroll
             for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
         }
-        if (a.Anext)
-            fused_correct<C>(p, npx, K, a.rho_mode, a.cumulative, a.I0, a.Aprev, gp, a.S + (size_t)p * K, a.rho,
-                             a.E, a.Anext);
     }
     if (a.counters && (threadIdx.x & 63) == 0) {
+        // one atomic per wave and counter
+        atomicAdd(&a.counters[0], n_seg);
+        atomicAdd(&a.counters[1], n_hit);
+        atomicAdd(&a.counters[2], n_esc);
+        atomicAdd(&a.counters[3], n_cont);
+    }
+}
+
+// A lane whose pixel is done idles until this many lanes of its wave are done
+// (or no lane has work left); the wave then finishes them together and they
+// take new pixels.
+constexpr int kRefillBatch = 4;
+
+// The single-job per-pixel tracer: the same per-pixel work as trace_tile (each
+// pixel's samples and segments in order, the same sums), but lanes are not
+// bound to one pixel.  A wave takes chunks of 64 pixels from the launch's queue
+// (or a fixed stride of them) and hands their pixels to lanes as the lanes
+// free up, so that a wave does not wait for its slowest pixel.
+template <int C>
+__device__ __forceinline__ void trace_pixels(const TraceArgs& a, const Surface& S) {
+    const int W = a.sa.W, Hh = a.sa.Hh;
+    const int npx = W * Hh;
+    const int sh = a.tile_shift;  // chunk width 2^sh
+    const int tw = 1 << sh;
+    const int chunks_x = (W + tw - 1) >> sh;
+    const int nchunks = chunks_for(W, Hh, tw);
+    const bool flat = (a.flags & kFlagFlat) != 0;
+    const int K = a.K;
+    const int KC = K * C;
+    const int batch = a.ready_batch;
+    const bool vec4 = (K & 3) == 0 && (reinterpret_cast<uintptr_t>(a.G) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.S) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.box_S) & 15) == 0;
+    const bool box = a.box_z > 0.0f;
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned* queue = a.tile_cost ? a.tile_cost + nchunks : nullptr;
+    const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+    // wave-uniform: the next chunk of the fixed stride, the current chunk and
+    // its next pixel, and whether the chunks have run out
+    int stride_next = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    int cur = 0, pos = kChunkPixels;
+    bool drained = false;
+
+    int M = 0;
+    if (a.flags & kFlagQuadrature) {
+        M = 1;
+        while (M * M < a.spp) ++M;
+    }
+    // wave-wide event counts (uniform across the wave, so they live in SGPRs)
+    unsigned long long n_seg = 0, n_hit = 0, n_esc = 0, n_cont = 0;
+
+    // lane state: the pixel held (if any) and its progress
+    bool has = false;      // a pixel is held
+    bool finished = true;  // no segment left to trace (no pixel, or all samples done)
+    int i = 0, j = 0;      // the pixel
+    bool ready = false;
+    int s = 0, b = 1;
+    int res = trv::kGoOn, qi = 0, qj = 0;
+    float beta[C], eacc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        beta[c] = 1.0f;
+        eacc[c] = 0.0f;
+    }
+    int ci = 0, cj = 0;
+    trv::Walker w;
+    bool need_setup = false;
+    int chain = 0;
+
+    for (;;) {
+        // finish the lanes whose pixels are done, a few at a time
+        {
+            const int n_done = __popcll(__ballot(has && finished));
+            const int n_busy = __popcll(__ballot(!finished));
+            if (n_done > 0 && (n_done >= kRefillBatch || n_busy == 0)) {
+                if (has && finished) {
+                    // G = (hit sums + escape sum) / spp
+                    float* gp = a.G + (size_t)(j * W + i) * KC;
+                    const float fspp = (float)a.spp;
+                    for (int k = 0; k < K; ++k) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
+                    }
+                    // the pixel's time: its start was subtracted when it was taken
+                    // (modulo 2^32, exact while a chunk's total stays below 2^32 ticks)
+                    if (a.tile_cost)
+                        atomicAdd(&a.tile_cost[(j >> (6 - sh)) * chunks_x + (i >> sh)], (unsigned)wall_clock64());
+                    has = false;
+                }
+            }
+        }
+        // lanes without a pixel take the next ones of the wave's chunk, and the
+        // wave takes a new chunk when that one runs out
+        while (!drained) {
+            const unsigned long long want = __ballot(!has);
+            if (want == 0ull) break;
+            const int n = __popcll(want);
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(want >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)want, 0u));
+            const int avail = kChunkPixels - pos;
+            int next = -1;
+            if (n > avail) {
+                int k;
+                if (queue) {
+                    const int leader = __ffsll((long long)__ballot(true)) - 1;
+                    unsigned v = 0u;
+                    if (lane == leader) v = atomicAdd(queue, 1u);
+                    k = (int)__shfl(v, leader);
+                } else {
+                    k = stride_next;
+                    stride_next += nwaves;
+                }
+                if (k >= nchunks) drained = true;
+                else next = a.order ? a.order[k] : k;
+            }
+            int c_take = -1, loc = 0;
+            if (!has) {
+                if (rank < avail) {
+                    c_take = cur;
+                    loc = pos + rank;
+                } else if (next >= 0) {
+                    c_take = next;
+                    loc = rank - avail;
+                }
+            }
+            const int ii = c_take >= 0 ? (c_take % chunks_x) * tw + (loc & (tw - 1)) : 0;
+            const int jj = c_take >= 0 ? (c_take / chunks_x) * (kChunkPixels >> sh) + (loc >> sh) : 0;
+            const bool take = c_take >= 0 && ii < W && jj < Hh;  // else the lane asks again (a ragged chunk)
+            // each pixel taken starts its chunk's clock now: the wave subtracts
+            // the start times at once, per chunk
+            if (a.tile_cost) {
+                const unsigned now = (unsigned)wall_clock64();
+                const unsigned n_cur = (unsigned)__popcll(__ballot(take && c_take == cur));
+                const unsigned n_next = (unsigned)__popcll(__ballot(take && c_take != cur));
+                if (lane == __ffsll((long long)__ballot(true)) - 1) {
+                    if (n_cur) atomicSub(&a.tile_cost[cur], now * n_cur);
+                    if (n_next) atomicSub(&a.tile_cost[next], now * n_next);
+                }
+            }
+            if (next >= 0) {
+                cur = next;
+                pos = n - avail;
+            } else {
+                pos += n < avail ? n : avail;
+            }
+            if (take) {
+                has = true;
+                i = ii;
+                j = jj;
+                float* gp = a.G + (size_t)(jj * W + ii) * KC;
+                for (int x = 0; x < KC; ++x) gp[x] = 0.0f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    beta[c] = 1.0f;
+                    eacc[c] = 0.0f;
+                }
+                s = 0;
+                b = 1;
+                ci = i;
+                cj = j;
+                finished = a.B < 1;
+                need_setup = !finished;
+            }
+        }
+        if (!__any(has)) break;        // the chunks have run out and every pixel is finished
+        if (__all(finished)) continue;  // every held pixel is done: finish them
+        n_seg += __popcll(__ballot(need_setup));
+        if (need_setup) {
+            float u1, u2;
+            if (M > 0 && b == 1) {
+                u1 = ((float)(s / M) + 0.5f) / (float)M;
+                u2 = ((float)(s % M) + 0.5f) / (float)M;
+            } else {
+                const dm::U4 r = dm::philox((uint32_t)(j * W + i), (uint32_t)s, (uint32_t)a.t * 256u + (uint32_t)b,
+                                            (uint32_t)a.tag, a.key0, a.key1);
+                u1 = dm::unit24(r.x);
+                u2 = dm::unit24(r.y);
+            }
+            const float* nq = a.n + 3 * (cj * W + ci);
+            const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
+            trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
+            // a segment the horizon bounds let go is ready at once (an escape)
+            ready = trv::leaves_at_once(w, S);
+            res = trv::kMiss;
+            need_setup = false;
+        }
+        // Segments let go at once are shaded (and replaced) straight away, for a
+        // few rounds, so that their lanes do not sit out a traversal phase.
+        if (chain < kEscapeRounds && __any(!finished && ready)) {
+            ++chain;
+        } else {
+            chain = 0;
+            // traversal phase: a few walker steps per pair of ballots
+            for (;;) {
+#pragma unroll
+                for (int u = 0; u < kStepsPerVote; ++u) {
+                    if (!finished && !ready) {
+                        res = trv::walker_step<false>(w, S, qi, qj);
+                        ready = res != trv::kGoOn;
+                    }
+                }
+                const int n_act = __popcll(__ballot(!finished));
+                const int n_rdy = __popcll(__ballot(!finished && ready));
+                if (n_rdy >= (n_act < batch ? n_act : batch)) break;
+            }
+        }
+        // shading phase
+        {
+            const bool shade = !finished && ready;
+            n_esc += __popcll(__ballot(shade && res == trv::kMiss));
+            n_hit += __popcll(__ballot(shade && res != trv::kMiss));
+            n_cont += __popcll(__ballot(shade && res != trv::kMiss && b < a.B));
+        }
+        if (!finished && ready) {
+            bool next_sample = true;
+            // an escape that meets a wall is shaded like a surface hit, from
+            // the wall texel's albedo and direct light, and ends the path
+            const int wt = (box && res == trv::kMiss)
+                               ? wall_texel(a.box_z, a.box_th, a.box_tw, W, Hh, ci, cj, w.r.oz, w.r.dx, w.r.dy,
+                                            w.r.dz)
+                               : -1;
+            if (res == trv::kMiss && wt < 0) {
+                int er, ec;
+                dm::env_texel(w.r.dx, w.r.dy, w.r.dz, a.env_h, a.env_w, er, ec);
+                const float* L = a.env + (er * a.env_w + ec) * C;
+#pragma unroll
+                for (int c = 0; c < C; ++c) eacc[c] = fmaf(beta[c], dm::kPi * L[c], eacc[c]);
+            } else {
+                const int q = qj * W + qi;
+                const bool on_wall = wt >= 0;
+                float wgt[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    wgt[c] = beta[c] * (on_wall ? a.box_albedo[(size_t)wt * C + c] : a.rho[c * npx + q]);
+                accumulate_hit<C>(a.G + (size_t)(j * W + i) * KC, on_wall ? a.box_S + (size_t)wt * K : a.S + (size_t)q * K,
+                                  wgt, K, vec4);
+                if (!on_wall && b < a.B) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) beta[c] = wgt[c];
+                    ci = qi;
+                    cj = qj;
+                    ++b;
+                    next_sample = false;
+                }
+            }
+            if (next_sample) {
+                ++s;
+                b = 1;
+#pragma unroll
+                for (int c = 0; c < C; ++c) beta[c] = 1.0f;
+                ci = i;
+                cj = j;
+                finished = s >= a.spp;
+            }
+            need_setup = !finished;
+        }
+    }
+    if (a.counters && lane == 0) {
         // one atomic per wave and counter
         atomicAdd(&a.counters[0], n_seg);
         atomicAdd(&a.counters[1], n_hit);
@@ -1522,32 +1769,14 @@ __global__ void __launch_bounds__(256) k_fill_push0_broadcast(const float* __res
     G[x] = v;
 }
 
-// Blocks take their tiles in XCD order, or in the given order (a permutation of
-// the tiles: block b < tiles takes order[b]).  With tile_cost, each block
-// records its time (wall clock, its slowest wave's) under its tile.
+// Persistent: the grid is at most what the GPU holds at once, and each wave
+// works until the chunks run out (see trace_pixels).
 template <int C>
 __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(a.sa.off, a.sa.wc, s_lvl);
-    const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
-    int tile;
-    if (a.order) {
-        if ((int)blockIdx.x >= tiles) return;
-        tile = a.order[blockIdx.x];
-    } else {
-        tile = xcd_tile(blockIdx.x, gridDim.x);
-        if (tile >= tiles) return;
-    }
     const Surface S = make_surface(a.sa, s_lvl);
-    const unsigned long long t0 = wall_clock64();
-    trace_tile<C>(a, S, tile);
-    if (a.tile_cost) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned long long dt = wall_clock64() - t0;
-            a.tile_cost[tile] = dt < 0xFFFFFFFFull ? (unsigned)dt : 0xFFFFFFFFu;
-        }
-    }
+    trace_pixels<C>(a, S);
 }
 
 // Tiles by descending cost: a counting sort over kOrderBuckets cost classes in
@@ -1834,12 +2063,6 @@ __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
     a.order = nullptr;
     a.tile_cost = nullptr;
     a.records = nullptr;
-    a.I0 = nullptr;
-    a.Aprev = nullptr;
-    a.Anext = nullptr;
-    a.E = nullptr;
-    a.rho_mode = 0;
-    a.cumulative = 0;
     a.env_h = J.env_h;
     a.env_w = J.env_w;
     a.C = J.C;
@@ -2259,6 +2482,28 @@ hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t 
     return hipGetLastError();
 }
 
+// Blocks of the single-job tracer that the current device holds at once (its
+// compute units times the blocks per unit at the tracer's occupancy), cached
+// per device.
+constexpr int kMaxDevices = 64;
+static int trace_resident_blocks(int C) {
+    static std::atomic<int> cache[2][kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = -1;
+    if (dev >= 0) {
+        const int v = cache[C == 1 ? 0 : 1][dev].load(std::memory_order_relaxed);
+        if (v > 0) return v;
+    }
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const void* f = C == 1 ? reinterpret_cast<const void*>(&k_trace<1>) : reinterpret_cast<const void*>(&k_trace<3>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 256, 0) != hipSuccess || per < 1) per = 1;
+    const int v = cus * per;
+    if (dev >= 0) cache[C == 1 ? 0 : 1][dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
 hipError_t trace(TraceArgs a, hipStream_t st) {
     if (a.records) {
         const int npx = a.sa.W * a.sa.Hh;
@@ -2273,8 +2518,14 @@ hipError_t trace(TraceArgs a, hipStream_t st) {
         }
         return hipGetLastError();
     }
-    const int tiles = tiles_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
-    const int grid = (tiles + 7) / 8 * 8;
+    const int chunks = chunks_for(a.sa.W, a.sa.Hh, 1 << a.tile_shift);
+    if (a.tile_cost)  // chunk costs and the queue slot start at zero
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for((long long)chunks + 1, 256)), dim3(256), 0, st, a.tile_cost,
+                           0u, chunks + 1);
+    // at most the blocks the GPU holds at once (4 waves, so 4 chunks, per block)
+    const int want = (chunks + 3) / 4;
+    const int held = trace_resident_blocks(a.C);
+    const int grid = want < held ? want : held;
     if (a.C == 1) hipLaunchKernelGGL(k_trace<1>, dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_trace<3>, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();

@@ -26,6 +26,19 @@ __host__ __device__ inline int max_trace_tiles(int W, int H) {
     for (int tw = 8; tw <= 64; tw *= 2) m = tiles_for(W, H, tw) > m ? tiles_for(W, H, tw) : m;
     return m;
 }
+// Chunks: the single-job tracer hands out pixels by chunks of one wave's 64,
+// tile_w x (64 / tile_w) of them, in row-major chunk order.
+constexpr int kChunkPixels = 64;
+__host__ __device__ inline int chunk_rows(int tile_w) { return kChunkPixels / tile_w; }
+__host__ __device__ inline int chunks_for(int W, int H, int tile_w) {
+    const int th = chunk_rows(tile_w);
+    return ((W + tile_w - 1) / tile_w) * ((H + th - 1) / th);
+}
+__host__ __device__ inline int max_trace_chunks(int W, int H) {
+    int m = 0;
+    for (int tw = 8; tw <= 64; tw *= 2) m = chunks_for(W, H, tw) > m ? chunks_for(W, H, tw) : m;
+    return m;
+}
 constexpr int kMaxMgLevels = 16;
 constexpr int kFlagQuadrature = 1;
 constexpr int kFlagFlat = 4;
@@ -67,19 +80,16 @@ struct TraceArgs {
     int C, K;
     int spp, B, t, tag, flags;
     int ready_batch;   // lanes that must have a result before the wave shades
-    int tile_shift;    // tile width 2^tile_shift (8..64 pixels), 256 / width rows
+    int tile_shift;    // tile (batched tracer) or chunk (single-job tracer) width 2^tile_shift
     uint32_t key0, key1;
-    const int* order;     // tile of each block (a permutation of the tiles), or null: XCD order
-    unsigned* tile_cost;  // per tile, the block's time in wall-clock ticks (written), or null
+    // Single-job tracer only (the batched one leaves both null): the chunks in
+    // the order they are handed out (a permutation), or null: row-major; and
+    // per chunk the sum of its pixels' times in wall-clock ticks, then one slot
+    // for the launch's chunk queue (both cleared by the launcher), or null:
+    // each wave takes a fixed stride of the chunks.
+    const int* order;
+    unsigned* tile_cost;
     float* records;       // per-path mode: segment records (split_record_bytes), or null
-    // Stage 5 fused into the per-pixel tracer: with Anext set, each lane corrects
-    // its pixel as soon as its G is final (E too when set); the trace reads none
-    // of these, so no lane can see another's correction.
-    const float* I0;      // [K][C][H][W]
-    const float* Aprev;   // [K][C][H][W]
-    float* Anext;         // [K][C][H][W], or null: no fused correction
-    float* E;             // [K][C][H][W] or null
-    int rho_mode, cumulative;
     // Walls (the known environment as geometry), or box_z <= 0: none.  A ray
     // that leaves the surface and meets a wall below box_z adds the wall
     // texel's term like a surface hit (row box_S, weight beta times its albedo).
@@ -193,8 +203,10 @@ hipError_t direct(const SurfaceArgs& sa, const float* n, const LightSet& L, int 
                   hipStream_t st, float box_z = 0.0f);
 // The walls' direct irradiance at texel centres, S [4][th][tw][K].
 hipError_t box_shade(int W, int H, const BoxArgs& b, const LightSet& L, float* S, hipStream_t st);
+// The single-job tracer (per-pixel, or per-path for small problems).  With
+// tile_cost set it first clears the chunk costs and the queue slot.
 hipError_t trace(TraceArgs a, hipStream_t st);
-// order[0..tiles) = the tiles by descending cost (ties in any order).
+// order[0..tiles) = the tiles (or chunks) by descending cost (ties in any order).
 hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t st);
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
                    const float* Aprev, const float* G, const float* S, const float* rho, float* E,

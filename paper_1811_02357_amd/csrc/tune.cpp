@@ -320,11 +320,11 @@ int irtps_autotune(const irtps_problem* pr, const irtps_params* pa, const irtps_
             if (err != hipSuccess) break;
             ta.tile_shift = shift;
             ta.ready_batch = rb;
-            // as in the solve: a launch in XCD order records the tiles' times,
-            // the timed launches deal the tiles heaviest first
+            // as in the solve: a launch in row-major order records the chunks'
+            // times, the timed launches deal the chunks heaviest first
             ta.order = nullptr;
             err = kern::trace(ta, st);
-            if (err == hipSuccess) err = kern::order_tiles(tile_cost, kern::tiles_for(W, H, 1 << shift), tile_order, st);
+            if (err == hipSuccess) err = kern::order_tiles(tile_cost, kern::chunks_for(W, H, 1 << shift), tile_order, st);
             ta.order = tile_order;
             float t_ms = 0.0f;
             for (int rep = 0; rep < kRepeats && err == hipSuccess; ++rep) {  // the faster of two
