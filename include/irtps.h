@@ -190,9 +190,10 @@ int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* para
  * surface (Eq.5-7), subtract the indirect estimate (stage 5), PS and integrate
  * warm-started from H_t.  ws_dev must hold irtps_workspace_bytes() bytes,
  * 256-byte aligned; it needs no initialisation and carries nothing between
- * calls (besides the loop's buffers it keeps each tracer tile's launch time,
- * which orders the next iteration's tiles, and for problems of at most 16384
- * pixels the per-path tracer's segment records; neither changes a result). */
+ * calls (besides the loop's buffers it keeps the tracer's per-chunk pixel
+ * times, which order the next iteration's chunks, and for problems of at most
+ * 16384 pixels the per-path tracer's segment records; neither changes a
+ * result). */
 int irtps_solve(const irtps_problem* problem, const irtps_params* params,
                 const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
                 void* stream);
@@ -454,10 +455,11 @@ int irtps_server_stats(irtps_server* server, irtps_server_statistics* stats);
 int irtps_server_destroy(irtps_server* server);
 
 /* ---- tuning ----------------------------------------------------------------- */
-/* The tracer's schedule: a 256-thread block traces a tile of tile_w x (256 /
- * tile_w) pixels (tile_w 8, 16, 32 or 64), and a 64-lane wave shades once
- * ready_batch of its lanes hold a finished segment.  A schedule changes speed
- * only, never a result bit.  Every trace uses, field by field, the forced value
+/* The tracer's schedule: tile_w (8, 16, 32 or 64) is the width of the pixel
+ * chunks a wave of the single-job tracer takes (tile_w x 64 / tile_w pixels)
+ * and of the tiles a block of the batched tracer traces (tile_w x 256 / tile_w
+ * pixels), and a 64-lane wave shades once ready_batch of its lanes hold a
+ * finished segment.  A schedule changes speed only, never a result bit.  Every trace uses, field by field, the forced value
  * (irtps_set_schedule), else the tuning table's entry for its class (device
  * architecture, round(log2 sqrt(W H)), ceil(log2 K), C, B), else 16 x 16 tiles
  * and 32 lanes. */
@@ -483,8 +485,8 @@ int irtps_get_ready_batch(void);
  * schedule, then pyramid and direct light; written to outputs and the
  * workspace) and, for each of the IRTPS_TUNE_CANDIDATES schedules (tile_w in
  * 8, 16, 32, 64 times ready_batch in 24, 32, 40, 48, 56, in that order), runs
- * one trace launch that records the tiles' times and then times launches that
- * deal the tiles heaviest first, as the solve's later iterations do (the
+ * one trace launch that records the chunks' times and then times launches that
+ * deal the chunks heaviest first, as the solve's later iterations do (the
  * faster of two; ms_out, if not NULL, receives the times in milliseconds).
  * The fastest goes into the process's tuning table for the problem's class and
  * to *best.  Workspace as for irtps_solve (irtps_workspace_bytes); the call

@@ -1370,8 +1370,14 @@ __device__ __forceinline__ void trace_pixels(const TraceArgs& a, const Surface& 
                 u1 = ((float)(s / M) + 0.5f) / (float)M;
                 u2 = ((float)(s % M) + 0.5f) / (float)M;
             } else {
+                // The key enters each setup as an opaque scalar, so that the
+                // round keys are derived here with scalar adds instead of being
+                // held through the whole loop (spilled to vector lanes and read
+                // back one by one).
+                uint32_t k0 = a.key0, k1 = a.key1;
+                __asm__ volatile("" : "+s"(k0), "+s"(k1));
                 const dm::U4 r = dm::philox((uint32_t)(j * W + i), (uint32_t)s, (uint32_t)a.t * 256u + (uint32_t)b,
-                                            (uint32_t)a.tag, a.key0, a.key1);
+                                            (uint32_t)a.tag, k0, k1);
                 u1 = dm::unit24(r.x);
                 u2 = dm::unit24(r.y);
             }
@@ -1779,7 +1785,8 @@ __global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
     trace_pixels<C>(a, S);
 }
 
-// Tiles by descending cost: a counting sort over kOrderBuckets cost classes in
+// Tiles (the single-job tracer's chunks) by descending cost: a counting sort
+// over kOrderBuckets cost classes in
 // one block (classes of 2^s ticks, s the least shift that fits the largest
 // cost).  Slots within a class go by LDS atomics, so ties fall in any order;
 // the trace does not depend on the order.
