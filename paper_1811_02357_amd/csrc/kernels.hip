@@ -1499,9 +1499,14 @@ __global__ void __launch_bounds__(256) k_direct(SurfaceArgs sa, const float* __r
     direct_wave(S, p, n, L.K, &L.l[0][0], L.s, flat != 0, S_out, box_z);
 }
 
-// The tracer is issue- and latency-bound: ask for seven waves per SIMD (at most
-// 72 VGPRs); eight forces spills to scratch, six measure slower.
+// The tracers are issue- and latency-bound: the lane-bound ones ask for seven
+// waves per SIMD (at most 72 VGPRs; eight force spills to scratch, six measured
+// slower).  The single-job tracer, whose lanes take new pixels, holds more
+// state across its loop and does best with six (80 VGPRs and more scalar
+// registers, so fewer values parked in vector lanes; five and seven measured
+// slower).
 #define IRTPS_TRACER_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7)))
+#define IRTPS_REFILL_OCCUPANCY __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
 
 // Per-path mode, first pass: lane (s, p) traces sample s of pixel p (Eq.5-7, the
 // same segment arithmetic as trace_tile) and records every segment: code q for
@@ -1778,7 +1783,7 @@ __global__ void __launch_bounds__(256) k_fill_push0_broadcast(const float* __res
 // Persistent: the grid is at most what the GPU holds at once, and each wave
 // works until the chunks run out (see trace_pixels).
 template <int C>
-__global__ void IRTPS_TRACER_OCCUPANCY k_trace(TraceArgs a) {
+__global__ void IRTPS_REFILL_OCCUPANCY k_trace(TraceArgs a) {
     __shared__ int2 s_lvl[trv::kMaxLevels];
     load_level_table(a.sa.off, a.sa.wc, s_lvl);
     const Surface S = make_surface(a.sa, s_lvl);
@@ -2049,7 +2054,7 @@ __device__ __forceinline__ bool participates(const JobDesc& J, int init) {
 }
 
 __device__ __forceinline__ TraceArgs job_trace_args(const JobDesc& J, int tag) {
-    TraceArgs a;
+    TraceArgs a{};  // every field not set below is zero or null (no walls)
     a.sa.H = J.depth;
     a.sa.pyr = J.pyr;
     a.sa.W = J.W;
