@@ -475,11 +475,11 @@ def test_solve_rgb_ragged(dev):
     _compare_solve(ref, got, "fbm150x97")
 
 
-# 160 x 120 = 19200 pixels: the per-pixel tracer, which corrects each pixel itself
+# 160 x 120 = 19200 pixels: the per-pixel tracer (lanes refilled from chunks), then the correction kernel
 @pytest.mark.parametrize("rho_mode,flags,stop_tol", [(irtps.RHO_FIT, 0, 0.0), (irtps.RHO_PREV, 0, 0.0),
                                                      (irtps.RHO_FIT, irtps.FLAG_LITERAL_CUMULATIVE, 0.0),
                                                      (irtps.RHO_PREV, irtps.FLAG_LITERAL_CUMULATIVE, 1e-30)])
-def test_solve_fused_correction_modes(dev, rho_mode, flags, stop_tol):
+def test_solve_correction_modes(dev, rho_mode, flags, stop_tol):
     say(f"case: solve RGB fbm 160x120 rho_mode={rho_mode} flags={flags} stop_tol={stop_tol}")
     sc = scenes.fbm_terrain(seed=11, size=160, channels=3, num_lights=8, env_shape=(16, 32),
                             ptp=16.0, spp=8, bounces=2, iterations=3, render_spp=8, render_bounces=2)
@@ -491,8 +491,36 @@ def test_solve_fused_correction_modes(dev, rho_mode, flags, stop_tol):
     assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
 
 
+def test_refill_tracer_every_chunk_shape(dev):
+    """The single-job tracer hands pixels to lanes from 64-pixel chunks taken
+    from a queue (row-major in the first iteration, heaviest first by the
+    previous iteration's pixel times afterwards).  On a problem above the
+    per-path limit whose sides are ragged for every chunk shape (161 x 109,
+    RGB), the solve equals the oracle's bit for bit, and so does every forced
+    chunk width and ready batch, down to one lane."""
+    say("case: solve RGB fbm 161x109 (per-pixel tracer), T 3, under five schedules")
+    sc = scenes.fbm_terrain(seed=8, size=192, channels=3, num_lights=7, env_shape=(16, 32), ptp=24.0,
+                            spp=6, bounces=2, iterations=3, render_spp=8, render_bounces=2)
+    sc.heights = np.ascontiguousarray(sc.heights[:109, :161])
+    sc.normals = np.ascontiguousarray(sc.normals[:109, :161])
+    sc.albedo = np.ascontiguousarray(sc.albedo[:, :109, :161])
+    ref, got = _solve_both(sc, dev)
+    _compare_solve(ref, got, "fbm161x109")
+    I0, _ = O.render_scene(sc)
+    args = (T(I0, dev), sc.light_dirs, sc.light_intensity, T(sc.env, dev), sc.spp, sc.bounces, sc.iterations)
+    try:
+        for tile_w, lanes in ((8, 1), (16, 64), (32, 24), (64, 40)):
+            irtps.set_schedule(tile_w, lanes)
+            out = irtps.solve(*args, seed=sc.seed)
+            for key in ("normals", "albedo", "depth", "indirect", "counters"):
+                assert np.array_equal(H(out[key]), got[key]), (tile_w, lanes, key)
+    finally:
+        irtps.set_schedule(0, 0)
+    say("  every schedule equals the oracle's solve")
+
+
 # shadow-aware PS inside the loop: the per-path tracer (48 x 40), the per-pixel
-# tracer with its fused correction (160 x 120 RGB), and the cumulative reading
+# tracer (160 x 120 RGB), and the cumulative reading
 @pytest.mark.parametrize("case", ["step_hill", "step_hill_env", "fbm160x120", "bowl64_cumulative"])
 def test_solve_shadow_aware(dev, case):
     say(f"case: solve with shadow-aware PS, {case}")
@@ -782,7 +810,7 @@ def test_solve_in_box(dev, case):
     """The loop inside walls: inputs rendered in the walls (oracle), then the
     GPU solve against the oracle's (the walls' light computed once per solve,
     direct light with wall shadows, wall hits in the gather: the per-path
-    tracer at 64^2, the per-pixel tracer with fused correction at 160 x 120).
+    tracer at 64^2, the per-pixel tracer at 160 x 120).
     The batched engine refuses walls."""
     say(f"case: solve in walls, {case}")
     name = case.replace("_shadow_aware", "").replace("_stop", "")
@@ -806,8 +834,8 @@ def test_solve_graph_replays_equal_eager(dev, case):
     """IRTPS_FLAG_GRAPH: the first call captures the solve into a hipGraph, later
     identical calls replay it.  Every replay, with eager solves and host
     synchronisations in between, must equal the eager solve bit for bit (the
-    per-path tracer at 64^2; the per-pixel tracer with heaviest-first tile order
-    and fused correction at 160 x 120)."""
+    per-path tracer at 64^2; the per-pixel tracer with heaviest-first chunk
+    order at 160 x 120)."""
     say(f"case: solve replayed from a hipGraph, {case}")
     extra = irtps.flag_exact_r(2) if case.endswith("exact_r2") else 0
     if case.startswith("bowl64"):
