@@ -519,6 +519,29 @@ def test_refill_tracer_every_chunk_shape(dev):
     say("  every schedule equals the oracle's solve")
 
 
+@pytest.mark.parametrize("name,shape,C,K,spp,B", [("row_strip", (2, 9001), 1, 3, 2, 2),
+                                                  ("column_strip", (9001, 2), 3, 5, 2, 2),
+                                                  ("no_bounces", (130, 130), 3, 4, 3, 0),
+                                                  ("one_sample", (129, 131), 3, 6, 1, 3)])
+def test_refill_tracer_edge_cases(dev, name, shape, C, K, spp, B):
+    """The per-pixel tracer's chunks on two-pixel-wide strips (most pixels of
+    every chunk outside the image), with B = 0 (every pixel done before its
+    first segment: G = 0), with one sample per pixel, and with light counts
+    that are not a multiple of 4 (no float4 rows): the solve against the
+    oracle's, all above the per-path limit of 16384 pixels."""
+    Hh, W = shape
+    say(f"case: refill tracer edge case {name} {Hh}x{W} C={C} K={K} spp={spp} B={B}")
+    rng = np.random.default_rng(Hh * 7 + W * 3 + C)
+    Hf = rng.uniform(0.0, 3.0, (Hh, W)).astype(F32)
+    sc = scenes._scene(name, Hf, rng.uniform(0.3, 0.9, (C, Hh, W)), scenes.fibonacci_lights(K),
+                       rng.uniform(0.6, 1.4, K), rng.uniform(0.1, 1.0, (4, 8, C)), spp=spp, bounces=B, iterations=2)
+    I0, _ = O.render(sc.heights, sc.normals, sc.albedo, sc.light_dirs, sc.light_intensity, sc.env, 4, 2, 3)
+    ref, got = _solve_both(sc, dev, I0=I0)
+    _compare_solve(ref, got, name)
+    if B == 0:
+        assert not got["indirect"].any()
+
+
 # shadow-aware PS inside the loop: the per-path tracer (48 x 40), the per-pixel
 # tracer (160 x 120 RGB), and the cumulative reading
 @pytest.mark.parametrize("case", ["step_hill", "step_hill_env", "fbm160x120", "bowl64_cumulative"])
