@@ -12,7 +12,9 @@ environment; solve with 256 spp, 3 bounces, 5 iterations (FP32).  The input
 images are rendered on the GPU (64 spp, 3 bounces) before timing.
 
 Prints one JSON line.  `value` is traced gather segments (rays) per second of
-the whole job.  The `roofline` object is for the tracer kernel, timed with HIP
+the whole job; `radiance_samples_per_s` counts K C per segment (one path serves
+every light and channel), and the direct light's shadow rays are counted apart
+(`shadow_rays_per_step`, `shadow_rays_per_s` over the whole step).  The `roofline` object is for the tracer kernel, timed with HIP
 events around its launches inside the timed steps: it is bound by VALU issue,
 so it is given in lane-operations (counted wave64 VALU instructions times
 their active lanes, from the committed counter profile of the same machine
@@ -734,6 +736,12 @@ def main():
         "p99_ms": float(np.quantile(step_ms, 0.99)),
         "segments_per_step": seg_per_step,
         "counters_per_step": {"segments": cnt[0], "hits": cnt[1], "escapes": cnt[2], "continuations": cnt[3]},
+        # one gather segment serves every light and channel: K C radiance samples
+        "radiance_samples_per_s": value * K * C,
+        # the direct light's shadow rays (K per sample and iteration), counted
+        # apart from the gather segments; rate over the whole step
+        "shadow_rays_per_step": K * npx * sc.iterations,
+        "shadow_rays_per_s": K * npx * sc.iterations * args.steps / (sum(step_ms) / 1e3),
         "trace_kernel": {"launches": launches, "avg_ms": per_launch_ms,
                          "share_of_step": trace_ms / sum(step_ms)},
         # the tracer's bytes by the algorithmic yardstick against HBM; the
