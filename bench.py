@@ -230,7 +230,25 @@ def cpu_baseline(sc, args):
         out["one_thread"] = {"value": one["segments"] / one["s"], "unit": "rays/s", "cores": one["threads"],
                              "sample": (f"{args.cpu_tile_1t}x{args.cpu_tile_1t} centre tile, whole solve, "
                                         f"one thread: {one['segments']} segments in {one['s']:.1f} s")}
+    out["bowl64_whole"] = _oracle_small_solve()
     return out
+
+
+def _oracle_small_solve():
+    """The oracle's whole solve of the 64 x 64 bowl (K 8, grey; spp 16, B 1,
+    T 3) on all host threads, inputs rendered by the oracle (untimed): a full
+    run, not a sample."""
+    from oracle import oracle as O
+    from paper_1811_02357_amd import scenes
+    sc = scenes.bowl_64()
+    I0, _ = O.render_scene(sc)
+    t0 = time.perf_counter()
+    r = O.solve(I0, sc.light_dirs, sc.light_intensity, sc.env, sc.spp, sc.bounces, sc.iterations, seed=sc.seed)
+    dt = time.perf_counter() - t0
+    seg = r["counters"]["segments"]
+    return {"value": seg / dt, "unit": "rays/s", "cores": O.num_threads(), "s": dt,
+            "reconstructions_per_s": 1.0 / dt,
+            "sample": f"64x64 bowl, whole solve (K 8, spp 16, B 1, T 3): {seg} segments in {dt:.3f} s"}
 
 
 def _job(sc, dev, irtps, torch, np):
