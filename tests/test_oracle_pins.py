@@ -94,6 +94,19 @@ def test_philox_matches_an_independent_implementation():
         assert o.tolist() == _philox_reference(c, keys[2])
 
 
+def test_philox_published_known_answers():
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) against the known-answer
+    vectors its authors publish with their reference implementation (Random123):
+    counter and key all zeros, all ones, and the digits of pi."""
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in kat:
+        assert tuple(O.philox(list(ctr), list(key))) == want, (ctr, key)
+        assert tuple(O.philox_n(np.array([ctr], np.uint32), key)[0].tolist()) == want
+
+
 # ---------------------------------------------------------------------------
 # Polynomials standing in for transcendentals.
 def test_sincos_quarter_exhaustive():
