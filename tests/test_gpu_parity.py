@@ -97,6 +97,14 @@ def test_philox_probe(dev):
         got = H(irtps.probe_philox(T(ctr.view(np.int32), dev), seed)).view(np.uint32)
         ref = O.philox_n(ctr, (seed & 0xFFFFFFFF, seed >> 32))
         assert np.array_equal(got, ref)
+    # the published Philox4x32-10 known answers, on the GPU itself
+    kat = [((0, 0, 0, 0), 0, (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0xFFFFFFFF,) * 4, 0xFFFFFFFFFFFFFFFF, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), 0x299F31D0A4093822,
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for c, seed, want in kat:
+        got = H(irtps.probe_philox(T(np.array([c], np.uint32).view(np.int32), dev), seed)).view(np.uint32)
+        assert tuple(got[0].tolist()) == want, (c, hex(seed))
 
 
 def _probe_valu_model(blocks, iters, active, kind):
