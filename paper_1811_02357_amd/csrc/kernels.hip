@@ -1111,8 +1111,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             const float* nq = a.n + 3 * (cj * a.sa.W + ci);
             const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
             trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
-            // a segment the horizon bounds let go is ready at once (an escape)
-            ready = trv::leaves_at_once(w, S);
+            // a segment the horizon bounds let go is ready at once (an escape);
+            // one that only the near bound clears starts its walk beyond the
+            // near bound's reach
+            const int hz = trv::horizon_class(w, S);
+            ready = hz == 2;
+            if (hz == 1) trv::walker_skip_near(w);
             res = trv::kMiss;
             need_setup = false;
         }
@@ -1384,8 +1388,12 @@ __device__ __forceinline__ void trace_pixels(const TraceArgs& a, const Surface& 
             const float* nq = a.n + 3 * (cj * W + ci);
             const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
             trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
-            // a segment the horizon bounds let go is ready at once (an escape)
-            ready = trv::leaves_at_once(w, S);
+            // a segment the horizon bounds let go is ready at once (an escape);
+            // one that only the near bound clears starts its walk beyond the
+            // near bound's reach
+            const int hz = trv::horizon_class(w, S);
+            ready = hz == 2;
+            if (hz == 1) trv::walker_skip_near(w);
             res = trv::kMiss;
             need_setup = false;
         }

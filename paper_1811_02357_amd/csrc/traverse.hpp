@@ -17,7 +17,8 @@
 // less than a sample).  Cells touching the domain border are never skipped, so
 // the escape test is always taken at the same crossing as in the flat walk.
 // Escape windows and horizon bounds end a pyramid walk early only when no
-// crossing ahead can hit, which is the flat walk's result too.
+// crossing ahead can hit, which is the flat walk's result too; the near horizon
+// bound alone lets a walk start past the crossings it proves to miss.
 #pragma once
 
 #include "device_math.hpp"
@@ -233,6 +234,44 @@ __device__ __forceinline__ bool leaves_at_once(const Ray& r, float hn, const flo
     const float s = r.slope;
     return ((int)(r.dz >= 0.0f) & (int)(s >= hn) & (int)(s >= fmaf(hb.y, r.oz, hb.x)) &
             (int)(s >= fmaf(hb.w, r.oz, hb.z))) != 0;
+}
+
+// The start sample's horizon bounds for a walker: 2 when all three prove that
+// no crossing can hit (as leaves_at_once); 1 when only the near bound holds,
+// which proves it for every crossing within kHorizonReach of horizontal travel
+// (such a crossing reads only samples within that travel, and a rising ray of
+// at least the bound's slope is at or above their escape margins there); 0
+// otherwise or in a flat walk.
+__device__ __forceinline__ int horizon_class(const Walker& w, const Surface& S) {
+    const Ray& r = w.r;
+    if (w.level < 0) return 0;
+    const unsigned q = quadrant(r);
+    const float hn = ld32(S.nearh, (unsigned)(r.j0 * S.W + r.i0) * 4u + q);
+    const float4 hb = ld32(S.hzb, __umul24((unsigned)r.qrow + ((unsigned)r.j0 >> kQuadShift), (unsigned)S.QW) +
+                                      ((unsigned)r.i0 >> kQuadShift));
+    const float s = r.slope;
+    const bool near = ((int)(r.dz >= 0.0f) & (int)(s >= hn)) != 0;
+    const bool far = ((int)(s >= fmaf(hb.y, r.oz, hb.x)) & (int)(s >= fmaf(hb.w, r.oz, hb.z))) != 0;
+    return near ? (far ? 2 : 1) : 0;
+}
+
+// A walker whose near bound holds (horizon_class 1) resumes both crossing
+// families at their first crossing at or after the parameter of kHorizonReach
+// of horizontal travel, rounded down (the hardware reciprocal square root is
+// within a few ulp; the 0.999 keeps the limit below the exact one), so that no
+// crossing beyond that travel is passed over.  The crossings passed over all
+// miss, and one outside the domain is followed only by others outside it (the
+// domain is convex and the walk's coordinates are monotone in t), so the
+// result is the flat walk's.  Called straight after walker_init.
+__device__ __forceinline__ void walker_skip_near(Walker& w) {
+    const Ray& r = w.r;
+    const float hd2 = fmaf(r.dx, r.dx, r.dy * r.dy);
+    if (!(hd2 > 0.0f)) return;  // a ray along z has no crossings
+    const float t_lim = (float)kHorizonReach * __builtin_amdgcn_rsqf(hd2) * 0.999f;
+    // the search returns the walk's own products m |1/d|, so a family that
+    // moves no further keeps its first crossing bit for bit
+    w.mx = first_index_at_or_after(r.ainv_x, fabsf(r.dx), t_lim, w.tX);
+    w.my = first_index_at_or_after(r.ainv_y, fabsf(r.dy), t_lim, w.tY);
 }
 
 // The same, reading the bounds of the ray's start sample (never in a flat walk).
