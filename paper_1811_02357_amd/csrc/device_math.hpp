@@ -31,6 +31,16 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// The 64-bit product of a (per lane) and m (uniform) in one v_mad_u64_u32,
+// whose carry-out goes to VCC.  The compiler splits such a product into
+// v_mul_lo_u32 and v_mul_hi_u32; measured on gfx950 with independent chains,
+// the pair takes about 12.7 cycles per wave64 and the single instruction 7.9.
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t m) {
+    uint64_t p;
+    __asm__("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(p) : "v"(a), "s"(m) : "vcc");
+    return p;
+}
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -39,10 +49,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t a_lo = 0xD2511F53u * c0;
-        const uint32_t a_hi = __umulhi(0xD2511F53u, c0);
-        const uint32_t b_lo = 0xCD9E8D57u * c2;
-        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t a = mul_wide(c0, 0xD2511F53u);
+        const uint64_t b = mul_wide(c2, 0xCD9E8D57u);
+        const uint32_t a_lo = (uint32_t)a, a_hi = (uint32_t)(a >> 32);
+        const uint32_t b_lo = (uint32_t)b, b_hi = (uint32_t)(b >> 32);
         const uint32_t y0 = b_hi ^ c1 ^ k0;
         const uint32_t y2 = a_hi ^ c3 ^ k1;
         c0 = y0;

@@ -140,9 +140,9 @@ struct Ray {
 // one-sample apron of every cell covers the nudge.
 constexpr float kNudge = 0.03125f;
 
-__device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float dx, float dy,
-                                        float dz) {
-    Ray r;
+// The ray's start, direction, quadrant and slope: all that the horizon test
+// and the shading of an escape read.
+__device__ __forceinline__ void ray_begin(Ray& r, const Surface& S, int i0, int j0, float dx, float dy, float dz) {
     r.i0 = i0;
     r.j0 = j0;
     r.oz = ld32(S.H, (unsigned)(j0 * S.W + i0));
@@ -152,14 +152,25 @@ __device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float 
     r.sx = signbit(dx) ? -1 : 1;
     r.sy = signbit(dy) ? -1 : 1;
     r.qrow = ((r.sx < 0 ? 1 : 0) + (r.sy < 0 ? 2 : 0)) * S.QH;
-    r.nx0 = (float)i0 + (float)r.sx * kNudge;
-    r.ny0 = (float)j0 + (float)r.sy * kNudge;
-    r.ainv_x = fabsf(1.0f / dx);
-    r.ainv_y = fabsf(1.0f / dy);
     // dz / |(dx, dy)| from the hardware reciprocal square root (within a few ulp),
     // shrunk by 1e-5 so that it never exceeds the exact slope
     const float hd2 = fmaf(dx, dx, dy * dy);
     r.slope = (dz > 0.0f && hd2 > 0.0f) ? dz * __builtin_amdgcn_rsqf(hd2) * 0.99999f : 0.0f;
+}
+
+// The rest, which only a walk reads: the nudged origin and the reciprocals.
+__device__ __forceinline__ void ray_finish(Ray& r) {
+    r.nx0 = (float)r.i0 + (float)r.sx * kNudge;
+    r.ny0 = (float)r.j0 + (float)r.sy * kNudge;
+    r.ainv_x = fabsf(1.0f / r.dx);
+    r.ainv_y = fabsf(1.0f / r.dy);
+}
+
+__device__ __forceinline__ Ray make_ray(const Surface& S, int i0, int j0, float dx, float dy,
+                                        float dz) {
+    Ray r;
+    ray_begin(r, S, i0, j0, dx, dy, dz);
+    ray_finish(r);
     return r;
 }
 
@@ -211,16 +222,23 @@ struct Walker {
     int mx, my, level;
 };
 
-__device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0, int j0, float dx,
-                                            float dy, float dz, bool flat) {
-    w.r = make_ray(S, i0, j0, dx, dy, dz);
+// The crossing state of a walker whose ray has begun (ray_begin): the ray's
+// remaining fields and the first crossing of each family.
+__device__ __forceinline__ void walker_finish(Walker& w, bool flat) {
+    ray_finish(w.r);
     w.mx = 1;
     w.my = 1;
     w.level = flat ? -1 : kMinSkipLevel;
     // a ray along z has no crossings: t = inf on both families ends the walk
-    const bool vertical = dx == 0.0f && dy == 0.0f;
+    const bool vertical = w.r.dx == 0.0f && w.r.dy == 0.0f;
     w.tX = vertical ? __builtin_inff() : t_x(w.r, 1);
     w.tY = vertical ? __builtin_inff() : t_y(w.r, 1);
+}
+
+__device__ __forceinline__ void walker_init(Walker& w, const Surface& S, int i0, int j0, float dx,
+                                            float dy, float dz, bool flat) {
+    ray_begin(w.r, S, i0, j0, dx, dy, dz);
+    walker_finish(w, flat);
 }
 
 // Quadrant index of a ray: 0..3 = (dx < 0) + 2 (dy < 0).
@@ -241,10 +259,8 @@ __device__ __forceinline__ bool leaves_at_once(const Ray& r, float hn, const flo
 // which proves it for every crossing within kHorizonReach of horizontal travel
 // (such a crossing reads only samples within that travel, and a rising ray of
 // at least the bound's slope is at or above their escape margins there); 0
-// otherwise or in a flat walk.
-__device__ __forceinline__ int horizon_class(const Walker& w, const Surface& S) {
-    const Ray& r = w.r;
-    if (w.level < 0) return 0;
+// otherwise.  Reads only what ray_begin sets; a flat walk never asks.
+__device__ __forceinline__ int horizon_class(const Ray& r, const Surface& S) {
     const unsigned q = quadrant(r);
     const float hn = ld32(S.nearh, (unsigned)(r.j0 * S.W + r.i0) * 4u + q);
     const float4 hb = ld32(S.hzb, __umul24((unsigned)r.qrow + ((unsigned)r.j0 >> kQuadShift), (unsigned)S.QW) +
