@@ -135,18 +135,38 @@ struct V3 {
     float x, y, z;
 };
 
+// Correctly rounded square root of x = +0 or x in [2^-96, 2^126): the hardware
+// estimate s moved one unit in the last place down or up by the signs of the
+// fused residuals x - s' s of its two neighbours s' (the rounding correction
+// the compiler applies to sqrtf, without the rescaling of tiny operands and the
+// zero, infinity and NaN cases, which such x do not need).
+__device__ __forceinline__ float sqrt_rn(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float dn = __uint_as_float(__float_as_uint(s) - 1u);
+    const float up = __uint_as_float(__float_as_uint(s) + 1u);
+    const float r_dn = fmaf(-dn, s, x);
+    const float r_up = fmaf(-up, s, x);
+    const float t = r_dn <= 0.0f ? dn : s;
+    return r_up > 0.0f ? up : t;
+}
+
+// u1 is k 2^-24 with 0 <= k < 2^24, or (k + 1/2) / M with M < 2^16 in the
+// quadrature, so both square-root operands are +0 or at least 2^-24.
 __device__ __forceinline__ V3 cosine_dir(float nx, float ny, float nz, float u1, float u2) {
-    const float radius = sqrtf(u1);
-    const float height = sqrtf(1.0f - u1);
+    const float radius = sqrt_rn(u1);
+    const float height = sqrt_rn(1.0f - u1);
     const float turns = u2 * 4.0f;
     const int quadrant = (int)turns;
     const float frac = turns - (float)quadrant;
     float s, c;
     quarter_sincos(frac, s, c);
-    float ex = c, ey = s;                           // quadrant 0
-    if (quadrant == 1) { ex = -s; ey = c; }
-    else if (quadrant == 2) { ex = -c; ey = -s; }
-    else if (quadrant == 3) { ex = s; ey = -c; }
+    // (cos, sin) of the angle turned by `quadrant` quarter turns: (c, s),
+    // (-s, c), (-c, -s), (s, -c); swaps and sign flips only, so exact
+    const bool odd = (quadrant & 1) != 0;
+    const unsigned flip_x = (unsigned)((quadrant ^ (quadrant >> 1)) & 1) << 31;
+    const unsigned flip_y = (unsigned)(quadrant >> 1) << 31;
+    const float ex = __uint_as_float(__float_as_uint(odd ? s : c) ^ flip_x);
+    const float ey = __uint_as_float(__float_as_uint(odd ? c : s) ^ flip_y);
     const float lx = radius * ex;
     const float ly = radius * ey;
 

@@ -177,6 +177,26 @@ def test_sample_probe(dev):
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
 
 
+def test_sample_probe_every_uniform(dev):
+    """Every u1 and every u2 of the 2^-24 grid the sampler draws (u2 through an
+    odd multiplier, a bijection of the grid), so both square roots and all four
+    quarter-turn rotations are checked for every operand they can get."""
+    say("case: cosine sampling probe, all 2^24 grid values of u1 and u2")
+    rng = np.random.default_rng(3)
+    n = rng.standard_normal((64, 3))
+    n[:4] = [[0, 0, 1], [0, 0, -1], [1e-7, 0, -1], [0.6, -0.8, 0]]
+    n = (n / np.linalg.norm(n, axis=1, keepdims=True)).astype(F32)
+    step = 1 << 22
+    for k0 in range(0, 1 << 24, step):
+        k = np.arange(k0, k0 + step, dtype=np.int64)
+        u = np.stack([k, (k * 0x9E3779B9) & 0xFFFFFF], 1).astype(np.float64) * 2.0 ** -24
+        u = u.astype(F32)
+        nk = n[k % 64]
+        got = H(irtps.probe_sample(T(nk, dev), T(u, dev)))
+        ref = O.sample_cosine_n(nk, u)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), k0
+
+
 def test_env_texel_probe(dev):
     say("case: environment texel probe")
     rng = np.random.default_rng(2)
