@@ -1267,6 +1267,7 @@ __device__ __forceinline__ void trace_pixels(const TraceArgs& a, const Surface& 
     }
     int ci = 0, cj = 0;
     trv::Walker w;
+    w.mx = 1;  // no walk pending (a pending walk has crossing index 0)
     bool need_setup = false;
     int chain = 0;
 
