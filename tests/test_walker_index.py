@@ -7,7 +7,9 @@ cell's exit t.  It takes ceil(t |d|) and tries its two neighbours, which is
 exact when the travel t |d| stays below 2^15 samples (both the estimate and the
 true threshold are then within 2^-8 of t |d|).  This test checks that claim in
 binary32 against a brute-force search, on random directions and exits and on
-exits placed exactly on, and one ulp either side of, crossing parameters.
+exits placed exactly on, and one ulp either side of, crossing parameters; and
+that the near-horizon pass at a walk's start passes over no crossing beyond the
+near bound's reach.
 """
 import numpy as np
 
@@ -64,3 +66,37 @@ def test_three_candidates_on_and_next_to_crossing_parameters():
     for t in (on, np.nextafter(on, f32(np.inf)), np.nextafter(on, f32(0))):
         t = t.astype(f32)
         np.testing.assert_array_equal(three_candidates(ainv, d_abs, t), brute_force(ainv, d_abs, t))
+
+
+def test_near_pass_passes_over_only_crossings_within_the_near_reach():
+    """A walk that only the near horizon bound clears resumes each family at its
+    first crossing with fl(m |1/d|) >= t_lim, t_lim = 24 rsq(dx^2 + dy^2) 0.999
+    (the hardware reciprocal square root is within a few ulp: here it is taken
+    8 ulp either side of the exact value).  Every crossing passed over must lie
+    within 24 samples of horizontal travel, exactly, where the near bound proves
+    that it misses; and the resumed crossing is the brute-force first one."""
+    rng = np.random.default_rng(9)
+    n = 4000
+    reach = 24
+    theta = rng.uniform(0, 2 * np.pi, n)
+    r = np.where(rng.random(n) < 0.2, rng.uniform(1e-4, 1e-2, n), rng.uniform(0.05, 1, n))
+    dx, dy = (r * np.cos(theta)).astype(f32), (r * np.sin(theta)).astype(f32)
+    dx[:50] = f32(0)
+    dy[50:100] = f32(-0.0)
+    hd2 = (dx * dx + dy * dy).astype(f32)
+    exact = 1.0 / np.sqrt(hd2.astype(np.float64))
+    for ulps in (-8, 0, 8):
+        rsq = exact.astype(f32)
+        for _ in range(abs(ulps)):
+            rsq = np.nextafter(rsq, f32(np.inf) if ulps > 0 else f32(0))
+        t_lim = (f32(reach) * rsq * f32(0.999)).astype(f32)
+        for d in (dx, dy):
+            d_abs = np.abs(d).astype(f32)
+            with np.errstate(divide="ignore"):
+                ainv = np.abs(f32(1) / d).astype(f32)
+            moving = d_abs > 0
+            m = three_candidates(ainv[moving], d_abs[moving], t_lim[moving])
+            np.testing.assert_array_equal(m, brute_force(ainv[moving], d_abs[moving], t_lim[moving]))
+            # the last crossing passed over, m - 1, at its exact parameter
+            travel = (m - 1) / d_abs[moving].astype(np.float64) * np.sqrt(hd2[moving].astype(np.float64))
+            assert np.all(travel < reach), travel.max()
