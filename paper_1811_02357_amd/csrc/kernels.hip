@@ -1092,6 +1092,7 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
     for (int c = 0; c < C; ++c) beta[c] = 1.0f;
     int ci = i, cj = j;  // sample the current segment starts from
     trv::Walker w;
+    w.mx = 1;  // no walk pending (a pending walk has crossing index 0)
     bool need_setup = !finished;
     int chain = 0;  // shading rounds since the last traversal phase
 
@@ -1110,13 +1111,17 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             }
             const float* nq = a.n + 3 * (cj * a.sa.W + ci);
             const dm::V3 d = dm::cosine_dir(nq[0], nq[1], nq[2], u1, u2);
-            trv::walker_init(w, S, ci, cj, d.x, d.y, d.z, flat);
+            trv::ray_begin(w.r, S, ci, cj, d.x, d.y, d.z);
             // a segment the horizon bounds let go is ready at once (an escape);
-            // one that only the near bound clears starts its walk beyond the
-            // near bound's reach
+            // the walker state of the others is completed when the next
+            // traversal phase starts, so that the set-up passes of rounds that
+            // only shade escapes leave it out
             const int hz = flat ? 0 : trv::horizon_class(w.r, S);
             ready = hz == 2;
-            if (hz == 1) trv::walker_skip_near(w);
+            // a pending walk has crossing index 0 (a walker's are >= 1) and
+            // keeps the horizon class in its level field until then
+            w.mx = hz == 2 ? 1 : 0;
+            w.level = hz;
             res = trv::kMiss;
             need_setup = false;
         }
@@ -1127,6 +1132,12 @@ __device__ __forceinline__ void trace_tile(const TraceArgs& a, const Surface& S,
             ++chain;
         } else {
         chain = 0;
+        if (w.mx == 0) {
+            // walks that only the near horizon bound clears start past its reach
+            const bool pass_near = w.level == 1;
+            trv::walker_finish(w, flat);
+            if (pass_near) trv::walker_skip_near(w);
+        }
         // traversal phase
         for (;;) {
             // a few walker steps per pair of ballots: a lane that finishes early
