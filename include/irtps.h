@@ -192,8 +192,9 @@ int irtps_workspace_bytes(const irtps_problem* problem, const irtps_params* para
  * 256-byte aligned; it needs no initialisation and carries nothing between
  * calls (besides the loop's buffers it keeps the tracer's per-chunk pixel
  * times, which order the next iteration's chunks, and for problems of at most
- * 16384 pixels the per-path tracer's segment records; neither changes a
- * result). */
+ * 16384 pixels the per-path tracer's segment records, for larger ones the
+ * sums of each pixel's escape terms, which the correction adds to the hit sums;
+ * none of these changes a result). */
 int irtps_solve(const irtps_problem* problem, const irtps_params* params,
                 const irtps_outputs* outputs, void* ws_dev, size_t ws_bytes,
                 void* stream);

@@ -156,15 +156,18 @@ int solve_launches(const irtps_problem* pr, const irtps_params* pa, const irtps_
             // iteration's times, so that the launch ends on short ones (the
             // surface changes little between iterations).
             ta.tile_cost = tile_cost;
-            // a small problem traces one path per (pixel, sample) lane instead
+            // a small problem traces one path per (pixel, sample) lane instead;
+            // a larger one hands its escape sums to the correction, which forms
+            // the means
             ta.records = rec_bytes ? reinterpret_cast<float*>(base + lay.total) : nullptr;
+            ta.esc_sums = rec_bytes ? nullptr : reinterpret_cast<float*>(base + lay.total);
             if (t > 0 && !ta.records) {
                 HIP_TRY(kern::order_tiles(tile_cost, kern::chunks_for(W, H, 1 << sched.tile_shift), tile_order, st));
                 ta.order = tile_order;
             }
             HIP_TRY(traced(ta, st));
             HIP_TRY(kern::correct(npx, C, K, pa->rho_mode, cumulative ? 1 : 0, pr->images_dev, Aprev, G, S,
-                                  out->albedo_dev, E, A, st));
+                                  out->albedo_dev, E, A, st, ta.esc_sums, pa->spp));
         }
         if (pa->flags & IRTPS_FLAG_SHADOW_AWARE_PS)  // per pixel, the lights that reach it (S of H_t, n_t)
             HIP_TRY(kern::ps_solve_masked(npx, C, K, M, Ls, A, S, out->normals_dev, out->albedo_dev, st));

@@ -259,16 +259,19 @@ inline SolveLayout solve_layout(int W, int H, int C, int K) {
 }
 
 // The solve's workspace: the layout above, then a tail: with the r-ray variant
-// its pull-push levels, else (small problems) the per-path tracer's segment
-// records.
+// its pull-push levels, else for small problems the per-path tracer's segment
+// records, and for the others the per-pixel tracer's escape sums.
 inline size_t split_bytes(int W, int H, int C, int spp, int B) {
     return align_up((size_t)kern::split_record_bytes((long long)W * H, C, spp, B));
 }
 inline size_t fill_bytes(int W, int H, int C) {
     return align_up(sizeof(float) * (size_t)kern::fill_plan(W, H, C).total_v0);
 }
+inline size_t esc_sum_bytes(int W, int H, int C) { return align_up(sizeof(float) * (size_t)W * H * C); }
 inline size_t tail_bytes(int W, int H, int C, const irtps_params* pa) {
-    return kern::exact_r_of(pa->flags) ? fill_bytes(W, H, C) : split_bytes(W, H, C, pa->spp, pa->bounces);
+    if (kern::exact_r_of(pa->flags)) return fill_bytes(W, H, C);
+    const size_t rec = split_bytes(W, H, C, pa->spp, pa->bounces);
+    return rec ? rec : esc_sum_bytes(W, H, C);
 }
 // ... and, with a box, the walls' direct irradiance after the tail.
 inline size_t solve_workspace_bytes(const irtps_problem* pr, const irtps_params* pa) {

@@ -1289,12 +1289,19 @@ __device__ __forceinline__ void trace_pixels(const TraceArgs& a, const Surface& 
             const int n_busy = __popcll(__ballot(!finished));
             if (n_done > 0 && (n_done >= kRefillBatch || n_busy == 0)) {
                 if (has && finished) {
-                    // G = (hit sums + escape sum) / spp
-                    float* gp = a.G + (size_t)(j * W + i) * KC;
-                    const float fspp = (float)a.spp;
-                    for (int k = 0; k < K; ++k) {
+                    if (a.esc_sums) {
+                        // G keeps the hit sums; correct() forms the means
+                        float* ep = a.esc_sums + (size_t)(j * W + i) * C;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
+                        for (int c = 0; c < C; ++c) ep[c] = eacc[c];
+                    } else {
+                        // G = (hit sums + escape sum) / spp
+                        float* gp = a.G + (size_t)(j * W + i) * KC;
+                        const float fspp = (float)a.spp;
+                        for (int k = 0; k < K; ++k) {
+#pragma unroll
+                            for (int c = 0; c < C; ++c) gp[k * C + c] = (gp[k * C + c] + eacc[c]) / fspp;
+                        }
                     }
                     // the pixel's time: its start was subtracted when it was taken
                     // (modulo 2^32, exact while a chunk's total stays below 2^32 ticks)
@@ -1881,7 +1888,8 @@ __global__ void __launch_bounds__(64) k_correct(int npx, int K, int rho_mode, in
                                                 const float* __restrict__ I0, const float* __restrict__ Aprev,
                                                 const float* __restrict__ G, const float* __restrict__ S,
                                                 const float* __restrict__ rho, float* __restrict__ E,
-                                                float* __restrict__ Anext) {
+                                                float* __restrict__ Anext, const float* __restrict__ esc,
+                                                int spp) {
     extern __shared__ float sm[];
     const int KC = K * C, rows = correct_rows(K, C);
     const int p0 = blockIdx.x * rows;
@@ -1892,6 +1900,18 @@ __global__ void __launch_bounds__(64) k_correct(int npx, int K, int rho_mode, in
     stage_rows(S + (size_t)p0 * K, n, K, sS);
     __syncthreads();
     const int t = threadIdx.x;
+    if (esc && t < n) {
+        // the means from the tracer's hit and escape sums, as its finish forms them
+        float* row = sG + t * (KC + 1);
+        const float fspp = (float)spp;
+        float e[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) e[c] = esc[(size_t)(p0 + t) * C + c];
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) row[k * C + c] = (row[k * C + c] + e[c]) / fspp;
+        }
+    }
     if (t < n)
         correct_px<C>(p0 + t, npx, K, rho_mode, cumulative, I0, Aprev, sG + t * (KC + 1), sS + t * (K + 1), rho, E,
                       Anext);
@@ -2575,16 +2595,16 @@ hipError_t trace(TraceArgs a, hipStream_t st) {
 
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
                    const float* Aprev, const float* G, const float* S, const float* rho, float* E,
-                   float* Anext, hipStream_t st) {
+                   float* Anext, hipStream_t st, const float* esc_sums, int spp) {
     const int rows = correct_rows(K, C);
     const unsigned g = blocks_for(npx, rows);
     const size_t lds = sizeof(float) * rows * (K * C + 1 + K + 1);
     if (C == 1)
         hipLaunchKernelGGL(k_correct<1>, dim3(g), dim3(64), lds, st, npx, K, rho_mode, cumulative, I0, Aprev, G, S,
-                           rho, E, Anext);
+                           rho, E, Anext, esc_sums, spp);
     else
         hipLaunchKernelGGL(k_correct<3>, dim3(g), dim3(64), lds, st, npx, K, rho_mode, cumulative, I0, Aprev, G, S,
-                           rho, E, Anext);
+                           rho, E, Anext, esc_sums, spp);
     return hipGetLastError();
 }
 

@@ -90,6 +90,10 @@ struct TraceArgs {
     const int* order;
     unsigned* tile_cost;
     float* records;       // per-path mode: segment records (split_record_bytes), or null
+    // Single-job tracer: per pixel the C sums of its escapes' terms, [H][W][C];
+    // G then keeps the per-light hit sums and correct() forms the means.  Null:
+    // G holds the means.
+    float* esc_sums;
     // Walls (the known environment as geometry), or box_z <= 0: none.  A ray
     // that leaves the surface and meets a wall below box_z adds the wall
     // texel's term like a surface hit (row box_S, weight beta times its albedo).
@@ -208,9 +212,12 @@ hipError_t box_shade(int W, int H, const BoxArgs& b, const LightSet& L, float* S
 hipError_t trace(TraceArgs a, hipStream_t st);
 // order[0..tiles) = the tiles (or chunks) by descending cost (ties in any order).
 hipError_t order_tiles(const unsigned* cost, int tiles, int* order, hipStream_t st);
+// Stage 5.  With esc_sums (the tracer's escape sums, esc_sums in TraceArgs) G
+// holds hit sums and each mean is formed here as (G + esc) / spp, the
+// tracer's own finishing arithmetic.
 hipError_t correct(int npx, int C, int K, int rho_mode, int cumulative, const float* I0,
                    const float* Aprev, const float* G, const float* S, const float* rho, float* E,
-                   float* Anext, hipStream_t st);
+                   float* Anext, hipStream_t st, const float* esc_sums = nullptr, int spp = 1);
 hipError_t compose(int npx, int C, int K, const float* rho, const float* S, const float* G, float* I,
                    hipStream_t st);
 // Apron-max levels of P at pyr, then the block tables at pyr + quad_off.

@@ -105,9 +105,10 @@ def test_size_limits_on_host():
 
 
 def test_workspace_holds_small_problem_records():
-    """Up to 16384 pixels (and 64 MiB of records) the solve workspace carries the
-    per-path tracer's segment records, (1 + C) floats per pixel, sample and
-    segment; beyond that it does not."""
+    """Up to 16384 pixels (and 64 MiB of records) the solve workspace ends with
+    the per-path tracer's segment records, (1 + C) floats per pixel, sample and
+    segment; otherwise (no segments, more pixels, more records) with the
+    per-pixel tracer's escape sums, C floats per pixel."""
     L = irtps.lib()
     n = ct.c_size_t()
     l = np.zeros((8, 3), np.float32)
@@ -122,8 +123,11 @@ def test_workspace_holds_small_problem_records():
     def align(x):
         return (x + 255) // 256 * 256
 
-    assert ws(64, 64, 1, 16, 1) - ws(64, 64, 1, 16, 0) == align(64 * 64 * 16 * 1 * 2 * 4)
-    assert ws(128, 128, 3, 32, 3) - ws(128, 128, 3, 32, 0) == align(128 * 128 * 32 * 3 * 4 * 4)
+    def esc(W, H, C):
+        return align(W * H * C * 4)
+
+    assert ws(64, 64, 1, 16, 1) - ws(64, 64, 1, 16, 0) == align(64 * 64 * 16 * 1 * 2 * 4) - esc(64, 64, 1)
+    assert ws(128, 128, 3, 32, 3) - ws(128, 128, 3, 32, 0) == align(128 * 128 * 32 * 3 * 4 * 4) - esc(128, 128, 3)
     assert ws(129, 128, 1, 16, 1) == ws(129, 128, 1, 16, 0)       # more than 16384 pixels
     assert ws(128, 128, 3, 128, 3) == ws(128, 128, 3, 128, 0)     # records above 64 MiB
 
@@ -187,7 +191,8 @@ def test_exact_r_flag_and_fill_workspace_on_host():
         return (x + 255) // 256 * 256
 
     for W, H, C in ((64, 64, 1), (37, 61, 3), (2, 300, 1), (1000, 3, 3)):
-        base = ws(W, H, C, 0, B=0)  # no records at B = 0
+        # no records at B = 0: the tail holds the escape sums, C floats per pixel
+        base = ws(W, H, C, 0, B=0) - align(W * H * C * 4)
         for r in range(1, 8):
             assert ws(W, H, C, irtps.flag_exact_r(r)) - base == align(4 * _fill_floats(W, H, C, True))
         b = ct.c_size_t()
