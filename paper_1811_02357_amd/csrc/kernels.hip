@@ -54,6 +54,10 @@ __device__ __forceinline__ Surface make_surface(const float* H, const float* pyr
     S.hzb = reinterpret_cast<const float4*>(tab + 30 * p4);
     S.nearh = tab + trv::near_horizon_offset(W, Hh);
     S.top = levels - 1;
+    S.Wm1 = W - 1;
+    S.Hm1 = Hh - 1;
+    S.fWm1 = (float)(W - 1);
+    S.fHm1 = (float)(Hh - 1);
     S.hmax = S.quad[0];  // quadrant (+x, +y) of block (0, 0): every sample
     return S;
 }

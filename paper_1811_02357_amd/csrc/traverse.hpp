@@ -112,6 +112,8 @@ struct Surface {
     int W, Hh;
     int QW, QH;          // blocks of the quadrant tables
     int top;             // index of the 1x1 level
+    int Wm1, Hm1;        // W - 1, Hh - 1
+    float fWm1, fHm1;    // the same as floats
     float hmax;          // highest sample
 };
 
@@ -372,8 +374,11 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
                 tY = x_exit ? t_o : t_exit;
             }
             // a skip climbs a level; a failed test descends one, or, at the
-            // finest skip level, falls through to the crossing
-            level = skip ? (l < S.top ? l + 1 : l) : (l > kMinSkipLevel ? l - 1 : l);
+            // finest skip level, falls through to the crossing.  A skipped cell
+            // is finite, so it keeps two samples from every border: 2^(l+1) <=
+            // W - 3 < 2^top, and the level climbed to is still below the 1x1
+            // top level (whose cell is +inf), so no clamp is needed.
+            level = skip ? l + 1 : (l > kMinSkipLevel ? l - 1 : l);
             cross = !skip && l <= kMinSkipLevel;
         }
     }
@@ -385,10 +390,10 @@ __device__ __forceinline__ int walker_step(Walker& w, const Surface& S, int& qi,
         const int m = xline ? mx : my;
         const int o_major = xline ? r.i0 : r.j0;
         const int major = __mul24(xline ? r.sx : r.sy, m) + o_major;  // sx, sy are +-1
-        const int n_major = xline ? S.W : S.Hh;
-        const int n_minor = xline ? S.Hh : S.W;
+        const int last_major = xline ? S.Wm1 : S.Hm1;
+        const float last_minor = xline ? S.fHm1 : S.fWm1;
         const float minor = fmaf(t_now, xline ? r.dy : r.dx, (float)(xline ? r.j0 : r.i0));
-        if ((unsigned)major > (unsigned)(n_major - 1) || !(minor >= 0.0f && minor <= (float)(n_minor - 1))) {
+        if ((unsigned)major > (unsigned)last_major || !(minor >= 0.0f && minor <= last_minor)) {
             res = kMiss;  // the ray has left the domain
         } else {
             const float fm = floorf(minor);
