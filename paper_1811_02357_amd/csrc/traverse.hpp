@@ -280,7 +280,8 @@ __device__ __forceinline__ int horizon_class(const Ray& r, const Surface& S) {
 // crossing beyond that travel is passed over.  The crossings passed over all
 // miss, and one outside the domain is followed only by others outside it (the
 // domain is convex and the walk's coordinates are monotone in t), so the
-// result is the flat walk's.  Called straight after walker_init.
+// result is the flat walk's.  Called straight after walker_finish (or
+// walker_init), before the walker's first step.
 __device__ __forceinline__ void walker_skip_near(Walker& w) {
     const Ray& r = w.r;
     const float hd2 = fmaf(r.dx, r.dx, r.dy * r.dy);
