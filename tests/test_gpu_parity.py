@@ -519,6 +519,22 @@ def test_solve_correction_modes(dev, rho_mode, flags, stop_tol):
     assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
 
 
+# Above the per-path limit the solve's tracer hands its escape sums to the
+# correction, which forms the means: with the sampling and walk options and with
+# no segments at all (B = 0: every sum is zero).
+@pytest.mark.parametrize("flags,bounces", [(irtps.FLAG_QUADRATURE, 2), (irtps.FLAG_FLAT_TRAVERSAL, 2), (0, 0)])
+def test_solve_per_pixel_tracer_options(dev, flags, bounces):
+    say(f"case: solve RGB fbm 160x120 flags={flags} B={bounces} (per-pixel tracer)")
+    sc = scenes.fbm_terrain(seed=12, size=160, channels=3, num_lights=8, env_shape=(16, 32),
+                            ptp=16.0, spp=16, bounces=bounces, iterations=2, render_spp=8, render_bounces=2)
+    sc.heights = np.ascontiguousarray(sc.heights[:120])
+    sc.normals = np.ascontiguousarray(sc.normals[:120])
+    sc.albedo = np.ascontiguousarray(sc.albedo[:, :120])
+    ref, got = _solve_both(sc, dev, flags=flags)
+    _compare_solve(ref, got, "fbm160x120")
+    assert np.array_equal(got["depth"], ref["depth"]) and np.array_equal(got["indirect"], ref["indirect"])
+
+
 def test_refill_tracer_every_chunk_shape(dev):
     """The single-job tracer hands pixels to lanes from 64-pixel chunks taken
     from a queue (row-major in the first iteration, heaviest first by the
